@@ -1,0 +1,135 @@
+"""CPU oracle for GraphCage / TOCAB (Chen 2019). TEST INFRASTRUCTURE ONLY.
+
+Only tests/, the smoke check and the benchmark's CPU-baseline leg may import
+this package. It shares no code with the GPU library: the plain C definitions
+live in oracle.c (FP64 / int64, single-threaded) and this module only
+marshals numpy arrays into them. Graphs are out-edge CSR (rowptr, colidx).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+INF32 = np.iinfo(np.int32).max
+UNIFORM, LEAK = 0, 1
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        lib = ctypes.CDLL(_build.LIB)
+        vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        lib.oracle_pagerank.argtypes = [i32, vp, vp, f64, i32, i32, vp, vp]
+        lib.oracle_ppr.argtypes = [i32, vp, vp, f64, i32, vp, vp]
+        lib.oracle_bfs.argtypes = [i32, vp, vp, i32, vp]
+        lib.oracle_dijkstra.argtypes = [i32, vp, vp, vp, i32, vp]
+        lib.oracle_transpose.argtypes = [i32, vp, vp, vp, vp, vp, vp]
+        lib.oracle_partition.argtypes = [i32, i32, vp, vp, vp, i32, i32, vp, vp,
+                                         vp, vp, vp, vp, vp, vp]
+        for f in ("oracle_pagerank", "oracle_ppr", "oracle_bfs", "oracle_dijkstra",
+                  "oracle_transpose", "oracle_partition"):
+            getattr(lib, f).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def pagerank(n, rowptr, colidx, d=0.85, iters=20, mode=UNIFORM, r0=None):
+    """FP64 PageRank iterate `iters` from r0 (default uniform 1/n)."""
+    rowptr, colidx = _i32(rowptr), _i32(colidx)
+    r0 = np.full(n, 1.0 / n) if r0 is None else np.ascontiguousarray(r0, dtype=np.float64)
+    out = np.empty(n, dtype=np.float64)
+    rc = _load().oracle_pagerank(n, _ptr(rowptr), _ptr(colidx), d, mode, iters, _ptr(r0), _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_pagerank rc={rc}")
+    return out
+
+
+def ppr(n, rowptr, colidx, p, d=0.85, iters=20):
+    """FP64 personalised PageRank iterate `iters` from r0 = p."""
+    rowptr, colidx = _i32(rowptr), _i32(colidx)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    out = np.empty(n, dtype=np.float64)
+    rc = _load().oracle_ppr(n, _ptr(rowptr), _ptr(colidx), d, iters, _ptr(p), _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_ppr rc={rc}")
+    return out
+
+
+def bfs(n, rowptr, colidx, source):
+    rowptr, colidx = _i32(rowptr), _i32(colidx)
+    out = np.empty(n, dtype=np.int32)
+    rc = _load().oracle_bfs(n, _ptr(rowptr), _ptr(colidx), int(source), _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_bfs rc={rc}")
+    return out
+
+
+def dijkstra(n, rowptr, colidx, weights, source):
+    rowptr, colidx, weights = _i32(rowptr), _i32(colidx), _i32(weights)
+    out = np.empty(n, dtype=np.int32)
+    rc = _load().oracle_dijkstra(n, _ptr(rowptr), _ptr(colidx), _ptr(weights), int(source), _ptr(out))
+    if rc != 0:
+        raise ValueError(f"oracle_dijkstra rc={rc}")
+    return out
+
+
+def transpose(n, rowptr, colidx, weights=None):
+    rowptr, colidx = _i32(rowptr), _i32(colidx)
+    weights = None if weights is None else _i32(weights)
+    t_rowptr = np.empty(n + 1, dtype=np.int32)
+    t_colidx = np.empty(colidx.shape[0], dtype=np.int32)
+    t_w = None if weights is None else np.empty(colidx.shape[0], dtype=np.int32)
+    rc = _load().oracle_transpose(n, _ptr(rowptr), _ptr(colidx), _ptr(weights), _ptr(t_rowptr),
+                                  _ptr(t_colidx), _ptr(t_w))
+    if rc != 0:
+        raise ValueError(f"oracle_transpose rc={rc}")
+    return t_rowptr, t_colidx, t_w
+
+
+class Partition:
+    """Reference TOCAB partition (see oracle_partition in oracle.c)."""
+
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+
+def partition(n_rows, n_cols, rowptr, colidx, W, k, weights=None):
+    rowptr, colidx = _i32(rowptr), _i32(colidx)
+    weights = None if weights is None else _i32(weights)
+    lib = _load()
+    B, P = ctypes.c_int64(), ctypes.c_int64()
+    rc = lib.oracle_partition(n_rows, n_cols, _ptr(rowptr), _ptr(colidx), _ptr(weights), W, k,
+                              ctypes.byref(B), ctypes.byref(P), None, None, None, None, None, None)
+    if rc != 0:
+        raise ValueError(f"oracle_partition rc={rc}")
+    B, P = B.value, P.value
+    R = (n_rows + k - 1) // k
+    m = colidx.shape[0]
+    blk_rowoff = np.empty(B + 1, dtype=np.int64)
+    row_ptr = np.empty(P + 1, dtype=np.int64)
+    id_map = np.empty(P, dtype=np.int32)
+    col = np.empty(m, dtype=np.int32)
+    wout = None if weights is None else np.empty(m, dtype=np.int32)
+    range_ptr = np.empty(B * (R + 1), dtype=np.int64)
+    B2, P2 = ctypes.c_int64(), ctypes.c_int64()
+    rc = lib.oracle_partition(n_rows, n_cols, _ptr(rowptr), _ptr(colidx), _ptr(weights), W, k,
+                              ctypes.byref(B2), ctypes.byref(P2), _ptr(blk_rowoff), _ptr(row_ptr),
+                              _ptr(id_map), _ptr(col), _ptr(wout), _ptr(range_ptr))
+    if rc != 0:
+        raise ValueError(f"oracle_partition rc={rc}")
+    return Partition(B=B, P=P, R=R, W=W, k=k, blk_rowoff=blk_rowoff, row_ptr=row_ptr,
+                     id_map=id_map, col=col, w=wout, range_ptr=range_ptr.reshape(B, R + 1))

@@ -1,0 +1,109 @@
+"""Pins the oracle's TOCAB partition (Section 3.1, preprocessing phase).
+
+Checked against invariants that define the partition independently of how it
+is built, against a brute-force count of distinct (row, block) pairs, and the
+block-count formula against the subgraph counts printed in Table 4.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from tests import graphs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def check_partition(n_rows, n_cols, rowptr, colidx, w, W, k, p):
+    m = colidx.shape[0]
+    B = -(-n_cols // W)
+    R = -(-n_rows // k)
+    assert p.B == B  # (iv)
+    # brute force: distinct (row, block) pairs (v)
+    rows = np.repeat(np.arange(n_rows, dtype=np.int64), np.diff(rowptr))
+    pairs = np.unique(rows * B + colidx // W) if m else np.zeros(0, np.int64)
+    assert p.P == pairs.shape[0]
+    assert p.blk_rowoff[0] == 0 and p.blk_rowoff[-1] == p.P
+    assert p.row_ptr[0] == 0 and p.row_ptr[-1] == m
+    # (i) mapping every local arc back through id_map gives exactly the arc multiset
+    lens = np.diff(p.row_ptr)
+    assert np.all(lens >= 1)  # (iii) no empty local row
+    back_rows = np.repeat(p.id_map.astype(np.int64), lens)
+    got = np.sort(back_rows * n_cols + p.col)
+    want = np.sort(rows * n_cols + colidx)
+    np.testing.assert_array_equal(got, want)
+    if w is not None:
+        gw = dict(zip((rows * n_cols + colidx).tolist(), w.tolist()))
+        assert all(gw[int(a)] == int(b) for a, b in zip(back_rows * n_cols + p.col, p.w))
+    for s in range(B):
+        lo, hi = p.blk_rowoff[s], p.blk_rowoff[s + 1]
+        ids = p.id_map[lo:hi]
+        assert np.all(np.diff(ids) > 0)  # (iii) ascending global ids
+        a0, a1 = p.row_ptr[lo], p.row_ptr[hi]
+        assert np.all(p.col[a0:a1] // W == s)  # (ii)
+        for l in range(lo, hi):  # columns ascending inside a local row
+            assert np.all(np.diff(p.col[p.row_ptr[l]:p.row_ptr[l + 1]]) > 0)
+        # (vi) range cuts partition id_map by floor(id / k)
+        rp = p.range_ptr[s]
+        assert rp[0] == lo and rp[R] == hi
+        for j in range(R):
+            seg = ids[rp[j] - lo:rp[j + 1] - lo]
+            assert np.all(seg // k == j)
+
+
+@pytest.mark.parametrize("g", graphs.all_small() + [gg.rmat(10, 16, seed=1), gg.grid(30, 33, 0.05, 3)],
+                         ids=lambda g: g.name)
+@pytest.mark.parametrize("W,k", [(1, 32), (2, 64), (8, 32), (64, 1024), (1 << 20, 32)])
+def test_partition_invariants(g, W, k):
+    w = g.with_weights(9).weights
+    # pull: blocks over the transposed graph's columns (sources)
+    tr, tc, tw = oracle.transpose(g.n, g.rowptr, g.colidx, w)
+    p = oracle.partition(g.n, g.n, tr, tc, W, k, tw)
+    check_partition(g.n, g.n, tr, tc, tw, W, k, p)
+    # push: the same code on the graph itself (blocks over destinations)
+    q = oracle.partition(g.n, g.n, g.rowptr, g.colidx, W, k, w)
+    check_partition(g.n, g.n, g.rowptr, g.colidx, w, W, k, q)
+
+
+def test_partition_blocked_sums_equal_unblocked():
+    """Summing each block's local rows back (what the merge does) gives the
+    unblocked per-row sums exactly for integer values."""
+    g = gg.rmat(11, 16, seed=4)
+    tr, tc, _ = oracle.transpose(g.n, g.rowptr, g.colidx)
+    vals = (np.arange(g.n, dtype=np.int64) * 7919) % 1009
+    want = np.add.reduceat(np.append(vals[tc], 0), tr[:-1])[:g.n] * (np.diff(tr) > 0)
+    for W in (1, 16, 512, 4096):
+        p = oracle.partition(g.n, g.n, tr, tc, W, 256)
+        part = np.add.reduceat(np.append(vals[p.col], 0), p.row_ptr[:-1])[:p.P]
+        got = np.zeros(g.n, np.int64)
+        np.add.at(got, p.id_map, part)
+        np.testing.assert_array_equal(got, want)
+
+
+def test_block_count_reproduces_table4():
+    """ceil(N / 2^18) matches every printed subgraph count once the rounding
+    of Table 2's vertex counts is allowed for; other widths do not."""
+    rows = []
+    with open(os.path.join(HERE, "golden", "table4_subgraph_counts.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                name, nv, count = line.split()
+                rows.append((name, float(nv), int(count)))
+    assert len(rows) == 8
+
+    def consistent(W):
+        ok = 0
+        for _, nv, count in rows:
+            digits = len(str(nv).split(".")[1]) if "." in str(nv) and not str(nv).endswith(".0") else 0
+            half = 0.5 * 10 ** (-digits) * 1e6
+            lo = math.ceil((nv * 1e6 - half) / W)
+            hi = math.ceil((nv * 1e6 + half) / W)
+            ok += lo <= count <= hi
+        return ok
+
+    assert consistent(1 << 18) == 8
+    for W in (256, 1 << 16, 1 << 17, 1 << 19, 1 << 20, 250000):
+        assert consistent(W) < 8
