@@ -1,0 +1,187 @@
+/*
+ * graphcage.h - C ABI of the MI355X (gfx950) GraphCage / TOCAB library.
+ *
+ * GraphCage (Chen, "GraphCage: Cache Aware Graph Processing on GPUs", 2019)
+ * runs vertex programs over a CSR graph in the pull direction (Algorithm 1)
+ * or the push direction (Algorithm 2) and adds throughput-oriented cache
+ * blocking (TOCAB, Section 3.1): a static 1D partition into subgraphs whose
+ * vertex values fit in the last-level cache, processed one block after the
+ * other (Algorithms 4 and 5) and merged range by range (Figure 5).
+ *
+ * Conventions shared by every call:
+ *  - Every function returns a gc_status. Arguments are checked before any
+ *    work is queued: on a non-zero return nothing was queued and no output
+ *    was touched; gc_last_error() then holds a message (per thread).
+ *  - Work is queued on the caller's HIP stream `stream` (NULL = the null
+ *    stream). Calls return before the GPU finishes unless stated otherwise;
+ *    device faults surface as GC_EHIP from a later synchronising call.
+ *  - A graph or partition handle keeps per-iteration scratch inside it, so
+ *    one handle must not be used from two streams at the same time.
+ *  - Vertex ids are int32 in [0, n); arc counts m < 2^31.
+ *  - Device buffers the caller passes stay owned by the caller.
+ *  - Memory the library needs comes from the allocator set with
+ *    gc_set_allocator (default: hipMalloc / hipFree).
+ */
+#ifndef GRAPHCAGE_H
+#define GRAPHCAGE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GC_OK = 0,
+  GC_EINVAL = -1,       /* bad argument or malformed graph                    */
+  GC_ENOMEM = -2,       /* the allocator returned NULL                        */
+  GC_EHIP = -3,         /* a HIP runtime call failed                          */
+  GC_EUNSUPPORTED = -4, /* valid request this build does not handle           */
+  GC_EOVERFLOW = -5     /* a result would not fit its integer type            */
+} gc_status;
+
+#define GC_UNREACHED INT32_MAX /* depth / distance of a vertex not reached     */
+
+/* graph_load_csr flags */
+#define GC_DEVICE_PTRS 1u /* rowptr/colidx/weight are device pointers          */
+#define GC_VALIDATE 2u    /* check monotone rowptr, column range, sorted rows,  */
+                          /* no self-loops and no duplicate arcs (host check)   */
+
+/* directions */
+#define GC_PULL 0 /* gather over in-arcs (transposed graph); blocks by source  */
+#define GC_PUSH 1 /* scatter over out-arcs; blocks by destination              */
+
+/* PageRank treatment of vertices without out-arcs (the paper leaves it open) */
+#define GC_DANGLING_UNIFORM 0 /* their rank is spread evenly (sum stays 1)     */
+#define GC_DANGLING_LEAK 1    /* their rank leaves the system                   */
+
+/* traversal policies (bfs_pull / sssp_pull) */
+#define GC_POLICY_PULL 0      /* every level: topology-driven pull             */
+#define GC_POLICY_PUSH 1      /* every level: data-driven push with a queue    */
+#define GC_POLICY_HEURISTIC 2 /* per level: working-set rule of Section 3.3    */
+
+typedef struct gc_graph_s* gc_graph;
+typedef struct gc_tocab_s* gc_tocab;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* gc_last_error(void);
+
+/* Replaces the device allocator used for every buffer the library owns.
+ * alloc(bytes, stream, ctx) returns device memory or NULL; release(ptr,
+ * stream, ctx) gives it back. Both NULL restores hipMalloc / hipFree. Must
+ * not be called while handles made with the previous allocator are alive. */
+int gc_set_allocator(void* (*alloc)(size_t bytes, hipStream_t stream, void* ctx),
+                     void (*release)(void* ptr, hipStream_t stream, void* ctx), void* ctx);
+
+/* Loads a graph given as out-arc CSR (row = source; Section 2.1, "CSR
+ * format"): rowptr int32[n+1], colidx int32[m], optional weight int32[m]
+ * (NULL: unweighted). With GC_DEVICE_PTRS the arrays are device memory,
+ * else host memory. The library copies them and builds on the GPU the
+ * transposed CSR the pull direction reads (row = destination, columns sorted
+ * ascending, weights carried along; Algorithm 1 takes G^T). Rows of the input
+ * must be sorted ascending without duplicates or self-loops (checked with
+ * GC_VALIDATE). Synchronises `stream` once. Free with graph_free. */
+int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* colidx,
+                   const int32_t* weight, uint32_t flags, hipStream_t stream, gc_graph* out);
+
+int graph_info(gc_graph g, int32_t* n, int64_t* m, int32_t* weighted);
+
+/* Copies the transposed CSR (row = destination) into caller buffers (device
+ * or host, any mix): t_rowptr int32[n+1], t_colidx int32[m], t_weight
+ * int32[m] (may be NULL). Queued on `stream`. */
+int graph_export_transpose(gc_graph g, int32_t* t_rowptr, int32_t* t_colidx, int32_t* t_weight,
+                           hipStream_t stream);
+
+int graph_free(gc_graph g);
+
+/* TOCAB preprocessing (Section 3.1; Figures 3 and 4). dir = GC_PULL blocks
+ * the transposed graph by source (column blocking), GC_PUSH blocks the graph
+ * itself by destination (row blocking); the same code does both.
+ * block_width W: power of two in [2^10, 2^26]; B = ceil(n / W) <= 32768.
+ * merge_range k: power of two in [256, 16384], width of the merge ranges of
+ * Figure 5 (0 = 4096). Inside block s only rows with at least one arc there
+ * get a local id, in ascending global order; id_map maps local to global.
+ * Synchronises `stream` once (it sizes its buffers). Free with tocab_free. */
+int tocab_partition(gc_graph g, int32_t dir, int32_t block_width, int32_t merge_range,
+                    hipStream_t stream, gc_tocab* out);
+
+/* B, P (number of local rows over all blocks), W, k, direction and the
+ * device bytes the partition holds. Any pointer may be NULL. */
+int tocab_info(gc_tocab t, int32_t* B, int64_t* P, int32_t* W, int32_t* k, int32_t* dir,
+               int64_t* bytes);
+
+/* Copies the partition into caller buffers (device or host). Layout, blocks
+ * concatenated in block order:
+ *   blk_rowoff int32[B+1]   first local row of each block
+ *   row_ptr    int32[P+1]   first arc of each local row
+ *   id_map     int32[P]     global row of each local row (ascending per block)
+ *   col        int32[m]     global column of each arc (ascending per row)
+ *   weight     int32[m]     arc weights (NULL to skip; unweighted: ignored)
+ *   range_ptr  int32[(R+1)*B], R = ceil(n / k): entry [j*B + s] is the first
+ *              local row of block s whose global id is >= j*k.
+ * Queued on `stream`. */
+int tocab_export(gc_tocab t, int32_t* blk_rowoff, int32_t* row_ptr, int32_t* id_map, int32_t* col,
+                 int32_t* weight, int32_t* range_ptr, hipStream_t stream);
+
+int tocab_free(gc_tocab t);
+
+/* PageRank iterations (Algorithm 1 pull, Algorithm 2 push; with t != NULL
+ * Algorithm 4 + Figure 5 merge for a GC_PULL partition, Algorithm 5 for a
+ * GC_PUSH partition). One iteration:
+ *   c[u] = r[u] / outdeg(u) (0 if outdeg(u) = 0), s[v] = sum_{u->v} c[u],
+ *   r'[v] = (1 - d)/n + d * (s[v] + D/n)   (UNIFORM, D = rank on vertices
+ *                                          without out-arcs; LEAK: no D/n)
+ * rank_in, rank_out: device float[n], must not overlap; after the call
+ * rank_out holds iterate k + iters given iterate k in rank_in (iters = 0
+ * copies). dir_if_plain selects pull or push when t == NULL. Sums are
+ * accumulated in FP64 inside a row; ranks are stored as FP32. Queues work
+ * only: no host synchronisation and no allocation. */
+int pagerank_iter(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, int32_t dangling,
+                  const float* rank_in, float* rank_out, int32_t iters, hipStream_t stream);
+
+/* Breadth-first search from `source` over out-arcs. depth: device
+ * int32[n] out, depth[source] = 0, GC_UNREACHED when unreachable. The pull
+ * levels are topology driven with status arrays (Section 3.3): with a
+ * GC_PULL partition t they run blocked, each block writing a local `next`
+ * that the merge reduces; t == NULL pulls over the whole transposed graph.
+ * policy chooses pull, data-driven push, or the working-set heuristic per
+ * level. levels (host, nullable) receives the number of levels run.
+ * Synchronises `stream` once per level to read the frontier size. */
+int bfs_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32_t* levels,
+             uint32_t policy, hipStream_t stream);
+
+/* Single-source shortest paths from `source` over out-arcs with the graph's
+ * positive weights: synchronous Bellman-Ford rounds that relax the in-arcs
+ * of every vertex from the vertices changed in the previous round (min-merge
+ * over blocks with a GC_PULL partition), or data-driven push rounds, chosen
+ * by `policy` as for bfs_pull. dist: device int32[n] out, GC_UNREACHED when
+ * unreachable. Requires a weighted graph (GC_EINVAL otherwise). Distances
+ * are int32: if a finite distance would reach INT32_MAX the call returns
+ * GC_EOVERFLOW (dist is then not meaningful). rounds (host, nullable)
+ * receives the number of rounds. Synchronises once per round. */
+int sssp_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* dist, int32_t* rounds,
+              uint32_t policy, hipStream_t stream);
+
+/* Waits for `stream` and reports a pending asynchronous HIP error. */
+int gc_sync(hipStream_t stream);
+
+/* Measurement support. While on, every kernel launch is bracketed by a
+ * pair of HIP events recorded on the launching stream, so per-kernel device
+ * time can be read back without an external profiler. enable = 1 clears
+ * old records and starts, 0 stops. gc_profile_count gives the number of
+ * distinct kernels recorded; gc_profile_get returns, for index in [0,
+ * count), the kernel's name (NUL-terminated, truncated to name_len), its
+ * summed event time in ms and its number of launches. Both wait for the
+ * recorded events to complete. */
+int gc_profile(int32_t enable);
+int gc_profile_count(int32_t* count);
+int gc_profile_get(int32_t index, char* name, int32_t name_len, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRAPHCAGE_H */

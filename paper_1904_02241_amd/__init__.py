@@ -1,0 +1,260 @@
+"""Python binding of the GraphCage / TOCAB HIP library (libgraphcage.so).
+
+Argument marshalling only: every step runs inside the library's HIP
+kernels. The functions carry the C ABI's names (include/graphcage.h).
+Device arrays are torch CUDA tensors (HIP on ROCm); host arrays are numpy
+arrays. PyTorch provides device memory (its caching allocator is installed
+as the library's allocator on import) and streams; it computes nothing.
+
+Importing fails loudly when the built library is missing: there is no
+fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgraphcage.so")
+
+GC_OK, GC_EINVAL, GC_ENOMEM, GC_EHIP, GC_EUNSUPPORTED, GC_EOVERFLOW = 0, -1, -2, -3, -4, -5
+GC_UNREACHED = np.iinfo(np.int32).max
+GC_DEVICE_PTRS, GC_VALIDATE = 1, 2
+GC_PULL, GC_PUSH = 0, 1
+GC_DANGLING_UNIFORM, GC_DANGLING_LEAK = 0, 1
+GC_POLICY_PULL, GC_POLICY_PUSH, GC_POLICY_HEURISTIC = 0, 1, 2
+
+# every exported entry point, with (restype, argtypes)
+_vp, _i32, _i64, _u32, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_float
+_p_i32, _p_i64 = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+_ALLOC_FN = ctypes.CFUNCTYPE(_vp, ctypes.c_size_t, _vp, _vp)
+_FREE_FN = ctypes.CFUNCTYPE(None, _vp, _vp, _vp)
+SIGNATURES = {
+    "gc_last_error": (ctypes.c_char_p, []),
+    "gc_set_allocator": (ctypes.c_int, [_ALLOC_FN, _FREE_FN, _vp]),
+    "graph_load_csr": (ctypes.c_int, [_i32, _i64, _vp, _vp, _vp, _u32, _vp, ctypes.POINTER(_vp)]),
+    "graph_info": (ctypes.c_int, [_vp, _p_i32, _p_i64, _p_i32]),
+    "graph_export_transpose": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "graph_free": (ctypes.c_int, [_vp]),
+    "tocab_partition": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, ctypes.POINTER(_vp)]),
+    "tocab_info": (ctypes.c_int, [_vp, _p_i32, _p_i64, _p_i32, _p_i32, _p_i32, _p_i64]),
+    "tocab_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "tocab_free": (ctypes.c_int, [_vp]),
+    "pagerank_iter": (ctypes.c_int, [_vp, _vp, _i32, _f32, _i32, _vp, _vp, _i32, _vp]),
+    "bfs_pull": (ctypes.c_int, [_vp, _vp, _i32, _vp, _p_i32, _u32, _vp]),
+    "sssp_pull": (ctypes.c_int, [_vp, _vp, _i32, _vp, _p_i32, _u32, _vp]),
+    "gc_sync": (ctypes.c_int, [_vp]),
+    "gc_profile": (ctypes.c_int, [_i32]),
+    "gc_profile_count": (ctypes.c_int, [_p_i32]),
+    "gc_profile_get": (ctypes.c_int, [_i32, ctypes.c_char_p, _i32, ctypes.POINTER(ctypes.c_double), _p_i64]),
+}
+
+
+class GraphCageError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_1904_02241_amd/build.py "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc, what):
+    if rc != GC_OK:
+        raise GraphCageError(rc, f"{what}: {lib.gc_last_error().decode()}")
+
+
+# ---------------------------------------------------------------------------
+# torch as the device allocator and stream provider
+
+def _torch():
+    import torch
+    return torch
+
+
+@_ALLOC_FN
+def _torch_alloc(nbytes, stream, ctx):
+    try:
+        return _torch().cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:
+        return None
+
+
+@_FREE_FN
+def _torch_free(ptr, stream, ctx):
+    _torch().cuda.caching_allocator_delete(int(ptr))
+
+
+def use_torch_allocator(enable=True):
+    """Route the library's own device buffers through torch's caching allocator."""
+    if enable:
+        _check(lib.gc_set_allocator(_torch_alloc, _torch_free, None), "gc_set_allocator")
+    else:
+        _check(lib.gc_set_allocator(_ALLOC_FN(), _FREE_FN(), None), "gc_set_allocator")
+
+
+use_torch_allocator(True)
+
+
+def _stream(stream):
+    if stream is None:
+        return _torch().cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+def _ptr(x):
+    """Device or host address of a torch tensor or numpy array (contiguous)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        assert x.flags["C_CONTIGUOUS"], "array must be contiguous"
+        return x.ctypes.data
+    assert x.is_contiguous(), "tensor must be contiguous"
+    return x.data_ptr()
+
+
+def _is_device(x):
+    return not isinstance(x, np.ndarray) and x.is_cuda
+
+
+# ---------------------------------------------------------------------------
+# handles
+
+class Graph:
+    def __init__(self, handle, n, m, weighted):
+        self.handle, self.n, self.m, self.weighted = handle, n, m, weighted
+
+    def free(self):
+        if self.handle:
+            _check(lib.graph_free(self.handle), "graph_free")
+            self.handle = None
+
+
+class Tocab:
+    def __init__(self, handle, graph):
+        self.handle, self.graph = handle, graph
+        self.info = tocab_info(self)
+
+    def free(self):
+        if self.handle:
+            _check(lib.tocab_free(self.handle), "tocab_free")
+            self.handle = None
+
+
+def _h(obj):
+    return None if obj is None else obj.handle
+
+
+# ---------------------------------------------------------------------------
+# C ABI, one wrapper per entry point
+
+def gc_last_error():
+    return lib.gc_last_error().decode()
+
+
+def gc_sync(stream=None):
+    _check(lib.gc_sync(_stream(stream)), "gc_sync")
+
+
+def graph_load_csr(rowptr, colidx, weight=None, validate=False, stream=None):
+    """Out-arc CSR (numpy int32 arrays or CUDA int32 tensors) -> Graph."""
+    n = int(rowptr.shape[0]) - 1
+    m = int(colidx.shape[0])
+    dev = _is_device(rowptr)
+    for a in (colidx, weight):
+        if a is not None and _is_device(a) != dev:
+            raise ValueError("rowptr, colidx and weight must all be host or all be device arrays")
+    flags = (GC_DEVICE_PTRS if dev else 0) | (GC_VALIDATE if validate else 0)
+    out = ctypes.c_void_p()
+    _check(lib.graph_load_csr(n, m, _ptr(rowptr), _ptr(colidx), _ptr(weight), flags, _stream(stream),
+                              ctypes.byref(out)), "graph_load_csr")
+    return Graph(out, n, m, weight is not None)
+
+
+def graph_info(g):
+    n, m, w = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+    _check(lib.graph_info(_h(g), ctypes.byref(n), ctypes.byref(m), ctypes.byref(w)), "graph_info")
+    return n.value, m.value, bool(w.value)
+
+
+def graph_export_transpose(g, t_rowptr, t_colidx, t_weight=None, stream=None):
+    _check(lib.graph_export_transpose(_h(g), _ptr(t_rowptr), _ptr(t_colidx), _ptr(t_weight), _stream(stream)),
+           "graph_export_transpose")
+
+
+def graph_free(g):
+    g.free()
+
+
+def tocab_partition(g, direction, block_width, merge_range=0, stream=None):
+    out = ctypes.c_void_p()
+    _check(lib.tocab_partition(_h(g), direction, block_width, merge_range, _stream(stream), ctypes.byref(out)),
+           "tocab_partition")
+    return Tocab(out, g)
+
+
+def tocab_info(t):
+    B, P, W, k, d, b = (ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(),
+                        ctypes.c_int64())
+    _check(lib.tocab_info(_h(t), ctypes.byref(B), ctypes.byref(P), ctypes.byref(W), ctypes.byref(k), ctypes.byref(d),
+                          ctypes.byref(b)), "tocab_info")
+    return {"B": B.value, "P": P.value, "W": W.value, "k": k.value, "dir": d.value, "bytes": b.value}
+
+
+def tocab_export(t, blk_rowoff, row_ptr, id_map, col, weight, range_ptr, stream=None):
+    _check(lib.tocab_export(_h(t), _ptr(blk_rowoff), _ptr(row_ptr), _ptr(id_map), _ptr(col), _ptr(weight),
+                            _ptr(range_ptr), _stream(stream)), "tocab_export")
+
+
+def tocab_free(t):
+    t.free()
+
+
+def pagerank_iter(g, t, dir_if_plain, damping, dangling, rank_in, rank_out, iters, stream=None):
+    _check(lib.pagerank_iter(_h(g), _h(t), dir_if_plain, damping, dangling, _ptr(rank_in), _ptr(rank_out), iters,
+                             _stream(stream)), "pagerank_iter")
+
+
+def bfs_pull(g, t, source, depth, policy=GC_POLICY_PULL, stream=None):
+    """Returns the number of levels run."""
+    levels = ctypes.c_int32(0)
+    _check(lib.bfs_pull(_h(g), _h(t), int(source), _ptr(depth), ctypes.byref(levels), policy, _stream(stream)),
+           "bfs_pull")
+    return levels.value
+
+
+def sssp_pull(g, t, source, dist, policy=GC_POLICY_PULL, stream=None):
+    """Returns the number of rounds run."""
+    rounds = ctypes.c_int32(0)
+    _check(lib.sssp_pull(_h(g), _h(t), int(source), _ptr(dist), ctypes.byref(rounds), policy, _stream(stream)),
+           "sssp_pull")
+    return rounds.value
+
+
+def gc_profile(enable):
+    _check(lib.gc_profile(1 if enable else 0), "gc_profile")
+
+
+def gc_profile_read():
+    """{kernel name: (total ms, launches)} of the events recorded so far."""
+    cnt = ctypes.c_int32()
+    _check(lib.gc_profile_count(ctypes.byref(cnt)), "gc_profile_count")
+    out = {}
+    for i in range(cnt.value):
+        name = ctypes.create_string_buffer(128)
+        ms, nl = ctypes.c_double(), ctypes.c_int64()
+        _check(lib.gc_profile_get(i, name, 128, ctypes.byref(ms), ctypes.byref(nl)), "gc_profile_get")
+        out[name.value.decode()] = (ms.value, nl.value)
+    return out

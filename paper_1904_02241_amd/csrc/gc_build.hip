@@ -1,0 +1,548 @@
+// Graph construction on the GPU: exclusive scan, CSR transpose with sorted
+// rows, and the TOCAB static partition (Section 3.1, preprocessing phase).
+// Runs once per graph / per block width; timed apart from the iterations.
+
+#include <algorithm>
+#include <climits>
+
+#include "gc_device.h"
+#include "gc_internal.h"
+
+namespace {
+
+using gcd::kWave;
+
+// ---------------------------------------------------------------------------
+// Exclusive scan (reduce tiles -> scan tile totals -> rescan tiles).
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// Work-group exclusive scan of one int per thread; *total gets the sum.
+__device__ int wg_excl_scan(int v, int* total) {
+  __shared__ int wave_tot[kScanThreads / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int incl = gcd::wave_incl_scan(v);
+  if (lane == kWave - 1) wave_tot[wid] = incl;
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kScanThreads / kWave; ++w) {
+    const int x = wave_tot[w];
+    off += (w < wid) ? x : 0;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* __restrict__ in, int64_t n,
+                                                              int32_t* __restrict__ tile_sum) {
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t idx = base + i * kScanThreads + threadIdx.x;
+    if (idx < n) s += in[idx];
+  }
+  int tot;
+  wg_excl_scan(s, &tot);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+}
+
+// One work-group scans all tile sums in place (exclusive).
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int32_t* __restrict__ tile_sum, int64_t nt) {
+  int carry = 0;
+  for (int64_t base = 0; base < nt; base += kScanTile) {
+    int vals[kScanItems];
+    int local = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      const int64_t idx = base + static_cast<int64_t>(threadIdx.x) * kScanItems + i;
+      vals[i] = idx < nt ? tile_sum[idx] : 0;
+      local += vals[i];
+    }
+    int tot;
+    int run = carry + wg_excl_scan(local, &tot);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      const int64_t idx = base + static_cast<int64_t>(threadIdx.x) * kScanItems + i;
+      if (idx < nt) tile_sum[idx] = run;
+      run += vals[i];
+    }
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* __restrict__ in,
+                                                             int32_t* __restrict__ out, int64_t n,
+                                                             const int32_t* __restrict__ tile_off) {
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile +
+                       static_cast<int64_t>(threadIdx.x) * kScanItems;
+  int vals[kScanItems];
+  int local = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t idx = base + i;
+    vals[i] = idx < n ? in[idx] : 0;
+    local += vals[i];
+  }
+  int tot;
+  int run = tile_off[blockIdx.x] + wg_excl_scan(local, &tot);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t idx = base + i;
+    if (idx < n) out[idx] = run;
+    if (idx == n - 1) out[n] = run + vals[i];
+    run += vals[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Transpose: in-degree count, scatter of (source, weight) keys, per-row sort.
+
+__global__ void k_indegree(const int32_t* __restrict__ colidx, int64_t m, int32_t* __restrict__ cnt) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < m; e += stride)
+    atomicAdd(&cnt[colidx[e]], 1);
+}
+
+constexpr int kScatterTile = 4096;
+
+// Row owning arc e: the last r with rowptr[r] <= e, searched in [lo, hi].
+__device__ __forceinline__ int32_t owner_row(const int32_t* rowptr, int32_t lo, int32_t hi, int64_t e) {
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo + 1) >> 1);
+    if (rowptr[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ rowptr, int32_t n,
+                                                 const int32_t* __restrict__ colidx,
+                                                 const int32_t* __restrict__ w, int64_t m,
+                                                 int32_t* __restrict__ cursor, uint64_t* __restrict__ keys) {
+  __shared__ int32_t r_lo, r_hi;
+  const int64_t e0 = static_cast<int64_t>(blockIdx.x) * kScatterTile;
+  const int64_t e1 = min(e0 + kScatterTile, m);
+  if (threadIdx.x == 0) {
+    r_lo = owner_row(rowptr, 0, n, e0);
+    r_hi = owner_row(rowptr, 0, n, e1 - 1);
+  }
+  __syncthreads();
+  const int32_t lo = r_lo, hi = r_hi;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int32_t u = owner_row(rowptr, lo, hi, e);
+    const int32_t v = colidx[e];
+    const int32_t pos = atomicAdd(&cursor[v], 1);
+    const uint32_t wv = w ? static_cast<uint32_t>(w[e]) : 0u;
+    keys[pos] = (static_cast<uint64_t>(static_cast<uint32_t>(u)) << 32) | wv;
+  }
+}
+
+constexpr int kSmallRow = 32;
+constexpr int kMidRow = 4096;  // rows up to this length sort inside LDS
+
+__device__ __forceinline__ void unpack_to(uint64_t key, int32_t* col, int32_t* w, int64_t pos) {
+  col[pos] = static_cast<int32_t>(key >> 32);
+  if (w) w[pos] = static_cast<int32_t>(key & 0xFFFFFFFFull);
+}
+
+// Rows of at most kSmallRow keys: insertion sort in place, then unpack.
+// Longer rows are queued for the work-group sorters.
+__global__ __launch_bounds__(256) void k_sort_small(const int32_t* __restrict__ t_rowptr, int32_t n,
+                                                    uint64_t* __restrict__ keys, int32_t* __restrict__ t_col,
+                                                    int32_t* __restrict__ t_w, int32_t* __restrict__ lists,
+                                                    int32_t* __restrict__ list_len) {
+  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t b = t_rowptr[v], e = t_rowptr[v + 1];
+  const int32_t len = e - b;
+  if (len > kMidRow) {
+    lists[n + atomicAdd(&list_len[1], 1)] = v;  // second half of lists: large rows
+    return;
+  }
+  if (len > kSmallRow) {
+    lists[atomicAdd(&list_len[0], 1)] = v;
+    return;
+  }
+  uint64_t* a = keys + b;
+  for (int32_t i = 1; i < len; ++i) {
+    const uint64_t x = a[i];
+    int32_t j = i - 1;
+    while (j >= 0 && a[j] > x) {
+      a[j + 1] = a[j];
+      --j;
+    }
+    a[j + 1] = x;
+  }
+  for (int32_t i = 0; i < len; ++i) unpack_to(a[i], t_col, t_w, b + i);
+}
+
+// Bitonic sort of `cnt` keys staged in LDS (padded to a power of two with
+// the largest key), ascending. All threads of the work-group take part.
+__device__ void lds_bitonic(uint64_t* s, int32_t cnt) {
+  int32_t p2 = 1;
+  while (p2 < cnt) p2 <<= 1;
+  for (int32_t i = cnt + threadIdx.x; i < p2; i += blockDim.x) s[i] = ~0ull;
+  __syncthreads();
+  for (int32_t size = 2; size <= p2; size <<= 1) {
+    for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int32_t i = threadIdx.x; i < (p2 >> 1); i += blockDim.x) {
+        const int32_t lo = 2 * i - (i & (stride - 1));
+        const int32_t hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const uint64_t a = s[lo], b = s[hi];
+        if ((a > b) == up) {
+          s[lo] = b;
+          s[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sort_mid(const int32_t* __restrict__ t_rowptr,
+                                                  const int32_t* __restrict__ rows, uint64_t* __restrict__ keys,
+                                                  int32_t* __restrict__ t_col, int32_t* __restrict__ t_w) {
+  __shared__ uint64_t s[kMidRow];
+  const int32_t v = rows[blockIdx.x];
+  const int32_t b = t_rowptr[v], len = t_rowptr[v + 1] - b;
+  for (int32_t i = threadIdx.x; i < len; i += blockDim.x) s[i] = keys[b + i];
+  __syncthreads();
+  lds_bitonic(s, len);
+  for (int32_t i = threadIdx.x; i < len; i += blockDim.x) unpack_to(s[i], t_col, t_w, b + i);
+}
+
+// Rows longer than kMidRow: sort kMidRow-sized chunks in LDS, then merge
+// runs pairwise (merge-path split per thread), ping-ponging between the
+// key buffer and `alt`; the last pass unpacks.
+__global__ __launch_bounds__(256) void k_sort_large(const int32_t* __restrict__ t_rowptr,
+                                                    const int32_t* __restrict__ rows, uint64_t* __restrict__ keys,
+                                                    uint64_t* __restrict__ alt, int32_t* __restrict__ t_col,
+                                                    int32_t* __restrict__ t_w) {
+  __shared__ uint64_t s[kMidRow];
+  const int32_t v = rows[blockIdx.x];
+  const int64_t b = t_rowptr[v];
+  const int64_t len = t_rowptr[v + 1] - b;
+  for (int64_t c0 = 0; c0 < len; c0 += kMidRow) {
+    const int32_t cnt = static_cast<int32_t>(min<int64_t>(kMidRow, len - c0));
+    for (int32_t i = threadIdx.x; i < cnt; i += blockDim.x) s[i] = keys[b + c0 + i];
+    __syncthreads();
+    lds_bitonic(s, cnt);
+    for (int32_t i = threadIdx.x; i < cnt; i += blockDim.x) keys[b + c0 + i] = s[i];
+    __syncthreads();
+  }
+  uint64_t* src = keys + b;
+  uint64_t* dst = alt + b;
+  const int64_t per = (len + blockDim.x - 1) / blockDim.x;
+  for (int64_t width = kMidRow; width < len; width <<= 1) {
+    int64_t p = static_cast<int64_t>(threadIdx.x) * per;
+    const int64_t pend = min(len, p + per);
+    while (p < pend) {
+      const int64_t pair = (p / (2 * width)) * (2 * width);
+      const int64_t a0 = pair, a1 = min(pair + width, len);
+      const int64_t b0 = a1, b1 = min(pair + 2 * width, len);
+      const int64_t la = a1 - a0, lb = b1 - b0;
+      const int64_t d = p - pair;
+      int64_t lo = max<int64_t>(0, d - lb), hi = min(d, la);
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (src[a0 + mid] < src[b0 + d - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+      }
+      int64_t i = lo, j = d - lo;
+      const int64_t stop = min(pend, pair + la + lb);
+      for (; p < stop; ++p) {
+        const bool take_a = (j >= lb) || (i < la && src[a0 + i] < src[b0 + j]);
+        dst[p] = take_a ? src[a0 + i++] : src[b0 + j++];
+      }
+    }
+    __syncthreads();
+    uint64_t* t = src;
+    src = dst;
+    dst = t;
+  }
+  for (int64_t i = threadIdx.x; i < len; i += blockDim.x) unpack_to(src[i], t_col, t_w, b + i);
+}
+
+// ---------------------------------------------------------------------------
+// TOCAB partition.
+//
+// One wave per merge range j (rows [j*k, (j+1)*k)). The wave takes the range's
+// rows 64 at a time, one row per lane, and visits the (row, block) segments
+// in ascending block order across the wave: in each round the smallest
+// current block s among the lanes is found, the lanes sitting on s are
+// ranked by lane (= by row, so local ids stay ascending), and they jump past
+// their segment with a binary search. Counting mode tallies rows per block;
+// assigning mode hands out local ids from the per-block bases of the range.
+
+__device__ __forceinline__ int32_t first_at_least(const int32_t* a, int32_t lo, int32_t hi, int64_t key) {
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if (static_cast<int64_t>(a[mid]) < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <bool kAssign>
+__global__ __launch_bounds__(64) void k_part_walk(const int32_t* __restrict__ a_rowptr,
+                                                  const int32_t* __restrict__ a_col, int32_t n_rows,
+                                                  int32_t log2W, int32_t B, int32_t log2k,
+                                                  int32_t* __restrict__ cnt_jmajor,
+                                                  const int32_t* __restrict__ range_ptr,
+                                                  int32_t* __restrict__ id_map, int32_t* __restrict__ len,
+                                                  int32_t* __restrict__ seg_start) {
+  extern __shared__ int32_t base[];  // [B], touched by lane 0 only inside the walk
+  const int32_t j = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int32_t s = lane; s < B; s += kWave)
+    base[s] = kAssign ? range_ptr[static_cast<int64_t>(j) * B + s] : 0;
+  __syncthreads();
+  const int32_t r_begin = j << log2k;
+  const int32_t r_end = static_cast<int32_t>(min<int64_t>(n_rows, static_cast<int64_t>(r_begin) + (1 << log2k)));
+  for (int32_t rb = r_begin; rb < r_end; rb += kWave) {
+    const int32_t r = rb + lane;
+    int32_t pos = 0, end = 0;
+    if (r < r_end) {
+      pos = a_rowptr[r];
+      end = a_rowptr[r + 1];
+    }
+    int32_t cur = pos < end ? (a_col[pos] >> log2W) : INT_MAX;
+    for (;;) {
+      const int32_t smin = gcd::wave_min(cur);
+      if (smin == INT_MAX) break;
+      const bool mine = cur == smin;
+      const uint64_t mask = __ballot(mine);
+      int32_t b0 = 0;
+      if (lane == 0) {
+        b0 = base[smin];
+        base[smin] = b0 + __popcll(mask);
+      }
+      b0 = __shfl(b0, 0, kWave);
+      if (mine) {
+        const int32_t seg_end = first_at_least(a_col, pos, end, (static_cast<int64_t>(smin) + 1) << log2W);
+        if (kAssign) {
+          const int32_t l = b0 + __popcll(mask & gcd::lanemask_lt());
+          id_map[l] = r;
+          len[l] = seg_end - pos;
+          seg_start[l] = pos;
+        }
+        pos = seg_end;
+        cur = pos < end ? (a_col[pos] >> log2W) : INT_MAX;
+      }
+    }
+  }
+  if (!kAssign) {
+    __syncthreads();
+    for (int32_t s = lane; s < B; s += kWave) cnt_jmajor[static_cast<int64_t>(j) * B + s] = base[s];
+  }
+}
+
+__global__ void k_transpose_counts(const int32_t* __restrict__ cnt_jmajor, int32_t* __restrict__ cnt_smajor,
+                                   int32_t B, int32_t R) {
+  const int64_t total = static_cast<int64_t>(B) * R;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int64_t s = i / R, j = i - s * R;
+    cnt_smajor[i] = cnt_jmajor[j * B + s];
+  }
+}
+
+// range_ptr[j*B + s] = first local row of block s at range j (j = R: block end)
+__global__ void k_range_ptr(const int32_t* __restrict__ base_smajor, int32_t B, int32_t R,
+                            int32_t* __restrict__ range_ptr, int32_t* __restrict__ blk_rowoff) {
+  const int64_t total = static_cast<int64_t>(R + 1) * B;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int64_t j = i / B, s = i - j * B;
+    range_ptr[i] = (j < R) ? base_smajor[s * R + j] : base_smajor[(s + 1) * R];
+    if (j == 0) blk_rowoff[s] = base_smajor[s * R];
+    if (i == 0) blk_rowoff[B] = base_smajor[static_cast<int64_t>(B) * R];
+  }
+}
+
+// Copies every local row's segment of columns (and weights); rows longer
+// than a wave are copied by the whole wave.
+__global__ __launch_bounds__(256) void k_part_copy(const int32_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ seg_start, int64_t P,
+                                                   const int32_t* __restrict__ a_col,
+                                                   const int32_t* __restrict__ a_w, int32_t* __restrict__ col,
+                                                   int32_t* __restrict__ w) {
+  const int64_t l = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  int32_t dst = 0, src = 0, cnt = 0;
+  if (l < P) {
+    dst = row_ptr[l];
+    cnt = row_ptr[l + 1] - dst;
+    src = seg_start[l];
+  }
+  const bool wide = cnt > kWave;
+  if (!wide) {
+    for (int32_t i = 0; i < cnt; ++i) {
+      col[dst + i] = a_col[src + i];
+      if (w) w[dst + i] = a_w[src + i];
+    }
+  }
+  uint64_t pending = __ballot(wide);
+  while (pending) {
+    const int owner = __ffsll(static_cast<long long>(pending)) - 1;
+    pending &= pending - 1;
+    const int32_t d2 = __shfl(dst, owner, kWave), s2 = __shfl(src, owner, kWave), c2 = __shfl(cnt, owner, kWave);
+    for (int32_t i = lane; i < c2; i += kWave) {
+      col[d2 + i] = a_col[s2 + i];
+      if (w) w[d2 + i] = a_w[s2 + i];
+    }
+  }
+}
+
+// Structural check that keeps later kernels in bounds: rowptr[0] = 0,
+// rowptr[n] = m, rowptr non-decreasing, every column in [0, n).
+__global__ void k_check_csr(const int32_t* __restrict__ rowptr, int32_t n, const int32_t* __restrict__ colidx,
+                            int64_t m, int32_t* __restrict__ bad) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t top = m > n ? m : n;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < top; i += stride) {
+    if (i < n) {
+      const int32_t a = rowptr[i], b = rowptr[i + 1];
+      if (b < a || a < 0 || b > m) atomicOr(bad, 1);
+      if (i == 0 && a != 0) atomicOr(bad, 1);
+      if (i == n - 1 && b != m) atomicOr(bad, 1);
+    }
+    if (i < m) {
+      const int32_t v = colidx[i];
+      if (v < 0 || v >= n) atomicOr(bad, 2);
+    }
+  }
+}
+
+inline int grid_for(int64_t items, int threads, int cap = 1 << 20) {
+  const int64_t g = (items + threads - 1) / threads;
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, cap)));
+}
+
+}  // namespace
+
+namespace gcx {
+
+hipError_t check_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* colidx, int32_t* bad_out,
+                     hipStream_t s) {
+  Buf bad(sizeof(int32_t), s);
+  if (!bad.p) return hipErrorOutOfMemory;
+  GC_HIP_TRY(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+  k_check_csr<<<grid_for(std::max<int64_t>(n, m), 256, 65536), 256, 0, s>>>(rowptr, n, colidx, m,
+                                                                              bad.as<int32_t>());
+  GC_HIP_TRY(hipGetLastError());
+  GC_HIP_TRY(hipMemcpyAsync(bad_out, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  return hipStreamSynchronize(s);
+}
+
+hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
+  if (n == 0) return hipMemsetAsync(out, 0, sizeof(int32_t), s);
+  const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  Buf tile(sizeof(int32_t) * tiles, s);
+  if (!tile.p) return hipErrorOutOfMemory;
+  k_scan_reduce<<<tiles, kScanThreads, 0, s>>>(in, n, tile.as<int32_t>());
+  k_scan_top<<<1, kScanThreads, 0, s>>>(tile.as<int32_t>(), tiles);
+  k_scan_apply<<<tiles, kScanThreads, 0, s>>>(in, out, n, tile.as<int32_t>());
+  GC_HIP_TRY(hipGetLastError());
+  return hipStreamSynchronize(s);  // the tile buffer is released on return
+}
+
+hipError_t build_transpose(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* colidx,
+                           const int32_t* w, int32_t* t_rowptr, int32_t* t_colidx, int32_t* t_w,
+                           hipStream_t s) {
+  Buf cnt(sizeof(int32_t) * (static_cast<size_t>(n) + 1), s);
+  Buf lists(sizeof(int32_t) * 2 * static_cast<size_t>(n), s);
+  Buf list_len(sizeof(int32_t) * 2, s);
+  Buf keys(sizeof(uint64_t) * std::max<int64_t>(m, 1), s);
+  if (!cnt.p || !lists.p || !list_len.p || !keys.p) return hipErrorOutOfMemory;
+  GC_HIP_TRY(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * n, s));
+  GC_HIP_TRY(hipMemsetAsync(list_len.p, 0, sizeof(int32_t) * 2, s));
+  if (m > 0) k_indegree<<<grid_for(m, 256, 65536), 256, 0, s>>>(colidx, m, cnt.as<int32_t>());
+  GC_HIP_TRY(hipGetLastError());
+  GC_HIP_TRY(scan_exclusive(cnt.as<int32_t>(), t_rowptr, n, s));
+  GC_HIP_TRY(hipMemcpyAsync(cnt.p, t_rowptr, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+  if (m > 0)
+    k_scatter<<<grid_for(m, kScatterTile), 256, 0, s>>>(rowptr, n, colidx, w, m, cnt.as<int32_t>(),
+                                                         keys.as<uint64_t>());
+  k_sort_small<<<grid_for(n, 256), 256, 0, s>>>(t_rowptr, n, keys.as<uint64_t>(), t_colidx, t_w,
+                                                lists.as<int32_t>(), list_len.as<int32_t>());
+  GC_HIP_TRY(hipGetLastError());
+  int32_t counts[2];
+  GC_HIP_TRY(hipMemcpyAsync(counts, list_len.p, sizeof(counts), hipMemcpyDeviceToHost, s));
+  GC_HIP_TRY(hipStreamSynchronize(s));
+  if (counts[0] > 0)
+    k_sort_mid<<<counts[0], 256, 0, s>>>(t_rowptr, lists.as<int32_t>(), keys.as<uint64_t>(), t_colidx, t_w);
+  if (counts[1] > 0) {
+    Buf alt(sizeof(uint64_t) * m, s);
+    if (!alt.p) return hipErrorOutOfMemory;
+    k_sort_large<<<counts[1], 256, 0, s>>>(t_rowptr, lists.as<int32_t>() + n, keys.as<uint64_t>(),
+                                           alt.as<uint64_t>(), t_colidx, t_w);
+    GC_HIP_TRY(hipGetLastError());
+    GC_HIP_TRY(hipStreamSynchronize(s));
+  }
+  GC_HIP_TRY(hipGetLastError());
+  return hipStreamSynchronize(s);
+}
+
+hipError_t build_partition(gc_tocab t, const int32_t* a_rowptr, const int32_t* a_col, const int32_t* a_w,
+                           hipStream_t s) {
+  const int32_t B = t->B, R = t->R;
+  const int64_t BR = static_cast<int64_t>(B) * R;
+  Buf cnt(sizeof(int32_t) * BR, s), cnt_s(sizeof(int32_t) * BR, s), base_s(sizeof(int32_t) * (BR + 1), s);
+  if (!cnt.p || !cnt_s.p || !base_s.p) return hipErrorOutOfMemory;
+  const size_t lds = sizeof(int32_t) * B;
+  GC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_part_walk<false>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  GC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_part_walk<true>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  k_part_walk<false><<<R, kWave, lds, s>>>(a_rowptr, a_col, t->n_rows, t->log2W, B, t->log2k,
+                                           cnt.as<int32_t>(), nullptr, nullptr, nullptr, nullptr);
+  k_transpose_counts<<<grid_for(BR, 256, 65536), 256, 0, s>>>(cnt.as<int32_t>(), cnt_s.as<int32_t>(), B, R);
+  GC_HIP_TRY(hipGetLastError());
+  GC_HIP_TRY(scan_exclusive(cnt_s.as<int32_t>(), base_s.as<int32_t>(), BR, s));
+
+  t->range_ptr = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * (R + 1) * static_cast<size_t>(B), s));
+  t->blk_rowoff = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * (B + 1), s));
+  if (!t->range_ptr || !t->blk_rowoff) return hipErrorOutOfMemory;
+  k_range_ptr<<<grid_for(static_cast<int64_t>(R + 1) * B, 256, 65536), 256, 0, s>>>(
+      base_s.as<int32_t>(), B, R, t->range_ptr, t->blk_rowoff);
+  GC_HIP_TRY(hipGetLastError());
+  int32_t P32 = 0;
+  GC_HIP_TRY(hipMemcpyAsync(&P32, base_s.as<int32_t>() + BR, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GC_HIP_TRY(hipStreamSynchronize(s));
+  const int64_t P = P32;
+  t->P = P;
+  const size_t Pn = static_cast<size_t>(std::max<int64_t>(P, 1));
+  const size_t mn = static_cast<size_t>(std::max<int64_t>(t->m, 1));
+  t->id_map = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * Pn, s));
+  t->row_ptr = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * (Pn + 1), s));
+  t->partial = static_cast<float*>(dev_alloc(sizeof(float) * Pn, s));
+  t->pmin = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * Pn, s));
+  t->col = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * mn, s));
+  if (t->weighted) t->w = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * mn, s));
+  if (!t->id_map || !t->row_ptr || !t->partial || !t->pmin || !t->col || (t->weighted && !t->w))
+    return hipErrorOutOfMemory;
+  t->bytes = sizeof(int32_t) * ((R + 1) * static_cast<int64_t>(B) + B + 1 + 4 * static_cast<int64_t>(Pn) + 1 +
+                                mn * (t->weighted ? 2 : 1));
+
+  Buf len(sizeof(int32_t) * Pn, s), seg(sizeof(int32_t) * Pn, s);
+  if (!len.p || !seg.p) return hipErrorOutOfMemory;
+  k_part_walk<true><<<R, kWave, lds, s>>>(a_rowptr, a_col, t->n_rows, t->log2W, B, t->log2k, nullptr,
+                                          t->range_ptr, t->id_map, len.as<int32_t>(), seg.as<int32_t>());
+  GC_HIP_TRY(hipGetLastError());
+  GC_HIP_TRY(scan_exclusive(len.as<int32_t>(), t->row_ptr, P, s));
+  if (P > 0)
+    k_part_copy<<<grid_for(P, 256, INT_MAX), 256, 0, s>>>(t->row_ptr, seg.as<int32_t>(), P, a_col,
+                                                          t->weighted ? a_w : nullptr, t->col, t->w);
+  GC_HIP_TRY(hipGetLastError());
+  return hipStreamSynchronize(s);
+}
+
+}  // namespace gcx

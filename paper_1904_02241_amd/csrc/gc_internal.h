@@ -1,0 +1,129 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "graphcage.h"
+
+// ---------------------------------------------------------------------------
+// Handles
+
+struct gc_graph_s {
+  int32_t n = 0;
+  int64_t m = 0;
+  bool weighted = false;
+  // out-arc CSR (row = source), as loaded
+  int32_t* rowptr = nullptr;
+  int32_t* colidx = nullptr;
+  int32_t* w = nullptr;
+  // transposed CSR (row = destination, columns ascending)
+  int32_t* t_rowptr = nullptr;
+  int32_t* t_colidx = nullptr;
+  int32_t* t_w = nullptr;
+  // PageRank scratch: contributions (two buffers for the fused plain pull),
+  // push accumulators, FP64 dangling partials / totals and a done counter
+  float* contrib[2] = {nullptr, nullptr};
+  float* sums = nullptr;
+  double* dpart = nullptr;    // one slot per apply work-group
+  double* dtotal = nullptr;   // [2] ping-pong dangling totals
+  unsigned* counter = nullptr;
+  int32_t dpart_slots = 0;
+  // traversal scratch
+  uint8_t* front = nullptr;   // status arrays (Section 3.3)
+  uint8_t* next = nullptr;
+  int32_t* queue[2] = {nullptr, nullptr};
+  int32_t* stats = nullptr;     // device counters read back once per level
+  int32_t* stats_host = nullptr;  // pinned mirror
+  int64_t bytes = 0;
+};
+
+struct gc_tocab_s {
+  gc_graph g = nullptr;
+  int32_t dir = GC_PULL;
+  int32_t W = 0, log2W = 0, k = 0, log2k = 0, B = 0, R = 0;
+  int32_t n_rows = 0, n_cols = 0;
+  int64_t P = 0;
+  int64_t m = 0;
+  bool weighted = false;
+  int32_t* blk_rowoff = nullptr;  // [B+1]
+  int32_t* row_ptr = nullptr;     // [P+1]
+  int32_t* id_map = nullptr;      // [P]
+  int32_t* col = nullptr;         // [m]
+  int32_t* w = nullptr;           // [m] or null
+  int32_t* range_ptr = nullptr;   // [(R+1)*B], j-major
+  float* partial = nullptr;       // [P] pull partial sums (Algorithm 4)
+  int32_t* pmin = nullptr;        // [P] traversal partials (next flags / min)
+  int64_t bytes = 0;
+};
+
+// ---------------------------------------------------------------------------
+// Runtime helpers (gc_runtime.hip)
+
+namespace gcx {
+
+void set_error(const char* fmt, ...);
+void* dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+// RAII buffer from the library allocator
+struct Buf {
+  void* p = nullptr;
+  hipStream_t s = nullptr;
+  Buf() = default;
+  Buf(size_t bytes, hipStream_t st) : p(dev_alloc(bytes, st)), s(st) {}
+  ~Buf() { if (p) dev_free(p, s); }
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  template <class T> T* as() const { return static_cast<T*>(p); }
+  void* release() { void* q = p; p = nullptr; return q; }
+};
+
+// ---- construction kernels (gc_build.hip) ----
+// Device-side structural check of an out-arc CSR; *bad_out != 0 if broken.
+hipError_t check_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* colidx, int32_t* bad_out,
+                     hipStream_t s);
+// Exclusive scan of int32 `in[0..n)` into `out[0..n]` (out[n] = total).
+hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t s);
+// Transposed CSR with rows sorted by column; weights carried (w may be null).
+hipError_t build_transpose(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* colidx,
+                           const int32_t* w, int32_t* t_rowptr, int32_t* t_colidx, int32_t* t_w,
+                           hipStream_t s);
+// TOCAB partition of CSR A (see tocab_partition); fills t's arrays.
+hipError_t build_partition(gc_tocab t, const int32_t* a_rowptr, const int32_t* a_col,
+                           const int32_t* a_w, hipStream_t s);
+
+// ---- PageRank (gc_pagerank.hip) ----
+hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int32_t dangling,
+                        const float* rank_in, float* rank_out, int32_t iters, hipStream_t s);
+
+// ---- traversal (gc_traverse.hip) ----
+hipError_t bfs_run(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32_t* levels,
+                   uint32_t policy, hipStream_t s);
+hipError_t sssp_run(gc_graph g, gc_tocab t, int32_t source, int32_t* dist, int32_t* rounds,
+                    uint32_t policy, hipStream_t s, bool* overflow);
+
+// Records HIP events around the launches made in its scope while
+// profiling is on (gc_profile); a no-op otherwise.
+class ProfScope {
+ public:
+  ProfScope(const char* name, hipStream_t s);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  const char* name_;
+  hipStream_t s_;
+  hipEvent_t start_ = nullptr, stop_ = nullptr;
+};
+
+}  // namespace gcx
+
+#define GC_HIP_TRY(expr)                    \
+  do {                                      \
+    hipError_t e_ = (expr);                 \
+    if (e_ != hipSuccess) return e_;        \
+  } while (0)

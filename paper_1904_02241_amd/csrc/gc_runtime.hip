@@ -1,0 +1,398 @@
+// Host side of the C ABI: error reporting, the device allocator hook,
+// argument validation (done before anything is queued), handle lifetime.
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "gc_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+void* (*g_alloc)(size_t, hipStream_t, void*) = nullptr;
+void (*g_release)(void*, hipStream_t, void*) = nullptr;
+void* g_ctx = nullptr;
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  if (e == hipErrorOutOfMemory) return fail(GC_ENOMEM, "%s: out of device memory", where);
+  return fail(GC_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int32_t ilog2(int64_t x) {
+  int32_t r = 0;
+  while ((int64_t(1) << r) < x) ++r;
+  return r;
+}
+
+// Host-side structural check of an out-arc CSR (GC_VALIDATE).
+int validate_host(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* colidx, const int32_t* w) {
+  if (rowptr[0] != 0) return fail(GC_EINVAL, "rowptr[0] = %d, expected 0", rowptr[0]);
+  if (rowptr[n] != m) return fail(GC_EINVAL, "rowptr[n] = %d but m = %lld", rowptr[n], (long long)m);
+  for (int32_t u = 0; u < n; ++u) {
+    if (rowptr[u + 1] < rowptr[u]) return fail(GC_EINVAL, "rowptr decreases at row %d", u);
+    for (int32_t j = rowptr[u]; j < rowptr[u + 1]; ++j) {
+      const int32_t v = colidx[j];
+      if (v < 0 || v >= n) return fail(GC_EINVAL, "colidx[%d] = %d out of range [0, %d)", j, v, n);
+      if (v == u) return fail(GC_EINVAL, "self-loop at vertex %d", u);
+      if (j > rowptr[u] && colidx[j - 1] >= v)
+        return fail(GC_EINVAL, "row %d not strictly ascending at arc %d", u, j);
+      if (w && w[j] <= 0) return fail(GC_EINVAL, "weight[%d] = %d is not positive", j, w[j]);
+    }
+  }
+  return GC_OK;
+}
+
+// True when p is device memory (or managed memory) usable by kernels.
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+void free_graph(gc_graph g) {
+  if (!g) return;
+  void* bufs[] = {g->rowptr, g->colidx, g->w, g->t_rowptr, g->t_colidx, g->t_w, g->contrib[0], g->contrib[1],
+                  g->sums, g->dpart, g->dtotal, g->counter, g->front, g->next, g->queue[0], g->queue[1],
+                  g->stats};
+  for (void* p : bufs)
+    if (p) gcx::dev_free(p, nullptr);
+  if (g->stats_host) (void)hipHostFree(g->stats_host);
+  delete g;
+}
+
+void free_tocab(gc_tocab t) {
+  if (!t) return;
+  void* bufs[] = {t->blk_rowoff, t->row_ptr, t->id_map, t->col, t->w, t->range_ptr, t->partial, t->pmin};
+  for (void* p : bufs)
+    if (p) gcx::dev_free(p, nullptr);
+  delete t;
+}
+
+}  // namespace
+
+namespace gcx {
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+void* dev_alloc(size_t bytes, hipStream_t s) {
+  if (bytes == 0) bytes = 1;
+  if (g_alloc) return g_alloc(bytes, s, g_ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dev_free(void* p, hipStream_t s) {
+  if (!p) return;
+  if (g_release) g_release(p, s, g_ctx);
+  else (void)hipFree(p);
+}
+
+}  // namespace gcx
+
+extern "C" {
+
+const char* gc_last_error(void) { return g_err; }
+
+int gc_set_allocator(void* (*alloc)(size_t, hipStream_t, void*), void (*release)(void*, hipStream_t, void*),
+                     void* ctx) {
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail(GC_EINVAL, "gc_set_allocator: give both functions or neither");
+  g_alloc = alloc;
+  g_release = release;
+  g_ctx = alloc ? ctx : nullptr;
+  return GC_OK;
+}
+
+int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* colidx, const int32_t* weight,
+                   uint32_t flags, hipStream_t stream, gc_graph* out) {
+  g_err[0] = '\0';
+  if (!out) return fail(GC_EINVAL, "graph_load_csr: out is NULL");
+  *out = nullptr;
+  if (n <= 0) return fail(GC_EINVAL, "graph_load_csr: n = %d must be positive", n);
+  if (n > INT32_MAX - 1) return fail(GC_EINVAL, "graph_load_csr: n too large");
+  if (m < 0 || m >= INT32_MAX) return fail(GC_EINVAL, "graph_load_csr: m = %lld outside [0, 2^31)", (long long)m);
+  if (!rowptr || (m > 0 && !colidx)) return fail(GC_EINVAL, "graph_load_csr: NULL rowptr or colidx");
+  if (flags & ~(GC_DEVICE_PTRS | GC_VALIDATE)) return fail(GC_EINVAL, "graph_load_csr: unknown flags 0x%x", flags);
+  const bool dev = (flags & GC_DEVICE_PTRS) != 0;
+
+  if (flags & GC_VALIDATE) {
+    std::vector<int32_t> hr, hc, hw;
+    const int32_t *pr = rowptr, *pc = colidx, *pw = weight;
+    if (dev) {
+      hr.resize(static_cast<size_t>(n) + 1);
+      hc.resize(static_cast<size_t>(m));
+      if (weight) hw.resize(static_cast<size_t>(m));
+      hipError_t e = hipMemcpy(hr.data(), rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost);
+      if (e == hipSuccess && m > 0) e = hipMemcpy(hc.data(), colidx, sizeof(int32_t) * m, hipMemcpyDeviceToHost);
+      if (e == hipSuccess && m > 0 && weight)
+        e = hipMemcpy(hw.data(), weight, sizeof(int32_t) * m, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(e, "graph_load_csr (validate copy)");
+      pr = hr.data();
+      pc = hc.data();
+      pw = weight ? hw.data() : nullptr;
+    }
+    const int rc = validate_host(n, m, pr, pc, pw);
+    if (rc != GC_OK) return rc;
+  } else if (!dev) {
+    if (rowptr[0] != 0 || rowptr[n] != m)
+      return fail(GC_EINVAL, "graph_load_csr: rowptr[0] must be 0 and rowptr[n] must equal m");
+  }
+
+  gc_graph g = new (std::nothrow) gc_graph_s;
+  if (!g) return fail(GC_ENOMEM, "graph_load_csr: host allocation failed");
+  g->n = n;
+  g->m = m;
+  g->weighted = weight != nullptr;
+  const size_t nb = sizeof(int32_t) * (static_cast<size_t>(n) + 1);
+  const size_t mb = sizeof(int32_t) * static_cast<size_t>(m > 0 ? m : 1);
+  g->dpart_slots = (n + 255) / 256;
+  g->rowptr = static_cast<int32_t*>(gcx::dev_alloc(nb, stream));
+  g->colidx = static_cast<int32_t*>(gcx::dev_alloc(mb, stream));
+  g->t_rowptr = static_cast<int32_t*>(gcx::dev_alloc(nb, stream));
+  g->t_colidx = static_cast<int32_t*>(gcx::dev_alloc(mb, stream));
+  if (g->weighted) {
+    g->w = static_cast<int32_t*>(gcx::dev_alloc(mb, stream));
+    g->t_w = static_cast<int32_t*>(gcx::dev_alloc(mb, stream));
+  }
+  g->contrib[0] = static_cast<float*>(gcx::dev_alloc(sizeof(float) * n, stream));
+  g->contrib[1] = static_cast<float*>(gcx::dev_alloc(sizeof(float) * n, stream));
+  g->sums = static_cast<float*>(gcx::dev_alloc(sizeof(float) * n, stream));
+  g->dpart = static_cast<double*>(gcx::dev_alloc(sizeof(double) * g->dpart_slots, stream));
+  g->dtotal = static_cast<double*>(gcx::dev_alloc(sizeof(double) * 2, stream));
+  g->counter = static_cast<unsigned*>(gcx::dev_alloc(sizeof(unsigned) * 4, stream));
+  g->front = static_cast<uint8_t*>(gcx::dev_alloc(static_cast<size_t>(n), stream));
+  g->next = static_cast<uint8_t*>(gcx::dev_alloc(static_cast<size_t>(n), stream));
+  g->queue[0] = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * n, stream));
+  g->queue[1] = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * n, stream));
+  g->stats = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * 16, stream));
+  bool ok = g->rowptr && g->colidx && g->t_rowptr && g->t_colidx && (!g->weighted || (g->w && g->t_w)) &&
+            g->contrib[0] && g->contrib[1] && g->sums && g->dpart && g->dtotal && g->counter && g->front &&
+            g->next && g->queue[0] && g->queue[1] && g->stats;
+  if (ok && hipHostMalloc(reinterpret_cast<void**>(&g->stats_host), sizeof(int32_t) * 16, hipHostMallocDefault) !=
+                hipSuccess) {
+    g->stats_host = nullptr;
+    ok = false;
+  }
+  if (!ok) {
+    free_graph(g);
+    return fail(GC_ENOMEM, "graph_load_csr: device allocation failed");
+  }
+  g->bytes = 2 * static_cast<int64_t>(nb) + 2 * static_cast<int64_t>(mb) * (g->weighted ? 2 : 1) +
+             12 * static_cast<int64_t>(n) + 2 * static_cast<int64_t>(n) + 8 * static_cast<int64_t>(n);
+
+  const hipMemcpyKind kind = hipMemcpyDefault;  // the runtime resolves host or device sources
+  hipError_t e = hipMemcpyAsync(g->rowptr, rowptr, nb, kind, stream);
+  if (e == hipSuccess && m > 0) e = hipMemcpyAsync(g->colidx, colidx, sizeof(int32_t) * m, kind, stream);
+  if (e == hipSuccess && m > 0 && g->weighted) e = hipMemcpyAsync(g->w, weight, sizeof(int32_t) * m, kind, stream);
+  int32_t bad = 0;
+  if (e == hipSuccess) e = gcx::check_csr(n, m, g->rowptr, g->colidx, &bad, stream);
+  if (e == hipSuccess && bad) {
+    free_graph(g);
+    return fail(GC_EINVAL, "graph_load_csr: %s", (bad & 1) ? "rowptr is not a valid offset array for m arcs"
+                                                            : "a column index is outside [0, n)");
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(g->counter, 0, sizeof(unsigned) * 4, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(g->dtotal, 0, sizeof(double) * 2, stream);
+  if (e == hipSuccess)
+    e = gcx::build_transpose(n, m, g->rowptr, g->colidx, g->w, g->t_rowptr, g->t_colidx, g->t_w, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    free_graph(g);
+    return hip_fail(e, "graph_load_csr");
+  }
+  *out = g;
+  return GC_OK;
+}
+
+int graph_info(gc_graph g, int32_t* n, int64_t* m, int32_t* weighted) {
+  if (!g) return fail(GC_EINVAL, "graph_info: NULL graph");
+  if (n) *n = g->n;
+  if (m) *m = g->m;
+  if (weighted) *weighted = g->weighted ? 1 : 0;
+  return GC_OK;
+}
+
+int graph_export_transpose(gc_graph g, int32_t* t_rowptr, int32_t* t_colidx, int32_t* t_weight,
+                           hipStream_t stream) {
+  if (!g) return fail(GC_EINVAL, "graph_export_transpose: NULL graph");
+  if (!t_rowptr || (g->m > 0 && !t_colidx)) return fail(GC_EINVAL, "graph_export_transpose: NULL output");
+  if (t_weight && !g->weighted) return fail(GC_EINVAL, "graph_export_transpose: graph has no weights");
+  hipError_t e = hipMemcpyAsync(t_rowptr, g->t_rowptr, sizeof(int32_t) * (g->n + 1), hipMemcpyDefault, stream);
+  if (e == hipSuccess && g->m > 0)
+    e = hipMemcpyAsync(t_colidx, g->t_colidx, sizeof(int32_t) * g->m, hipMemcpyDefault, stream);
+  if (e == hipSuccess && g->m > 0 && t_weight)
+    e = hipMemcpyAsync(t_weight, g->t_w, sizeof(int32_t) * g->m, hipMemcpyDefault, stream);
+  return e == hipSuccess ? GC_OK : hip_fail(e, "graph_export_transpose");
+}
+
+int graph_free(gc_graph g) {
+  if (!g) return fail(GC_EINVAL, "graph_free: NULL graph");
+  (void)hipDeviceSynchronize();
+  free_graph(g);
+  return GC_OK;
+}
+
+int tocab_partition(gc_graph g, int32_t dir, int32_t block_width, int32_t merge_range, hipStream_t stream,
+                    gc_tocab* out) {
+  g_err[0] = '\0';
+  if (!out) return fail(GC_EINVAL, "tocab_partition: out is NULL");
+  *out = nullptr;
+  if (!g) return fail(GC_EINVAL, "tocab_partition: NULL graph");
+  if (dir != GC_PULL && dir != GC_PUSH) return fail(GC_EINVAL, "tocab_partition: dir must be GC_PULL or GC_PUSH");
+  if (!is_pow2(block_width) || block_width < (1 << 10) || block_width > (1 << 26))
+    return fail(GC_EINVAL, "tocab_partition: block_width %d is not a power of two in [2^10, 2^26]", block_width);
+  if (merge_range == 0) merge_range = 4096;
+  if (!is_pow2(merge_range) || merge_range < 256 || merge_range > (1 << 14))
+    return fail(GC_EINVAL, "tocab_partition: merge_range %d is not a power of two in [256, 16384]", merge_range);
+  const int64_t B = (static_cast<int64_t>(g->n) + block_width - 1) / block_width;
+  const int64_t R = (static_cast<int64_t>(g->n) + merge_range - 1) / merge_range;
+  if (B > 32768) return fail(GC_EINVAL, "tocab_partition: %lld blocks exceed 32768; use a wider block", (long long)B);
+  if (B * (R + 1) > (int64_t(1) << 28))
+    return fail(GC_EUNSUPPORTED, "tocab_partition: %lld x %lld range table too large; widen block or merge range",
+                (long long)B, (long long)(R + 1));
+
+  gc_tocab t = new (std::nothrow) gc_tocab_s;
+  if (!t) return fail(GC_ENOMEM, "tocab_partition: host allocation failed");
+  t->g = g;
+  t->dir = dir;
+  t->W = block_width;
+  t->log2W = ilog2(block_width);
+  t->k = merge_range;
+  t->log2k = ilog2(merge_range);
+  t->B = static_cast<int32_t>(B);
+  t->R = static_cast<int32_t>(R);
+  t->n_rows = g->n;
+  t->n_cols = g->n;
+  t->m = g->m;
+  t->weighted = g->weighted;
+  const int32_t* a_rowptr = dir == GC_PULL ? g->t_rowptr : g->rowptr;
+  const int32_t* a_col = dir == GC_PULL ? g->t_colidx : g->colidx;
+  const int32_t* a_w = dir == GC_PULL ? g->t_w : g->w;
+  hipError_t e = gcx::build_partition(t, a_rowptr, a_col, a_w, stream);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(stream);
+    free_tocab(t);
+    return hip_fail(e, "tocab_partition");
+  }
+  *out = t;
+  return GC_OK;
+}
+
+int tocab_info(gc_tocab t, int32_t* B, int64_t* P, int32_t* W, int32_t* k, int32_t* dir, int64_t* bytes) {
+  if (!t) return fail(GC_EINVAL, "tocab_info: NULL partition");
+  if (B) *B = t->B;
+  if (P) *P = t->P;
+  if (W) *W = t->W;
+  if (k) *k = t->k;
+  if (dir) *dir = t->dir;
+  if (bytes) *bytes = t->bytes;
+  return GC_OK;
+}
+
+int tocab_export(gc_tocab t, int32_t* blk_rowoff, int32_t* row_ptr, int32_t* id_map, int32_t* col,
+                 int32_t* weight, int32_t* range_ptr, hipStream_t stream) {
+  if (!t) return fail(GC_EINVAL, "tocab_export: NULL partition");
+  if (!blk_rowoff || !row_ptr || !id_map || !col || !range_ptr) return fail(GC_EINVAL, "tocab_export: NULL output");
+  const hipMemcpyKind k = hipMemcpyDefault;
+  hipError_t e = hipMemcpyAsync(blk_rowoff, t->blk_rowoff, sizeof(int32_t) * (t->B + 1), k, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(row_ptr, t->row_ptr, sizeof(int32_t) * (t->P + 1), k, stream);
+  if (e == hipSuccess && t->P > 0) e = hipMemcpyAsync(id_map, t->id_map, sizeof(int32_t) * t->P, k, stream);
+  if (e == hipSuccess && t->m > 0) e = hipMemcpyAsync(col, t->col, sizeof(int32_t) * t->m, k, stream);
+  if (e == hipSuccess && t->m > 0 && weight && t->weighted)
+    e = hipMemcpyAsync(weight, t->w, sizeof(int32_t) * t->m, k, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(range_ptr, t->range_ptr, sizeof(int32_t) * (t->R + 1) * static_cast<size_t>(t->B), k, stream);
+  return e == hipSuccess ? GC_OK : hip_fail(e, "tocab_export");
+}
+
+int tocab_free(gc_tocab t) {
+  if (!t) return fail(GC_EINVAL, "tocab_free: NULL partition");
+  (void)hipDeviceSynchronize();
+  free_tocab(t);
+  return GC_OK;
+}
+
+int pagerank_iter(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, int32_t dangling,
+                  const float* rank_in, float* rank_out, int32_t iters, hipStream_t stream) {
+  if (!g) return fail(GC_EINVAL, "pagerank_iter: NULL graph");
+  if (t && t->g != g) return fail(GC_EINVAL, "pagerank_iter: partition belongs to another graph");
+  if (!t && dir_if_plain != GC_PULL && dir_if_plain != GC_PUSH)
+    return fail(GC_EINVAL, "pagerank_iter: dir_if_plain must be GC_PULL or GC_PUSH");
+  if (!(damping >= 0.0f && damping <= 1.0f)) return fail(GC_EINVAL, "pagerank_iter: damping outside [0, 1]");
+  if (dangling != GC_DANGLING_UNIFORM && dangling != GC_DANGLING_LEAK)
+    return fail(GC_EINVAL, "pagerank_iter: unknown dangling mode %d", dangling);
+  if (!rank_in || !rank_out) return fail(GC_EINVAL, "pagerank_iter: NULL rank buffer");
+  if (iters < 0) return fail(GC_EINVAL, "pagerank_iter: iters < 0");
+  if (!is_device_ptr(rank_in) || !is_device_ptr(rank_out))
+    return fail(GC_EINVAL, "pagerank_iter: rank buffers must be device memory");
+  const char* a = reinterpret_cast<const char*>(rank_in);
+  const char* b = reinterpret_cast<const char*>(rank_out);
+  const size_t bytes = sizeof(float) * static_cast<size_t>(g->n);
+  if (a < b + bytes && b < a + bytes) return fail(GC_EINVAL, "pagerank_iter: rank_in and rank_out overlap");
+  const hipError_t e = gcx::pagerank_run(g, t, dir_if_plain, damping, dangling, rank_in, rank_out, iters, stream);
+  return e == hipSuccess ? GC_OK : hip_fail(e, "pagerank_iter");
+}
+
+int bfs_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32_t* levels, uint32_t policy,
+             hipStream_t stream) {
+  if (!g) return fail(GC_EINVAL, "bfs_pull: NULL graph");
+  if (t && t->g != g) return fail(GC_EINVAL, "bfs_pull: partition belongs to another graph");
+  if (t && t->dir != GC_PULL) return fail(GC_EINVAL, "bfs_pull: partition must be GC_PULL");
+  if (source < 0 || source >= g->n) return fail(GC_EINVAL, "bfs_pull: source %d outside [0, %d)", source, g->n);
+  if (!depth) return fail(GC_EINVAL, "bfs_pull: NULL depth");
+  if (!is_device_ptr(depth)) return fail(GC_EINVAL, "bfs_pull: depth must be device memory");
+  if (policy > GC_POLICY_HEURISTIC) return fail(GC_EINVAL, "bfs_pull: unknown policy %u", policy);
+  const hipError_t e = gcx::bfs_run(g, t, source, depth, levels, policy, stream);
+  if (e == hipErrorNotSupported) return fail(GC_EUNSUPPORTED, "bfs_pull: not available in this build");
+  return e == hipSuccess ? GC_OK : hip_fail(e, "bfs_pull");
+}
+
+int sssp_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* dist, int32_t* rounds, uint32_t policy,
+              hipStream_t stream) {
+  if (!g) return fail(GC_EINVAL, "sssp_pull: NULL graph");
+  if (!g->weighted) return fail(GC_EINVAL, "sssp_pull: graph has no weights");
+  if (t && t->g != g) return fail(GC_EINVAL, "sssp_pull: partition belongs to another graph");
+  if (t && t->dir != GC_PULL) return fail(GC_EINVAL, "sssp_pull: partition must be GC_PULL");
+  if (source < 0 || source >= g->n) return fail(GC_EINVAL, "sssp_pull: source %d outside [0, %d)", source, g->n);
+  if (!dist) return fail(GC_EINVAL, "sssp_pull: NULL dist");
+  if (!is_device_ptr(dist)) return fail(GC_EINVAL, "sssp_pull: dist must be device memory");
+  if (policy > GC_POLICY_HEURISTIC) return fail(GC_EINVAL, "sssp_pull: unknown policy %u", policy);
+  bool overflow = false;
+  const hipError_t e = gcx::sssp_run(g, t, source, dist, rounds, policy, stream, &overflow);
+  if (e == hipErrorNotSupported) return fail(GC_EUNSUPPORTED, "sssp_pull: not available in this build");
+  if (e != hipSuccess) return hip_fail(e, "sssp_pull");
+  if (overflow) return fail(GC_EOVERFLOW, "sssp_pull: a distance reached INT32_MAX");
+  return GC_OK;
+}
+
+int gc_sync(hipStream_t stream) {
+  const hipError_t e = hipStreamSynchronize(stream);
+  return e == hipSuccess ? GC_OK : hip_fail(e, "gc_sync");
+}
+
+}  // extern "C"
