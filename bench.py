@@ -170,7 +170,7 @@ def main():
     head = forms[0]
     hres = results[head]
     info = hres["partition"] or {}
-    kern = {k: v for k, v in hres["kernels"].items() if k != "pr_init"}
+    kern = {k: v for k, v in hres["kernels"].items() if k not in ("pr_init", "pr_dangling")}
     dom = max(kern, key=lambda k: kern[k][0])
     dom_ms = kern[dom][0] / kern[dom][1]
     per_launch = kernel_bytes(dom, n, m, info)

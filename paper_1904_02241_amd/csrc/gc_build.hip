@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <vector>
 
 #include "gc_device.h"
 #include "gc_internal.h"
@@ -421,6 +422,48 @@ __global__ void k_check_csr(const int32_t* __restrict__ rowptr, int32_t n, const
   }
 }
 
+__global__ void k_tile_rows(const int32_t* __restrict__ row_ptr, int32_t rows, int32_t tile_arcs, int32_t n_tiles,
+                            int32_t* __restrict__ tile_row) {
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > n_tiles) return;
+  if (t == n_tiles) {
+    tile_row[t] = rows;
+    return;
+  }
+  tile_row[t] = first_at_least(row_ptr, 0, rows, static_cast<int64_t>(t) * tile_arcs);
+}
+
+__global__ void k_col16(const int32_t* __restrict__ col, int64_t m, int32_t mask, uint16_t* __restrict__ col16) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < m; i += stride)
+    col16[i] = static_cast<uint16_t>(col[i] & mask);
+}
+
+// First arc of every block (row_ptr at the block's first local row).
+__global__ void k_block_arcs(const int32_t* __restrict__ blk_rowoff, const int32_t* __restrict__ row_ptr, int32_t B,
+                             int32_t* __restrict__ out) {
+  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s <= B) out[s] = row_ptr[blk_rowoff[s]];
+}
+
+// Chunk c = (block s, j-th slice of kLdsChunkArcs arcs): rows of block s
+// whose first arc lies in [first_arc(s) + j*A, first_arc(s) + (j+1)*A).
+__global__ void k_chunks(const int32_t* __restrict__ blk_rowoff, const int32_t* __restrict__ row_ptr,
+                         const int32_t* __restrict__ chunk_first, const int32_t* __restrict__ blk_of_chunk,
+                         int32_t n_chunks, int32_t chunk_arcs, int32_t* __restrict__ beg, int32_t* __restrict__ end,
+                         int32_t* __restrict__ blk) {
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_chunks) return;
+  const int32_t s = blk_of_chunk[c];
+  const int32_t j = c - chunk_first[s];
+  const int32_t lo = blk_rowoff[s], hi = blk_rowoff[s + 1];
+  const int64_t a_s = row_ptr[lo];
+  beg[c] = j == 0 ? lo : first_at_least(row_ptr, lo, hi, a_s + static_cast<int64_t>(j) * chunk_arcs);
+  const bool last = (c + 1 == n_chunks) || blk_of_chunk[c + 1] != s;
+  end[c] = last ? hi : first_at_least(row_ptr, lo, hi, a_s + static_cast<int64_t>(j + 1) * chunk_arcs);
+  blk[c] = s;
+}
+
 inline int grid_for(int64_t items, int threads, int cap = 1 << 20) {
   const int64_t g = (items + threads - 1) / threads;
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, cap)));
@@ -440,6 +483,17 @@ hipError_t check_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t*
   GC_HIP_TRY(hipGetLastError());
   GC_HIP_TRY(hipMemcpyAsync(bad_out, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   return hipStreamSynchronize(s);
+}
+
+hipError_t build_tiles(const int32_t* row_ptr, int64_t rows, int64_t arcs, int32_t tile_arcs, int32_t** out,
+                       int32_t* n_tiles, hipStream_t s) {
+  const int64_t nt = arcs / tile_arcs + 1;  // arc index `arcs` (trailing empty rows) falls in the last tile
+  *n_tiles = static_cast<int32_t>(nt);
+  *out = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * (nt + 1), s));
+  if (!*out) return hipErrorOutOfMemory;
+  k_tile_rows<<<grid_for(nt + 1, 256, INT_MAX), 256, 0, s>>>(row_ptr, static_cast<int32_t>(rows), tile_arcs,
+                                                             static_cast<int32_t>(nt), *out);
+  return hipGetLastError();
 }
 
 hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
@@ -489,6 +543,42 @@ hipError_t build_transpose(int32_t n, int64_t m, const int32_t* rowptr, const in
   }
   GC_HIP_TRY(hipGetLastError());
   return hipStreamSynchronize(s);
+}
+
+// 16-bit columns and the chunk table of an LDS-resident partition.
+hipError_t build_lds_chunks(gc_tocab t, hipStream_t s) {
+  const int32_t B = t->B;
+  t->col16 = static_cast<uint16_t*>(dev_alloc(sizeof(uint16_t) * std::max<int64_t>(t->m, 1), s));
+  if (!t->col16) return hipErrorOutOfMemory;
+  if (t->m > 0) k_col16<<<grid_for(t->m, 256, 65536), 256, 0, s>>>(t->col, t->m, t->W - 1, t->col16);
+  Buf first(sizeof(int32_t) * (B + 1), s);
+  if (!first.p) return hipErrorOutOfMemory;
+  k_block_arcs<<<grid_for(B + 1, 256), 256, 0, s>>>(t->blk_rowoff, t->row_ptr, B, first.as<int32_t>());
+  GC_HIP_TRY(hipGetLastError());
+  std::vector<int32_t> h(B + 1);
+  GC_HIP_TRY(hipMemcpyAsync(h.data(), first.p, sizeof(int32_t) * (B + 1), hipMemcpyDeviceToHost, s));
+  GC_HIP_TRY(hipStreamSynchronize(s));
+  std::vector<int32_t> chunk_first(B + 1, 0), blk_of;
+  for (int32_t b = 0; b < B; ++b) {
+    const int64_t arcs = h[b + 1] - h[b];
+    const int32_t nc = static_cast<int32_t>(std::max<int64_t>(1, (arcs + kLdsChunkArcs - 1) / kLdsChunkArcs));
+    chunk_first[b + 1] = chunk_first[b] + nc;
+    for (int32_t j = 0; j < nc; ++j) blk_of.push_back(b);
+  }
+  const int32_t nch = chunk_first[B];
+  t->n_chunks = nch;
+  t->chunk_beg = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * nch, s));
+  t->chunk_end = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * nch, s));
+  t->chunk_blk = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * nch, s));
+  Buf d_first(sizeof(int32_t) * (B + 1), s), d_blk(sizeof(int32_t) * nch, s);
+  if (!t->chunk_beg || !t->chunk_end || !t->chunk_blk || !d_first.p || !d_blk.p) return hipErrorOutOfMemory;
+  GC_HIP_TRY(hipMemcpyAsync(d_first.p, chunk_first.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, s));
+  GC_HIP_TRY(hipMemcpyAsync(d_blk.p, blk_of.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice, s));
+  k_chunks<<<grid_for(nch, 256), 256, 0, s>>>(t->blk_rowoff, t->row_ptr, d_first.as<int32_t>(), d_blk.as<int32_t>(),
+                                              nch, kLdsChunkArcs, t->chunk_beg, t->chunk_end, t->chunk_blk);
+  GC_HIP_TRY(hipGetLastError());
+  t->bytes += static_cast<int64_t>(sizeof(uint16_t)) * t->m + 12 * static_cast<int64_t>(nch);
+  return hipStreamSynchronize(s);  // host vectors and Bufs are released on return
 }
 
 hipError_t build_partition(gc_tocab t, const int32_t* a_rowptr, const int32_t* a_col, const int32_t* a_w,
@@ -542,6 +632,8 @@ hipError_t build_partition(gc_tocab t, const int32_t* a_rowptr, const int32_t* a
     k_part_copy<<<grid_for(P, 256, INT_MAX), 256, 0, s>>>(t->row_ptr, seg.as<int32_t>(), P, a_col,
                                                           t->weighted ? a_w : nullptr, t->col, t->w);
   GC_HIP_TRY(hipGetLastError());
+  GC_HIP_TRY(build_tiles(t->row_ptr, P, t->m, pull_tile_arcs(), &t->tile_row, &t->n_tiles, s));
+  if (t->W <= kLdsMaxWidth) GC_HIP_TRY(build_lds_chunks(t, s));
   return hipStreamSynchronize(s);
 }
 

@@ -26,7 +26,9 @@ struct gc_graph_s {
   // PageRank scratch: contributions (two buffers for the fused plain pull),
   // push accumulators, FP64 dangling partials / totals and a done counter
   float* contrib[2] = {nullptr, nullptr};
-  float* sums = nullptr;
+  double* sums = nullptr;     // push accumulators (FP64 atomics)
+  int32_t* tile_row_in = nullptr;  // pull tiles over the transposed graph
+  int32_t n_tiles_in = 0;
   double* dpart = nullptr;    // one slot per apply work-group
   double* dtotal = nullptr;   // [2] ping-pong dangling totals
   unsigned* counter = nullptr;
@@ -35,6 +37,8 @@ struct gc_graph_s {
   uint8_t* front = nullptr;   // status arrays (Section 3.3)
   uint8_t* next = nullptr;
   int32_t* queue[2] = {nullptr, nullptr};
+  uint32_t* visited = nullptr;  // BFS: bitmap of vertices with a final depth
+  int32_t* mark = nullptr;      // SSSP push: round in which a vertex was queued
   int32_t* stats = nullptr;     // device counters read back once per level
   int32_t* stats_host = nullptr;  // pinned mirror
   int64_t bytes = 0;
@@ -55,6 +59,15 @@ struct gc_tocab_s {
   int32_t* w = nullptr;           // [m] or null
   int32_t* range_ptr = nullptr;   // [(R+1)*B], j-major
   float* partial = nullptr;       // [P] pull partial sums (Algorithm 4)
+  int32_t* tile_row = nullptr;    // [n_tiles+1] first local row of each pull tile
+  int32_t n_tiles = 0;
+  // LDS-resident blocks (W <= kLdsMaxWidth): columns as 16-bit offsets inside
+  // the block, and chunks of one block's local rows for one work-group each
+  uint16_t* col16 = nullptr;      // [m]
+  int32_t* chunk_beg = nullptr;   // [n_chunks]
+  int32_t* chunk_end = nullptr;   // [n_chunks]
+  int32_t* chunk_blk = nullptr;   // [n_chunks]
+  int32_t n_chunks = 0;
   int32_t* pmin = nullptr;        // [P] traversal partials (next flags / min)
   int64_t bytes = 0;
 };
@@ -91,11 +104,20 @@ hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, hipStream_
 hipError_t build_transpose(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* colidx,
                            const int32_t* w, int32_t* t_rowptr, int32_t* t_colidx, int32_t* t_w,
                            hipStream_t s);
+// Pull tile table: tile i owns the rows whose first arc lies in
+// [i*tile_arcs, (i+1)*tile_arcs); out[i] = first such row, out[n_tiles] = rows.
+hipError_t build_tiles(const int32_t* row_ptr, int64_t rows, int64_t arcs, int32_t tile_arcs,
+                       int32_t** out, int32_t* n_tiles, hipStream_t s);
 // TOCAB partition of CSR A (see tocab_partition); fills t's arrays.
 hipError_t build_partition(gc_tocab t, const int32_t* a_rowptr, const int32_t* a_col,
                            const int32_t* a_w, hipStream_t s);
 
 // ---- PageRank (gc_pagerank.hip) ----
+int32_t pull_tile_arcs();
+// Largest block width whose FP32 contribution slice is staged in LDS.
+constexpr int32_t kLdsMaxWidth = 1 << 15;
+// Arcs per chunk of an LDS-resident block (one work-group each).
+constexpr int32_t kLdsChunkArcs = 1 << 16;
 hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int32_t dangling,
                         const float* rank_in, float* rank_out, int32_t iters, hipStream_t s);
 

@@ -22,16 +22,20 @@ namespace {
 using gcd::kWave;
 
 constexpr int kThreads = 256;
-constexpr int kHeavyRow = 32;  // longer rows are summed by a whole wave
+
+constexpr int kTileArcs = 2048;                  // arcs per pull tile (tile table granularity)
+constexpr int kStageCap = 4096;                  // arcs a tile may stage in LDS
+constexpr int kPerThread = kStageCap / kThreads;  // staged arcs per thread
+constexpr int kFlatB = 1024;                     // merges over at most this many blocks flatten their slices
+
+static_assert(kTileArcs <= kStageCap, "a tile's short rows must fit the stage");
 
 struct Update {
   double base;      // (1 - d) / n
   double d;         // damping
   double inv_n;     // 1 / n, applied to D in uniform mode (0 in leak mode)
   const double* dtotal_in;
-  double* dtotal_out;
-  double* dpart;
-  unsigned* counter;
+  double* dpart;    // one dangling partial per work-group of the update kernel
   const int32_t* rowptr;  // out-arc CSR: outdeg(v) = rowptr[v+1] - rowptr[v]
   float* contrib;         // written for the next iteration
   float* rank_out;        // written on the last iteration only (else null)
@@ -49,7 +53,8 @@ __device__ __forceinline__ double update_vertex(const Update& u, int32_t v, doub
   return deg ? 0.0 : static_cast<double>(r32);
 }
 
-// Work-group sum of one double per thread (fixed reduction tree).
+// Work-group sum of one double per thread (fixed reduction tree), returned
+// to every thread.
 __device__ __forceinline__ double wg_sum(double x) {
   __shared__ double part[kThreads / kWave];
   x = gcd::wave_sum(x);
@@ -62,35 +67,32 @@ __device__ __forceinline__ double wg_sum(double x) {
   return t;
 }
 
-// Publishes this work-group's dangling partial; the last work-group to
-// arrive sums all partials in index order into *dtotal_out and resets the
-// arrival counter for the next launch.
-__device__ void finish_dangling(const Update& u, double mine) {
-  __shared__ bool last;
-  const double total_mine = wg_sum(mine);
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&u.dpart[blockIdx.x], total_mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned prev = atomicAdd(u.counter, 1u);
-    last = prev == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
+__device__ __forceinline__ void publish_dangling(const Update& u, double mine) {
+  const double t = wg_sum(mine);
+  if (threadIdx.x == 0) u.dpart[blockIdx.x] = t;
+}
+
+// D for the next iteration: the partials summed in index order by one
+// work-group (deterministic).
+__global__ __launch_bounds__(1024) void k_reduce_dangling(const double* __restrict__ dpart, int32_t count,
+                                                          double* __restrict__ dtotal) {
+  __shared__ double part[1024 / kWave];
   double acc = 0.0;
-  for (uint32_t i = threadIdx.x; i < gridDim.x; i += kThreads)
-    acc += __hip_atomic_load(&u.dpart[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const double total = wg_sum(acc);
+  for (int32_t i = threadIdx.x; i < count; i += 1024) acc += dpart[i];
+  acc = gcd::wave_sum(acc);
+  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    *u.dtotal_out = total;
-    __hip_atomic_store(u.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double t = 0.0;
+    for (int w = 0; w < 1024 / kWave; ++w) t += part[w];
+    *dtotal = t;
   }
 }
 
 // Contributions of the starting vector and its dangling mass; zeroes the
 // push accumulators when given.
 __global__ __launch_bounds__(kThreads) void k_pr_init(const float* __restrict__ rank_in, Update u,
-                                                      float* __restrict__ sums) {
+                                                      double* __restrict__ sums) {
   const int32_t v = blockIdx.x * kThreads + threadIdx.x;
   double mine = 0.0;
   if (v < u.n) {
@@ -98,86 +100,293 @@ __global__ __launch_bounds__(kThreads) void k_pr_init(const float* __restrict__ 
     const int32_t deg = u.rowptr[v + 1] - u.rowptr[v];
     u.contrib[v] = deg ? static_cast<float>(static_cast<double>(r) / deg) : 0.0f;
     mine = deg ? 0.0 : static_cast<double>(r);
-    if (sums) sums[v] = 0.0f;
+    if (sums) sums[v] = 0.0;
   }
-  finish_dangling(u, mine);
+  publish_dangling(u, mine);
 }
 
-// Sum of c over one row's columns [b, e), four loads in flight per step.
-__device__ __forceinline__ double row_sum(const int32_t* __restrict__ col, const float* __restrict__ c,
-                                          int32_t b, int32_t e) {
+// Gathers c[col[a0 + i]] for i < len (len <= kStageCap) into LDS: every lane
+// first issues its column loads (coalesced across the work-group, streamed
+// past the cache), then the gathers, so all loads of a tile are in flight
+// together. Indices past the end are clamped to the last arc instead of
+// branched around, which keeps the loads free of control flow (a branch per
+// load would make each one wait for the previous).
+__device__ __forceinline__ void stage_gather(const int32_t* __restrict__ col, const float* __restrict__ c,
+                                             int32_t a0, int32_t len, float* vals) {
+  if (len <= 0) return;
+  int32_t idx[kPerThread];
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int32_t i = min(static_cast<int32_t>(threadIdx.x) + k * kThreads, len - 1);
+    idx[k] = gcd::ld_stream(col + a0 + i);
+  }
+  float x[kPerThread];
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) x[k] = c[idx[k]];
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const int32_t i = threadIdx.x + k * kThreads;
+    if (i < len) vals[i] = x[k];
+  }
+}
+
+// Sum of c over columns [b, e) (b < e) by the whole work-group (hub rows).
+__device__ double wg_row_sum(const int32_t* __restrict__ col, const float* __restrict__ c, int32_t b, int32_t e) {
   double s = 0.0;
-  int32_t i = b;
-  for (; i + 4 <= e; i += 4) {
-    const int32_t c0 = gcd::ld_stream(col + i), c1 = gcd::ld_stream(col + i + 1);
-    const int32_t c2 = gcd::ld_stream(col + i + 2), c3 = gcd::ld_stream(col + i + 3);
-    const float x0 = c[c0], x1 = c[c1], x2 = c[c2], x3 = c[c3];
-    s += static_cast<double>(x0) + static_cast<double>(x1) + static_cast<double>(x2) + static_cast<double>(x3);
+  for (int32_t base = b; base < e; base += kStageCap) {
+    int32_t idx[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k)
+      idx[k] = gcd::ld_stream(col + min(base + static_cast<int32_t>(threadIdx.x) + k * kThreads, e - 1));
+    float x[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) x[k] = c[idx[k]];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k)
+      if (base + static_cast<int32_t>(threadIdx.x) + k * kThreads < e) s += static_cast<double>(x[k]);
   }
-  for (; i < e; ++i) s += static_cast<double>(c[gcd::ld_stream(col + i)]);
-  return s;
+  return wg_sum(s);
 }
 
-// Coarse-grained load balancing of the pull direction (Section 3.2): one
-// lane per row serially; rows longer than kHeavyRow are taken by the whole
-// wave, which reduces its lanes' partial sums. No atomics.
-__device__ __forceinline__ double pull_row(const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                                           const float* __restrict__ c, int64_t row, int64_t rows) {
-  const int lane = threadIdx.x & (kWave - 1);
-  int32_t b = 0, e = 0;
-  if (row < rows) {
-    b = gcd::ld_stream(ptr + row);
-    e = gcd::ld_stream(ptr + row + 1);
+// One pull tile (coarse-grained load balancing of the pull direction,
+// Section 3.2): the tile owns the rows whose first arc lies in its
+// kTileArcs-wide slice of the arc array. Their arcs are gathered into LDS
+// together; then each thread sums whole short rows serially in FP64, and a
+// last row too long for the stage is summed by the whole work-group. No
+// atomics. emit(row, sum) is called once per owned row.
+template <class Emit>
+__device__ __forceinline__ void pull_tile(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                          const float* __restrict__ c, int32_t r0, int32_t r1, float* vals,
+                                          Emit&& emit) {
+  const int32_t a0 = row_ptr[r0];
+  const int32_t last_b = row_ptr[r1 - 1];
+  const int32_t a_end = row_ptr[r1];
+  const bool long_last = (a_end - a0) > kStageCap;
+  stage_gather(col, c, a0, (long_last ? last_b : a_end) - a0, vals);
+  __syncthreads();
+  const int32_t r_short_end = long_last ? r1 - 1 : r1;
+  for (int32_t r = r0 + threadIdx.x; r < r_short_end; r += kThreads) {
+    const int32_t b = row_ptr[r] - a0, e = row_ptr[r + 1] - a0;
+    double s = 0.0;
+    for (int32_t i = b; i < e; ++i) s += static_cast<double>(vals[i]);
+    emit(r, s);
   }
-  const bool heavy = (e - b) > kHeavyRow;
-  double sum = heavy ? 0.0 : row_sum(col, c, b, e);
-  uint64_t pending = __ballot(heavy);
-  while (pending) {
-    const int owner = __ffsll(static_cast<long long>(pending)) - 1;
-    pending &= pending - 1;
-    const int32_t hb = __shfl(b, owner, kWave), he = __shfl(e, owner, kWave);
-    double acc = 0.0;
-    for (int32_t i = hb + lane; i < he; i += kWave) acc += static_cast<double>(c[gcd::ld_stream(col + i)]);
-    acc = gcd::wave_sum(acc);
-    if (lane == owner) sum = acc;
+  if (long_last) {
+    const double s = wg_row_sum(col, c, last_b, a_end);
+    if (threadIdx.x == 0) emit(r1 - 1, s);
   }
-  return sum;
 }
 
-// Algorithm 4 over every subgraph in one launch (local rows are stored
-// block after block, so consecutive work-groups stay inside one block and
-// its slice of c stays cache resident): partial[l] = sum of c over the
-// local row's columns, written densely by local id.
+// Algorithm 4 over every subgraph in one launch. Local rows are stored block
+// after block, so consecutive tiles stay inside one block and its slice of
+// c stays cache resident: partial[l] = sum of c over local row l, written
+// densely by local id.
 __global__ __launch_bounds__(kThreads) void k_pr_tocab_pull(const int32_t* __restrict__ row_ptr,
                                                             const int32_t* __restrict__ col,
+                                                            const int32_t* __restrict__ tile_row,
                                                             const float* __restrict__ c,
-                                                            float* __restrict__ partial, int64_t P) {
-  const int64_t l = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-  const double s = pull_row(row_ptr, col, c, l, P);
-  if (l < P) gcd::st_stream(partial + l, static_cast<float>(s));
+                                                            float* __restrict__ partial) {
+  __shared__ float vals[kStageCap];
+  const int32_t r0 = tile_row[blockIdx.x], r1 = tile_row[blockIdx.x + 1];
+  if (r0 >= r1) return;
+  pull_tile(row_ptr, col, c, r0, r1, vals,
+            [&](int32_t r, double s) { gcd::st_stream(partial + r, static_cast<float>(s)); });
+}
+
+// Algorithm 4 with the block's slice of c resident in LDS (block widths up
+// to kLdsMaxWidth): gfx950 serves random 4-byte reads from LDS about ten
+// times faster than from L2, so on this GPU the block is sized for the
+// 160 KB LDS of a compute unit rather than for the last-level cache. One
+// work-group takes a chunk of one block's local rows: it loads the slice
+// c[sW, sW + W) into LDS once (coalesced), then walks the chunk in steps of
+// kLdsStep arcs, staging the gathered values (16-bit column offsets, read
+// from the LDS slice) and summing whole rows per thread as in pull_tile; a
+// row too long for the stage is summed by the whole work-group.
+constexpr int kLdsThreads = 1024;
+constexpr int kLdsStep = 4096;
+constexpr int kLdsPer = kLdsStep / kLdsThreads;
+
+__device__ __forceinline__ double wg1024_sum(double x) {
+  __shared__ double part[kLdsThreads / kWave];
+  x = gcd::wave_sum(x);
+  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = x;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < kLdsThreads / kWave; ++w) t += part[w];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
+    const int32_t* __restrict__ row_ptr, const uint16_t* __restrict__ col16, const int32_t* __restrict__ chunk_beg,
+    const int32_t* __restrict__ chunk_end, const int32_t* __restrict__ chunk_blk, int32_t log2W, int32_t n,
+    const float* __restrict__ c, float* __restrict__ partial) {
+  extern __shared__ float lds[];
+  const int32_t W = 1 << log2W;
+  float* slice = lds;
+  float* vals = lds + W;
+  const int32_t r0 = chunk_beg[blockIdx.x], r1 = chunk_end[blockIdx.x];
+  if (r0 >= r1) return;
+  const int32_t v0 = chunk_blk[blockIdx.x] << log2W;
+  const int32_t cnt = min(W, n - v0);
+  for (int32_t i = threadIdx.x; i < cnt; i += kLdsThreads) slice[i] = c[v0 + i];
+  __syncthreads();
+  for (int32_t rb = r0; rb < r1;) {
+    const int32_t a0 = row_ptr[rb];
+    // rows whose first arc lies in [a0, a0 + kLdsStep)
+    int32_t lo = rb + 1, hi = r1;
+    while (lo < hi) {
+      const int32_t mid = lo + ((hi - lo) >> 1);
+      if (row_ptr[mid] < a0 + kLdsStep) lo = mid + 1;
+      else hi = mid;
+    }
+    const int32_t re = lo;
+    const int32_t last_b = row_ptr[re - 1], a_end = row_ptr[re];
+    const bool long_last = (a_end - a0) > kLdsStep;
+    const int32_t len = (long_last ? last_b : a_end) - a0;
+    if (len > 0) {
+      int32_t u[kLdsPer];
+#pragma unroll
+      for (int k = 0; k < kLdsPer; ++k)
+        u[k] = gcd::ld_stream(col16 + a0 + min(static_cast<int32_t>(threadIdx.x) + k * kLdsThreads, len - 1));
+#pragma unroll
+      for (int k = 0; k < kLdsPer; ++k) {
+        const int32_t i = threadIdx.x + k * kLdsThreads;
+        if (i < len) vals[i] = slice[u[k]];
+      }
+    }
+    __syncthreads();
+    const int32_t r_short_end = long_last ? re - 1 : re;
+    for (int32_t r = rb + threadIdx.x; r < r_short_end; r += kLdsThreads) {
+      const int32_t b = row_ptr[r] - a0, e = row_ptr[r + 1] - a0;
+      double sum = 0.0;
+      for (int32_t i = b; i < e; ++i) sum += static_cast<double>(vals[i]);
+      gcd::st_stream(partial + r, static_cast<float>(sum));
+    }
+    if (long_last) {
+      double sum = 0.0;
+      for (int32_t base = last_b; base < a_end; base += kLdsStep) {
+        int32_t u[kLdsPer];
+#pragma unroll
+        for (int k = 0; k < kLdsPer; ++k)
+          u[k] = gcd::ld_stream(col16 + min(base + static_cast<int32_t>(threadIdx.x) + k * kLdsThreads, a_end - 1));
+#pragma unroll
+        for (int k = 0; k < kLdsPer; ++k)
+          if (base + static_cast<int32_t>(threadIdx.x) + k * kLdsThreads < a_end)
+            sum += static_cast<double>(slice[u[k]]);
+      }
+      sum = wg1024_sum(sum);
+      if (threadIdx.x == 0) partial[re - 1] = static_cast<float>(sum);
+    }
+    __syncthreads();  // the stage is rewritten by the next step
+    rb = re;
+  }
+}
+
+// Algorithm 1 with the update fused (same tiles over the transposed graph):
+// reads c from one buffer and writes the next iteration's c into the other.
+__global__ __launch_bounds__(kThreads) void k_pr_plain_pull(const int32_t* __restrict__ t_rowptr,
+                                                            const int32_t* __restrict__ t_col,
+                                                            const int32_t* __restrict__ tile_row,
+                                                            const float* __restrict__ c_in, Update u) {
+  __shared__ float vals[kStageCap];
+  const int32_t r0 = tile_row[blockIdx.x], r1 = tile_row[blockIdx.x + 1];
+  double mine = 0.0;
+  if (r0 < r1) {
+    const double D = *u.dtotal_in;
+    pull_tile(t_rowptr, t_col, c_in, r0, r1, vals,
+              [&](int32_t v, double s) { mine += update_vertex(u, v, s, D); });
+  }
+  publish_dangling(u, mine);
 }
 
 // Figure 5 merge fused with the update: work-group j owns vertices
-// [j*K, (j+1)*K). For every block s it reads the slice of partial sums whose
-// local rows map into that range (contiguous, since local ids ascend with
-// global ids), accumulates them in LDS (FP64), then updates its vertices
-// with coalesced writes.
-template <int K>
+// [j*K, (j+1)*K). For every block s the local rows mapping into that range
+// form one contiguous slice of partial / id_map (local ids ascend with
+// global ids); the work-group walks all B slices as one flattened list so
+// that every lane keeps several independent loads in flight, accumulates
+// into LDS (FP64), then updates its vertices with coalesced writes.
+template <int K, bool kFlat>
 __global__ __launch_bounds__(kThreads) void k_pr_merge(const int32_t* __restrict__ range_ptr, int32_t B,
                                                        const int32_t* __restrict__ id_map,
                                                        const float* __restrict__ partial, Update u) {
   __shared__ double acc[K];
+  __shared__ int32_t seg_lo[kFlat ? kFlatB : 1];
+  __shared__ int32_t seg_pre[kFlat ? kFlatB + 1 : 1];
   const int32_t v0 = blockIdx.x * K;
   for (int i = threadIdx.x; i < K; i += kThreads) acc[i] = 0.0;
-  __syncthreads();
   const int32_t* lo = range_ptr + static_cast<int64_t>(blockIdx.x) * B;
   const int32_t* hi = lo + B;
-  for (int32_t s = 0; s < B; ++s) {
-    const int32_t a = lo[s], z = hi[s];
-    for (int32_t l = a + threadIdx.x; l < z; l += kThreads) {
-      const int32_t v = gcd::ld_stream(id_map + l);
-      const float p = gcd::ld_stream(partial + l);
-      atomicAdd(&acc[v - v0], static_cast<double>(p));
+  if (kFlat) {
+    // slice starts and an exclusive scan of slice lengths (one pass, B <= kFlatB)
+    __shared__ int32_t wave_tot[kThreads / kWave];
+    constexpr int kItems = kFlatB / kThreads;
+    int32_t len[kItems];
+    int32_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int32_t s = threadIdx.x * kItems + k;
+      len[k] = 0;
+      if (s < B) {
+        const int32_t a = lo[s];
+        seg_lo[s] = a;
+        len[k] = hi[s] - a;
+      }
+      mine += len[k];
+    }
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const int32_t incl = gcd::wave_incl_scan(mine);
+    if (lane == kWave - 1) wave_tot[wid] = incl;
+    __syncthreads();
+    int32_t off = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / kWave; ++w) off += (w < wid) ? wave_tot[w] : 0;
+    int32_t run = off + incl - mine;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      const int32_t s = threadIdx.x * kItems + k;
+      if (s < B) seg_pre[s] = run;
+      run += len[k];
+    }
+    if (threadIdx.x == kThreads - 1) seg_pre[B] = run;
+    __syncthreads();
+    const int32_t total = seg_pre[B];
+    constexpr int kUnroll = 8;
+    int32_t s = 0;
+    for (int32_t f0 = threadIdx.x; f0 < total; f0 += kThreads * kUnroll) {
+      // flat positions past the end reuse the first (valid) local row and are masked
+      int32_t l[kUnroll];
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) {
+        const int32_t f = f0 + k * kThreads;
+        if (f < total) {
+          while (seg_pre[s + 1] <= f) ++s;
+          l[k] = seg_lo[s] + (f - seg_pre[s]);
+        } else {
+          l[k] = l[0];
+        }
+      }
+      int32_t v[kUnroll];
+      float p[kUnroll];
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k) {
+        v[k] = gcd::ld_stream(id_map + l[k]);
+        p[k] = gcd::ld_stream(partial + l[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < kUnroll; ++k)
+        if (f0 + k * kThreads < total) atomicAdd(&acc[v[k] - v0], static_cast<double>(p[k]));
+    }
+  } else {
+    __syncthreads();
+    for (int32_t s = 0; s < B; ++s) {
+      const int32_t a = lo[s], z = hi[s];
+      for (int32_t l = a + threadIdx.x; l < z; l += kThreads) {
+        const int32_t v = gcd::ld_stream(id_map + l);
+        const float p = gcd::ld_stream(partial + l);
+        atomicAdd(&acc[v - v0], static_cast<double>(p));
+      }
     }
   }
   __syncthreads();
@@ -187,33 +396,20 @@ __global__ __launch_bounds__(kThreads) void k_pr_merge(const int32_t* __restrict
     const int32_t v = v0 + i;
     if (v < u.n) mine += update_vertex(u, v, acc[i], D);
   }
-  finish_dangling(u, mine);
-}
-
-// Algorithm 1 with the update fused: reads c from one buffer and writes the
-// next iteration's c into the other.
-__global__ __launch_bounds__(kThreads) void k_pr_plain_pull(const int32_t* __restrict__ t_rowptr,
-                                                            const int32_t* __restrict__ t_col,
-                                                            const float* __restrict__ c_in, Update u) {
-  const int32_t v = blockIdx.x * kThreads + threadIdx.x;
-  const double s = pull_row(t_rowptr, t_col, c_in, v, u.n);
-  const double D = *u.dtotal_in;
-  double mine = 0.0;
-  if (v < u.n) mine = update_vertex(u, v, s, D);
-  finish_dangling(u, mine);
+  publish_dangling(u, mine);
 }
 
 // Push with thread+warp+CTA style fine-grained balancing (Section 2.1,
 // applied to push in Section 3.2): the work-group's 256 rows are laid end to
 // end by an exclusive scan of their lengths and every lane takes one arc at
-// a time, locating its row by binary search; each arc is an FP32 atomic add
+// a time, locating its row by binary search; each arc is an FP64 atomic add
 // into sums[dst]. With id_map (Algorithm 5) rows are a push partition's
 // local sources and the destinations of one block stay inside a W-wide
 // slice of sums.
 __global__ __launch_bounds__(kThreads) void k_pr_push(const int32_t* __restrict__ row_ptr,
                                                       const int32_t* __restrict__ id_map,
                                                       const int32_t* __restrict__ col,
-                                                      const float* __restrict__ c, float* __restrict__ sums,
+                                                      const float* __restrict__ c, double* __restrict__ sums,
                                                       int64_t rows) {
   __shared__ int32_t start[kThreads];
   __shared__ int32_t first[kThreads];
@@ -249,45 +445,56 @@ __global__ __launch_bounds__(kThreads) void k_pr_push(const int32_t* __restrict_
       else hi = mid - 1;
     }
     const int32_t e = first[lo] + (a - start[lo]);
-    atomicAdd(&sums[col[e]], val[lo]);
+    atomicAdd(&sums[col[e]], static_cast<double>(val[lo]));
   }
 }
 
 // Update after a push pass; clears sums for the next pass.
-__global__ __launch_bounds__(kThreads) void k_pr_apply(float* __restrict__ sums, Update u) {
+__global__ __launch_bounds__(kThreads) void k_pr_apply(double* __restrict__ sums, Update u) {
   const int32_t v = blockIdx.x * kThreads + threadIdx.x;
   const double D = *u.dtotal_in;
   double mine = 0.0;
   if (v < u.n) {
-    const float s = sums[v];
-    sums[v] = 0.0f;
-    mine = update_vertex(u, v, static_cast<double>(s), D);
+    const double s = sums[v];
+    sums[v] = 0.0;
+    mine = update_vertex(u, v, s, D);
   }
-  finish_dangling(u, mine);
+  publish_dangling(u, mine);
 }
 
 template <int K>
 void launch_merge(int32_t R, hipStream_t s, const int32_t* rp, int32_t B, const int32_t* id_map,
                   const float* partial, const Update& u) {
-  k_pr_merge<K><<<R, kThreads, 0, s>>>(rp, B, id_map, partial, u);
+  if (B <= kFlatB) k_pr_merge<K, true><<<R, kThreads, 0, s>>>(rp, B, id_map, partial, u);
+  else k_pr_merge<K, false><<<R, kThreads, 0, s>>>(rp, B, id_map, partial, u);
 }
 
 }  // namespace
 
 namespace gcx {
 
+int32_t pull_tile_arcs() { return kTileArcs; }
+
+hipError_t pagerank_setup() {
+  // the LDS-resident pull stages up to kLdsMaxWidth + kLdsStep floats
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_tocab_pull_lds),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             static_cast<int>(sizeof(float) * (kLdsMaxWidth + kLdsStep)));
+}
+
 hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int32_t dangling,
                         const float* rank_in, float* rank_out, int32_t iters, hipStream_t s) {
   const int32_t n = g->n;
   if (iters == 0)
     return hipMemcpyAsync(rank_out, rank_in, sizeof(float) * n, hipMemcpyDeviceToDevice, s);
+  static const hipError_t setup = pagerank_setup();
+  GC_HIP_TRY(setup);
   const bool push = t ? (t->dir == GC_PUSH) : (dir == GC_PUSH);
   Update u;
   u.d = damping;
   u.base = (1.0 - static_cast<double>(damping)) / n;
   u.inv_n = dangling == GC_DANGLING_UNIFORM ? 1.0 / n : 0.0;
   u.dpart = g->dpart;
-  u.counter = g->counter;
   u.rowptr = g->rowptr;
   u.n = n;
   u.rank_out = nullptr;
@@ -295,27 +502,34 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
 
   // contributions of rank_in and D of iteration 0 -> dtotal[0]
   u.dtotal_in = nullptr;
-  u.dtotal_out = g->dtotal;
   u.contrib = g->contrib[0];
   {
     ProfScope prof("pr_init", s);
     k_pr_init<<<vgrid, kThreads, 0, s>>>(rank_in, u, push ? g->sums : nullptr);
   }
+  k_reduce_dangling<<<1, 1024, 0, s>>>(g->dpart, vgrid, g->dtotal);
   GC_HIP_TRY(hipGetLastError());
 
   int cur = 0;
   for (int32_t it = 0; it < iters; ++it) {
     u.dtotal_in = g->dtotal + (it & 1);
-    u.dtotal_out = g->dtotal + ((it + 1) & 1);
+    double* dtotal_out = g->dtotal + ((it + 1) & 1);
     u.rank_out = (it == iters - 1) ? rank_out : nullptr;
+    int32_t parts = vgrid;  // work-groups of the update kernel
     if (t && !push) {
-      const int64_t P = t->P;
-      if (P > 0) {
+      if (t->col16) {
         ProfScope prof("pr_tocab_pull", s);
-        k_pr_tocab_pull<<<static_cast<uint32_t>((P + kThreads - 1) / kThreads), kThreads, 0, s>>>(
-            t->row_ptr, t->col, g->contrib[0], t->partial, P);
+        const size_t lds = sizeof(float) * (static_cast<size_t>(t->W) + kLdsStep);
+        k_pr_tocab_pull_lds<<<t->n_chunks, kLdsThreads, lds, s>>>(t->row_ptr, t->col16, t->chunk_beg, t->chunk_end,
+                                                                  t->chunk_blk, t->log2W, n, g->contrib[0],
+                                                                  t->partial);
+      } else {
+        ProfScope prof("pr_tocab_pull", s);
+        k_pr_tocab_pull<<<t->n_tiles, kThreads, 0, s>>>(t->row_ptr, t->col, t->tile_row, g->contrib[0],
+                                                        t->partial);
       }
       u.contrib = g->contrib[0];  // safe in place: the pull pass has finished reading c
+      parts = t->R;
       ProfScope prof("pr_merge", s);
       switch (t->k) {
         case 256: launch_merge<256>(t->R, s, t->range_ptr, t->B, t->id_map, t->partial, u); break;
@@ -329,10 +543,10 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
       }
     } else if (!push) {
       u.contrib = g->contrib[cur ^ 1];
-      {
-        ProfScope prof("pr_plain_pull", s);
-        k_pr_plain_pull<<<vgrid, kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, g->contrib[cur], u);
-      }
+      parts = g->n_tiles_in;
+      ProfScope prof("pr_plain_pull", s);
+      k_pr_plain_pull<<<g->n_tiles_in, kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, g->tile_row_in,
+                                                         g->contrib[cur], u);
       cur ^= 1;
     } else {
       if (t) {
@@ -349,6 +563,10 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
       u.contrib = g->contrib[0];
       ProfScope prof("pr_apply", s);
       k_pr_apply<<<vgrid, kThreads, 0, s>>>(g->sums, u);
+    }
+    {
+      ProfScope prof("pr_dangling", s);
+      k_reduce_dangling<<<1, 1024, 0, s>>>(g->dpart, parts, dtotal_out);
     }
     GC_HIP_TRY(hipGetLastError());
   }

@@ -1,6 +1,7 @@
 // Host side of the C ABI: error reporting, the device allocator hook,
 // argument validation (done before anything is queued), handle lifetime.
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -69,7 +70,7 @@ void free_graph(gc_graph g) {
   if (!g) return;
   void* bufs[] = {g->rowptr, g->colidx, g->w, g->t_rowptr, g->t_colidx, g->t_w, g->contrib[0], g->contrib[1],
                   g->sums, g->dpart, g->dtotal, g->counter, g->front, g->next, g->queue[0], g->queue[1],
-                  g->stats};
+                  g->stats, g->tile_row_in, g->visited, g->mark};
   for (void* p : bufs)
     if (p) gcx::dev_free(p, nullptr);
   if (g->stats_host) (void)hipHostFree(g->stats_host);
@@ -78,7 +79,8 @@ void free_graph(gc_graph g) {
 
 void free_tocab(gc_tocab t) {
   if (!t) return;
-  void* bufs[] = {t->blk_rowoff, t->row_ptr, t->id_map, t->col, t->w, t->range_ptr, t->partial, t->pmin};
+  void* bufs[] = {t->blk_rowoff, t->row_ptr, t->id_map, t->col, t->w, t->range_ptr, t->partial, t->pmin,
+                  t->tile_row, t->col16, t->chunk_beg, t->chunk_end, t->chunk_blk};
   for (void* p : bufs)
     if (p) gcx::dev_free(p, nullptr);
   delete t;
@@ -170,7 +172,7 @@ int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* c
   g->weighted = weight != nullptr;
   const size_t nb = sizeof(int32_t) * (static_cast<size_t>(n) + 1);
   const size_t mb = sizeof(int32_t) * static_cast<size_t>(m > 0 ? m : 1);
-  g->dpart_slots = (n + 255) / 256;
+  g->dpart_slots = static_cast<int32_t>(std::max<int64_t>((n + 255) / 256, m / gcx::pull_tile_arcs() + 2));
   g->rowptr = static_cast<int32_t*>(gcx::dev_alloc(nb, stream));
   g->colidx = static_cast<int32_t*>(gcx::dev_alloc(mb, stream));
   g->t_rowptr = static_cast<int32_t*>(gcx::dev_alloc(nb, stream));
@@ -181,7 +183,7 @@ int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* c
   }
   g->contrib[0] = static_cast<float*>(gcx::dev_alloc(sizeof(float) * n, stream));
   g->contrib[1] = static_cast<float*>(gcx::dev_alloc(sizeof(float) * n, stream));
-  g->sums = static_cast<float*>(gcx::dev_alloc(sizeof(float) * n, stream));
+  g->sums = static_cast<double*>(gcx::dev_alloc(sizeof(double) * n, stream));
   g->dpart = static_cast<double*>(gcx::dev_alloc(sizeof(double) * g->dpart_slots, stream));
   g->dtotal = static_cast<double*>(gcx::dev_alloc(sizeof(double) * 2, stream));
   g->counter = static_cast<unsigned*>(gcx::dev_alloc(sizeof(unsigned) * 4, stream));
@@ -190,7 +192,9 @@ int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* c
   g->queue[0] = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * n, stream));
   g->queue[1] = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * n, stream));
   g->stats = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * 16, stream));
-  bool ok = g->rowptr && g->colidx && g->t_rowptr && g->t_colidx && (!g->weighted || (g->w && g->t_w)) &&
+  g->visited = static_cast<uint32_t*>(gcx::dev_alloc(sizeof(uint32_t) * ((static_cast<size_t>(n) + 31) / 32), stream));
+  g->mark = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * n, stream));
+  bool ok = g->visited && g->mark && g->rowptr && g->colidx && g->t_rowptr && g->t_colidx && (!g->weighted || (g->w && g->t_w)) &&
             g->contrib[0] && g->contrib[1] && g->sums && g->dpart && g->dtotal && g->counter && g->front &&
             g->next && g->queue[0] && g->queue[1] && g->stats;
   if (ok && hipHostMalloc(reinterpret_cast<void**>(&g->stats_host), sizeof(int32_t) * 16, hipHostMallocDefault) !=
@@ -220,6 +224,8 @@ int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* c
   if (e == hipSuccess) e = hipMemsetAsync(g->dtotal, 0, sizeof(double) * 2, stream);
   if (e == hipSuccess)
     e = gcx::build_transpose(n, m, g->rowptr, g->colidx, g->w, g->t_rowptr, g->t_colidx, g->t_w, stream);
+  if (e == hipSuccess)
+    e = gcx::build_tiles(g->t_rowptr, n, m, gcx::pull_tile_arcs(), &g->tile_row_in, &g->n_tiles_in, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
     free_graph(g);

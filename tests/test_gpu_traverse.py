@@ -1,0 +1,150 @@
+"""GPU BFS / SSSP parity: depths and distances bit-exact against the oracle
+(queue BFS, binary-heap Dijkstra) for every level policy and both pull
+forms (plain and TOCAB)."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from tests import graphs
+from tests.gpu_util import dev, host, load, torch
+
+pytestmark = pytest.mark.gpu
+
+GRAPHS = {
+    "rmat16": lambda: gg.rmat(16, 16, seed=1),
+    "rmat15_noperm": lambda: gg.rmat(15, 16, seed=2, permute=False),
+    "grid300x301": lambda: gg.grid(300, 301, 0.05, seed=3),
+    "grid_norewire": lambda: gg.grid(200, 190, 0.0, seed=3),
+    "uniform": lambda: gg.uniform(70001, 200000, seed=4),
+    "star_in": lambda: graphs.star_in(9000),
+    "star_out": lambda: graphs.star_out(9000),
+    "chain": lambda: graphs.chain(3000),
+    "two_components": graphs.two_components,
+    "dangling_mix": graphs.dangling_mix,
+}
+
+# (policy name, use a TOCAB partition)
+VARIANTS = [("pull", False), ("pull", True), ("push", False), ("heuristic", False), ("heuristic", True)]
+
+
+def _policy(gc, name):
+    return {"pull": gc.GC_POLICY_PULL, "push": gc.GC_POLICY_PUSH, "heuristic": gc.GC_POLICY_HEURISTIC}[name]
+
+
+def _sources(g, count=3):
+    s = list(gg.sources(g, count, seed=21))
+    return s + [0] if 0 not in s else s
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("policy,tocab", VARIANTS)
+def test_bfs_bit_exact(name, policy, tocab):
+    import paper_1904_02241_amd as gc
+    g = GRAPHS[name]()
+    print(f"bfs {name} {policy} tocab={tocab}", flush=True)
+    h = load(g)
+    part = gc.tocab_partition(h, gc.GC_PULL, 1 << 10, 512) if tocab else None
+    depth = torch().empty(g.n, dtype=torch().int32, device="cuda")
+    for s in _sources(g):
+        levels = gc.bfs_pull(h, part, s, depth, _policy(gc, policy))
+        got = host(depth)
+        want = oracle.bfs(g.n, g.rowptr, g.colidx, s)
+        np.testing.assert_array_equal(got, want)
+        assert levels == int(want[want != oracle.INF32].max()) + 1
+    if part:
+        part.free()
+    h.free()
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("policy,tocab", VARIANTS)
+def test_sssp_bit_exact(name, policy, tocab):
+    import paper_1904_02241_amd as gc
+    g = GRAPHS[name]().with_weights(31)
+    print(f"sssp {name} {policy} tocab={tocab}", flush=True)
+    h = load(g, weights=True)
+    part = gc.tocab_partition(h, gc.GC_PULL, 1 << 10, 1024) if tocab else None
+    dist = torch().empty(g.n, dtype=torch().int32, device="cuda")
+    for s in _sources(g):
+        gc.sssp_pull(h, part, s, dist, _policy(gc, policy))
+        got = host(dist)
+        want = oracle.dijkstra(g.n, g.rowptr, g.colidx, g.weights, s)
+        np.testing.assert_array_equal(got, want)
+    if part:
+        part.free()
+    h.free()
+
+
+def test_bfs_equals_unit_weight_sssp():
+    import paper_1904_02241_amd as gc
+    g = gg.rmat(14, 16, seed=9)
+    g.weights = np.ones(g.m, np.int32)
+    h = load(g, weights=True)
+    part = gc.tocab_partition(h, gc.GC_PULL, 1 << 11, 2048)
+    a = torch().empty(g.n, dtype=torch().int32, device="cuda")
+    b = torch().empty_like(a)
+    for s in gg.sources(g, 3, seed=1):
+        gc.bfs_pull(h, part, s, a, gc.GC_POLICY_HEURISTIC)
+        gc.sssp_pull(h, part, s, b, gc.GC_POLICY_HEURISTIC)
+        np.testing.assert_array_equal(host(a), host(b))
+    part.free()
+    h.free()
+
+
+def test_sssp_overflow_is_reported():
+    import paper_1904_02241_amd as gc
+    g = graphs.chain(5)
+    g.weights = np.full(g.m, 1 << 30, np.int32)
+    h = load(g, weights=True)
+    dist = torch().empty(g.n, dtype=torch().int32, device="cuda")
+    for policy in (gc.GC_POLICY_PULL, gc.GC_POLICY_PUSH):
+        with pytest.raises(gc.GraphCageError) as e:
+            gc.sssp_pull(h, None, 0, dist, policy)
+        assert e.value.code == gc.GC_EOVERFLOW
+    # a chain whose distances stay below INT32_MAX is fine
+    g2 = graphs.chain(3)
+    g2.weights = np.full(g2.m, 1 << 29, np.int32)
+    h2 = load(g2, weights=True)
+    d2 = torch().empty(g2.n, dtype=torch().int32, device="cuda")
+    gc.sssp_pull(h2, None, 0, d2, gc.GC_POLICY_PULL)
+    np.testing.assert_array_equal(host(d2), [0, 1 << 29, 1 << 30])
+    h.free()
+    h2.free()
+
+
+def test_traversal_rejects_bad_arguments():
+    import paper_1904_02241_amd as gc
+    g = gg.rmat(10, 8, seed=1)
+    h = load(g)
+    d = torch().empty(g.n, dtype=torch().int32, device="cuda")
+    with pytest.raises(gc.GraphCageError) as e:
+        gc.sssp_pull(h, None, 0, d)  # unweighted
+    assert e.value.code == gc.GC_EINVAL
+    for bad in (-1, g.n):
+        with pytest.raises(gc.GraphCageError):
+            gc.bfs_pull(h, None, bad, d)
+    push_part = gc.tocab_partition(h, gc.GC_PUSH, 1 << 10, 256)
+    with pytest.raises(gc.GraphCageError):
+        gc.bfs_pull(h, push_part, 0, d)
+    with pytest.raises(gc.GraphCageError):
+        gc.bfs_pull(h, None, 0, d, policy=7)
+    host_buf = np.zeros(g.n, np.int32)
+    with pytest.raises(gc.GraphCageError):
+        gc.bfs_pull(h, None, 0, host_buf)
+    push_part.free()
+    h.free()
+
+
+def test_isolated_source():
+    import paper_1904_02241_amd as gc
+    g = graphs.dangling_mix()  # vertex 5 has no arcs at all
+    h = load(g.with_weights(3), weights=True)
+    d = torch().empty(g.n, dtype=torch().int32, device="cuda")
+    assert gc.bfs_pull(h, None, 5, d, gc.GC_POLICY_HEURISTIC) == 1
+    want = np.full(g.n, oracle.INF32, np.int32)
+    want[5] = 0
+    np.testing.assert_array_equal(host(d), want)
+    gc.sssp_pull(h, None, 5, d, gc.GC_POLICY_PULL)
+    np.testing.assert_array_equal(host(d), want)
+    h.free()
