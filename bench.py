@@ -77,6 +77,34 @@ def run_form(gc, torch, g, part, plain_dir, n, m, steps, warmup):
             "gteps": m / (wall_ms / steps * 1e-3) / 1e9, "kernels": prof, "checks": checks}
 
 
+def run_traversal(gc, torch, g, gh, part, sources, kind, policies):
+    """Times BFS or SSSP from each source under each (name, policy, uses
+    partition) entry. GTEPS per source (Graph500 style) = out-arcs of the
+    reached vertices / time; reported as the harmonic mean over sources."""
+    outdeg = np.diff(gh.rowptr).astype(np.int64)
+    buf = torch.empty(gh.n, dtype=torch.int32, device="cuda")
+    fn = gc.bfs_pull if kind == "bfs" else gc.sssp_pull
+    out = {}
+    for name, policy, use_part in policies:
+        rates, times, levels = [], [], []
+        for src in sources:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lv = fn(g, part if use_part else None, int(src), buf, policy)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            reached = buf.cpu().numpy() != gc.GC_UNREACHED
+            arcs = int(outdeg[reached].sum())
+            rates.append(arcs / dt / 1e9)
+            times.append(dt * 1e3)
+            levels.append(lv)
+        hm = len(rates) / sum(1.0 / r for r in rates)
+        out[name] = {"gteps_hmean": round(hm, 3), "ms_mean": round(float(np.mean(times)), 3),
+                     "levels": levels}
+        log(f"{kind} {name}: {hm:.2f} GTEPS (harmonic mean), {np.mean(times):.2f} ms mean, levels {levels}")
+    return out
+
+
 def traffic_from_profiles(kernel, src_file):
     """HBM bytes per launch from a committed rocprofv3 --pmc summary, or None
     when the kernel's source changed since the counters were taken."""
@@ -120,6 +148,7 @@ def main():
                     help="comma list; the first is the headline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--bfs-sources", type=int, default=8, help="BFS sources on the same graph (0 = skip)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 1 GiB torch copy first (counter scale reference)")
     args = ap.parse_args()
@@ -167,6 +196,17 @@ def main():
         results[form] = res
         log(f"{form}: {res['ms_per_step']:.3f} ms/iter, {res['gteps']:.1f} GTEPS, {res['checks']}")
 
+    traversal = None
+    if args.bfs_sources > 0:
+        if gc.GC_PULL not in parts:
+            parts[gc.GC_PULL] = gc.tocab_partition(g, gc.GC_PULL, args.block_width, args.merge_range)
+        srcs = gg.sources(gh, args.bfs_sources, seed=2)
+        pols = [("plain_pull", gc.GC_POLICY_PULL, False), ("tocab_pull", gc.GC_POLICY_PULL, True),
+                ("push", gc.GC_POLICY_PUSH, False), ("heuristic_tocab", gc.GC_POLICY_HEURISTIC, True),
+                ("heuristic_plain", gc.GC_POLICY_HEURISTIC, False)]
+        traversal = {"bfs": run_traversal(gc, torch, g, gh, parts[gc.GC_PULL], srcs, "bfs", pols),
+                     "sources": [int(x) for x in srcs]}
+
     head = forms[0]
     hres = results[head]
     info = hres["partition"] or {}
@@ -206,6 +246,7 @@ def main():
         "step_algorithmic_GBs": round(step_bytes / (hres["ms_per_step"] * 1e-3) / 1e9, 1),
         "cpu_baseline": cpu,
         "forms": forms_out,
+        "traversal": traversal,
     }
     print(json.dumps(out), flush=True)
     for p in parts.values():

@@ -100,13 +100,26 @@ int graph_free(gc_graph g);
 /* TOCAB preprocessing (Section 3.1; Figures 3 and 4). dir = GC_PULL blocks
  * the transposed graph by source (column blocking), GC_PUSH blocks the graph
  * itself by destination (row blocking); the same code does both.
- * block_width W: power of two in [2^10, 2^26]; B = ceil(n / W) <= 32768.
+ * block_width W: power of two in [2^10, 2^26]; B = ceil(n / W) <= 32768;
+ * 0 = chosen by tocab_autotune (with its merge range unless one is given).
  * merge_range k: power of two in [256, 16384], width of the merge ranges of
- * Figure 5 (0 = 4096). Inside block s only rows with at least one arc there
+ * Figure 5 (0 = 4096, or the autotuned value when W = 0). Inside block s only rows with at least one arc there
  * get a local id, in ascending global order; id_map maps local to global.
  * Synchronises `stream` once (it sizes its buffers). Free with tocab_free. */
 int tocab_partition(gc_graph g, int32_t dir, int32_t block_width, int32_t merge_range,
                     hipStream_t stream, gc_tocab* out);
+
+/* Chooses W and k for `dir` on this graph (the paper picks its subgraph
+ * size with a sweep, Section 4.3): candidate widths 2^12 .. min(2^22, n)
+ * are timed on PageRank iterations of the graph itself with successive
+ * halving (2, 4, 8, ... iterations; the faster half survives each round),
+ * then merge ranges 2048 / 4096 / 8192 are compared for the winner. Builds
+ * and frees candidate partitions (needs room for one at a time), allocates
+ * two rank vectors, synchronises `stream`. The result is cached per graph
+ * signature (n, m, sampled offsets) for the life of the process.
+ * ms_per_iter (nullable) receives the winner's time per iteration. */
+int tocab_autotune(gc_graph g, int32_t dir, int32_t* block_width, int32_t* merge_range, float* ms_per_iter,
+                   hipStream_t stream);
 
 /* B, P (number of local rows over all blocks), W, k, direction and the
  * device bytes the partition holds. Any pointer may be NULL. */

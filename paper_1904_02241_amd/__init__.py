@@ -38,6 +38,7 @@ SIGNATURES = {
     "graph_free": (ctypes.c_int, [_vp]),
     "tocab_partition": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, ctypes.POINTER(_vp)]),
     "tocab_info": (ctypes.c_int, [_vp, _p_i32, _p_i64, _p_i32, _p_i32, _p_i32, _p_i64]),
+    "tocab_autotune": (ctypes.c_int, [_vp, _i32, _p_i32, _p_i32, ctypes.POINTER(ctypes.c_float), _vp]),
     "tocab_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tocab_free": (ctypes.c_int, [_vp]),
     "pagerank_iter": (ctypes.c_int, [_vp, _vp, _i32, _f32, _i32, _vp, _vp, _i32, _vp]),
@@ -203,6 +204,14 @@ def tocab_partition(g, direction, block_width, merge_range=0, stream=None):
     _check(lib.tocab_partition(_h(g), direction, block_width, merge_range, _stream(stream), ctypes.byref(out)),
            "tocab_partition")
     return Tocab(out, g)
+
+
+def tocab_autotune(g, direction, stream=None):
+    """(block_width, merge_range, ms per PageRank iteration) chosen for g."""
+    W, k, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+    _check(lib.tocab_autotune(_h(g), direction, ctypes.byref(W), ctypes.byref(k), ctypes.byref(ms), _stream(stream)),
+           "tocab_autotune")
+    return W.value, k.value, ms.value
 
 
 def tocab_info(t):

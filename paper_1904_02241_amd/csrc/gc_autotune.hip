@@ -1,0 +1,132 @@
+// Block-width autotuner: successive halving over candidate (W, k) pairs,
+// each timed on PageRank iterations of the graph itself with HIP events.
+// The paper picks its subgraph size by a sweep (Section 4.3); here the sweep
+// runs per graph and its result is cached for the process.
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "gc_internal.h"
+
+namespace {
+
+struct Candidate {
+  int32_t W, k;
+  double ms = 0.0;  // best time per iteration seen
+};
+
+using Key = std::tuple<int32_t, int64_t, int32_t, uint64_t>;
+std::mutex g_mu;
+std::map<Key, Candidate> g_cache;
+
+bool allowed(int64_t n, int32_t W, int32_t k) {
+  const int64_t B = (n + W - 1) / W, R = (n + k - 1) / k;
+  return B <= 32768 && B * (R + 1) <= (int64_t(1) << 28);
+}
+
+// Times `iters` PageRank iterations on partition t (after one warm-up).
+hipError_t time_iters(gc_graph g, gc_tocab t, int32_t iters, float* ra, float* rb, hipStream_t s, double* ms) {
+  GC_HIP_TRY(gcx::pagerank_run(g, t, t->dir, 0.85f, GC_DANGLING_UNIFORM, ra, rb, 1, s));
+  hipEvent_t e0, e1;
+  GC_HIP_TRY(hipEventCreate(&e0));
+  GC_HIP_TRY(hipEventCreate(&e1));
+  hipError_t e = hipEventRecord(e0, s);
+  if (e == hipSuccess) e = gcx::pagerank_run(g, t, t->dir, 0.85f, GC_DANGLING_UNIFORM, rb, ra, iters, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float f = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = static_cast<double>(f) / iters;
+  return e;
+}
+
+}  // namespace
+
+namespace gcx {
+
+hipError_t autotune(gc_graph g, int32_t dir, int32_t* W_out, int32_t* k_out, float* ms_out, hipStream_t s) {
+  // graph signature: sizes plus a hash of sampled offsets
+  std::vector<int32_t> sample(65);
+  const int64_t n = g->n;
+  for (int i = 0; i <= 64; ++i) {
+    const int64_t v = n * i / 64;
+    GC_HIP_TRY(hipMemcpyAsync(&sample[i], g->rowptr + v, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  }
+  GC_HIP_TRY(hipStreamSynchronize(s));
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the sample
+  for (int32_t x : sample) {
+    for (int b = 0; b < 4; ++b) {
+      h ^= static_cast<uint8_t>(x >> (8 * b));
+      h *= 1099511628211ull;
+    }
+  }
+  const Key key{g->n, g->m, dir, h};
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+      *W_out = it->second.W;
+      *k_out = it->second.k;
+      *ms_out = static_cast<float>(it->second.ms);
+      return hipSuccess;
+    }
+  }
+  int32_t top = 1 << 10;
+  while (top < n && top < (1 << 22)) top <<= 1;
+  std::vector<Candidate> cand;
+  for (int32_t W = 1 << 12; W <= std::max(top, 1 << 12); W <<= 1)
+    if (W >= (1 << 10) && allowed(n, W, 4096)) cand.push_back({W, 4096});
+  if (cand.empty()) cand.push_back({1 << 22, 4096});
+  Buf ra(sizeof(float) * n, s), rb(sizeof(float) * n, s);
+  if (!ra.p || !rb.p) return hipErrorOutOfMemory;
+  // uniform start vector: any vector gives the same amount of work
+  {
+    std::vector<float> init(static_cast<size_t>(n), 1.0f / static_cast<float>(n));
+    GC_HIP_TRY(hipMemcpyAsync(ra.p, init.data(), sizeof(float) * n, hipMemcpyHostToDevice, s));
+    GC_HIP_TRY(hipStreamSynchronize(s));
+  }
+  auto evaluate = [&](Candidate& c, int32_t iters) -> hipError_t {
+    gc_tocab t = nullptr;
+    if (tocab_partition(g, dir, c.W, c.k, s, &t) != GC_OK) return hipErrorInvalidValue;
+    double ms = 0.0;
+    const hipError_t e = time_iters(g, t, iters, ra.as<float>(), rb.as<float>(), s, &ms);
+    (void)hipStreamSynchronize(s);
+    tocab_free(t);
+    if (e == hipSuccess) c.ms = ms;
+    return e;
+  };
+  // successive halving on W, then the merge range for the winner
+  int32_t iters = 2;
+  while (cand.size() > 1) {
+    for (auto& c : cand) GC_HIP_TRY(evaluate(c, iters));
+    std::sort(cand.begin(), cand.end(), [](const Candidate& a, const Candidate& b) { return a.ms < b.ms; });
+    cand.resize((cand.size() + 1) / 2);
+    iters *= 2;
+  }
+  Candidate best = cand[0];
+  if (best.ms == 0.0) GC_HIP_TRY(evaluate(best, iters));
+  for (int32_t k : {2048, 8192}) {
+    if (!allowed(n, best.W, k)) continue;
+    Candidate c{best.W, k};
+    GC_HIP_TRY(evaluate(c, iters));
+    Candidate b2 = best;
+    GC_HIP_TRY(evaluate(b2, iters));  // re-time the incumbent under the same conditions
+    best = (c.ms < b2.ms) ? c : b2;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cache[key] = best;
+  }
+  *W_out = best.W;
+  *k_out = best.k;
+  *ms_out = static_cast<float>(best.ms);
+  return hipSuccess;
+}
+
+}  // namespace gcx

@@ -433,6 +433,8 @@ __global__ void k_tile_rows(const int32_t* __restrict__ row_ptr, int32_t rows, i
   tile_row[t] = first_at_least(row_ptr, 0, rows, static_cast<int64_t>(t) * tile_arcs);
 }
 
+// Low 16 bits of (value & mask): a column inside its block, or a row inside
+// its merge range.
 __global__ void k_col16(const int32_t* __restrict__ col, int64_t m, int32_t mask, uint16_t* __restrict__ col16) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < m; i += stride)
@@ -633,7 +635,14 @@ hipError_t build_partition(gc_tocab t, const int32_t* a_rowptr, const int32_t* a
                                                           t->weighted ? a_w : nullptr, t->col, t->w);
   GC_HIP_TRY(hipGetLastError());
   GC_HIP_TRY(build_tiles(t->row_ptr, P, t->m, pull_tile_arcs(), &t->tile_row, &t->n_tiles, s));
-  if (t->W <= kLdsMaxWidth) GC_HIP_TRY(build_lds_chunks(t, s));
+  t->id16 = static_cast<uint16_t*>(dev_alloc(sizeof(uint16_t) * Pn, s));
+  if (!t->id16) return hipErrorOutOfMemory;
+  if (P > 0) k_col16<<<grid_for(P, 256, 65536), 256, 0, s>>>(t->id_map, P, t->k - 1, t->id16);
+  t->bytes += static_cast<int64_t>(sizeof(uint16_t)) * P;
+  if (t->W <= kLdsMaxWidth) {
+    GC_HIP_TRY(build_tiles(t->row_ptr, P, t->m, wave_tile_arcs(), &t->wtile_row, &t->n_wtiles, s));
+    GC_HIP_TRY(build_lds_chunks(t, s));
+  }
   return hipStreamSynchronize(s);
 }
 

@@ -59,11 +59,14 @@ struct gc_tocab_s {
   int32_t* w = nullptr;           // [m] or null
   int32_t* range_ptr = nullptr;   // [(R+1)*B], j-major
   float* partial = nullptr;       // [P] pull partial sums (Algorithm 4)
+  uint16_t* id16 = nullptr;       // [P] id_map mod k: position inside the merge range
   int32_t* tile_row = nullptr;    // [n_tiles+1] first local row of each pull tile
   int32_t n_tiles = 0;
   // LDS-resident blocks (W <= kLdsMaxWidth): columns as 16-bit offsets inside
   // the block, and chunks of one block's local rows for one work-group each
   uint16_t* col16 = nullptr;      // [m]
+  int32_t* wtile_row = nullptr;   // first local row of each wave tile of wave_tile_arcs() arcs
+  int32_t n_wtiles = 0;
   int32_t* chunk_beg = nullptr;   // [n_chunks]
   int32_t* chunk_end = nullptr;   // [n_chunks]
   int32_t* chunk_blk = nullptr;   // [n_chunks]
@@ -114,12 +117,16 @@ hipError_t build_partition(gc_tocab t, const int32_t* a_rowptr, const int32_t* a
 
 // ---- PageRank (gc_pagerank.hip) ----
 int32_t pull_tile_arcs();
+int32_t wave_tile_arcs();
 // Largest block width whose FP32 contribution slice is staged in LDS.
 constexpr int32_t kLdsMaxWidth = 1 << 15;
 // Arcs per chunk of an LDS-resident block (one work-group each).
 constexpr int32_t kLdsChunkArcs = 1 << 16;
 hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int32_t dangling,
                         const float* rank_in, float* rank_out, int32_t iters, hipStream_t s);
+
+// ---- autotuner (gc_autotune.hip) ----
+hipError_t autotune(gc_graph g, int32_t dir, int32_t* W_out, int32_t* k_out, float* ms_out, hipStream_t s);
 
 // ---- traversal (gc_traverse.hip) ----
 hipError_t bfs_run(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32_t* levels,

@@ -53,6 +53,12 @@ __device__ __forceinline__ double update_vertex(const Update& u, int32_t v, doub
   return deg ? 0.0 : static_cast<double>(r32);
 }
 
+// Orders LDS accesses between the lanes of one wave.
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Work-group sum of one double per thread (fixed reduction tree), returned
 // to every thread.
 __device__ __forceinline__ double wg_sum(double x) {
@@ -197,90 +203,77 @@ __global__ __launch_bounds__(kThreads) void k_pr_tocab_pull(const int32_t* __res
 // to kLdsMaxWidth): gfx950 serves random 4-byte reads from LDS about ten
 // times faster than from L2, so on this GPU the block is sized for the
 // 160 KB LDS of a compute unit rather than for the last-level cache. One
-// work-group takes a chunk of one block's local rows: it loads the slice
-// c[sW, sW + W) into LDS once (coalesced), then walks the chunk in steps of
-// kLdsStep arcs, staging the gathered values (16-bit column offsets, read
-// from the LDS slice) and summing whole rows per thread as in pull_tile; a
-// row too long for the stage is summed by the whole work-group.
+// work-group takes a chunk of one block's local rows and loads the slice
+// c[sW, sW + W) into LDS once (coalesced). Its waves then work
+// independently on the kWaveTile-arc tiles covering the chunk: a wave
+// stages the tile's gathered values (16-bit column offsets read as one
+// 8-byte load per lane, values read from the LDS slice) in its own LDS
+// strip, each lane sums whole rows that start in the tile, and the one row
+// that may run past the tile's end is finished by the whole wave.
 constexpr int kLdsThreads = 1024;
-constexpr int kLdsStep = 4096;
-constexpr int kLdsPer = kLdsStep / kLdsThreads;
-
-__device__ __forceinline__ double wg1024_sum(double x) {
-  __shared__ double part[kLdsThreads / kWave];
-  x = gcd::wave_sum(x);
-  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = x;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int w = 0; w < kLdsThreads / kWave; ++w) t += part[w];
-  __syncthreads();
-  return t;
-}
+constexpr int kLdsWaves = kLdsThreads / kWave;
+constexpr int kWaveTile = 4 * kWave;  // 4 arcs per lane
 
 __global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
-    const int32_t* __restrict__ row_ptr, const uint16_t* __restrict__ col16, const int32_t* __restrict__ chunk_beg,
-    const int32_t* __restrict__ chunk_end, const int32_t* __restrict__ chunk_blk, int32_t log2W, int32_t n,
-    const float* __restrict__ c, float* __restrict__ partial) {
+    const int32_t* __restrict__ row_ptr, const uint16_t* __restrict__ col16, const int32_t* __restrict__ wtile_row,
+    const int32_t* __restrict__ chunk_beg, const int32_t* __restrict__ chunk_end, const int32_t* __restrict__ chunk_blk,
+    int32_t log2W, int32_t n, int32_t m, const float* __restrict__ c, float* __restrict__ partial) {
   extern __shared__ float lds[];
   const int32_t W = 1 << log2W;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   float* slice = lds;
-  float* vals = lds + W;
+  float* stage = lds + W + wid * kWaveTile;
   const int32_t r0 = chunk_beg[blockIdx.x], r1 = chunk_end[blockIdx.x];
   if (r0 >= r1) return;
   const int32_t v0 = chunk_blk[blockIdx.x] << log2W;
   const int32_t cnt = min(W, n - v0);
   for (int32_t i = threadIdx.x; i < cnt; i += kLdsThreads) slice[i] = c[v0 + i];
   __syncthreads();
-  for (int32_t rb = r0; rb < r1;) {
-    const int32_t a0 = row_ptr[rb];
-    // rows whose first arc lies in [a0, a0 + kLdsStep)
-    int32_t lo = rb + 1, hi = r1;
-    while (lo < hi) {
-      const int32_t mid = lo + ((hi - lo) >> 1);
-      if (row_ptr[mid] < a0 + kLdsStep) lo = mid + 1;
-      else hi = mid;
+  const int32_t q0 = row_ptr[r0] / kWaveTile, q1 = (row_ptr[r1] - 1) / kWaveTile;
+  for (int32_t q = q0 + wid; q <= q1; q += kLdsWaves) {
+    const int32_t rb = max(r0, wtile_row[q]), re = min(r1, wtile_row[q + 1]);
+    if (rb >= re) continue;  // no chunk row starts here (middle of a long row)
+    const int32_t tb = q * kWaveTile;
+    const int32_t te = min(tb + kWaveTile, m);
+    uint16_t u[4];
+    if (tb + kWaveTile <= m) {
+      const uint64_t four = gcd::ld_stream(reinterpret_cast<const uint64_t*>(col16 + tb) + lane);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) u[j] = static_cast<uint16_t>(four >> (16 * j));
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) u[j] = col16[min(tb + 4 * lane + j, m - 1)];
     }
-    const int32_t re = lo;
-    const int32_t last_b = row_ptr[re - 1], a_end = row_ptr[re];
-    const bool long_last = (a_end - a0) > kLdsStep;
-    const int32_t len = (long_last ? last_b : a_end) - a0;
-    if (len > 0) {
-      int32_t u[kLdsPer];
 #pragma unroll
-      for (int k = 0; k < kLdsPer; ++k)
-        u[k] = gcd::ld_stream(col16 + a0 + min(static_cast<int32_t>(threadIdx.x) + k * kLdsThreads, len - 1));
-#pragma unroll
-      for (int k = 0; k < kLdsPer; ++k) {
-        const int32_t i = threadIdx.x + k * kLdsThreads;
-        if (i < len) vals[i] = slice[u[k]];
+    for (int j = 0; j < 4; ++j) stage[4 * lane + j] = slice[u[j]];
+    wave_lds_fence();
+    bool over = false;
+    int32_t over_row = 0, over_end = 0;
+    double over_sum = 0.0;
+    for (int32_t r = rb + lane; r < re; r += kWave) {
+      const int32_t b = row_ptr[r], e = row_ptr[r + 1];
+      const int32_t ee = min(e, te);
+      double sum = 0.0;
+      for (int32_t i = b; i < ee; ++i) sum += static_cast<double>(stage[i - tb]);
+      if (e > te) {  // only the tile's last row can run past its end
+        over = true;
+        over_row = r;
+        over_end = e;
+        over_sum = sum;
+      } else {
+        gcd::st_stream(partial + r, static_cast<float>(sum));
       }
     }
-    __syncthreads();
-    const int32_t r_short_end = long_last ? re - 1 : re;
-    for (int32_t r = rb + threadIdx.x; r < r_short_end; r += kLdsThreads) {
-      const int32_t b = row_ptr[r] - a0, e = row_ptr[r + 1] - a0;
-      double sum = 0.0;
-      for (int32_t i = b; i < e; ++i) sum += static_cast<double>(vals[i]);
-      gcd::st_stream(partial + r, static_cast<float>(sum));
+    const uint64_t ob = __ballot(over);
+    if (ob) {
+      const int owner = __ffsll(static_cast<long long>(ob)) - 1;
+      const int32_t oe = __shfl(over_end, owner, kWave);
+      double acc = 0.0;
+      for (int32_t i = te + lane; i < oe; i += kWave) acc += static_cast<double>(slice[col16[i]]);
+      acc = gcd::wave_sum(acc);
+      if (lane == owner) partial[over_row] = static_cast<float>(over_sum + acc);
     }
-    if (long_last) {
-      double sum = 0.0;
-      for (int32_t base = last_b; base < a_end; base += kLdsStep) {
-        int32_t u[kLdsPer];
-#pragma unroll
-        for (int k = 0; k < kLdsPer; ++k)
-          u[k] = gcd::ld_stream(col16 + min(base + static_cast<int32_t>(threadIdx.x) + k * kLdsThreads, a_end - 1));
-#pragma unroll
-        for (int k = 0; k < kLdsPer; ++k)
-          if (base + static_cast<int32_t>(threadIdx.x) + k * kLdsThreads < a_end)
-            sum += static_cast<double>(slice[u[k]]);
-      }
-      sum = wg1024_sum(sum);
-      if (threadIdx.x == 0) partial[re - 1] = static_cast<float>(sum);
-    }
-    __syncthreads();  // the stage is rewritten by the next step
-    rb = re;
+    wave_lds_fence();  // the strip is rewritten by the next tile
   }
 }
 
@@ -309,7 +302,7 @@ __global__ __launch_bounds__(kThreads) void k_pr_plain_pull(const int32_t* __res
 // into LDS (FP64), then updates its vertices with coalesced writes.
 template <int K, bool kFlat>
 __global__ __launch_bounds__(kThreads) void k_pr_merge(const int32_t* __restrict__ range_ptr, int32_t B,
-                                                       const int32_t* __restrict__ id_map,
+                                                       const uint16_t* __restrict__ id16,
                                                        const float* __restrict__ partial, Update u) {
   __shared__ double acc[K];
   __shared__ int32_t seg_lo[kFlat ? kFlatB : 1];
@@ -352,40 +345,81 @@ __global__ __launch_bounds__(kThreads) void k_pr_merge(const int32_t* __restrict
     if (threadIdx.x == kThreads - 1) seg_pre[B] = run;
     __syncthreads();
     const int32_t total = seg_pre[B];
-    constexpr int kUnroll = 8;
+    // Each wave walks a contiguous quarter of the flattened list in windows
+    // of kWin positions, 8 consecutive ones per lane. The slice of every
+    // position comes from marking the slices that start inside the window
+    // (LDS max, so the last of several empty slices wins) followed by a
+    // running max along the window: no chain of dependent lookups.
+    constexpr int kWin = 8 * kWave;
+    __shared__ int32_t mark[kThreads / kWave][kWin];
+    int32_t* mk = mark[wid];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) mk[8 * lane + k] = -1;
+    const int32_t per_wave = ((total + 4 * kWin - 1) / (4 * kWin)) * kWin;
+    const int32_t F0 = min(total, wid * per_wave), F1 = min(total, F0 + per_wave);
     int32_t s = 0;
-    for (int32_t f0 = threadIdx.x; f0 < total; f0 += kThreads * kUnroll) {
-      // flat positions past the end reuse the first (valid) local row and are masked
-      int32_t l[kUnroll];
-#pragma unroll
-      for (int k = 0; k < kUnroll; ++k) {
-        const int32_t f = f0 + k * kThreads;
-        if (f < total) {
-          while (seg_pre[s + 1] <= f) ++s;
-          l[k] = seg_lo[s] + (f - seg_pre[s]);
-        } else {
-          l[k] = l[0];
-        }
+    if (F0 < F1) {  // last slice starting at or before F0 (non-empty by construction)
+      int32_t lo2 = 0, hi2 = B - 1;
+      while (lo2 < hi2) {
+        const int32_t mid = (lo2 + hi2 + 1) >> 1;
+        if (seg_pre[mid] <= F0) lo2 = mid;
+        else hi2 = mid - 1;
       }
-      int32_t v[kUnroll];
-      float p[kUnroll];
+      s = lo2;
+    }
+    for (int32_t F = F0; F < F1; F += kWin) {
+      wave_lds_fence();
+      for (int32_t ss = s + 1 + lane;; ss += kWave) {
+        if (ss >= B) break;
+        const int32_t st = seg_pre[ss];
+        if (st >= F + kWin) break;
+        if (st >= F) atomicMax(&mk[st - F], ss);
+      }
+      wave_lds_fence();
+      int32_t run = -1, sk[8];
 #pragma unroll
-      for (int k = 0; k < kUnroll; ++k) {
-        v[k] = gcd::ld_stream(id_map + l[k]);
+      for (int k = 0; k < 8; ++k) {
+        run = max(run, mk[8 * lane + k]);
+        sk[k] = run;
+      }
+      int32_t incl = run;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t t = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl = max(incl, t);
+      }
+      int32_t excl = __shfl_up(incl, 1, kWave);
+      excl = max(lane == 0 ? -1 : excl, s);
+      const int32_t l_first = seg_lo[s] + (F - seg_pre[s]);
+      int32_t l[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int32_t f = F + 8 * lane + k;
+        const int32_t q = max(sk[k], excl);
+        l[k] = f < F1 ? seg_lo[q] + (f - seg_pre[q]) : l_first;
+      }
+      uint16_t v[8];
+      float p[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        v[k] = gcd::ld_stream(id16 + l[k]);
         p[k] = gcd::ld_stream(partial + l[k]);
       }
 #pragma unroll
-      for (int k = 0; k < kUnroll; ++k)
-        if (f0 + k * kThreads < total) atomicAdd(&acc[v[k] - v0], static_cast<double>(p[k]));
+      for (int k = 0; k < 8; ++k)
+        if (F + 8 * lane + k < F1) atomicAdd(&acc[v[k]], static_cast<double>(p[k]));
+      s = max(s, __shfl(incl, kWave - 1, kWave));
+#pragma unroll
+      for (int k = 0; k < 8; ++k) mk[8 * lane + k] = -1;
     }
   } else {
     __syncthreads();
     for (int32_t s = 0; s < B; ++s) {
       const int32_t a = lo[s], z = hi[s];
       for (int32_t l = a + threadIdx.x; l < z; l += kThreads) {
-        const int32_t v = gcd::ld_stream(id_map + l);
+        const uint16_t v = gcd::ld_stream(id16 + l);
         const float p = gcd::ld_stream(partial + l);
-        atomicAdd(&acc[v - v0], static_cast<double>(p));
+        atomicAdd(&acc[v], static_cast<double>(p));
       }
     }
   }
@@ -463,10 +497,10 @@ __global__ __launch_bounds__(kThreads) void k_pr_apply(double* __restrict__ sums
 }
 
 template <int K>
-void launch_merge(int32_t R, hipStream_t s, const int32_t* rp, int32_t B, const int32_t* id_map,
+void launch_merge(int32_t R, hipStream_t s, const int32_t* rp, int32_t B, const uint16_t* id16,
                   const float* partial, const Update& u) {
-  if (B <= kFlatB) k_pr_merge<K, true><<<R, kThreads, 0, s>>>(rp, B, id_map, partial, u);
-  else k_pr_merge<K, false><<<R, kThreads, 0, s>>>(rp, B, id_map, partial, u);
+  if (B <= kFlatB) k_pr_merge<K, true><<<R, kThreads, 0, s>>>(rp, B, id16, partial, u);
+  else k_pr_merge<K, false><<<R, kThreads, 0, s>>>(rp, B, id16, partial, u);
 }
 
 }  // namespace
@@ -475,11 +509,13 @@ namespace gcx {
 
 int32_t pull_tile_arcs() { return kTileArcs; }
 
+int32_t wave_tile_arcs() { return kWaveTile; }
+
 hipError_t pagerank_setup() {
-  // the LDS-resident pull stages up to kLdsMaxWidth + kLdsStep floats
+  // the LDS-resident pull holds a slice of up to kLdsMaxWidth floats plus one strip per wave
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_tocab_pull_lds),
                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                             static_cast<int>(sizeof(float) * (kLdsMaxWidth + kLdsStep)));
+                             static_cast<int>(sizeof(float) * (kLdsMaxWidth + kLdsThreads * 4)));
 }
 
 hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int32_t dangling,
@@ -519,10 +555,10 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
     if (t && !push) {
       if (t->col16) {
         ProfScope prof("pr_tocab_pull", s);
-        const size_t lds = sizeof(float) * (static_cast<size_t>(t->W) + kLdsStep);
-        k_pr_tocab_pull_lds<<<t->n_chunks, kLdsThreads, lds, s>>>(t->row_ptr, t->col16, t->chunk_beg, t->chunk_end,
-                                                                  t->chunk_blk, t->log2W, n, g->contrib[0],
-                                                                  t->partial);
+        const size_t lds = sizeof(float) * (static_cast<size_t>(t->W) + kLdsThreads * 4);
+        k_pr_tocab_pull_lds<<<t->n_chunks, kLdsThreads, lds, s>>>(
+            t->row_ptr, t->col16, t->wtile_row, t->chunk_beg, t->chunk_end, t->chunk_blk, t->log2W, n,
+            static_cast<int32_t>(t->m), g->contrib[0], t->partial);
       } else {
         ProfScope prof("pr_tocab_pull", s);
         k_pr_tocab_pull<<<t->n_tiles, kThreads, 0, s>>>(t->row_ptr, t->col, t->tile_row, g->contrib[0],
@@ -532,13 +568,13 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
       parts = t->R;
       ProfScope prof("pr_merge", s);
       switch (t->k) {
-        case 256: launch_merge<256>(t->R, s, t->range_ptr, t->B, t->id_map, t->partial, u); break;
-        case 512: launch_merge<512>(t->R, s, t->range_ptr, t->B, t->id_map, t->partial, u); break;
-        case 1024: launch_merge<1024>(t->R, s, t->range_ptr, t->B, t->id_map, t->partial, u); break;
-        case 2048: launch_merge<2048>(t->R, s, t->range_ptr, t->B, t->id_map, t->partial, u); break;
-        case 4096: launch_merge<4096>(t->R, s, t->range_ptr, t->B, t->id_map, t->partial, u); break;
-        case 8192: launch_merge<8192>(t->R, s, t->range_ptr, t->B, t->id_map, t->partial, u); break;
-        case 16384: launch_merge<16384>(t->R, s, t->range_ptr, t->B, t->id_map, t->partial, u); break;
+        case 256: launch_merge<256>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
+        case 512: launch_merge<512>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
+        case 1024: launch_merge<1024>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
+        case 2048: launch_merge<2048>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
+        case 4096: launch_merge<4096>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
+        case 8192: launch_merge<8192>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
+        case 16384: launch_merge<16384>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
         default: return hipErrorInvalidValue;
       }
     } else if (!push) {

@@ -80,7 +80,7 @@ void free_graph(gc_graph g) {
 void free_tocab(gc_tocab t) {
   if (!t) return;
   void* bufs[] = {t->blk_rowoff, t->row_ptr, t->id_map, t->col, t->w, t->range_ptr, t->partial, t->pmin,
-                  t->tile_row, t->col16, t->chunk_beg, t->chunk_end, t->chunk_blk};
+                  t->tile_row, t->col16, t->chunk_beg, t->chunk_end, t->chunk_blk, t->wtile_row, t->id16};
   for (void* p : bufs)
     if (p) gcx::dev_free(p, nullptr);
   delete t;
@@ -270,6 +270,14 @@ int tocab_partition(gc_graph g, int32_t dir, int32_t block_width, int32_t merge_
   *out = nullptr;
   if (!g) return fail(GC_EINVAL, "tocab_partition: NULL graph");
   if (dir != GC_PULL && dir != GC_PUSH) return fail(GC_EINVAL, "tocab_partition: dir must be GC_PULL or GC_PUSH");
+  if (block_width == 0) {
+    int32_t W = 0, k = 0;
+    float ms = 0.0f;
+    const int rc = tocab_autotune(g, dir, &W, &k, &ms, stream);
+    if (rc != GC_OK) return rc;
+    block_width = W;
+    if (merge_range == 0) merge_range = k;
+  }
   if (!is_pow2(block_width) || block_width < (1 << 10) || block_width > (1 << 26))
     return fail(GC_EINVAL, "tocab_partition: block_width %d is not a power of two in [2^10, 2^26]", block_width);
   if (merge_range == 0) merge_range = 4096;
@@ -306,6 +314,18 @@ int tocab_partition(gc_graph g, int32_t dir, int32_t block_width, int32_t merge_
     return hip_fail(e, "tocab_partition");
   }
   *out = t;
+  return GC_OK;
+}
+
+int tocab_autotune(gc_graph g, int32_t dir, int32_t* block_width, int32_t* merge_range, float* ms_per_iter,
+                   hipStream_t stream) {
+  if (!g) return fail(GC_EINVAL, "tocab_autotune: NULL graph");
+  if (dir != GC_PULL && dir != GC_PUSH) return fail(GC_EINVAL, "tocab_autotune: dir must be GC_PULL or GC_PUSH");
+  if (!block_width || !merge_range) return fail(GC_EINVAL, "tocab_autotune: NULL output");
+  float ms = 0.0f;
+  const hipError_t e = gcx::autotune(g, dir, block_width, merge_range, &ms, stream);
+  if (e != hipSuccess) return hip_fail(e, "tocab_autotune");
+  if (ms_per_iter) *ms_per_iter = ms;
   return GC_OK;
 }
 

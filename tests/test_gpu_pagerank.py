@@ -122,3 +122,20 @@ def test_pagerank_rmat22_tocab_and_plain():
         err = l1(got, want)
         print(f"{form}: L1 = {err:.3e}", flush=True)
         assert err <= L1_TOL
+
+
+def test_autotune_picks_a_valid_width_and_caches_it():
+    import paper_1904_02241_amd as gc
+    g = gg.rmat(16, 16, seed=1)
+    h = load(g)
+    W, k, ms = gc.tocab_autotune(h, gc.GC_PULL)
+    assert W & (W - 1) == 0 and (1 << 12) <= W <= (1 << 16)
+    assert k in (2048, 4096, 8192) and ms > 0
+    assert gc.tocab_autotune(h, gc.GC_PULL) == (W, k, ms)  # cached for this graph
+    part = gc.tocab_partition(h, gc.GC_PULL, 0, 0)  # width 0: autotuned
+    assert (part.info["W"], part.info["k"]) == (W, k)
+    got, r0 = pagerank_gpu(g, "tocab_pull", oracle.UNIFORM, handles={"g": h}, W=W, k=k)
+    want = oracle.pagerank(g.n, g.rowptr, g.colidx, 0.85, 20, r0=r0)
+    assert l1(got, want) <= L1_TOL
+    part.free()
+    h.free()
