@@ -62,9 +62,12 @@ typedef enum {
 #define GC_POLICY_PULL 0      /* every level: topology-driven pull             */
 #define GC_POLICY_PUSH 1      /* every level: data-driven push with a queue    */
 #define GC_POLICY_HEURISTIC 2 /* per level: working-set rule of Section 3.3    */
+#define GC_POLICY_LEARNED 3   /* per level: attached scheduler network (below), */
+                              /* heuristic when it gives no finite answer       */
 
 typedef struct gc_graph_s* gc_graph;
 typedef struct gc_tocab_s* gc_tocab;
+typedef struct gc_sched_s* gc_sched;
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* gc_last_error(void);
@@ -177,6 +180,59 @@ int bfs_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32_t* le
  * receives the number of rounds. Synchronises once per round. */
 int sssp_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* dist, int32_t* rounds,
               uint32_t policy, hipStream_t stream);
+
+/* Per-level record of the last bfs_pull / sssp_pull on g: actions[i] is the
+ * way level i ran (0 push, 1 plain pull, 2 TOCAB pull with the call's
+ * partition, or 2 + j for the j-th partition attached with sched_attach) and
+ * ms[i] its wall time including the level's synchronisation. Up to `max`
+ * entries are written; *count receives the number of levels. */
+int traversal_trace(gc_graph g, int32_t* actions, float* ms, int32_t max, int32_t* count);
+
+/* ---- learned level scheduler ---------------------------------------------
+ * Not in the paper: a small network that picks, per traversal level, among
+ * data-driven push, plain topology-driven pull and TOCAB pull over one of
+ * several block widths, trained on per-level timings the traversal itself
+ * produces. Network: GC_SCHED_INPUTS -> GC_SCHED_HIDDEN -> GC_SCHED_HIDDEN ->
+ * K, ReLU after the hidden layers, FP32; output k is the predicted log time
+ * (ms) of action k and the arg-min is run. Parameters, row-major:
+ *   W1[64][6], b1[64], W2[64][64], b2[64], W3[K][64], b3[K].
+ * Features of a level (sched_features): log1p(frontier size), log1p(frontier
+ * out-arcs), log1p(m / n), log2(ceil(n / 2^18) + 1), level / 16,
+ * log1p(previous level's time in microseconds). */
+#define GC_SCHED_INPUTS 6
+#define GC_SCHED_HIDDEN 64
+
+int sched_param_count(int32_t n_actions, int64_t* count);
+/* New network with K = n_actions outputs (1..64) from initial parameters
+ * (host or device, sched_param_count floats; the caller draws them). */
+int sched_create(int32_t n_actions, const float* params, gc_sched* out);
+int sched_get_params(gc_sched m, float* params, hipStream_t stream);
+/* y[batch][K] = network(x[batch][6]); device buffers. */
+int sched_forward(gc_sched m, const float* x, int32_t batch, float* y, hipStream_t stream);
+/* Masked mean squared error sum(mask (y - t)^2) / sum(mask) of the outputs
+ * against targets t (log ms), and its gradient with respect to the
+ * parameters (same layout); device buffers; deterministic. */
+int sched_loss_grad(gc_sched m, const float* x, const float* t, const float* mask, int32_t batch, float* loss,
+                    float* grad, hipStream_t stream);
+/* `steps` full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8) at rate
+ * lr; loss_hist (device, nullable) receives the loss before each step. */
+int sched_train(gc_sched m, const float* x, const float* t, const float* mask, int32_t batch, int32_t steps, float lr,
+                float* loss_hist, hipStream_t stream);
+int sched_free(gc_sched m);
+/* The 6 features of a level (host arithmetic, also used internally). */
+int sched_features(int32_t n, int64_t m, int32_t frontier, int64_t frontier_arcs, int32_t level, float prior_ms,
+                   float* features);
+/* Training rows for a network with K = 2 + n_parts actions: traverses from
+ * each source (kind 0 = BFS, 1 = SSSP) and at every level runs every action
+ * from the same saved state, timing each with HIP events, then continues with
+ * the fastest. Writes host features[rows][6] and times_ms[rows][K] (up to
+ * max_rows) and *rows. parts must be GC_PULL partitions of g. */
+int sched_collect(gc_graph g, const gc_tocab* parts, int32_t n_parts, int32_t kind, const int32_t* sources,
+                  int32_t n_sources, float* features, float* times_ms, int32_t max_rows, int32_t* rows,
+                  hipStream_t stream);
+/* Attaches network m (K = 2 + n_parts) and its TOCAB partitions to g for
+ * GC_POLICY_LEARNED; m = NULL detaches. The handles must outlive the use. */
+int sched_attach(gc_graph g, gc_sched m, const gc_tocab* parts, int32_t n_parts);
 
 /* Waits for `stream` and reports a pending asynchronous HIP error. */
 int gc_sync(hipStream_t stream);

@@ -22,7 +22,8 @@ GC_UNREACHED = np.iinfo(np.int32).max
 GC_DEVICE_PTRS, GC_VALIDATE = 1, 2
 GC_PULL, GC_PUSH = 0, 1
 GC_DANGLING_UNIFORM, GC_DANGLING_LEAK = 0, 1
-GC_POLICY_PULL, GC_POLICY_PUSH, GC_POLICY_HEURISTIC = 0, 1, 2
+GC_POLICY_PULL, GC_POLICY_PUSH, GC_POLICY_HEURISTIC, GC_POLICY_LEARNED = 0, 1, 2, 3
+GC_SCHED_INPUTS, GC_SCHED_HIDDEN = 6, 64
 
 # every exported entry point, with (restype, argtypes)
 _vp, _i32, _i64, _u32, _f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_float
@@ -45,6 +46,17 @@ SIGNATURES = {
     "bfs_pull": (ctypes.c_int, [_vp, _vp, _i32, _vp, _p_i32, _u32, _vp]),
     "sssp_pull": (ctypes.c_int, [_vp, _vp, _i32, _vp, _p_i32, _u32, _vp]),
     "gc_sync": (ctypes.c_int, [_vp]),
+    "traversal_trace": (ctypes.c_int, [_vp, _vp, _vp, _i32, _p_i32]),
+    "sched_param_count": (ctypes.c_int, [_i32, _p_i64]),
+    "sched_create": (ctypes.c_int, [_i32, _vp, ctypes.POINTER(_vp)]),
+    "sched_get_params": (ctypes.c_int, [_vp, _vp, _vp]),
+    "sched_forward": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp]),
+    "sched_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp]),
+    "sched_train": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _f32, _vp, _vp]),
+    "sched_free": (ctypes.c_int, [_vp]),
+    "sched_features": (ctypes.c_int, [_i32, _i64, _i32, _i64, _i32, _f32, _vp]),
+    "sched_collect": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _p_i32, _vp]),
+    "sched_attach": (ctypes.c_int, [_vp, _vp, _vp, _i32]),
     "gc_profile": (ctypes.c_int, [_i32]),
     "gc_profile_count": (ctypes.c_int, [_p_i32]),
     "gc_profile_get": (ctypes.c_int, [_i32, ctypes.c_char_p, _i32, ctypes.POINTER(ctypes.c_double), _p_i64]),
@@ -267,3 +279,97 @@ def gc_profile_read():
         _check(lib.gc_profile_get(i, name, 128, ctypes.byref(ms), ctypes.byref(nl)), "gc_profile_get")
         out[name.value.decode()] = (ms.value, nl.value)
     return out
+
+
+# ---------------------------------------------------------------------------
+# learned level scheduler
+
+def traversal_trace(g, max_levels=4096):
+    """(actions, ms) of every level of the last bfs_pull / sssp_pull on g."""
+    acts = np.zeros(max_levels, np.int32)
+    ms = np.zeros(max_levels, np.float32)
+    cnt = ctypes.c_int32()
+    _check(lib.traversal_trace(_h(g), acts.ctypes.data, ms.ctypes.data, max_levels, ctypes.byref(cnt)),
+           "traversal_trace")
+    k = min(cnt.value, max_levels)
+    return acts[:k], ms[:k]
+
+
+def sched_param_count(n_actions):
+    c = ctypes.c_int64()
+    _check(lib.sched_param_count(n_actions, ctypes.byref(c)), "sched_param_count")
+    return c.value
+
+
+class Sched:
+    def __init__(self, handle, n_actions):
+        self.handle, self.n_actions = handle, n_actions
+
+    def free(self):
+        if self.handle:
+            _check(lib.sched_free(self.handle), "sched_free")
+            self.handle = None
+
+
+def sched_create(n_actions, params):
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    assert params.shape == (sched_param_count(n_actions),)
+    out = ctypes.c_void_p()
+    _check(lib.sched_create(n_actions, params.ctypes.data, ctypes.byref(out)), "sched_create")
+    return Sched(out, n_actions)
+
+
+def sched_get_params(m):
+    out = np.empty(sched_param_count(m.n_actions), np.float32)
+    _check(lib.sched_get_params(_h(m), out.ctypes.data, _stream(None)), "sched_get_params")
+    gc_sync()
+    return out
+
+
+def sched_forward(m, x, y, stream=None):
+    _check(lib.sched_forward(_h(m), _ptr(x), int(x.shape[0]), _ptr(y), _stream(stream)), "sched_forward")
+
+
+def sched_loss_grad(m, x, t, mask, loss, grad, stream=None):
+    _check(lib.sched_loss_grad(_h(m), _ptr(x), _ptr(t), _ptr(mask), int(x.shape[0]), _ptr(loss), _ptr(grad),
+                               _stream(stream)), "sched_loss_grad")
+
+
+def sched_train(m, x, t, mask, steps, lr, loss_hist=None, stream=None):
+    _check(lib.sched_train(_h(m), _ptr(x), _ptr(t), _ptr(mask), int(x.shape[0]), steps, lr, _ptr(loss_hist),
+                           _stream(stream)), "sched_train")
+
+
+def sched_free(m):
+    m.free()
+
+
+def sched_features(n, m, frontier, frontier_arcs, level, prior_ms):
+    out = np.empty(GC_SCHED_INPUTS, np.float32)
+    _check(lib.sched_features(n, m, frontier, frontier_arcs, level, prior_ms, out.ctypes.data), "sched_features")
+    return out
+
+
+def _handles(parts):
+    arr = (ctypes.c_void_p * max(1, len(parts)))()
+    for i, p in enumerate(parts):
+        arr[i] = p.handle.value if isinstance(p.handle, ctypes.c_void_p) else p.handle
+    return arr
+
+
+def sched_collect(g, parts, kind, sources, max_rows=100000, stream=None):
+    """(features [rows, 6], times_ms [rows, 2 + len(parts)]) of every level."""
+    K = 2 + len(parts)
+    feats = np.zeros((max_rows, GC_SCHED_INPUTS), np.float32)
+    times = np.zeros((max_rows, K), np.float32)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    rows = ctypes.c_int32()
+    _check(lib.sched_collect(_h(g), _handles(parts), len(parts), kind, src.ctypes.data, src.shape[0],
+                             feats.ctypes.data, times.ctypes.data, max_rows, ctypes.byref(rows), _stream(stream)),
+           "sched_collect")
+    return feats[:rows.value], times[:rows.value]
+
+
+def sched_attach(g, m, parts=()):
+    _check(lib.sched_attach(_h(g), _h(m), _handles(parts) if m is not None else None,
+                            len(parts) if m is not None else 0), "sched_attach")

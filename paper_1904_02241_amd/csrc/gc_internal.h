@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "graphcage.h"
 
@@ -42,6 +43,12 @@ struct gc_graph_s {
   int32_t* stats = nullptr;     // device counters read back once per level
   int32_t* stats_host = nullptr;  // pinned mirror
   int64_t bytes = 0;
+  // learned level scheduler attached to this graph (sched_attach)
+  gc_sched sched = nullptr;
+  std::vector<gc_tocab> sched_parts;
+  // per-level record of the last traversal: action and wall time (ms)
+  std::vector<int32_t> trace_action;
+  std::vector<float> trace_ms;
 };
 
 struct gc_tocab_s {
@@ -133,6 +140,13 @@ hipError_t bfs_run(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32
                    uint32_t policy, hipStream_t s);
 hipError_t sssp_run(gc_graph g, gc_tocab t, int32_t source, int32_t* dist, int32_t* rounds,
                     uint32_t policy, hipStream_t s, bool* overflow);
+hipError_t collect(gc_graph g, gc_tocab* parts, int32_t n_parts, bool bfs, const int32_t* sources, int32_t n_src,
+                   float* features, float* times, int32_t max_rows, int32_t* rows, hipStream_t s);
+void sched_features(int64_t n, int64_t m, int64_t n_f, int64_t m_f, int32_t level, double prior_ms, float* f);
+
+// ---- scheduler network (gc_sched.hip) ----
+int32_t sched_actions(gc_sched m);
+hipError_t sched_decide(gc_sched m, const float* features, hipStream_t s, int32_t* action);
 
 // Records HIP events around the launches made in its scope while
 // profiling is on (gc_profile); a no-op otherwise.

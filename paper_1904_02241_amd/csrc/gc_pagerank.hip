@@ -345,72 +345,31 @@ __global__ __launch_bounds__(kThreads) void k_pr_merge(const int32_t* __restrict
     if (threadIdx.x == kThreads - 1) seg_pre[B] = run;
     __syncthreads();
     const int32_t total = seg_pre[B];
-    // Each wave walks a contiguous quarter of the flattened list in windows
-    // of kWin positions, 8 consecutive ones per lane. The slice of every
-    // position comes from marking the slices that start inside the window
-    // (LDS max, so the last of several empty slices wins) followed by a
-    // running max along the window: no chain of dependent lookups.
-    constexpr int kWin = 8 * kWave;
-    __shared__ int32_t mark[kThreads / kWave][kWin];
-    int32_t* mk = mark[wid];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) mk[8 * lane + k] = -1;
-    const int32_t per_wave = ((total + 4 * kWin - 1) / (4 * kWin)) * kWin;
-    const int32_t F0 = min(total, wid * per_wave), F1 = min(total, F0 + per_wave);
+    constexpr int kUnroll = 8;
     int32_t s = 0;
-    if (F0 < F1) {  // last slice starting at or before F0 (non-empty by construction)
-      int32_t lo2 = 0, hi2 = B - 1;
-      while (lo2 < hi2) {
-        const int32_t mid = (lo2 + hi2 + 1) >> 1;
-        if (seg_pre[mid] <= F0) lo2 = mid;
-        else hi2 = mid - 1;
-      }
-      s = lo2;
-    }
-    for (int32_t F = F0; F < F1; F += kWin) {
-      wave_lds_fence();
-      for (int32_t ss = s + 1 + lane;; ss += kWave) {
-        if (ss >= B) break;
-        const int32_t st = seg_pre[ss];
-        if (st >= F + kWin) break;
-        if (st >= F) atomicMax(&mk[st - F], ss);
-      }
-      wave_lds_fence();
-      int32_t run = -1, sk[8];
+    for (int32_t f0 = threadIdx.x; f0 < total; f0 += kThreads * kUnroll) {
+      // flat positions past the end reuse the first (valid) local row and are masked
+      int32_t l[kUnroll];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        run = max(run, mk[8 * lane + k]);
-        sk[k] = run;
+      for (int k = 0; k < kUnroll; ++k) {
+        const int32_t f = f0 + k * kThreads;
+        if (f < total) {
+          while (seg_pre[s + 1] <= f) ++s;
+          l[k] = seg_lo[s] + (f - seg_pre[s]);
+        } else {
+          l[k] = l[0];
+        }
       }
-      int32_t incl = run;
+      uint16_t v[kUnroll];
+      float p[kUnroll];
 #pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const int32_t t = __shfl_up(incl, o, kWave);
-        if (lane >= o) incl = max(incl, t);
-      }
-      int32_t excl = __shfl_up(incl, 1, kWave);
-      excl = max(lane == 0 ? -1 : excl, s);
-      const int32_t l_first = seg_lo[s] + (F - seg_pre[s]);
-      int32_t l[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int32_t f = F + 8 * lane + k;
-        const int32_t q = max(sk[k], excl);
-        l[k] = f < F1 ? seg_lo[q] + (f - seg_pre[q]) : l_first;
-      }
-      uint16_t v[8];
-      float p[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < kUnroll; ++k) {
         v[k] = gcd::ld_stream(id16 + l[k]);
         p[k] = gcd::ld_stream(partial + l[k]);
       }
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (F + 8 * lane + k < F1) atomicAdd(&acc[v[k]], static_cast<double>(p[k]));
-      s = max(s, __shfl(incl, kWave - 1, kWave));
-#pragma unroll
-      for (int k = 0; k < 8; ++k) mk[8 * lane + k] = -1;
+      for (int k = 0; k < kUnroll; ++k)
+        if (f0 + k * kThreads < total) atomicAdd(&acc[v[k]], static_cast<double>(p[k]));
     }
   } else {
     __syncthreads();

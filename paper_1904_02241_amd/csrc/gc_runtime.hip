@@ -392,7 +392,8 @@ int bfs_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32_t* le
   if (source < 0 || source >= g->n) return fail(GC_EINVAL, "bfs_pull: source %d outside [0, %d)", source, g->n);
   if (!depth) return fail(GC_EINVAL, "bfs_pull: NULL depth");
   if (!is_device_ptr(depth)) return fail(GC_EINVAL, "bfs_pull: depth must be device memory");
-  if (policy > GC_POLICY_HEURISTIC) return fail(GC_EINVAL, "bfs_pull: unknown policy %u", policy);
+  if (policy > GC_POLICY_LEARNED) return fail(GC_EINVAL, "bfs_pull: unknown policy %u", policy);
+  if (policy == GC_POLICY_LEARNED && !g->sched) return fail(GC_EINVAL, "bfs_pull: no scheduler attached");
   const hipError_t e = gcx::bfs_run(g, t, source, depth, levels, policy, stream);
   if (e == hipErrorNotSupported) return fail(GC_EUNSUPPORTED, "bfs_pull: not available in this build");
   return e == hipSuccess ? GC_OK : hip_fail(e, "bfs_pull");
@@ -407,12 +408,69 @@ int sssp_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* dist, int32_t* ro
   if (source < 0 || source >= g->n) return fail(GC_EINVAL, "sssp_pull: source %d outside [0, %d)", source, g->n);
   if (!dist) return fail(GC_EINVAL, "sssp_pull: NULL dist");
   if (!is_device_ptr(dist)) return fail(GC_EINVAL, "sssp_pull: dist must be device memory");
-  if (policy > GC_POLICY_HEURISTIC) return fail(GC_EINVAL, "sssp_pull: unknown policy %u", policy);
+  if (policy > GC_POLICY_LEARNED) return fail(GC_EINVAL, "sssp_pull: unknown policy %u", policy);
+  if (policy == GC_POLICY_LEARNED && !g->sched) return fail(GC_EINVAL, "sssp_pull: no scheduler attached");
   bool overflow = false;
   const hipError_t e = gcx::sssp_run(g, t, source, dist, rounds, policy, stream, &overflow);
   if (e == hipErrorNotSupported) return fail(GC_EUNSUPPORTED, "sssp_pull: not available in this build");
   if (e != hipSuccess) return hip_fail(e, "sssp_pull");
   if (overflow) return fail(GC_EOVERFLOW, "sssp_pull: a distance reached INT32_MAX");
+  return GC_OK;
+}
+
+int traversal_trace(gc_graph g, int32_t* actions, float* ms, int32_t max, int32_t* count) {
+  if (!g || !count || max < 0) return fail(GC_EINVAL, "traversal_trace: bad argument");
+  const int32_t nl = static_cast<int32_t>(g->trace_action.size());
+  for (int32_t i = 0; i < std::min(nl, max); ++i) {
+    if (actions) actions[i] = g->trace_action[i];
+    if (ms) ms[i] = g->trace_ms[i];
+  }
+  *count = nl;
+  return GC_OK;
+}
+
+int sched_features(int32_t n, int64_t m, int32_t frontier, int64_t frontier_arcs, int32_t level, float prior_ms,
+                   float* features) {
+  if (n <= 0 || m < 0 || frontier < 0 || frontier_arcs < 0 || level < 0 || !features)
+    return fail(GC_EINVAL, "sched_features: bad argument");
+  gcx::sched_features(n, m, frontier, frontier_arcs, level, prior_ms, features);
+  return GC_OK;
+}
+
+int sched_collect(gc_graph g, const gc_tocab* parts, int32_t n_parts, int32_t kind, const int32_t* sources,
+                  int32_t n_sources, float* features, float* times_ms, int32_t max_rows, int32_t* rows,
+                  hipStream_t stream) {
+  if (!g || (n_parts > 0 && !parts) || n_parts < 0 || n_parts > 62 || !sources || n_sources < 0 || !features ||
+      !times_ms || max_rows < 0 || !rows)
+    return fail(GC_EINVAL, "sched_collect: bad argument");
+  if (kind != 0 && kind != 1) return fail(GC_EINVAL, "sched_collect: kind must be 0 (BFS) or 1 (SSSP)");
+  if (kind == 1 && !g->weighted) return fail(GC_EINVAL, "sched_collect: SSSP needs a weighted graph");
+  for (int32_t i = 0; i < n_parts; ++i)
+    if (!parts[i] || parts[i]->g != g || parts[i]->dir != GC_PULL)
+      return fail(GC_EINVAL, "sched_collect: partition %d is not a GC_PULL partition of this graph", i);
+  for (int32_t i = 0; i < n_sources; ++i)
+    if (sources[i] < 0 || sources[i] >= g->n) return fail(GC_EINVAL, "sched_collect: source %d out of range", i);
+  std::vector<gc_tocab> ps(parts, parts + n_parts);
+  const hipError_t e = gcx::collect(g, ps.data(), n_parts, kind == 0, sources, n_sources, features, times_ms,
+                                    max_rows, rows, stream);
+  return e == hipSuccess ? GC_OK : hip_fail(e, "sched_collect");
+}
+
+int sched_attach(gc_graph g, gc_sched m, const gc_tocab* parts, int32_t n_parts) {
+  if (!g) return fail(GC_EINVAL, "sched_attach: NULL graph");
+  if (!m) {
+    g->sched = nullptr;
+    g->sched_parts.clear();
+    return GC_OK;
+  }
+  if (n_parts < 0 || (n_parts > 0 && !parts)) return fail(GC_EINVAL, "sched_attach: bad partitions");
+  if (gcx::sched_actions(m) != 2 + n_parts)
+    return fail(GC_EINVAL, "sched_attach: network has %d outputs, needs 2 + %d", gcx::sched_actions(m), n_parts);
+  for (int32_t i = 0; i < n_parts; ++i)
+    if (!parts[i] || parts[i]->g != g || parts[i]->dir != GC_PULL)
+      return fail(GC_EINVAL, "sched_attach: partition %d is not a GC_PULL partition of this graph", i);
+  g->sched = m;
+  g->sched_parts.assign(parts, parts + n_parts);
   return GC_OK;
 }
 

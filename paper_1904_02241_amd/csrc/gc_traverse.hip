@@ -18,7 +18,9 @@
 // The host reads the frontier size and its out-arc count once per level.
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
+#include <cmath>
 
 #include "gc_device.h"
 #include "gc_internal.h"
@@ -26,6 +28,8 @@
 namespace {
 
 using gcd::kWave;
+using gcx::Buf;
+using gcx::ProfScope;
 
 constexpr int kThreads = 256;
 constexpr int32_t kInf = INT32_MAX;
@@ -472,12 +476,6 @@ struct Heuristic {
   }
 };
 
-Mode choose(uint32_t policy, gc_tocab t, Heuristic& h, int64_t n, int64_t n_f, int64_t m_f, int64_t m_u) {
-  if (policy == GC_POLICY_PUSH) return Mode::kPush;
-  if (policy == GC_POLICY_PULL) return t ? Mode::kTocab : Mode::kPull;
-  return h.pick(n, n_f, m_f, m_u, t != nullptr);
-}
-
 template <template <int> class Kern, class... Args>
 hipError_t launch_by_k(int32_t k, int32_t R, hipStream_t s, Args... args) {
   switch (k) {
@@ -509,8 +507,8 @@ struct SsspMerge {
   }
 };
 
-// Shared per-level bookkeeping: reads the next frontier's size and out-arc
-// count, clears the old frontier's status bytes, and swaps the buffers.
+// Per-level bookkeeping: reads the next frontier's size and out-arc count,
+// clears the old frontier's status bytes, and swaps the buffers.
 struct Frontier {
   gc_graph g;
   hipStream_t s;
@@ -552,36 +550,20 @@ hipError_t init_state(gc_graph g, int32_t* value, int32_t source, bool bfs, hipS
   return hipGetLastError();
 }
 
-}  // namespace
-
-namespace gcx {
-
-hipError_t bfs_run(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32_t* levels, uint32_t policy,
-                   hipStream_t s) {
+// Enqueues one level (BFS depth `level` -> level+1, or SSSP round `level`)
+// in the given mode; t is the partition used by a TOCAB level.
+hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t level, Mode mode, gc_tocab t,
+                     hipStream_t s) {
   const int32_t n = g->n;
-  GC_HIP_TRY(init_state(g, depth, source, true, s));
-  Frontier f{g, s};
-  f.m_f = 0;
-  {
-    int32_t rp[2];
-    GC_HIP_TRY(hipMemcpyAsync(rp, g->rowptr + source, sizeof(rp), hipMemcpyDeviceToHost, s));
-    GC_HIP_TRY(hipStreamSynchronize(s));
-    f.m_f = rp[1] - rp[0];
-  }
-  int64_t m_u = g->m - f.m_f;
-  Heuristic h;
-  int32_t level = 0;
-  while (f.n_f > 0) {
-    const Mode mode = choose(policy, t, h, n, f.n_f, f.m_f, m_u);
-    GC_HIP_TRY(f.begin_level());
+  if (bfs) {
     if (mode == Mode::kPush) {
       ProfScope prof("bfs_push", s);
-      k_bfs_push<<<grid_for(f.n_f, kThreads), kThreads, 0, s>>>(f.queue(), f.n_f, g->rowptr, g->colidx, depth,
+      k_bfs_push<<<grid_for(f.n_f, kThreads), kThreads, 0, s>>>(f.queue(), f.n_f, g->rowptr, g->colidx, value,
                                                                  level, f.next(), g->visited, f.queue_next(),
                                                                  g->stats);
     } else if (mode == Mode::kPull) {
       ProfScope prof("bfs_pull", s);
-      k_bfs_pull<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, n, f.front(), depth, level,
+      k_bfs_pull<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, n, f.front(), value, level,
                                                              f.next(), g->visited, f.queue_next(), g->stats);
     } else {
       uint8_t* flag = reinterpret_cast<uint8_t*>(t->pmin);
@@ -592,64 +574,218 @@ hipError_t bfs_run(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32
       }
       ProfScope prof("bfs_merge", s);
       GC_HIP_TRY((launch_by_k<BfsMerge>(t->k, t->R, s, t->range_ptr, t->B, static_cast<const int32_t*>(t->id_map),
-                                        static_cast<const uint8_t*>(flag), n, depth, level, f.next(), g->visited,
+                                        static_cast<const uint8_t*>(flag), n, value, level, f.next(), g->visited,
                                         f.queue_next(), g->stats)));
     }
-    GC_HIP_TRY(hipGetLastError());
-    GC_HIP_TRY(f.end_level(nullptr));
-    m_u -= f.m_f;
-    ++level;
-  }
-  if (levels) *levels = level;
-  return hipSuccess;
-}
-
-hipError_t sssp_run(gc_graph g, gc_tocab t, int32_t source, int32_t* dist, int32_t* rounds, uint32_t policy,
-                    hipStream_t s, bool* overflow) {
-  const int32_t n = g->n;
-  GC_HIP_TRY(init_state(g, dist, source, false, s));
-  Frontier f{g, s};
-  {
-    int32_t rp[2];
-    GC_HIP_TRY(hipMemcpyAsync(rp, g->rowptr + source, sizeof(rp), hipMemcpyDeviceToHost, s));
-    GC_HIP_TRY(hipStreamSynchronize(s));
-    f.m_f = rp[1] - rp[0];
-  }
-  Heuristic h;
-  int32_t round = 0;
-  *overflow = false;
-  while (f.n_f > 0) {
-    if (round > n) return hipErrorInvalidValue;  // cannot happen with positive weights
-    // SSSP revisits vertices, so the unexplored-arc count of BFS does not
-    // apply; the whole arc set stands in for it.
-    const Mode mode = choose(policy, t, h, n, f.n_f, f.m_f, g->m);
-    GC_HIP_TRY(f.begin_level());
+  } else {
     if (mode == Mode::kPush) {
       ProfScope prof("sssp_push", s);
-      k_sssp_push<<<grid_for(f.n_f, kThreads), kThreads, 0, s>>>(f.queue(), f.n_f, g->rowptr, g->colidx, g->w, dist,
-                                                                  round, g->mark, f.next(), f.queue_next(), g->stats);
+      k_sssp_push<<<grid_for(f.n_f, kThreads), kThreads, 0, s>>>(f.queue(), f.n_f, g->rowptr, g->colidx, g->w,
+                                                                  value, level, g->mark, f.next(), f.queue_next(),
+                                                                  g->stats);
     } else if (mode == Mode::kPull) {
       ProfScope prof("sssp_pull", s);
-      k_sssp_pull<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, g->t_w, n, f.front(), dist,
+      k_sssp_pull<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, g->t_w, n, f.front(), value,
                                                               f.next(), f.queue_next(), g->stats);
     } else {
       {
         ProfScope prof("sssp_tocab", s);
-        k_sssp_tocab<<<grid_for(t->P, kThreads), kThreads, 0, s>>>(t->row_ptr, t->col, t->w, t->P, f.front(), dist,
+        k_sssp_tocab<<<grid_for(t->P, kThreads), kThreads, 0, s>>>(t->row_ptr, t->col, t->w, t->P, f.front(), value,
                                                                     t->pmin, g->stats);
       }
       ProfScope prof("sssp_merge", s);
       GC_HIP_TRY((launch_by_k<SsspMerge>(t->k, t->R, s, t->range_ptr, t->B, static_cast<const int32_t*>(t->id_map),
-                                         static_cast<const int32_t*>(t->pmin), n, dist, f.next(), f.queue_next(),
+                                         static_cast<const int32_t*>(t->pmin), n, value, f.next(), f.queue_next(),
                                          g->stats)));
     }
-    GC_HIP_TRY(hipGetLastError());
-    GC_HIP_TRY(f.end_level(overflow));
-    if (*overflow) break;
-    ++round;
   }
-  if (rounds) *rounds = round;
+  return hipGetLastError();
+}
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int64_t source_degree(gc_graph g, int32_t source, hipStream_t s, hipError_t* e) {
+  int32_t rp[2] = {0, 0};
+  *e = hipMemcpyAsync(rp, g->rowptr + source, sizeof(rp), hipMemcpyDeviceToHost, s);
+  if (*e == hipSuccess) *e = hipStreamSynchronize(s);
+  return rp[1] - rp[0];
+}
+
+// Action k of the learned scheduler: 0 push, 1 plain pull, 2 + i TOCAB pull
+// over the i-th attached partition.
+void action_mode(int32_t a, gc_tocab* parts, Mode* mode, gc_tocab* t) {
+  *t = nullptr;
+  if (a == 0) *mode = Mode::kPush;
+  else if (a == 1) *mode = Mode::kPull;
+  else {
+    *mode = Mode::kTocab;
+    *t = parts[a - 2];
+  }
+}
+
+int32_t mode_action(Mode m) { return m == Mode::kPush ? 0 : (m == Mode::kPull ? 1 : 2); }
+
+}  // namespace
+
+namespace gcx {
+
+void sched_features(int64_t n, int64_t m, int64_t n_f, int64_t m_f, int32_t level, double prior_ms, float* f) {
+  f[0] = static_cast<float>(std::log1p(static_cast<double>(n_f)));
+  f[1] = static_cast<float>(std::log1p(static_cast<double>(m_f)));
+  f[2] = static_cast<float>(std::log1p(static_cast<double>(m) / static_cast<double>(std::max<int64_t>(n, 1))));
+  f[3] = static_cast<float>(std::log2(static_cast<double>((n + (1 << 18) - 1) >> 18) + 1.0));
+  f[4] = static_cast<float>(level) / 16.0f;
+  f[5] = static_cast<float>(std::log1p(prior_ms * 1000.0));
+}
+
+hipError_t traverse(gc_graph g, gc_tocab t, int32_t source, int32_t* value, int32_t* count, uint32_t policy,
+                    hipStream_t s, bool bfs, bool* overflow) {
+  const int32_t n = g->n;
+  GC_HIP_TRY(init_state(g, value, source, bfs, s));
+  Frontier f{g, s};
+  hipError_t e;
+  f.m_f = source_degree(g, source, s, &e);
+  GC_HIP_TRY(e);
+  int64_t m_u = g->m - f.m_f;
+  Heuristic h;
+  int32_t level = 0;
+  double prior_ms = 0.0;
+  g->trace_action.clear();
+  g->trace_ms.clear();
+  if (overflow) *overflow = false;
+  while (f.n_f > 0) {
+    if (!bfs && level > n) return hipErrorInvalidValue;  // cannot happen with positive weights
+    // SSSP revisits vertices, so the unexplored-arc count of BFS does not
+    // apply; the whole arc set stands in for it.
+    const int64_t unexplored = bfs ? m_u : g->m;
+    Mode mode = Mode::kPush;
+    gc_tocab lt = t;
+    int32_t action = -1;
+    if (policy == GC_POLICY_LEARNED && g->sched) {
+      float feats[GC_SCHED_INPUTS];
+      sched_features(n, g->m, f.n_f, f.m_f, level, prior_ms, feats);
+      GC_HIP_TRY(sched_decide(g->sched, feats, s, &action));
+      if (action >= 0 && action < sched_actions(g->sched)) action_mode(action, g->sched_parts.data(), &mode, &lt);
+      else action = -1;
+    }
+    if (action < 0) {
+      if (policy == GC_POLICY_PUSH) mode = Mode::kPush;
+      else if (policy == GC_POLICY_PULL) mode = t ? Mode::kTocab : Mode::kPull;
+      else mode = h.pick(n, f.n_f, f.m_f, unexplored, t != nullptr);  // heuristic, or learned fallback
+      lt = t;
+      action = mode_action(mode);
+    }
+    const double t0 = now_ms();
+    GC_HIP_TRY(f.begin_level());
+    GC_HIP_TRY(run_level(g, f, bfs, value, level, mode, lt, s));
+    GC_HIP_TRY(f.end_level(overflow));
+    prior_ms = now_ms() - t0;
+    g->trace_action.push_back(action);
+    g->trace_ms.push_back(static_cast<float>(prior_ms));
+    if (overflow && *overflow) break;
+    if (bfs) m_u -= f.m_f;
+    ++level;
+  }
+  if (count) *count = level;
   return hipSuccess;
+}
+
+hipError_t bfs_run(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32_t* levels, uint32_t policy,
+                   hipStream_t s) {
+  return traverse(g, t, source, depth, levels, policy, s, true, nullptr);
+}
+
+hipError_t sssp_run(gc_graph g, gc_tocab t, int32_t source, int32_t* dist, int32_t* rounds, uint32_t policy,
+                    hipStream_t s, bool* overflow) {
+  return traverse(g, t, source, dist, rounds, policy, s, false, overflow);
+}
+
+// Training data for the scheduler: at every level of a traversal from each
+// source, the level is run once per action from the same state (snapshot
+// and restore of the frontier state), each run timed with HIP events; the
+// traversal then continues with the fastest action. One row per level:
+// 6 features and K = 2 + n_parts times in ms.
+hipError_t collect(gc_graph g, gc_tocab* parts, int32_t n_parts, bool bfs, const int32_t* sources, int32_t n_src,
+                   float* features, float* times, int32_t max_rows, int32_t* rows, hipStream_t s) {
+  const int32_t n = g->n;
+  const int32_t K = 2 + n_parts;
+  const size_t words = (static_cast<size_t>(n) + 31) / 32;
+  Buf value(sizeof(int32_t) * n, s), sv(sizeof(int32_t) * n, s), sfront(n, s), snext(n, s),
+      svis(sizeof(uint32_t) * words, s), smark(sizeof(int32_t) * n, s), squeue(sizeof(int32_t) * n, s);
+  if (!value.p || !sv.p || !sfront.p || !snext.p || !svis.p || !smark.p || !squeue.p) return hipErrorOutOfMemory;
+  hipEvent_t e0, e1;
+  GC_HIP_TRY(hipEventCreate(&e0));
+  GC_HIP_TRY(hipEventCreate(&e1));
+  int32_t r = 0;
+  hipError_t err = hipSuccess;
+  for (int32_t si = 0; si < n_src && err == hipSuccess; ++si) {
+    err = init_state(g, value.as<int32_t>(), sources[si], bfs, s);
+    if (err != hipSuccess) break;
+    Frontier f{g, s};
+    f.m_f = source_degree(g, sources[si], s, &err);
+    int32_t level = 0;
+    double prior_ms = 0.0;
+    bool overflow = false;
+    while (err == hipSuccess && f.n_f > 0 && r < max_rows && !overflow) {
+      sched_features(n, g->m, f.n_f, f.m_f, level, prior_ms, features + static_cast<size_t>(r) * GC_SCHED_INPUTS);
+      // snapshot the state this level starts from
+      const hipMemcpyKind dd = hipMemcpyDeviceToDevice;
+      err = hipMemcpyAsync(sv.p, value.p, sizeof(int32_t) * n, dd, s);
+      if (err == hipSuccess) err = hipMemcpyAsync(sfront.p, f.front(), n, dd, s);
+      if (err == hipSuccess) err = hipMemcpyAsync(snext.p, f.next(), n, dd, s);
+      if (err == hipSuccess) err = hipMemcpyAsync(svis.p, g->visited, sizeof(uint32_t) * words, dd, s);
+      if (err == hipSuccess && !bfs) err = hipMemcpyAsync(smark.p, g->mark, sizeof(int32_t) * n, dd, s);
+      if (err == hipSuccess) err = hipMemcpyAsync(squeue.p, f.queue(), sizeof(int32_t) * f.n_f, dd, s);
+      const Frontier start = f;
+      auto restore = [&]() -> hipError_t {
+        f = start;
+        GC_HIP_TRY(hipMemcpyAsync(value.p, sv.p, sizeof(int32_t) * n, dd, s));
+        GC_HIP_TRY(hipMemcpyAsync(f.front(), sfront.p, n, dd, s));
+        GC_HIP_TRY(hipMemcpyAsync(f.next(), snext.p, n, dd, s));
+        GC_HIP_TRY(hipMemcpyAsync(g->visited, svis.p, sizeof(uint32_t) * words, dd, s));
+        if (!bfs) GC_HIP_TRY(hipMemcpyAsync(g->mark, smark.p, sizeof(int32_t) * n, dd, s));
+        return hipMemcpyAsync(f.queue(), squeue.p, sizeof(int32_t) * f.n_f, dd, s);
+      };
+      float* row_t = times + static_cast<size_t>(r) * K;
+      int32_t best = 0;
+      for (int32_t a = 0; a < K && err == hipSuccess; ++a) {
+        Mode mode;
+        gc_tocab lt;
+        action_mode(a, parts, &mode, &lt);
+        if (a > 0) err = restore();
+        if (err == hipSuccess) err = f.begin_level();
+        if (err == hipSuccess) err = hipEventRecord(e0, s);
+        if (err == hipSuccess) err = run_level(g, f, bfs, value.as<int32_t>(), level, mode, lt, s);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = f.end_level(&overflow);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        row_t[a] = ms;
+        if (ms < row_t[best]) best = a;
+      }
+      if (err != hipSuccess) break;
+      // continue the traversal with the fastest action
+      if (best != K - 1) {
+        Mode mode;
+        gc_tocab lt;
+        action_mode(best, parts, &mode, &lt);
+        err = restore();
+        if (err == hipSuccess) err = f.begin_level();
+        if (err == hipSuccess) err = run_level(g, f, bfs, value.as<int32_t>(), level, mode, lt, s);
+        if (err == hipSuccess) err = f.end_level(&overflow);
+      }
+      prior_ms = row_t[best];
+      ++r;
+      ++level;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *rows = r;
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  return err;
 }
 
 }  // namespace gcx
