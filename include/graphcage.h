@@ -234,6 +234,40 @@ int sched_collect(gc_graph g, const gc_tocab* parts, int32_t n_parts, int32_t ki
  * GC_POLICY_LEARNED; m = NULL detaches. The handles must outlive the use. */
 int sched_attach(gc_graph g, gc_sched m, const gc_tocab* parts, int32_t n_parts);
 
+/* ---- batched persistent form ----------------------------------------------
+ * Not in the paper: PageRank on many graphs of uneven size, each over its
+ * own TOCAB pull partition (merge range 1024; widths[i] = 0 lets the
+ * autotuner choose among widths >= 2^16, whose slices stay in the
+ * last-level cache), together with personalised PageRank
+ *   r'[v] = (1 - d) p[v] + d (s[v] + D p[v]),  r0 = p = one-hot(seed)
+ * for up to 64 seeds on one graph (one lane per seed, an N x 64 FP32 state),
+ * all iterations in ONE persistent kernel launch whose phases are separated
+ * by grid barriers. The grid holds as many work-groups as stay resident; a
+ * barrier that waits too long sets a flag (batch_status) and every
+ * work-group leaves, so the launch always ends. */
+typedef struct gc_batch_s* gc_batch;
+
+/* Builds partitions and per-graph state (synchronises). The graph handles
+ * must outlive the batch. n_graphs may be 0 (PPR only) and n_seeds 0. */
+int batch_create(const gc_graph* graphs, int32_t n_graphs, const int32_t* block_widths, gc_graph ppr_graph,
+                 const int32_t* seeds, int32_t n_seeds, hipStream_t stream, gc_batch* out);
+/* rank_offsets[n_graphs + 1]: each graph's slice of the concatenated rank
+ * vectors; block_widths[n_graphs]; grid = persistent work-groups. */
+int batch_info(gc_batch b, int64_t* rank_offsets, int32_t* block_widths, int32_t* grid, int64_t* bytes);
+/* Queues the launch: `iters` iterations on every graph from ranks_in
+ * (device float[total n], concatenated) into ranks_out, and PPR into
+ * ppr_out (device float[n][n_seeds]). No allocation, no host sync. */
+int batch_run(gc_batch b, float damping, int32_t iters, const float* ranks_in, float* ranks_out, float* ppr_out,
+              hipStream_t stream);
+/* Captures batch_run with these arguments into a HIP graph (replaces any
+ * earlier capture); batch_launch replays it on `stream`. */
+int batch_capture(gc_batch b, float damping, int32_t iters, const float* ranks_in, float* ranks_out, float* ppr_out);
+int batch_launch(gc_batch b, hipStream_t stream);
+/* Synchronises `stream`; *barrier_timeout = 1 if the last launch's barrier
+ * gave up waiting (its results are then not valid). */
+int batch_status(gc_batch b, hipStream_t stream, int32_t* barrier_timeout);
+int batch_free(gc_batch b);
+
 /* Waits for `stream` and reports a pending asynchronous HIP error. */
 int gc_sync(hipStream_t stream);
 

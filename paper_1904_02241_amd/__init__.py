@@ -57,6 +57,13 @@ SIGNATURES = {
     "sched_features": (ctypes.c_int, [_i32, _i64, _i32, _i64, _i32, _f32, _vp]),
     "sched_collect": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _p_i32, _vp]),
     "sched_attach": (ctypes.c_int, [_vp, _vp, _vp, _i32]),
+    "batch_create": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, ctypes.POINTER(_vp)]),
+    "batch_info": (ctypes.c_int, [_vp, _vp, _vp, _p_i32, _p_i64]),
+    "batch_run": (ctypes.c_int, [_vp, _f32, _i32, _vp, _vp, _vp, _vp]),
+    "batch_capture": (ctypes.c_int, [_vp, _f32, _i32, _vp, _vp, _vp]),
+    "batch_launch": (ctypes.c_int, [_vp, _vp]),
+    "batch_status": (ctypes.c_int, [_vp, _vp, _p_i32]),
+    "batch_free": (ctypes.c_int, [_vp]),
     "gc_profile": (ctypes.c_int, [_i32]),
     "gc_profile_count": (ctypes.c_int, [_p_i32]),
     "gc_profile_get": (ctypes.c_int, [_i32, ctypes.c_char_p, _i32, ctypes.POINTER(ctypes.c_double), _p_i64]),
@@ -373,3 +380,59 @@ def sched_collect(g, parts, kind, sources, max_rows=100000, stream=None):
 def sched_attach(g, m, parts=()):
     _check(lib.sched_attach(_h(g), _h(m), _handles(parts) if m is not None else None,
                             len(parts) if m is not None else 0), "sched_attach")
+
+
+# ---------------------------------------------------------------------------
+# batched persistent form
+
+class Batch:
+    def __init__(self, handle, graphs, n_seeds):
+        self.handle, self.graphs, self.n_seeds = handle, graphs, n_seeds
+        G = len(graphs)
+        offs = np.zeros(G + 1, np.int64)
+        widths = np.zeros(max(G, 1), np.int32)
+        grid, nbytes = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib.batch_info(handle, offs.ctypes.data, widths.ctypes.data, ctypes.byref(grid), ctypes.byref(nbytes)),
+               "batch_info")
+        self.rank_offsets, self.block_widths, self.grid, self.bytes = offs, widths[:G], grid.value, nbytes.value
+
+    def free(self):
+        if self.handle:
+            _check(lib.batch_free(self.handle), "batch_free")
+            self.handle = None
+
+
+def batch_create(graphs, block_widths=None, ppr_graph=None, seeds=(), stream=None):
+    G = len(graphs)
+    hs = _handles(graphs)
+    w = None if block_widths is None else np.ascontiguousarray(block_widths, np.int32)
+    sd = np.ascontiguousarray(seeds, np.int32)
+    out = ctypes.c_void_p()
+    _check(lib.batch_create(hs if G else None, G, None if w is None else w.ctypes.data, _h(ppr_graph),
+                            sd.ctypes.data if len(sd) else None, len(sd), _stream(stream), ctypes.byref(out)),
+           "batch_create")
+    return Batch(out, list(graphs), len(sd))
+
+
+def batch_run(b, damping, iters, ranks_in, ranks_out, ppr_out, stream=None):
+    _check(lib.batch_run(_h(b), damping, iters, _ptr(ranks_in), _ptr(ranks_out), _ptr(ppr_out), _stream(stream)),
+           "batch_run")
+
+
+def batch_capture(b, damping, iters, ranks_in, ranks_out, ppr_out):
+    _check(lib.batch_capture(_h(b), damping, iters, _ptr(ranks_in), _ptr(ranks_out), _ptr(ppr_out)), "batch_capture")
+
+
+def batch_launch(b, stream=None):
+    _check(lib.batch_launch(_h(b), _stream(stream)), "batch_launch")
+
+
+def batch_status(b, stream=None):
+    """True when the last launch finished without a barrier time-out."""
+    flag = ctypes.c_int32()
+    _check(lib.batch_status(_h(b), _stream(stream), ctypes.byref(flag)), "batch_status")
+    return flag.value == 0
+
+
+def batch_free(b):
+    b.free()

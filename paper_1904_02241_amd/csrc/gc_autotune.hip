@@ -19,7 +19,7 @@ struct Candidate {
   double ms = 0.0;  // best time per iteration seen
 };
 
-using Key = std::tuple<int32_t, int64_t, int32_t, uint64_t>;
+using Key = std::tuple<int32_t, int64_t, int32_t, uint64_t, int32_t>;
 std::mutex g_mu;
 std::map<Key, Candidate> g_cache;
 
@@ -50,7 +50,8 @@ hipError_t time_iters(gc_graph g, gc_tocab t, int32_t iters, float* ra, float* r
 
 namespace gcx {
 
-hipError_t autotune(gc_graph g, int32_t dir, int32_t* W_out, int32_t* k_out, float* ms_out, hipStream_t s) {
+hipError_t autotune(gc_graph g, int32_t dir, int32_t min_W, int32_t* W_out, int32_t* k_out, float* ms_out,
+                    hipStream_t s) {
   // graph signature: sizes plus a hash of sampled offsets
   std::vector<int32_t> sample(65);
   const int64_t n = g->n;
@@ -66,7 +67,7 @@ hipError_t autotune(gc_graph g, int32_t dir, int32_t* W_out, int32_t* k_out, flo
       h *= 1099511628211ull;
     }
   }
-  const Key key{g->n, g->m, dir, h};
+  const Key key{g->n, g->m, dir, h, min_W};
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_cache.find(key);
@@ -80,9 +81,10 @@ hipError_t autotune(gc_graph g, int32_t dir, int32_t* W_out, int32_t* k_out, flo
   int32_t top = 1 << 10;
   while (top < n && top < (1 << 22)) top <<= 1;
   std::vector<Candidate> cand;
-  for (int32_t W = 1 << 12; W <= std::max(top, 1 << 12); W <<= 1)
-    if (W >= (1 << 10) && allowed(n, W, 4096)) cand.push_back({W, 4096});
-  if (cand.empty()) cand.push_back({1 << 22, 4096});
+  const int32_t lo = std::max(1 << 12, min_W);
+  for (int32_t W = lo; W <= std::max(top, lo); W <<= 1)
+    if (allowed(n, W, 4096)) cand.push_back({W, 4096});
+  if (cand.empty()) cand.push_back({std::max(1 << 22, lo), 4096});
   Buf ra(sizeof(float) * n, s), rb(sizeof(float) * n, s);
   if (!ra.p || !rb.p) return hipErrorOutOfMemory;
   // uniform start vector: any vector gives the same amount of work

@@ -133,7 +133,9 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
                         const float* rank_in, float* rank_out, int32_t iters, hipStream_t s);
 
 // ---- autotuner (gc_autotune.hip) ----
-hipError_t autotune(gc_graph g, int32_t dir, int32_t* W_out, int32_t* k_out, float* ms_out, hipStream_t s);
+// Candidate widths start at max(2^12, min_W).
+hipError_t autotune(gc_graph g, int32_t dir, int32_t min_W, int32_t* W_out, int32_t* k_out, float* ms_out,
+                    hipStream_t s);
 
 // ---- traversal (gc_traverse.hip) ----
 hipError_t bfs_run(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32_t* levels,

@@ -17,66 +17,9 @@
 #include "gc_device.h"
 #include "gc_internal.h"
 
+#include "gc_pr_device.h"
+
 namespace {
-
-using gcd::kWave;
-
-constexpr int kThreads = 256;
-
-constexpr int kTileArcs = 2048;                  // arcs per pull tile (tile table granularity)
-constexpr int kStageCap = 4096;                  // arcs a tile may stage in LDS
-constexpr int kPerThread = kStageCap / kThreads;  // staged arcs per thread
-constexpr int kFlatB = 1024;                     // merges over at most this many blocks flatten their slices
-
-static_assert(kTileArcs <= kStageCap, "a tile's short rows must fit the stage");
-
-struct Update {
-  double base;      // (1 - d) / n
-  double d;         // damping
-  double inv_n;     // 1 / n, applied to D in uniform mode (0 in leak mode)
-  const double* dtotal_in;
-  double* dpart;    // one dangling partial per work-group of the update kernel
-  const int32_t* rowptr;  // out-arc CSR: outdeg(v) = rowptr[v+1] - rowptr[v]
-  float* contrib;         // written for the next iteration
-  float* rank_out;        // written on the last iteration only (else null)
-  int32_t n;
-};
-
-// r'[v] from the neighbour sum; writes c'[v] (and r'[v] on the last pass),
-// returns r'[v] when v has no out-arcs (its share of the next D), else 0.
-__device__ __forceinline__ double update_vertex(const Update& u, int32_t v, double sum, double D) {
-  const double r = u.base + u.d * (sum + D * u.inv_n);
-  const float r32 = static_cast<float>(r);
-  const int32_t deg = u.rowptr[v + 1] - u.rowptr[v];
-  u.contrib[v] = deg ? static_cast<float>(static_cast<double>(r32) / deg) : 0.0f;
-  if (u.rank_out) u.rank_out[v] = r32;
-  return deg ? 0.0 : static_cast<double>(r32);
-}
-
-// Orders LDS accesses between the lanes of one wave.
-__device__ __forceinline__ void wave_lds_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
-// Work-group sum of one double per thread (fixed reduction tree), returned
-// to every thread.
-__device__ __forceinline__ double wg_sum(double x) {
-  __shared__ double part[kThreads / kWave];
-  x = gcd::wave_sum(x);
-  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = x;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int w = 0; w < kThreads / kWave; ++w) t += part[w];
-  __syncthreads();
-  return t;
-}
-
-__device__ __forceinline__ void publish_dangling(const Update& u, double mine) {
-  const double t = wg_sum(mine);
-  if (threadIdx.x == 0) u.dpart[blockIdx.x] = t;
-}
 
 // D for the next iteration: the partials summed in index order by one
 // work-group (deterministic).
@@ -109,78 +52,6 @@ __global__ __launch_bounds__(kThreads) void k_pr_init(const float* __restrict__ 
     if (sums) sums[v] = 0.0;
   }
   publish_dangling(u, mine);
-}
-
-// Gathers c[col[a0 + i]] for i < len (len <= kStageCap) into LDS: every lane
-// first issues its column loads (coalesced across the work-group, streamed
-// past the cache), then the gathers, so all loads of a tile are in flight
-// together. Indices past the end are clamped to the last arc instead of
-// branched around, which keeps the loads free of control flow (a branch per
-// load would make each one wait for the previous).
-__device__ __forceinline__ void stage_gather(const int32_t* __restrict__ col, const float* __restrict__ c,
-                                             int32_t a0, int32_t len, float* vals) {
-  if (len <= 0) return;
-  int32_t idx[kPerThread];
-#pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {
-    const int32_t i = min(static_cast<int32_t>(threadIdx.x) + k * kThreads, len - 1);
-    idx[k] = gcd::ld_stream(col + a0 + i);
-  }
-  float x[kPerThread];
-#pragma unroll
-  for (int k = 0; k < kPerThread; ++k) x[k] = c[idx[k]];
-#pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {
-    const int32_t i = threadIdx.x + k * kThreads;
-    if (i < len) vals[i] = x[k];
-  }
-}
-
-// Sum of c over columns [b, e) (b < e) by the whole work-group (hub rows).
-__device__ double wg_row_sum(const int32_t* __restrict__ col, const float* __restrict__ c, int32_t b, int32_t e) {
-  double s = 0.0;
-  for (int32_t base = b; base < e; base += kStageCap) {
-    int32_t idx[kPerThread];
-#pragma unroll
-    for (int k = 0; k < kPerThread; ++k)
-      idx[k] = gcd::ld_stream(col + min(base + static_cast<int32_t>(threadIdx.x) + k * kThreads, e - 1));
-    float x[kPerThread];
-#pragma unroll
-    for (int k = 0; k < kPerThread; ++k) x[k] = c[idx[k]];
-#pragma unroll
-    for (int k = 0; k < kPerThread; ++k)
-      if (base + static_cast<int32_t>(threadIdx.x) + k * kThreads < e) s += static_cast<double>(x[k]);
-  }
-  return wg_sum(s);
-}
-
-// One pull tile (coarse-grained load balancing of the pull direction,
-// Section 3.2): the tile owns the rows whose first arc lies in its
-// kTileArcs-wide slice of the arc array. Their arcs are gathered into LDS
-// together; then each thread sums whole short rows serially in FP64, and a
-// last row too long for the stage is summed by the whole work-group. No
-// atomics. emit(row, sum) is called once per owned row.
-template <class Emit>
-__device__ __forceinline__ void pull_tile(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
-                                          const float* __restrict__ c, int32_t r0, int32_t r1, float* vals,
-                                          Emit&& emit) {
-  const int32_t a0 = row_ptr[r0];
-  const int32_t last_b = row_ptr[r1 - 1];
-  const int32_t a_end = row_ptr[r1];
-  const bool long_last = (a_end - a0) > kStageCap;
-  stage_gather(col, c, a0, (long_last ? last_b : a_end) - a0, vals);
-  __syncthreads();
-  const int32_t r_short_end = long_last ? r1 - 1 : r1;
-  for (int32_t r = r0 + threadIdx.x; r < r_short_end; r += kThreads) {
-    const int32_t b = row_ptr[r] - a0, e = row_ptr[r + 1] - a0;
-    double s = 0.0;
-    for (int32_t i = b; i < e; ++i) s += static_cast<double>(vals[i]);
-    emit(r, s);
-  }
-  if (long_last) {
-    const double s = wg_row_sum(col, c, last_b, a_end);
-    if (threadIdx.x == 0) emit(r1 - 1, s);
-  }
 }
 
 // Algorithm 4 over every subgraph in one launch. Local rows are stored block
@@ -295,94 +166,15 @@ __global__ __launch_bounds__(kThreads) void k_pr_plain_pull(const int32_t* __res
 }
 
 // Figure 5 merge fused with the update: work-group j owns vertices
-// [j*K, (j+1)*K). For every block s the local rows mapping into that range
-// form one contiguous slice of partial / id_map (local ids ascend with
-// global ids); the work-group walks all B slices as one flattened list so
-// that every lane keeps several independent loads in flight, accumulates
-// into LDS (FP64), then updates its vertices with coalesced writes.
+// [j*K, (j+1)*K); it accumulates every block's partial sums for the range
+// in LDS (merge_accumulate), then updates its vertices with coalesced writes.
 template <int K, bool kFlat>
 __global__ __launch_bounds__(kThreads) void k_pr_merge(const int32_t* __restrict__ range_ptr, int32_t B,
                                                        const uint16_t* __restrict__ id16,
                                                        const float* __restrict__ partial, Update u) {
   __shared__ double acc[K];
-  __shared__ int32_t seg_lo[kFlat ? kFlatB : 1];
-  __shared__ int32_t seg_pre[kFlat ? kFlatB + 1 : 1];
+  merge_accumulate<K, kFlat>(range_ptr, B, id16, partial, blockIdx.x, acc);
   const int32_t v0 = blockIdx.x * K;
-  for (int i = threadIdx.x; i < K; i += kThreads) acc[i] = 0.0;
-  const int32_t* lo = range_ptr + static_cast<int64_t>(blockIdx.x) * B;
-  const int32_t* hi = lo + B;
-  if (kFlat) {
-    // slice starts and an exclusive scan of slice lengths (one pass, B <= kFlatB)
-    __shared__ int32_t wave_tot[kThreads / kWave];
-    constexpr int kItems = kFlatB / kThreads;
-    int32_t len[kItems];
-    int32_t mine = 0;
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      const int32_t s = threadIdx.x * kItems + k;
-      len[k] = 0;
-      if (s < B) {
-        const int32_t a = lo[s];
-        seg_lo[s] = a;
-        len[k] = hi[s] - a;
-      }
-      mine += len[k];
-    }
-    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-    const int32_t incl = gcd::wave_incl_scan(mine);
-    if (lane == kWave - 1) wave_tot[wid] = incl;
-    __syncthreads();
-    int32_t off = 0;
-#pragma unroll
-    for (int w = 0; w < kThreads / kWave; ++w) off += (w < wid) ? wave_tot[w] : 0;
-    int32_t run = off + incl - mine;
-#pragma unroll
-    for (int k = 0; k < kItems; ++k) {
-      const int32_t s = threadIdx.x * kItems + k;
-      if (s < B) seg_pre[s] = run;
-      run += len[k];
-    }
-    if (threadIdx.x == kThreads - 1) seg_pre[B] = run;
-    __syncthreads();
-    const int32_t total = seg_pre[B];
-    constexpr int kUnroll = 8;
-    int32_t s = 0;
-    for (int32_t f0 = threadIdx.x; f0 < total; f0 += kThreads * kUnroll) {
-      // flat positions past the end reuse the first (valid) local row and are masked
-      int32_t l[kUnroll];
-#pragma unroll
-      for (int k = 0; k < kUnroll; ++k) {
-        const int32_t f = f0 + k * kThreads;
-        if (f < total) {
-          while (seg_pre[s + 1] <= f) ++s;
-          l[k] = seg_lo[s] + (f - seg_pre[s]);
-        } else {
-          l[k] = l[0];
-        }
-      }
-      uint16_t v[kUnroll];
-      float p[kUnroll];
-#pragma unroll
-      for (int k = 0; k < kUnroll; ++k) {
-        v[k] = gcd::ld_stream(id16 + l[k]);
-        p[k] = gcd::ld_stream(partial + l[k]);
-      }
-#pragma unroll
-      for (int k = 0; k < kUnroll; ++k)
-        if (f0 + k * kThreads < total) atomicAdd(&acc[v[k]], static_cast<double>(p[k]));
-    }
-  } else {
-    __syncthreads();
-    for (int32_t s = 0; s < B; ++s) {
-      const int32_t a = lo[s], z = hi[s];
-      for (int32_t l = a + threadIdx.x; l < z; l += kThreads) {
-        const uint16_t v = gcd::ld_stream(id16 + l);
-        const float p = gcd::ld_stream(partial + l);
-        atomicAdd(&acc[v], static_cast<double>(p));
-      }
-    }
-  }
-  __syncthreads();
   const double D = *u.dtotal_in;
   double mine = 0.0;
   for (int i = threadIdx.x; i < K; i += kThreads) {

@@ -323,7 +323,7 @@ int tocab_autotune(gc_graph g, int32_t dir, int32_t* block_width, int32_t* merge
   if (dir != GC_PULL && dir != GC_PUSH) return fail(GC_EINVAL, "tocab_autotune: dir must be GC_PULL or GC_PUSH");
   if (!block_width || !merge_range) return fail(GC_EINVAL, "tocab_autotune: NULL output");
   float ms = 0.0f;
-  const hipError_t e = gcx::autotune(g, dir, block_width, merge_range, &ms, stream);
+  const hipError_t e = gcx::autotune(g, dir, 0, block_width, merge_range, &ms, stream);
   if (e != hipSuccess) return hip_fail(e, "tocab_autotune");
   if (ms_per_iter) *ms_per_iter = ms;
   return GC_OK;
