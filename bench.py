@@ -135,6 +135,208 @@ def cpu_baseline(g, budget_s):
                       f"({dt:.1f} s)"}
 
 
+def suite_traversal(args, gc, gg, torch):
+    """Blocked pull BFS and SSSP on the rewired 4096x4096 grid and the uniform
+    graph of 2^25 vertices (average degree 8), weights in [1, 255]."""
+    graphs = [("grid4096", lambda: gg.grid(4096, 4096, 0.05, seed=3)),
+              ("uniform2^25", lambda: gg.uniform(1 << 25, 1 << 27, seed=4))]
+    out = {}
+    for name, make in graphs:
+        log(f"generating {name}")
+        gh = make().with_weights(11)
+        g = gc.graph_load_csr(gh.rowptr, gh.colidx, gh.weights)
+        part = gc.tocab_partition(g, gc.GC_PULL, args.block_width, args.merge_range)
+        srcs = gg.sources(gh, args.bfs_sources or 8, seed=5)
+        pols = [("plain_pull", gc.GC_POLICY_PULL, False), ("tocab_pull", gc.GC_POLICY_PULL, True),
+                ("push", gc.GC_POLICY_PUSH, False), ("heuristic_tocab", gc.GC_POLICY_HEURISTIC, True)]
+        out[name] = {"n": gh.n, "m": gh.m, "partition": part.info,
+                     "bfs": run_traversal(gc, torch, g, gh, part, srcs, "bfs", pols),
+                     "sssp": run_traversal(gc, torch, g, gh, part, srcs, "sssp", pols)}
+        part.free()
+        g.free()
+        del gh
+    best = max(v["gteps_hmean"] for v in out["uniform2^25"]["bfs"].values())
+    return {"metric": METRIC, "value": round(best, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.bfs_sources or 8,
+            "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "i32", "data": "synthetic",
+            "config": {"workload": "bfs_sssp_grid4096_uniform2^25", "block_width": args.block_width,
+                       "merge_range": args.merge_range, "sources": args.bfs_sources or 8},
+            "traversal": out}
+
+
+def suite_batched(args, gc, gg, torch):
+    """32 R-MAT graphs (scales 14-20) + 64 PPR seeds on R-MAT 22, 20
+    iterations in one captured persistent launch, against the same work as
+    separate per-graph plain-pull launches."""
+    scales = [14] * 5 + [15] * 5 + [16] * 5 + [17] * 5 + [18] * 4 + [19] * 4 + [20] * 4
+    log("generating 32 graphs + RMAT-22")
+    ghs = [gg.rmat(sc, 16, seed=100 + i) for i, sc in enumerate(scales)]
+    pgh = gg.rmat(22, 16, seed=6)
+    seeds = gg.sources(pgh, 64, seed=7)
+    hs = [gc.graph_load_csr(x.rowptr, x.colidx) for x in ghs]
+    hp = gc.graph_load_csr(pgh.rowptr, pgh.colidx)
+    t0 = time.perf_counter()
+    b = gc.batch_create(hs, None, hp, seeds)
+    log(f"batch_create (autotuned widths) {time.perf_counter() - t0:.2f} s; widths {list(b.block_widths)}, "
+        f"grid {b.grid}")
+    iters = 20
+    rin = torch.cat([torch.full((x.n,), 1.0 / x.n, dtype=torch.float32, device="cuda") for x in ghs])
+    rout = torch.empty_like(rin)
+    pout = torch.empty((pgh.n, 64), dtype=torch.float32, device="cuda")
+    gc.batch_capture(b, 0.85, iters, rin, rout, pout)
+    gc.batch_launch(b)
+    assert gc.batch_status(b)
+    times = []
+    for _ in range(max(1, args.steps // 4)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gc.batch_launch(b)
+        ok = gc.batch_status(b)
+        times.append((time.perf_counter() - t0) * 1e3)
+        assert ok
+    batch_ms = float(np.median(times))
+    # the same work as separate launches: plain pull PageRank per graph, and
+    # one single-vector run per seed (a plain pull iteration moves the same
+    # arcs as one personalised vector)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for h, x in zip(hs, ghs):
+        r0 = torch.full((x.n,), 1.0 / x.n, dtype=torch.float32, device="cuda")
+        gc.pagerank_iter(h, None, gc.GC_PULL, 0.85, gc.GC_DANGLING_UNIFORM, r0, torch.empty_like(r0), iters)
+    torch.cuda.synchronize()
+    graphs_ms = (time.perf_counter() - t0) * 1e3
+    r0 = torch.full((pgh.n,), 1.0 / pgh.n, dtype=torch.float32, device="cuda")
+    r1 = torch.empty_like(r0)
+    t0 = time.perf_counter()
+    for _ in range(64):
+        gc.pagerank_iter(hp, None, gc.GC_PULL, 0.85, gc.GC_DANGLING_UNIFORM, r0, r1, iters)
+    torch.cuda.synchronize()
+    ppr_ms = (time.perf_counter() - t0) * 1e3
+    arcs = sum(x.m for x in ghs) * iters + pgh.m * 64 * iters
+    val = arcs / (batch_ms * 1e-3) / 1e9
+    log(f"batched {batch_ms:.2f} ms vs separate {graphs_ms:.2f} + {ppr_ms:.2f} ms")
+    widths = [int(w) for w in b.block_widths]
+    b.free()
+    return {"metric": METRIC, "value": round(val, 2), "unit": "GTEPS", "n_gpus": 1, "steps": len(times),
+            "warmup": 1, "ms_per_step": round(batch_ms, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "batched_32rmat14-20_ppr64_rmat22", "iters": iters,
+                       "widths": widths, "ppr_seeds": 64,
+                       "sum_m": int(sum(x.m for x in ghs)), "ppr_m": int(pgh.m)},
+            "batched": {"one_launch_ms": round(batch_ms, 3), "separate_graphs_ms": round(graphs_ms, 3),
+                        "separate_ppr_ms": round(ppr_ms, 3),
+                        "speedup": round((graphs_ms + ppr_ms) / batch_ms, 2),
+                        "separate_gteps": round(arcs / ((graphs_ms + ppr_ms) * 1e-3) / 1e9, 2)}}
+
+
+def suite_learned(args, gc, gg, torch):
+    """Level scheduler: trained on the GPU from per-level timings on R-MAT 16
+    and R-MAT 24 (BFS and SSSP), evaluated on R-MAT 25 and the rewired grid
+    against the working-set heuristic and fixed policies."""
+    widths = [1 << s for s in range(16, 23)]
+    K = 2 + len(widths)
+    n_src = args.bfs_sources or 8
+    heur_w = 1 << 18
+
+    def load(gh):
+        g = gc.graph_load_csr(gh.rowptr, gh.colidx, gh.weights)
+        return g, [gc.tocab_partition(g, gc.GC_PULL, w, args.merge_range) for w in widths]
+
+    feats, times = [], []
+    t0 = time.perf_counter()
+    for scale in (16, 24):
+        log(f"collecting levels on RMAT-{scale}")
+        gh = gg.rmat(scale, 16, seed=1).with_weights(11)
+        g, parts = load(gh)
+        srcs = gg.sources(gh, n_src, seed=2)
+        for kind in (0, 1):
+            f, t = gc.sched_collect(g, parts, kind, srcs)
+            feats.append(f)
+            times.append(t)
+        for p in parts:
+            p.free()
+        g.free()
+    collect_s = time.perf_counter() - t0
+    X = np.concatenate(feats)
+    Tms = np.maximum(np.concatenate(times), 1e-4)
+    T = np.log(Tms).astype(np.float32)
+    # rows weighted by the square root of their level's best time: the
+    # decisions on long levels decide the total
+    best = Tms.min(axis=1)
+    w = np.sqrt(best / best.mean())
+    M = np.repeat(w[:, None], K, axis=1).astype(np.float32)
+    theta = gc.sched_init_params(K, seed=1)
+    m = gc.sched_create(K, theta)
+    steps = 4000
+    hist = torch.zeros(steps, dtype=torch.float32, device="cuda")
+    t0 = time.perf_counter()
+    gc.sched_train(m, torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), torch.from_numpy(M).cuda(), steps,
+                   3e-3, hist)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    h = hist.cpu().numpy()
+    log(f"collected {X.shape[0]} levels in {collect_s:.1f} s; trained in {train_s:.2f} s: loss {h[0]:.3f} -> "
+        f"{h[-1]:.4f}")
+    results = {}
+    for name, make in (("rmat25", lambda: gg.rmat(25, 16, seed=8)), ("grid4096", lambda: gg.grid(4096, 4096, 0.05, 3))):
+        log(f"evaluating on {name}")
+        gh = make().with_weights(11)
+        g, parts = load(gh)
+        gc.sched_attach(g, m, parts)
+        srcs = gg.sources(gh, n_src, seed=8)
+        buf = torch.empty(gh.n, dtype=torch.int32, device="cuda")
+        mid = parts[widths.index(heur_w)]
+        pols = {"learned": (gc.GC_POLICY_LEARNED, None), "heuristic": (gc.GC_POLICY_HEURISTIC, mid),
+                "always_pull": (gc.GC_POLICY_PULL, None), "always_tocab": (gc.GC_POLICY_PULL, mid),
+                "always_push": (gc.GC_POLICY_PUSH, None)}
+        res = {}
+        for kind, fn in (("bfs", gc.bfs_pull), ("sssp", gc.sssp_pull)):
+            res[kind] = {}
+            fn(g, None, int(srcs[0]), buf, gc.GC_POLICY_HEURISTIC)  # warm-up
+            for pname, (pol, part) in pols.items():
+                total = 0.0
+                acts = []
+                for src in srcs:
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    fn(g, part, int(src), buf, pol)
+                    torch.cuda.synchronize()
+                    total += (time.perf_counter() - t0) * 1e3
+                    a = gc.traversal_trace(g)[0]
+                    if pname != "learned":  # action 2 is the partition passed in
+                        a = np.where(a == 2, 2 + widths.index(heur_w), a)
+                    acts.extend(a.tolist())
+                res[kind][pname] = {"ms_total": round(total, 3),
+                                    "action_share": {lab: round(acts.count(i) / max(1, len(acts)), 3)
+                                                     for i, lab in enumerate(["push", "pull"] +
+                                                                             [f"tocab@2^{w.bit_length() - 1}"
+                                                                              for w in widths])
+                                                     if acts.count(i)}}
+            others = {k2: v["ms_total"] for k2, v in res[kind].items() if k2 != "learned"}
+            res[kind]["learned_gain_vs_heuristic"] = round(others["heuristic"] / res[kind]["learned"]["ms_total"], 3)
+            res[kind]["learned_gain_vs_always_pull"] = round(others["always_pull"] /
+                                                             res[kind]["learned"]["ms_total"], 3)
+            res[kind]["learned_gain_vs_best_fixed"] = round(min(others.values()) / res[kind]["learned"]["ms_total"], 3)
+            log(f"{name} {kind}: " + ", ".join(f"{k2} {v['ms_total']:.1f} ms" for k2, v in res[kind].items()
+                                               if isinstance(v, dict)))
+        results[name] = res
+        gc.sched_attach(g, None)
+        for p in parts:
+            p.free()
+        g.free()
+    m.free()
+    gain = results["rmat25"]["bfs"]["learned_gain_vs_heuristic"]
+    return {"metric": METRIC, "value": gain, "unit": "x vs working-set heuristic (RMAT-25 BFS total time)",
+            "n_gpus": 1, "steps": n_src, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "learned_scheduler_rmat25_grid4096", "sources": n_src,
+                       "actions": ["push", "pull"] + [f"tocab@2^{w.bit_length() - 1}" for w in widths],
+                       "heuristic_tocab_width": heur_w, "train_graphs": ["rmat16", "rmat24"],
+                       "train_levels": int(X.shape[0]), "train_steps": steps, "collect_seconds": round(collect_s, 1),
+                       "train_seconds": round(train_s, 2), "loss_first": float(h[0]), "loss_last": float(h[-1])},
+            "learned": results}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +351,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--bfs-sources", type=int, default=8, help="BFS sources on the same graph (0 = skip)")
+    ap.add_argument("--suite", default="pagerank", choices=["pagerank", "traversal", "batched", "learned"],
+                    help="pagerank: RMAT-24 PageRank forms + BFS (default); traversal: grid / uniform BFS+SSSP; "
+                         "batched: 32 graphs + 64 PPR seeds in one launch; learned: level scheduler")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 1 GiB torch copy first (counter scale reference)")
     args = ap.parse_args()
@@ -162,6 +367,10 @@ def main():
     import paper_1904_02241_amd as gc
 
     torch.cuda.init()
+    if args.suite != "pagerank":
+        fn = {"traversal": suite_traversal, "batched": suite_batched, "learned": suite_learned}[args.suite]
+        print(json.dumps(fn(args, gc, gg, torch)), flush=True)
+        return
     if args.traffic_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)

@@ -318,6 +318,19 @@ class Sched:
             self.handle = None
 
 
+def sched_init_params(n_actions, seed):
+    """Initial network parameters drawn by the caller (He-style uniform
+    weights, zero biases), in the layout sched_create expects."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in ((GC_SCHED_INPUTS, GC_SCHED_HIDDEN), (GC_SCHED_HIDDEN, GC_SCHED_HIDDEN),
+                            (GC_SCHED_HIDDEN, n_actions)):
+        bound = np.sqrt(6.0 / fan_in)
+        parts.append(rng.uniform(-bound, bound, size=(fan_out, fan_in)).ravel())
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def sched_create(n_actions, params):
     params = np.ascontiguousarray(params, dtype=np.float32)
     assert params.shape == (sched_param_count(n_actions),)

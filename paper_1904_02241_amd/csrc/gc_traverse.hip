@@ -613,6 +613,19 @@ int64_t source_degree(gc_graph g, int32_t source, hipStream_t s, hipError_t* e) 
   return rp[1] - rp[0];
 }
 
+// Two HIP events released on scope exit.
+struct EventPair {
+  hipEvent_t e[2] = {nullptr, nullptr};
+  hipError_t create() {
+    GC_HIP_TRY(hipEventCreate(&e[0]));
+    return hipEventCreate(&e[1]);
+  }
+  ~EventPair() {
+    for (hipEvent_t x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
+
 // Action k of the learned scheduler: 0 push, 1 plain pull, 2 + i TOCAB pull
 // over the i-th attached partition.
 void action_mode(int32_t a, gc_tocab* parts, Mode* mode, gc_tocab* t) {
@@ -655,6 +668,11 @@ hipError_t traverse(gc_graph g, gc_tocab t, int32_t source, int32_t* value, int3
   g->trace_action.clear();
   g->trace_ms.clear();
   if (overflow) *overflow = false;
+  // Under the learned policy the prior-level time fed to the network is the
+  // level's kernel time from HIP events, the measure its training rows hold.
+  const bool learned = policy == GC_POLICY_LEARNED && g->sched;
+  EventPair ev;
+  if (learned) GC_HIP_TRY(ev.create());
   while (f.n_f > 0) {
     if (!bfs && level > n) return hipErrorInvalidValue;  // cannot happen with positive weights
     // SSSP revisits vertices, so the unexplored-arc count of BFS does not
@@ -663,7 +681,7 @@ hipError_t traverse(gc_graph g, gc_tocab t, int32_t source, int32_t* value, int3
     Mode mode = Mode::kPush;
     gc_tocab lt = t;
     int32_t action = -1;
-    if (policy == GC_POLICY_LEARNED && g->sched) {
+    if (learned) {
       float feats[GC_SCHED_INPUTS];
       sched_features(n, g->m, f.n_f, f.m_f, level, prior_ms, feats);
       GC_HIP_TRY(sched_decide(g->sched, feats, s, &action));
@@ -679,11 +697,19 @@ hipError_t traverse(gc_graph g, gc_tocab t, int32_t source, int32_t* value, int3
     }
     const double t0 = now_ms();
     GC_HIP_TRY(f.begin_level());
+    if (learned) GC_HIP_TRY(hipEventRecord(ev.e[0], s));
     GC_HIP_TRY(run_level(g, f, bfs, value, level, mode, lt, s));
+    if (learned) GC_HIP_TRY(hipEventRecord(ev.e[1], s));
     GC_HIP_TRY(f.end_level(overflow));
-    prior_ms = now_ms() - t0;
+    const double wall_ms = now_ms() - t0;
+    prior_ms = wall_ms;
+    if (learned) {
+      float ms = 0.0f;
+      GC_HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+      prior_ms = ms;
+    }
     g->trace_action.push_back(action);
-    g->trace_ms.push_back(static_cast<float>(prior_ms));
+    g->trace_ms.push_back(static_cast<float>(wall_ms));
     if (overflow && *overflow) break;
     if (bfs) m_u -= f.m_f;
     ++level;
