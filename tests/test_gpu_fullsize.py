@@ -1,0 +1,104 @@
+"""Parity at the full benchmark sizes, in the launch configurations the
+benchmark times.
+
+* R-MAT 24 (N = 2^24, about 263M arcs): 20 PageRank iterations of every
+  form, L1 <= 1e-6 against the FP64 oracle run once for the whole module;
+  BFS depths from two sources and SSSP distances from one, bit-exact.
+* The rewired 4096 x 4096 grid and the uniform graph with 2^25 vertices and
+  2^28 arcs: BFS and SSSP from one source each, bit-exact, every policy.
+
+The oracle runs single-threaded, so each case computes its expected values
+once and is given a generous time limit."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from tests.gpu_util import host, load, pagerank_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+L1_TOL = 1e-6
+BENCH_W, BENCH_K = 1 << 18, 4096
+
+
+@pytest.fixture(scope="module")
+def rmat24():
+    g = gg.rmat(24, 16, seed=1).with_weights(11)
+    print(f"rmat24 n={g.n} m={g.m}", flush=True)
+    return g
+
+
+@pytest.fixture(scope="module")
+def rmat24_pagerank(rmat24):
+    g = rmat24
+    r0 = np.full(g.n, 1.0 / g.n, dtype=np.float32)
+    want = oracle.pagerank(g.n, g.rowptr, g.colidx, 0.85, 20, mode=oracle.UNIFORM, r0=r0)
+    return r0, want
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("form,W,k", [("tocab_pull", BENCH_W, BENCH_K), ("tocab_pull", 1 << 14, BENCH_K),
+                                      ("plain_pull", 1 << 10, 256), ("tocab_push", BENCH_W, BENCH_K),
+                                      ("plain_push", 1 << 10, 256)])
+def test_rmat24_pagerank_20_iterations(rmat24, rmat24_pagerank, form, W, k):
+    g = rmat24
+    r0, want = rmat24_pagerank
+    print(f"pagerank rmat24 {form} W={W} k={k}", flush=True)
+    got, _ = pagerank_gpu(g, form, oracle.UNIFORM, W=W, k=k, r0=r0)
+    err = float(np.abs(got.astype(np.float64) - want).sum())
+    print(f"L1 = {err:.3e}", flush=True)
+    assert err <= L1_TOL
+    assert abs(got.astype(np.float64).sum() - 1.0) < 1e-5
+
+
+@pytest.mark.timeout(600)
+def test_rmat24_traversals_bit_exact(rmat24):
+    import paper_1904_02241_amd as gc
+    g = rmat24
+    h = load(g, weights=True)
+    part = gc.tocab_partition(h, gc.GC_PULL, BENCH_W, BENCH_K)
+    d = torch().empty(g.n, dtype=torch().int32, device="cuda")
+    srcs = gg.sources(g, 2, seed=2)
+    for s in srcs:
+        want = oracle.bfs(g.n, g.rowptr, g.colidx, int(s))
+        for name, t, pol in (("plain_pull", None, gc.GC_POLICY_PULL), ("tocab_pull", part, gc.GC_POLICY_PULL),
+                             ("push", None, gc.GC_POLICY_PUSH), ("heuristic_tocab", part, gc.GC_POLICY_HEURISTIC)):
+            print(f"bfs rmat24 source {s} {name}", flush=True)
+            gc.bfs_pull(h, t, int(s), d, pol)
+            np.testing.assert_array_equal(host(d), want)
+    s = int(srcs[0])
+    want = oracle.dijkstra(g.n, g.rowptr, g.colidx, g.weights, s)
+    for name, t, pol in (("tocab_pull", part, gc.GC_POLICY_PULL), ("heuristic_tocab", part, gc.GC_POLICY_HEURISTIC)):
+        print(f"sssp rmat24 source {s} {name}", flush=True)
+        gc.sssp_pull(h, t, s, d, pol)
+        np.testing.assert_array_equal(host(d), want)
+    part.free()
+    h.free()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["grid4096", "uniform2^25"])
+def test_traversal_graphs_bit_exact(name):
+    import paper_1904_02241_amd as gc
+    g = (gg.grid(4096, 4096, 0.05, seed=3) if name == "grid4096" else gg.uniform(1 << 25, 1 << 27, seed=4))
+    g = g.with_weights(11)
+    print(f"{name} n={g.n} m={g.m}", flush=True)
+    h = load(g, weights=True)
+    part = gc.tocab_partition(h, gc.GC_PULL, BENCH_W, BENCH_K)
+    d = torch().empty(g.n, dtype=torch().int32, device="cuda")
+    s = int(gg.sources(g, 1, seed=5)[0])
+    policies = (("plain_pull", None, gc.GC_POLICY_PULL), ("tocab_pull", part, gc.GC_POLICY_PULL),
+                ("push", None, gc.GC_POLICY_PUSH), ("heuristic_tocab", part, gc.GC_POLICY_HEURISTIC))
+    want = oracle.bfs(g.n, g.rowptr, g.colidx, s)
+    for pname, t, pol in policies:
+        print(f"bfs {name} source {s} {pname}", flush=True)
+        gc.bfs_pull(h, t, s, d, pol)
+        np.testing.assert_array_equal(host(d), want)
+    want = oracle.dijkstra(g.n, g.rowptr, g.colidx, g.weights, s)
+    for pname, t, pol in policies:
+        print(f"sssp {name} source {s} {pname}", flush=True)
+        gc.sssp_pull(h, t, s, d, pol)
+        np.testing.assert_array_equal(host(d), want)
+    part.free()
+    h.free()

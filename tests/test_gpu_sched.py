@@ -42,11 +42,13 @@ def test_forward_matches_oracle(K, B):
     m.free()
 
 
-@pytest.mark.parametrize("K,B", [(2, 5), (5, 64), (9, 513)])
-def test_loss_and_gradient_match_oracle(K, B):
+@pytest.mark.parametrize("K,B,weighted", [(2, 5, False), (5, 64, False), (9, 513, False), (9, 200, True)])
+def test_loss_and_gradient_match_oracle(K, B, weighted):
     import paper_1904_02241_amd as gc
     theta = mlp.init_params(K, seed=10 + K).astype(np.float32)
     X, T, M = batch(K, B, seed=K)
+    if weighted:  # per-row weights, as the trainer uses them
+        M = M * np.random.default_rng(K).uniform(0.1, 3.0, size=(B, 1)).astype(np.float32)
     m = gc.sched_create(K, theta)
     loss = torch().zeros(1, dtype=torch().float32, device="cuda")
     grad = torch().zeros(gc.sched_param_count(K), dtype=torch().float32, device="cuda")
@@ -144,3 +146,77 @@ def test_network_without_finite_output_falls_back_to_heuristic():
     m.free()
     part.free()
     h.free()
+
+
+def test_trained_network_gains_over_heuristic():
+    """Trains the network on levels collected on R-MAT 16 and R-MAT 20 and
+    runs BFS and SSSP on R-MAT 21 under the learned policy, the working-set
+    heuristic and always-pull. Prints the gains; fails only if the learned
+    policy is clearly worse than the heuristic or not better than always
+    pulling (timings on a shared GPU are noisy, the margins are wide)."""
+    import time
+    import paper_1904_02241_amd as gc
+    widths = [1 << s for s in range(16, 21)]
+    K = 2 + len(widths)
+    X, T = [], []
+    for scale in (16, 20):
+        g = gg.rmat(scale, 16, seed=1).with_weights(11)
+        h = load(g, weights=True)
+        parts = [gc.tocab_partition(h, gc.GC_PULL, W, 4096) for W in widths]
+        srcs = gg.sources(g, 4, seed=2)
+        for kind in (0, 1):
+            f, t = gc.sched_collect(h, parts, kind, srcs)
+            X.append(f)
+            T.append(t)
+        for p in parts:
+            p.free()
+        h.free()
+    X = np.concatenate(X)
+    Tms = np.maximum(np.concatenate(T), 1e-4)
+    best = Tms.min(axis=1)
+    M = np.repeat(np.sqrt(best / best.mean())[:, None], K, axis=1).astype(np.float32)
+    m = gc.sched_create(K, mlp.init_params(K, seed=1).astype(np.float32))
+    gc.sched_train(m, dev(X), dev(np.log(Tms).astype(np.float32)), dev(M), 3000, 3e-3)
+
+    g = gg.rmat(21, 16, seed=8).with_weights(11)
+    h = load(g, weights=True)
+    parts = [gc.tocab_partition(h, gc.GC_PULL, W, 4096) for W in widths]
+    gc.sched_attach(h, m, parts)
+    d = torch().empty(g.n, dtype=torch().int32, device="cuda")
+    srcs = gg.sources(g, 4, seed=8)
+    mid = parts[widths.index(1 << 18)]
+    gains = {}
+    for kind, fn in (("bfs", gc.bfs_pull), ("sssp", gc.sssp_pull)):
+        fn(h, None, int(srcs[0]), d, gc.GC_POLICY_HEURISTIC)  # warm-up
+        total = {}
+        for name, pol, part in (("learned", gc.GC_POLICY_LEARNED, None), ("heuristic", gc.GC_POLICY_HEURISTIC, mid),
+                                ("always_pull", gc.GC_POLICY_PULL, None)):
+            ms = 0.0
+            for s in srcs:
+                best_ms = np.inf
+                for _ in range(2):
+                    torch().cuda.synchronize()
+                    t0 = time.perf_counter()
+                    fn(h, part, int(s), d, pol)
+                    torch().cuda.synchronize()
+                    best_ms = min(best_ms, (time.perf_counter() - t0) * 1e3)
+                ms += best_ms
+            total[name] = ms
+        # the learned traversal's result is still the exact one
+        s = int(srcs[-1])
+        fn(h, None, s, d, gc.GC_POLICY_LEARNED)
+        want = (oracle.bfs(g.n, g.rowptr, g.colidx, s) if kind == "bfs"
+                else oracle.dijkstra(g.n, g.rowptr, g.colidx, g.weights, s))
+        np.testing.assert_array_equal(host(d), want)
+        gains[kind] = (total["heuristic"] / total["learned"], total["always_pull"] / total["learned"])
+        print(f"{kind}: learned {total['learned']:.2f} ms, heuristic {total['heuristic']:.2f} ms, always pull "
+              f"{total['always_pull']:.2f} ms -> gain {gains[kind][0]:.3f}x over the heuristic, "
+              f"{gains[kind][1]:.3f}x over always-pull")
+    gc.sched_attach(h, None)
+    m.free()
+    for p in parts:
+        p.free()
+    h.free()
+    for kind, (vs_heur, vs_pull) in gains.items():
+        assert vs_heur >= 0.8, (kind, vs_heur)
+        assert vs_pull > 1.0, (kind, vs_pull)
