@@ -37,10 +37,16 @@ def kernel_bytes(name, n, m, info):
     """Algorithmic bytes one launch of `name` must move (each needed value once)."""
     P, B, k = info.get("P", 0), info.get("B", 0), info.get("k", 1)
     R = -(-n // k) if k else 0
+    stream = info.get("stream", False)
+    if name == "pr_tocab_pull" and stream:
+        # 16-bit columns + head words (16 B per 64 arcs) + partial writes + c once + position table
+        return 2 * m + m // 4 + 4 * P + 4 * n + info.get("table_bytes", 0)
+    if name == "pr_merge" and stream:  # partials + 16-bit ids + range starts + outdeg (rowptr) + c' writes
+        return 4 * P + 2 * P + 4 * (R + 1) + 4 * (n + 1) + 4 * n
     if name == "pr_tocab_pull":  # col + row_ptr + partial writes + one fill of every c slice
         return 4 * m + 4 * (P + 1) + 4 * P + 4 * n
-    if name == "pr_merge":  # partials + id_map + range table + outdeg (rowptr) + c' writes
-        return 4 * P + 4 * P + 4 * (R + 1) * B + 4 * (n + 1) + 4 * n
+    if name == "pr_merge":  # partials + 16-bit ids + range table + outdeg (rowptr) + c' writes
+        return 4 * P + 2 * P + 4 * (R + 1) * B + 4 * (n + 1) + 4 * n
     if name == "pr_plain_pull":  # in-CSR + c once + outdeg + c' writes
         return 4 * m + 4 * (n + 1) + 4 * n + 4 * (n + 1) + 4 * n
     if name in ("pr_tocab_push", "pr_plain_push"):  # col + row_ptr (+ id_map) + c + sums line per arc...

@@ -129,6 +129,14 @@ int tocab_autotune(gc_graph g, int32_t dir, int32_t* block_width, int32_t* merge
 int tocab_info(gc_tocab t, int32_t* B, int64_t* P, int32_t* W, int32_t* k, int32_t* dir,
                int64_t* bytes);
 
+/* Pull layout of partition t: *stream_layout = 1 when its blocks are small
+ * enough for the LDS-resident stream layout (16-bit columns, one head bit per
+ * arc, range-major partial sums), else 0; *chunks = work-groups of its pull
+ * kernel (0 without the stream layout); *table_bytes = bytes of its
+ * range-major position table. Any output may be NULL. Returns GC_EINVAL for a
+ * NULL partition. */
+int tocab_layout(gc_tocab t, int32_t* stream_layout, int32_t* chunks, int64_t* table_bytes);
+
 /* Copies the partition into caller buffers (device or host). Layout, blocks
  * concatenated in block order:
  *   blk_rowoff int32[B+1]   first local row of each block

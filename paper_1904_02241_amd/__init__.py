@@ -39,6 +39,7 @@ SIGNATURES = {
     "graph_free": (ctypes.c_int, [_vp]),
     "tocab_partition": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, ctypes.POINTER(_vp)]),
     "tocab_info": (ctypes.c_int, [_vp, _p_i32, _p_i64, _p_i32, _p_i32, _p_i32, _p_i64]),
+    "tocab_layout": (ctypes.c_int, [_vp, _p_i32, _p_i32, _p_i64]),
     "tocab_autotune": (ctypes.c_int, [_vp, _i32, _p_i32, _p_i32, ctypes.POINTER(ctypes.c_float), _vp]),
     "tocab_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tocab_free": (ctypes.c_int, [_vp]),
@@ -91,9 +92,17 @@ def _load():
 lib = _load()
 
 
+_alloc_error = None  # last exception of the torch allocator hook
+
+
 def _check(rc, what):
+    global _alloc_error
     if rc != GC_OK:
-        raise GraphCageError(rc, f"{what}: {lib.gc_last_error().decode()}")
+        msg = f"{what}: {lib.gc_last_error().decode()}"
+        if rc == GC_ENOMEM and _alloc_error:
+            msg += f" ({_alloc_error})"
+            _alloc_error = None
+        raise GraphCageError(rc, msg)
 
 
 # ---------------------------------------------------------------------------
@@ -106,9 +115,13 @@ def _torch():
 
 @_ALLOC_FN
 def _torch_alloc(nbytes, stream, ctx):
+    global _alloc_error
     try:
-        return _torch().cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
-    except Exception:
+        torch = _torch()
+        torch.cuda.init()
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception as e:  # reported by the failing call
+        _alloc_error = f"{type(e).__name__}: {e}"
         return None
 
 
@@ -166,6 +179,7 @@ class Tocab:
     def __init__(self, handle, graph):
         self.handle, self.graph = handle, graph
         self.info = tocab_info(self)
+        self.info.update(tocab_layout(self))
 
     def free(self):
         if self.handle:
@@ -239,6 +253,13 @@ def tocab_info(t):
     _check(lib.tocab_info(_h(t), ctypes.byref(B), ctypes.byref(P), ctypes.byref(W), ctypes.byref(k), ctypes.byref(d),
                           ctypes.byref(b)), "tocab_info")
     return {"B": B.value, "P": P.value, "W": W.value, "k": k.value, "dir": d.value, "bytes": b.value}
+
+
+def tocab_layout(t):
+    """{"stream": bool, "chunks": int, "table_bytes": int} of a partition's pull layout."""
+    st, ch, tb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check(lib.tocab_layout(_h(t), ctypes.byref(st), ctypes.byref(ch), ctypes.byref(tb)), "tocab_layout")
+    return {"stream": bool(st.value), "chunks": ch.value, "table_bytes": tb.value}
 
 
 def tocab_export(t, blk_rowoff, row_ptr, id_map, col, weight, range_ptr, stream=None):

@@ -441,29 +441,78 @@ __global__ void k_col16(const int32_t* __restrict__ col, int64_t m, int32_t mask
     col16[i] = static_cast<uint16_t>(col[i] & mask);
 }
 
-// First arc of every block (row_ptr at the block's first local row).
-__global__ void k_block_arcs(const int32_t* __restrict__ blk_rowoff, const int32_t* __restrict__ row_ptr, int32_t B,
-                             int32_t* __restrict__ out) {
-  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s <= B) out[s] = row_ptr[blk_rowoff[s]];
+// Head bit of every local row: bit row_ptr[r] of the arc bitmap.
+__global__ void k_heads_set(const int32_t* __restrict__ row_ptr, int64_t P, gc_head_word* __restrict__ heads) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; r < P; r += stride) {
+    const int64_t i = row_ptr[r];
+    atomicOr(reinterpret_cast<unsigned long long*>(&heads[i >> 6].bits), 1ull << (i & 63));
+  }
 }
 
-// Chunk c = (block s, j-th slice of kLdsChunkArcs arcs): rows of block s
-// whose first arc lies in [first_arc(s) + j*A, first_arc(s) + (j+1)*A).
-__global__ void k_chunks(const int32_t* __restrict__ blk_rowoff, const int32_t* __restrict__ row_ptr,
-                         const int32_t* __restrict__ chunk_first, const int32_t* __restrict__ blk_of_chunk,
-                         int32_t n_chunks, int32_t chunk_arcs, int32_t* __restrict__ beg, int32_t* __restrict__ end,
-                         int32_t* __restrict__ blk) {
-  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_chunks) return;
-  const int32_t s = blk_of_chunk[c];
-  const int32_t j = c - chunk_first[s];
-  const int32_t lo = blk_rowoff[s], hi = blk_rowoff[s + 1];
-  const int64_t a_s = row_ptr[lo];
-  beg[c] = j == 0 ? lo : first_at_least(row_ptr, lo, hi, a_s + static_cast<int64_t>(j) * chunk_arcs);
-  const bool last = (c + 1 == n_chunks) || blk_of_chunk[c + 1] != s;
-  end[c] = last ? hi : first_at_least(row_ptr, lo, hi, a_s + static_cast<int64_t>(j + 1) * chunk_arcs);
-  blk[c] = s;
+// Bits at and past arc m are set, so a row walk always stops at the end;
+// every word records the first local row whose head lies at or after it.
+__global__ void k_heads_finish(const int32_t* __restrict__ row_ptr, int64_t P, int64_t m, int64_t words,
+                               gc_head_word* __restrict__ heads) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words; w += stride) {
+    const int64_t lo = w << 6;
+    if (lo + 64 > m) heads[w].bits |= lo >= m ? ~0ull : (~0ull << (m - lo));
+    heads[w].row = first_at_least(row_ptr, 0, static_cast<int32_t>(P), lo);
+  }
+}
+
+// Bit 0 of the following word (after k_heads_finish; the last word's is set).
+__global__ void k_heads_next(int64_t words, gc_head_word* __restrict__ heads) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; w < words; w += stride)
+    heads[w].next = w + 1 < words ? static_cast<int32_t>(heads[w + 1].bits & 1ull) : 1;
+}
+
+// Rows of block b in merge range j, from the j-major range table.
+__global__ void k_seg_counts(const int32_t* __restrict__ range_ptr, int32_t B, int32_t R, int32_t* __restrict__ cnt) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;  // i = j*B + b
+  if (i >= static_cast<int64_t>(B) * R) return;
+  cnt[i] = range_ptr[i + B] - range_ptr[i];
+}
+
+// seg[b][j] = (first local row of block b in range j, shift that moves the
+// block-major row index to its range-major index); rstart[j] = first
+// range-major index of range j.
+__global__ void k_seg_table(const int32_t* __restrict__ range_ptr, const int32_t* __restrict__ rm_start, int32_t B,
+                            int32_t R, int64_t P, int2* __restrict__ seg, int32_t* __restrict__ rstart) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;  // i = b*(R+1) + j
+  if (i >= static_cast<int64_t>(B) * (R + 1)) return;
+  const int32_t b = static_cast<int32_t>(i / (R + 1)), j = static_cast<int32_t>(i % (R + 1));
+  const int64_t jb = static_cast<int64_t>(j) * B + b;
+  const int32_t first = range_ptr[jb];
+  seg[i] = make_int2(first, j < R ? rm_start[jb] - first : 0);
+  if (b == 0) rstart[j] = j < R ? rm_start[jb] : static_cast<int32_t>(P);
+}
+
+// First arc of every (block, range) boundary row.
+__global__ void k_seg_arcs(const int2* __restrict__ seg, int64_t count, const int32_t* __restrict__ row_ptr,
+                           int32_t* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = row_ptr[seg[i].x];
+}
+
+// id16 of every local row, scattered to the row's range-major index.
+__global__ void k_id16_stream(const int32_t* __restrict__ id_map, int64_t P, const int32_t* __restrict__ blk_rowoff,
+                              int32_t B, int32_t R, int32_t log2k, const int2* __restrict__ seg,
+                              uint16_t* __restrict__ id16s) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t r = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; r < P; r += stride) {
+    const int32_t v = id_map[r];
+    const int32_t j = v >> log2k;
+    int32_t lo = 0, hi = B;  // block: last b with blk_rowoff[b] <= r
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (blk_rowoff[mid] <= r) lo = mid;
+      else hi = mid;
+    }
+    id16s[r + seg[static_cast<int64_t>(lo) * (R + 1) + j].y] = static_cast<uint16_t>(v & ((1 << log2k) - 1));
+  }
 }
 
 inline int grid_for(int64_t items, int threads, int cap = 1 << 20) {
@@ -547,39 +596,98 @@ hipError_t build_transpose(int32_t n, int64_t m, const int32_t* rowptr, const in
   return hipStreamSynchronize(s);
 }
 
-// 16-bit columns and the chunk table of an LDS-resident partition.
-hipError_t build_lds_chunks(gc_tocab t, hipStream_t s) {
-  const int32_t B = t->B;
-  t->col16 = static_cast<uint16_t*>(dev_alloc(sizeof(uint16_t) * std::max<int64_t>(t->m, 1), s));
-  if (!t->col16) return hipErrorOutOfMemory;
-  if (t->m > 0) k_col16<<<grid_for(t->m, 256, 65536), 256, 0, s>>>(t->col, t->m, t->W - 1, t->col16);
-  Buf first(sizeof(int32_t) * (B + 1), s);
-  if (!first.p) return hipErrorOutOfMemory;
-  k_block_arcs<<<grid_for(B + 1, 256), 256, 0, s>>>(t->blk_rowoff, t->row_ptr, B, first.as<int32_t>());
+// Stream layout of an LDS-resident pull partition: padded 16-bit columns,
+// head bits, wave-tile rows, the range-major position table, range-major
+// id16, and chunks (one work-group each) cut at merge-range boundaries so
+// a chunk's slice of the position table fits in LDS beside the block's slice.
+hipError_t build_lds_stream(gc_tocab t, hipStream_t s) {
+  const int32_t B = t->B, R = t->R;
+  const int64_t P = t->P, m = t->m;
+  const int64_t entries = static_cast<int64_t>(B) * (R + 1);
+  const int64_t tile = wave_tile_arcs();
+  t->m_pad = (m / tile + 2) * tile;
+  const int64_t words = t->m_pad / 64 + 1;
+  t->col16 = static_cast<uint16_t*>(dev_alloc(sizeof(uint16_t) * t->m_pad, s));
+  t->heads = static_cast<gc_head_word*>(dev_alloc(sizeof(gc_head_word) * words, s));
+  t->seg = static_cast<int2*>(dev_alloc(sizeof(int2) * entries, s));
+  t->rstart = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * (R + 1), s));
+  t->id16s = static_cast<uint16_t*>(dev_alloc(sizeof(uint16_t) * (std::max<int64_t>(P, 1) + 8), s));
+  if (!t->col16 || !t->heads || !t->seg || !t->rstart || !t->id16s) return hipErrorOutOfMemory;
+  t->bytes += static_cast<int64_t>(sizeof(uint16_t)) * (t->m_pad + P) + 16 * words + 8 * entries + 4 * (R + 1);
+  GC_HIP_TRY(hipMemsetAsync(t->col16, 0, sizeof(uint16_t) * t->m_pad, s));
+  GC_HIP_TRY(hipMemsetAsync(t->heads, 0, sizeof(gc_head_word) * words, s));
+  if (m > 0) k_col16<<<grid_for(m, 256, 65536), 256, 0, s>>>(t->col, m, t->W - 1, t->col16);
+  if (P > 0) k_heads_set<<<grid_for(P, 256, 65536), 256, 0, s>>>(t->row_ptr, P, t->heads);
+  k_heads_finish<<<grid_for(words, 256, 65536), 256, 0, s>>>(t->row_ptr, P, m, words, t->heads);
+  k_heads_next<<<grid_for(words, 256, 65536), 256, 0, s>>>(words, t->heads);
   GC_HIP_TRY(hipGetLastError());
-  std::vector<int32_t> h(B + 1);
-  GC_HIP_TRY(hipMemcpyAsync(h.data(), first.p, sizeof(int32_t) * (B + 1), hipMemcpyDeviceToHost, s));
+
+  // range-major start of every (range j, block b) slice: exclusive scan of
+  // the slice sizes in j-major order
+  const int64_t BR = static_cast<int64_t>(B) * R;
+  Buf cnt(sizeof(int32_t) * std::max<int64_t>(BR, 1), s), rm(sizeof(int32_t) * (BR + 1), s);
+  Buf arcs(sizeof(int32_t) * entries, s);
+  if (!cnt.p || !rm.p || !arcs.p) return hipErrorOutOfMemory;
+  k_seg_counts<<<grid_for(BR, 256, INT_MAX), 256, 0, s>>>(t->range_ptr, B, R, cnt.as<int32_t>());
+  GC_HIP_TRY(hipGetLastError());
+  GC_HIP_TRY(scan_exclusive(cnt.as<int32_t>(), rm.as<int32_t>(), BR, s));
+  k_seg_table<<<grid_for(entries, 256, INT_MAX), 256, 0, s>>>(t->range_ptr, rm.as<int32_t>(), B, R, P, t->seg,
+                                                              t->rstart);
+  if (P > 0)
+    k_id16_stream<<<grid_for(P, 256, 65536), 256, 0, s>>>(t->id_map, P, t->blk_rowoff, B, R, t->log2k, t->seg,
+                                                          t->id16s);
+  k_seg_arcs<<<grid_for(entries, 256, INT_MAX), 256, 0, s>>>(t->seg, entries, t->row_ptr, arcs.as<int32_t>());
+  GC_HIP_TRY(hipGetLastError());
+
+  // chunks on the host from the boundary rows and their first arcs
+  std::vector<int2> hseg(entries);
+  std::vector<int32_t> harc(entries);
+  GC_HIP_TRY(hipMemcpyAsync(hseg.data(), t->seg, sizeof(int2) * entries, hipMemcpyDeviceToHost, s));
+  GC_HIP_TRY(hipMemcpyAsync(harc.data(), arcs.p, sizeof(int32_t) * entries, hipMemcpyDeviceToHost, s));
   GC_HIP_TRY(hipStreamSynchronize(s));
-  std::vector<int32_t> chunk_first(B + 1, 0), blk_of;
+  const int64_t target = std::max<int64_t>(kLdsChunkArcs, m / 1024);
+  const int32_t cap = lds_seg_cap(t->W);
+  std::vector<int32_t> beg, end, blk, j0v, nsv;
+  int32_t seg_max = 1;
   for (int32_t b = 0; b < B; ++b) {
-    const int64_t arcs = h[b + 1] - h[b];
-    const int32_t nc = static_cast<int32_t>(std::max<int64_t>(1, (arcs + kLdsChunkArcs - 1) / kLdsChunkArcs));
-    chunk_first[b + 1] = chunk_first[b] + nc;
-    for (int32_t j = 0; j < nc; ++j) blk_of.push_back(b);
+    const int64_t o = static_cast<int64_t>(b) * (R + 1);
+    int32_t j = 0;
+    while (j < R) {
+      const int32_t ja = j;
+      int64_t a = 0;
+      while (j < R && j - ja < cap && (j == ja || a < target)) {
+        a += harc[o + j + 1] - harc[o + j];
+        ++j;
+      }
+      const int32_t r0 = hseg[o + ja].x, r1 = hseg[o + j].x;
+      if (r1 > r0) {
+        beg.push_back(r0);
+        end.push_back(r1);
+        blk.push_back(b);
+        j0v.push_back(ja);
+        nsv.push_back(j - ja);
+        seg_max = std::max(seg_max, j - ja);
+      }
+    }
   }
-  const int32_t nch = chunk_first[B];
+  const int32_t nch = static_cast<int32_t>(beg.size());
   t->n_chunks = nch;
-  t->chunk_beg = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * nch, s));
-  t->chunk_end = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * nch, s));
-  t->chunk_blk = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * nch, s));
-  Buf d_first(sizeof(int32_t) * (B + 1), s), d_blk(sizeof(int32_t) * nch, s);
-  if (!t->chunk_beg || !t->chunk_end || !t->chunk_blk || !d_first.p || !d_blk.p) return hipErrorOutOfMemory;
-  GC_HIP_TRY(hipMemcpyAsync(d_first.p, chunk_first.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, s));
-  GC_HIP_TRY(hipMemcpyAsync(d_blk.p, blk_of.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice, s));
-  k_chunks<<<grid_for(nch, 256), 256, 0, s>>>(t->blk_rowoff, t->row_ptr, d_first.as<int32_t>(), d_blk.as<int32_t>(),
-                                              nch, kLdsChunkArcs, t->chunk_beg, t->chunk_end, t->chunk_blk);
-  GC_HIP_TRY(hipGetLastError());
-  t->bytes += static_cast<int64_t>(sizeof(uint16_t)) * t->m + 12 * static_cast<int64_t>(nch);
+  t->seg_max = seg_max;
+  const size_t cb = sizeof(int32_t) * std::max(nch, 1);
+  t->chunk_beg = static_cast<int32_t*>(dev_alloc(cb, s));
+  t->chunk_end = static_cast<int32_t*>(dev_alloc(cb, s));
+  t->chunk_blk = static_cast<int32_t*>(dev_alloc(cb, s));
+  t->chunk_j0 = static_cast<int32_t*>(dev_alloc(cb, s));
+  t->chunk_ns = static_cast<int32_t*>(dev_alloc(cb, s));
+  if (!t->chunk_beg || !t->chunk_end || !t->chunk_blk || !t->chunk_j0 || !t->chunk_ns) return hipErrorOutOfMemory;
+  t->bytes += 5 * static_cast<int64_t>(cb);
+  if (nch > 0) {
+    GC_HIP_TRY(hipMemcpyAsync(t->chunk_beg, beg.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice, s));
+    GC_HIP_TRY(hipMemcpyAsync(t->chunk_end, end.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice, s));
+    GC_HIP_TRY(hipMemcpyAsync(t->chunk_blk, blk.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice, s));
+    GC_HIP_TRY(hipMemcpyAsync(t->chunk_j0, j0v.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice, s));
+    GC_HIP_TRY(hipMemcpyAsync(t->chunk_ns, nsv.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice, s));
+  }
   return hipStreamSynchronize(s);  // host vectors and Bufs are released on return
 }
 
@@ -615,7 +723,7 @@ hipError_t build_partition(gc_tocab t, const int32_t* a_rowptr, const int32_t* a
   const size_t mn = static_cast<size_t>(std::max<int64_t>(t->m, 1));
   t->id_map = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * Pn, s));
   t->row_ptr = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * (Pn + 1), s));
-  t->partial = static_cast<float*>(dev_alloc(sizeof(float) * Pn, s));
+  t->partial = static_cast<float*>(dev_alloc(sizeof(float) * (Pn + 8), s));  // padded for 4-wide reads
   t->pmin = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * Pn, s));
   t->col = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * mn, s));
   if (t->weighted) t->w = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * mn, s));
@@ -639,10 +747,11 @@ hipError_t build_partition(gc_tocab t, const int32_t* a_rowptr, const int32_t* a
   if (!t->id16) return hipErrorOutOfMemory;
   if (P > 0) k_col16<<<grid_for(P, 256, 65536), 256, 0, s>>>(t->id_map, P, t->k - 1, t->id16);
   t->bytes += static_cast<int64_t>(sizeof(uint16_t)) * P;
-  if (t->W <= kLdsMaxWidth) {
-    GC_HIP_TRY(build_tiles(t->row_ptr, P, t->m, wave_tile_arcs(), &t->wtile_row, &t->n_wtiles, s));
-    GC_HIP_TRY(build_lds_chunks(t, s));
-  }
+  // the stream layout needs the whole range table of a block on the host
+  // once, and 32-bit arc indices past the padded end
+  if (t->dir == GC_PULL && t->W <= kLdsMaxWidth && static_cast<int64_t>(B) * (R + 1) <= (int64_t(1) << 25) &&
+      t->m + 1024 < INT32_MAX && 4 * (P + 8) < (int64_t(1) << 31))
+    GC_HIP_TRY(build_lds_stream(t, s));
   return hipStreamSynchronize(s);
 }
 

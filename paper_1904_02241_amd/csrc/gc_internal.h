@@ -51,6 +51,16 @@ struct gc_graph_s {
   std::vector<float> trace_ms;
 };
 
+// Row structure of 64 consecutive arcs of a stream-layout partition: bit i
+// set when arc 64w + i is the first arc of its local row, the number of
+// local rows that start before arc 64w (the index of the first row whose
+// head lies at or after the word), and bit 0 of the next word.
+struct alignas(16) gc_head_word {
+  uint64_t bits;
+  int32_t row;
+  int32_t next;
+};
+
 struct gc_tocab_s {
   gc_graph g = nullptr;
   int32_t dir = GC_PULL;
@@ -69,15 +79,25 @@ struct gc_tocab_s {
   uint16_t* id16 = nullptr;       // [P] id_map mod k: position inside the merge range
   int32_t* tile_row = nullptr;    // [n_tiles+1] first local row of each pull tile
   int32_t n_tiles = 0;
-  // LDS-resident blocks (W <= kLdsMaxWidth): columns as 16-bit offsets inside
-  // the block, and chunks of one block's local rows for one work-group each
-  uint16_t* col16 = nullptr;      // [m]
-  int32_t* wtile_row = nullptr;   // first local row of each wave tile of wave_tile_arcs() arcs
+  // Stream layout of an LDS-resident pull partition (W <= kLdsMaxWidth):
+  // 16-bit columns inside the block, one head bit per arc marking the first
+  // arc of every local row, and partial sums stored range-major (all blocks'
+  // partials of merge range j contiguous) so the merge reads one stream.
+  uint16_t* col16 = nullptr;      // [m_pad], zero past m
+  gc_head_word* heads = nullptr;  // [m_pad/64 + 1], bits at and past m set
+  int64_t m_pad = 0;              // multiple of wave_tile_arcs(), >= m + wave_tile_arcs()
+  int32_t* wtile_row = nullptr;   // unused by the stream layout
   int32_t n_wtiles = 0;
-  int32_t* chunk_beg = nullptr;   // [n_chunks]
-  int32_t* chunk_end = nullptr;   // [n_chunks]
-  int32_t* chunk_blk = nullptr;   // [n_chunks]
+  int2* seg = nullptr;            // [B][R+1]: first local row of block b in range j, shift to range-major index
+  int32_t* rstart = nullptr;      // [R+1] range-major start of merge range j
+  uint16_t* id16s = nullptr;      // [P] id16 in range-major order
+  int32_t* chunk_beg = nullptr;   // [n_chunks] first local row
+  int32_t* chunk_end = nullptr;   // [n_chunks] one past the last local row
+  int32_t* chunk_blk = nullptr;   // [n_chunks] block
+  int32_t* chunk_j0 = nullptr;    // [n_chunks] first merge range the chunk's rows fall in
+  int32_t* chunk_ns = nullptr;    // [n_chunks] number of merge ranges the chunk's rows span
   int32_t n_chunks = 0;
+  int32_t seg_max = 0;            // largest chunk_ns (sizes the work-group's LDS table)
   int32_t* pmin = nullptr;        // [P] traversal partials (next flags / min)
   int64_t bytes = 0;
 };
@@ -127,8 +147,15 @@ int32_t pull_tile_arcs();
 int32_t wave_tile_arcs();
 // Largest block width whose FP32 contribution slice is staged in LDS.
 constexpr int32_t kLdsMaxWidth = 1 << 15;
-// Arcs per chunk of an LDS-resident block (one work-group each).
+// Smallest number of arcs per chunk of an LDS-resident block (one work-group each).
 constexpr int32_t kLdsChunkArcs = 1 << 16;
+// LDS bytes one work-group of the LDS-resident pull may use: half a CU's
+// 160 KB (two resident work-groups) for slices up to 2^14 floats, all of it
+// for 2^15.
+inline int32_t lds_budget(int32_t W) { return W >= (1 << 15) ? 160 * 1024 - 512 : 80 * 1024 - 512; }
+// Largest range table (entries) that fits beside a W-float slice (with
+// 8 entries of padding).
+inline int32_t lds_seg_cap(int32_t W) { return ((lds_budget(W) - 4 * W) / 4 - 8) / 2; }
 hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int32_t dangling,
                         const float* rank_in, float* rank_out, int32_t iters, hipStream_t s);
 

@@ -73,79 +73,249 @@ __global__ __launch_bounds__(kThreads) void k_pr_tocab_pull(const int32_t* __res
 // Algorithm 4 with the block's slice of c resident in LDS (block widths up
 // to kLdsMaxWidth): gfx950 serves random 4-byte reads from LDS about ten
 // times faster than from L2, so on this GPU the block is sized for the
-// 160 KB LDS of a compute unit rather than for the last-level cache. One
-// work-group takes a chunk of one block's local rows and loads the slice
-// c[sW, sW + W) into LDS once (coalesced). Its waves then work
-// independently on the kWaveTile-arc tiles covering the chunk: a wave
-// stages the tile's gathered values (16-bit column offsets read as one
-// 8-byte load per lane, values read from the LDS slice) in its own LDS
-// strip, each lane sums whole rows that start in the tile, and the one row
-// that may run past the tile's end is finished by the whole wave.
+// 160 KB LDS of a compute unit rather than for the last-level cache.
+//
+// Stream layout: columns are 16-bit offsets inside the block and the row
+// structure is one head bit per arc (set on the first arc of every local
+// row, kept with a running row count per 64 arcs), so a tile of arcs is
+// read as plain streams with no row offsets. One work-group takes a chunk
+// (rows [r0, r1) of block b, whose rows fall in merge ranges j0 ..
+// j0+ns-1): it loads the slice c[bW, bW + W) and the chunk's part of the
+// range-major position table into LDS, then each wave walks kWaveTile-arc
+// tiles of the chunk. In a tile every lane holds 8 consecutive arcs (one
+// 16-byte load of columns), reads their contributions from the LDS slice
+// and takes the row boundaries from its head word; a segmented inclusive
+// scan across the wave (FP64) then gives the sum of every row whose head
+// lies in the tile. A row that runs past the tile end is finished by the
+// whole wave over the following tiles. Each row sum is stored at the row's
+// range-major index, so the merge reads every range as one stream. Loads
+// run two tiles ahead of the tile being reduced (all vector loads, which
+// complete in order, so waiting for one tile leaves the next in flight).
 constexpr int kLdsThreads = 1024;
 constexpr int kLdsWaves = kLdsThreads / kWave;
-constexpr int kWaveTile = 4 * kWave;  // 4 arcs per lane
+constexpr int kArcsPerLane = 8;
+constexpr int kWaveTile = kArcsPerLane * kWave;  // 512 arcs, 8 head words
 
-__global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
-    const int32_t* __restrict__ row_ptr, const uint16_t* __restrict__ col16, const int32_t* __restrict__ wtile_row,
-    const int32_t* __restrict__ chunk_beg, const int32_t* __restrict__ chunk_end, const int32_t* __restrict__ chunk_blk,
-    int32_t log2W, int32_t n, int32_t m, const float* __restrict__ c, float* __restrict__ partial) {
-  extern __shared__ float lds[];
-  const int32_t W = 1 << log2W;
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  float* slice = lds;
-  float* stage = lds + W + wid * kWaveTile;
-  const int32_t r0 = chunk_beg[blockIdx.x], r1 = chunk_end[blockIdx.x];
-  if (r0 >= r1) return;
-  const int32_t v0 = chunk_blk[blockIdx.x] << log2W;
-  const int32_t cnt = min(W, n - v0);
-  for (int32_t i = threadIdx.x; i < cnt; i += kLdsThreads) slice[i] = c[v0 + i];
-  __syncthreads();
-  const int32_t q0 = row_ptr[r0] / kWaveTile, q1 = (row_ptr[r1] - 1) / kWaveTile;
-  for (int32_t q = q0 + wid; q <= q1; q += kLdsWaves) {
-    const int32_t rb = max(r0, wtile_row[q]), re = min(r1, wtile_row[q + 1]);
-    if (rb >= re) continue;  // no chunk row starts here (middle of a long row)
-    const int32_t tb = q * kWaveTile;
-    const int32_t te = min(tb + kWaveTile, m);
-    uint16_t u[4];
-    if (tb + kWaveTile <= m) {
-      const uint64_t four = gcd::ld_stream(reinterpret_cast<const uint64_t*>(col16 + tb) + lane);
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+struct WaveTile {
+  u32x4 cols;  // this lane's 8 columns (16 bits each)
+  u32x4 hw;    // head word holding this lane's arcs: bits lo, bits hi, row count, next word's bit 0
+};
+
+__device__ __forceinline__ WaveTile load_wave_tile(const uint16_t* __restrict__ col16,
+                                                   const gc_head_word* __restrict__ heads, int32_t q, int lane) {
+  WaveTile t;
+  const int64_t tb = static_cast<int64_t>(q) * kWaveTile;
+  t.cols = gcd::ld_stream(reinterpret_cast<const u32x4*>(col16 + tb) + lane);
+  t.hw = *reinterpret_cast<const u32x4*>(heads + (tb >> 6) + (lane >> 3));
+  return t;
+}
+
+__device__ __forceinline__ uint64_t word_bits(const u32x4& w) {
+  return static_cast<uint64_t>(w[0]) | (static_cast<uint64_t>(w[1]) << 32);
+}
+
+// Merge-range index of local row r, searching forward from j: sb[j] is the
+// first row of the chunk's j-th merge range (ascending; sb[ns] lies past
+// the chunk and sb[ns+1..ns+3] hold INT32_MAX), four entries per step.
+__device__ __forceinline__ int32_t seek_range(const int32_t* sb, int32_t j, int32_t r) {
+  for (;;) {
+    const int32_t adv = (sb[j + 1] <= r) + (sb[j + 2] <= r) + (sb[j + 3] <= r) + (sb[j + 4] <= r);
+    j += adv;
+    if (adv < 4) return j;
+  }
+}
+constexpr int kSegPad = 4;  // LDS entries past the position table read by seek_range
+
+// Buffer resource over the partial sums: a store whose offset lies past the
+// resource's size is dropped by the hardware, which lets every lane issue
+// the same number of stores per tile (no branch around a store, so the
+// compiler can count outstanding memory operations and keep the prefetched
+// tiles in flight while the stores drain).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t partial_rsrc(float* partial, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(partial, 0, static_cast<int>(bytes), 0x00020000);
+}
+constexpr uint32_t kDropOffset = 0x80000000u;  // past any resource size below 2^31
+
+// One step of a wave-wide segmented inclusive scan of (F, A) pairs, the
+// value moved between lanes by a DPP control (lanes with no source receive
+// the identity (0, 0)): (F1, A1) then (F2, A2) gives (F1 | F2, F2 ? A2 : A1 + A2).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ void seg_scan_step(double& A, int& F) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(A), kCtrl, kRowMask, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(A), kCtrl, kRowMask, 0xF, false);
+  const int f = __builtin_amdgcn_update_dpp(0, F, kCtrl, kRowMask, 0xF, false);
+  if (!F) A += __hiloint2double(hi, lo);
+  F |= f;
+}
+
+// DPP controls (gfx9): shift right by n lanes inside each row of 16, copy
+// lane 15 / 31 into the following row(s), shift right by one lane across
+// the whole wave.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+
+__device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, int32_t q, int lane, const float* slice,
+                                                 const uint16_t* __restrict__ col16,
+                                                 const gc_head_word* __restrict__ heads, const int32_t* sb,
+                                                 const int32_t* sd, int32_t ns, int32_t r0, int32_t r1, int32_t& jc,
+                                                 __amdgpu_buffer_rsrc_t out, float* __restrict__ partial) {
+  const uint32_t wlo = t.hw[0], whi = t.hw[1];
+  const int32_t wrow = static_cast<int32_t>(t.hw[2]);
+  const int32_t ta = __builtin_amdgcn_readfirstlane(wrow);
+  const int32_t tz = __builtin_amdgcn_readlane(wrow + __popc(wlo) + __popc(whi), kWave - 1);
+  const int32_t ra = max(ta, r0), rz = min(tz, r1);  // rows of this chunk whose head is in the tile
+  if (ra < rz) jc = seek_range(sb, jc, ra);
+  // this lane's 8 head bits, the bit after them, and the heads before them
+  const int sub = lane & 7, sh = 8 * (sub & 3);
+  const uint32_t half = sub < 4 ? wlo : whi;
+  const uint32_t my8 = (half >> sh) & 0xFFu;
+  const uint32_t after = sub == 7 ? (t.hw[3] & 1u) : sub == 3 ? (whi & 1u) : (half >> (sh + 8)) & 1u;
+  const uint32_t ends = (my8 >> 1) | (after << 7);  // bit e: arc e is its row's last
+  const int32_t first = wrow + (sub < 4 ? 0 : __popc(wlo)) + __popc(half & ((1u << sh) - 1u));
+  float x[kArcsPerLane];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) u[j] = static_cast<uint16_t>(four >> (16 * j));
-    } else {
+  for (int e = 0; e < kArcsPerLane; ++e) x[e] = slice[(t.cols[e >> 1] >> (16 * (e & 1))) & 0xFFFFu];
+  double se[kArcsPerLane];
+  double run = 0.0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) u[j] = col16[min(tb + 4 * lane + j, m - 1)];
-    }
+  for (int e = 0; e < kArcsPerLane; ++e) {
+    run = ((my8 >> e) & 1u) ? static_cast<double>(x[e]) : run + static_cast<double>(x[e]);
+    se[e] = run;
+  }
+  // segmented inclusive scan of the lanes' open sums (flag: lane holds a head)
+  double A = run;
+  int F = my8 != 0u;
+  seg_scan_step<kDppRowShr1, 0xF>(A, F);
+  seg_scan_step<kDppRowShr2, 0xF>(A, F);
+  seg_scan_step<kDppRowShr4, 0xF>(A, F);
+  seg_scan_step<kDppRowShr8, 0xF>(A, F);
+  seg_scan_step<kDppRowBcast15, 0xA>(A, F);
+  seg_scan_step<kDppRowBcast31, 0xC>(A, F);
+  const double carry = __hiloint2double(
+      __builtin_amdgcn_update_dpp(0, __double2hiint(A), kDppWaveShr1, 0xF, 0xF, false),
+      __builtin_amdgcn_update_dpp(0, __double2loint(A), kDppWaveShr1, 0xF, 0xF, false));
+  // Range-major offsets. A lane's rows are consecutive, so while they stay in
+  // one merge range their offsets are consecutive too: look up the range of
+  // the lane's first row once and step from there; a lane whose rows reach
+  // the next range takes the slow path below.
+  const int32_t rlo = min(max(first - 1, ra), rz - 1);
+  int32_t jl = jc;
+  if (ra < rz) jl = seek_range(sb, jc, rlo);
+  const int32_t nb = sb[jl + 1];
+  const int32_t last = first - 1 + __popc(my8);  // row of the lane's last arc
+  uint32_t off[kArcsPerLane];
+  uint32_t o = 4u * static_cast<uint32_t>(first - 1 + sd[jl]);  // offset of row first - 1
+  int32_t r = first - 1;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) stage[4 * lane + j] = slice[u[j]];
-    wave_lds_fence();
-    bool over = false;
-    int32_t over_row = 0, over_end = 0;
-    double over_sum = 0.0;
-    for (int32_t r = rb + lane; r < re; r += kWave) {
-      const int32_t b = row_ptr[r], e = row_ptr[r + 1];
-      const int32_t ee = min(e, te);
-      double sum = 0.0;
-      for (int32_t i = b; i < ee; ++i) sum += static_cast<double>(stage[i - tb]);
-      if (e > te) {  // only the tile's last row can run past its end
-        over = true;
-        over_row = r;
-        over_end = e;
-        over_sum = sum;
-      } else {
-        gcd::st_stream(partial + r, static_cast<float>(sum));
+  for (int e = 0; e < kArcsPerLane; ++e) {
+    const uint32_t h = (my8 >> e) & 1u;
+    r += static_cast<int32_t>(h);
+    o += 4u * h;
+    if (!(my8 & ((2u << e) - 1u))) se[e] += carry;  // the row began in an earlier lane
+    off[e] = (((ends >> e) & 1u) && r >= ra && r < rz) ? o : kDropOffset;
+  }
+  if (__ballot(last >= nb && ra < rz)) {  // some lane's rows cross into another range
+    int32_t rr = first - 1, jj = jl;
+#pragma unroll
+    for (int e = 0; e < kArcsPerLane; ++e) {
+      rr += static_cast<int32_t>((my8 >> e) & 1u);
+      if (off[e] != kDropOffset && rr >= nb) {
+        jj = seek_range(sb, jj, rr);
+        off[e] = 4u * static_cast<uint32_t>(rr + sd[jj]);
       }
     }
-    const uint64_t ob = __ballot(over);
-    if (ob) {
-      const int owner = __ffsll(static_cast<long long>(ob)) - 1;
-      const int32_t oe = __shfl(over_end, owner, kWave);
-      double acc = 0.0;
-      for (int32_t i = te + lane; i < oe; i += kWave) acc += static_cast<double>(slice[col16[i]]);
-      acc = gcd::wave_sum(acc);
-      if (lane == owner) partial[over_row] = static_cast<float>(over_sum + acc);
-    }
-    wave_lds_fence();  // the strip is rewritten by the next tile
   }
+#pragma unroll
+  for (int e = 0; e < kArcsPerLane; ++e)
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(static_cast<float>(se[e])), out, off[e], 0, 0);
+  // the tile's last row continues into the next tile: the wave finishes it
+  const int32_t ro = tz - 1;
+  const uint32_t next_head = __builtin_amdgcn_readlane(static_cast<int32_t>(t.hw[3]), kWave - 1) & 1u;
+  if (!next_head && ro >= ra && ro < rz) {
+    double acc = __shfl(se[kArcsPerLane - 1], kWave - 1, kWave);
+    for (int32_t qq = q + 1;; ++qq) {
+      const WaveTile u = load_wave_tile(col16, heads, qq, lane);
+      const uint64_t hb = word_bits(u.hw);
+      // position of the tile's first head (kWaveTile if none): lowest lane group with a set bit
+      const uint64_t has = __ballot(hb != 0ull && (lane & 7) == 0);
+      const int32_t grp = has ? (__ffsll(static_cast<long long>(has)) - 1) >> 3 : 8;
+      const uint64_t gb = grp < 8 ? static_cast<uint64_t>(__shfl(static_cast<long long>(hb), grp * 8, kWave)) : 0ull;
+      const int32_t p = grp < 8 ? 64 * grp + __ffsll(static_cast<long long>(gb)) - 1 : kWaveTile;
+      double part = 0.0;
+#pragma unroll
+      for (int e = 0; e < kArcsPerLane; ++e)
+        if (kArcsPerLane * lane + e < p)
+          part += static_cast<double>(slice[(u.cols[e >> 1] >> (16 * (e & 1))) & 0xFFFFu]);
+      acc += gcd::wave_sum(part);
+      if (p < kWaveTile) break;  // bits past the last arc are set, so this ends
+    }
+    if (lane == 0) {
+      const int32_t j = seek_range(sb, jc, ro);
+      partial[ro + sd[j]] = static_cast<float>(acc);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
+    const int32_t* __restrict__ row_ptr, const uint16_t* __restrict__ col16,
+    const gc_head_word* __restrict__ heads, const int32_t* __restrict__ chunk_beg,
+    const int32_t* __restrict__ chunk_end, const int32_t* __restrict__ chunk_blk,
+    const int32_t* __restrict__ chunk_j0, const int32_t* __restrict__ chunk_ns, const int2* __restrict__ seg,
+    int32_t R, int32_t log2W, int32_t n, const float* __restrict__ c, float* __restrict__ partial,
+    uint32_t partial_bytes) {
+  extern __shared__ float lds[];
+  const int32_t W = 1 << log2W;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
+  const __amdgpu_buffer_rsrc_t out = partial_rsrc(partial, partial_bytes);
+  const int32_t ch = blockIdx.x;
+  const int32_t r0 = chunk_beg[ch], r1 = chunk_end[ch], b = chunk_blk[ch], j0 = chunk_j0[ch], ns = chunk_ns[ch];
+  float* slice = lds;
+  int32_t* sb = reinterpret_cast<int32_t*>(lds + W);  // ns + 1 boundaries, then kSegPad - 1 sentinels
+  int32_t* sd = sb + ns + kSegPad;                    // ns shifts, then one spare
+  {
+    const int32_t v0 = b << log2W;
+    const int32_t cnt = min(W, n - v0);
+    const float4* c4 = reinterpret_cast<const float4*>(c + v0);  // v0 is a multiple of W >= 2^10
+    float4* s4 = reinterpret_cast<float4*>(slice);
+    for (int32_t i = threadIdx.x; i < (cnt >> 2); i += kLdsThreads) s4[i] = c4[i];
+    for (int32_t i = (cnt & ~3) + threadIdx.x; i < cnt; i += kLdsThreads) slice[i] = c[v0 + i];
+    const int2* sg = seg + static_cast<int64_t>(b) * (R + 1) + j0;
+    for (int32_t i = threadIdx.x; i < ns + kSegPad; i += kLdsThreads) {
+      if (i <= ns) {
+        const int2 e = sg[i];
+        sb[i] = e.x;
+        sd[i] = e.y;  // i == ns: a spare, never used for a row of the chunk
+      } else {
+        sb[i] = INT32_MAX;
+      }
+    }
+  }
+  __syncthreads();
+  const int32_t q0 = row_ptr[r0] / kWaveTile, q1 = (row_ptr[r1] - 1) / kWaveTile;
+  int32_t q = q0 + wid;
+  if (q > q1) return;
+  constexpr int S = kLdsWaves;
+  int32_t jc = 0;  // sb[jc] <= first row of the current tile
+  // four tiles in registers: one is reduced while the next three load
+  WaveTile t0 = load_wave_tile(col16, heads, q, lane);
+  WaveTile t1 = load_wave_tile(col16, heads, min(q + S, q1), lane);
+  WaveTile t2 = load_wave_tile(col16, heads, min(q + 2 * S, q1), lane);
+  WaveTile t3;
+#define GC_PULL_STEP(cur, k, refill)                                                              \
+  refill = load_wave_tile(col16, heads, min(q + (k + 3) * S, q1), lane);                          \
+  reduce_wave_tile(cur, q + k * S, lane, slice, col16, heads, sb, sd, ns, r0, r1, jc, out, partial); \
+  if (q + (k + 1) * S > q1) break;
+  for (;;) {
+    GC_PULL_STEP(t0, 0, t3)
+    GC_PULL_STEP(t1, 1, t0)
+    GC_PULL_STEP(t2, 2, t1)
+    GC_PULL_STEP(t3, 3, t2)
+    q += 4 * S;
+  }
+#undef GC_PULL_STEP
 }
 
 // Algorithm 1 with the update fused (same tiles over the transposed graph):
@@ -182,6 +352,55 @@ __global__ __launch_bounds__(kThreads) void k_pr_merge(const int32_t* __restrict
     if (v < u.n) mine += update_vertex(u, v, acc[i], D);
   }
   publish_dangling(u, mine);
+}
+
+// Figure 5 merge over the stream layout, fused with the update: range j's
+// partial sums of every block are one contiguous slice [rstart[j],
+// rstart[j+1]) of partial / id16s, read with 16-byte / 8-byte loads (4
+// entries per load) and added into an FP64 LDS accumulator per vertex.
+constexpr int kMergeThreads = 512;
+
+template <int K>
+__global__ __launch_bounds__(kMergeThreads) void k_pr_merge_stream(const int32_t* __restrict__ rstart,
+                                                                   const uint16_t* __restrict__ id16s,
+                                                                   const float* __restrict__ partial, Update u) {
+  __shared__ double acc[K];
+  for (int i = threadIdx.x; i < K; i += kMergeThreads) acc[i] = 0.0;
+  __syncthreads();
+  const int32_t a = rstart[blockIdx.x], z = rstart[blockIdx.x + 1];
+  const int32_t g0 = a >> 2, g1 = (z + 3) >> 2;  // 4-entry groups covering [a, z)
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const f4* p4 = reinterpret_cast<const f4*>(partial);
+  const uint64_t* i4 = reinterpret_cast<const uint64_t*>(id16s);
+  constexpr int kU = 4;
+  for (int32_t g = g0 + static_cast<int32_t>(threadIdx.x); g < g1; g += kMergeThreads * kU) {
+    f4 p[kU];
+    uint64_t id[kU];
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      const int32_t gg = min(g + k * kMergeThreads, g1 - 1);  // clamped, masked below
+      p[k] = gcd::ld_stream(p4 + gg);
+      id[k] = gcd::ld_stream(i4 + gg);
+    }
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      const int32_t e0 = 4 * (g + k * kMergeThreads);
+      const float pv[4] = {p[k][0], p[k][1], p[k][2], p[k][3]};
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (e0 + e >= a && e0 + e < z)
+          atomicAdd(&acc[(id[k] >> (16 * e)) & 0xFFFFu], static_cast<double>(pv[e]));
+    }
+  }
+  __syncthreads();
+  const int32_t v0 = blockIdx.x * K;
+  const double D = *u.dtotal_in;
+  double mine = 0.0;
+  for (int i = threadIdx.x; i < K; i += kMergeThreads) {
+    const int32_t v = v0 + i;
+    if (v < u.n) mine += update_vertex(u, v, acc[i], D);
+  }
+  publish_dangling<kMergeThreads>(u, mine);
 }
 
 // Push with thread+warp+CTA style fine-grained balancing (Section 2.1,
@@ -263,10 +482,9 @@ int32_t pull_tile_arcs() { return kTileArcs; }
 int32_t wave_tile_arcs() { return kWaveTile; }
 
 hipError_t pagerank_setup() {
-  // the LDS-resident pull holds a slice of up to kLdsMaxWidth floats plus one strip per wave
+  // the LDS-resident pull holds a slice of up to kLdsMaxWidth floats plus its position table
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_tocab_pull_lds),
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             static_cast<int>(sizeof(float) * (kLdsMaxWidth + kLdsThreads * 4)));
+                             hipFuncAttributeMaxDynamicSharedMemorySize, lds_budget(kLdsMaxWidth));
 }
 
 hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int32_t dangling,
@@ -305,28 +523,49 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
     int32_t parts = vgrid;  // work-groups of the update kernel
     if (t && !push) {
       if (t->col16) {
-        ProfScope prof("pr_tocab_pull", s);
-        const size_t lds = sizeof(float) * (static_cast<size_t>(t->W) + kLdsThreads * 4);
-        k_pr_tocab_pull_lds<<<t->n_chunks, kLdsThreads, lds, s>>>(
-            t->row_ptr, t->col16, t->wtile_row, t->chunk_beg, t->chunk_end, t->chunk_blk, t->log2W, n,
-            static_cast<int32_t>(t->m), g->contrib[0], t->partial);
+        {
+          ProfScope prof("pr_tocab_pull", s);
+          const size_t lds = sizeof(float) * (static_cast<size_t>(t->W) + 2 * static_cast<size_t>(t->seg_max) + 2 * kSegPad);
+          if (t->n_chunks > 0)
+            k_pr_tocab_pull_lds<<<t->n_chunks, kLdsThreads, lds, s>>>(
+                t->row_ptr, t->col16, t->heads, t->chunk_beg, t->chunk_end, t->chunk_blk, t->chunk_j0,
+                t->chunk_ns, t->seg, t->R, t->log2W, n, g->contrib[0], t->partial,
+                static_cast<uint32_t>(sizeof(float) * (t->P + 8)));
+        }
+        u.contrib = g->contrib[0];
+        ProfScope prof("pr_merge", s);
+        switch (t->k) {
+          case 256: k_pr_merge_stream<256><<<t->R, kMergeThreads, 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
+          case 512: k_pr_merge_stream<512><<<t->R, kMergeThreads, 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
+          case 1024: k_pr_merge_stream<1024><<<t->R, kMergeThreads, 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
+          case 2048: k_pr_merge_stream<2048><<<t->R, kMergeThreads, 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
+          case 4096: k_pr_merge_stream<4096><<<t->R, kMergeThreads, 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
+          case 8192: k_pr_merge_stream<8192><<<t->R, kMergeThreads, 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
+          case 16384:
+            k_pr_merge_stream<16384><<<t->R, kMergeThreads, 0, s>>>(t->rstart, t->id16s, t->partial, u);
+            break;
+          default: return hipErrorInvalidValue;
+        }
+        parts = t->R;
       } else {
-        ProfScope prof("pr_tocab_pull", s);
-        k_pr_tocab_pull<<<t->n_tiles, kThreads, 0, s>>>(t->row_ptr, t->col, t->tile_row, g->contrib[0],
-                                                        t->partial);
-      }
-      u.contrib = g->contrib[0];  // safe in place: the pull pass has finished reading c
-      parts = t->R;
-      ProfScope prof("pr_merge", s);
-      switch (t->k) {
-        case 256: launch_merge<256>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
-        case 512: launch_merge<512>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
-        case 1024: launch_merge<1024>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
-        case 2048: launch_merge<2048>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
-        case 4096: launch_merge<4096>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
-        case 8192: launch_merge<8192>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
-        case 16384: launch_merge<16384>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
-        default: return hipErrorInvalidValue;
+        {
+          ProfScope prof("pr_tocab_pull", s);
+          k_pr_tocab_pull<<<t->n_tiles, kThreads, 0, s>>>(t->row_ptr, t->col, t->tile_row, g->contrib[0],
+                                                          t->partial);
+        }
+        u.contrib = g->contrib[0];  // safe in place: the pull pass has finished reading c
+        parts = t->R;
+        ProfScope prof("pr_merge", s);
+        switch (t->k) {
+          case 256: launch_merge<256>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
+          case 512: launch_merge<512>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
+          case 1024: launch_merge<1024>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
+          case 2048: launch_merge<2048>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
+          case 4096: launch_merge<4096>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
+          case 8192: launch_merge<8192>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
+          case 16384: launch_merge<16384>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
+          default: return hipErrorInvalidValue;
+        }
       }
     } else if (!push) {
       u.contrib = g->contrib[cur ^ 1];

@@ -54,20 +54,22 @@ __device__ __forceinline__ void wave_lds_fence() {
 
 // Work-group sum of one double per thread (fixed reduction tree), returned
 // to every thread.
+template <int NT = kThreads>
 __device__ __forceinline__ double wg_sum(double x) {
-  __shared__ double part[kThreads / kWave];
+  __shared__ double part[NT / kWave];
   x = gcd::wave_sum(x);
   if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = x;
   __syncthreads();
   double t = 0.0;
 #pragma unroll
-  for (int w = 0; w < kThreads / kWave; ++w) t += part[w];
+  for (int w = 0; w < NT / kWave; ++w) t += part[w];
   __syncthreads();
   return t;
 }
 
+template <int NT = kThreads>
 __device__ __forceinline__ void publish_dangling(const Update& u, double mine) {
-  const double t = wg_sum(mine);
+  const double t = wg_sum<NT>(mine);
   if (threadIdx.x == 0) u.dpart[blockIdx.x] = t;
 }
 

@@ -80,7 +80,8 @@ void free_graph(gc_graph g) {
 void free_tocab(gc_tocab t) {
   if (!t) return;
   void* bufs[] = {t->blk_rowoff, t->row_ptr, t->id_map, t->col, t->w, t->range_ptr, t->partial, t->pmin,
-                  t->tile_row, t->col16, t->chunk_beg, t->chunk_end, t->chunk_blk, t->wtile_row, t->id16};
+                  t->tile_row, t->col16, t->chunk_beg, t->chunk_end, t->chunk_blk, t->wtile_row, t->id16,
+                  t->heads, t->seg, t->rstart, t->id16s, t->chunk_j0, t->chunk_ns};
   for (void* p : bufs)
     if (p) gcx::dev_free(p, nullptr);
   delete t;
@@ -337,6 +338,15 @@ int tocab_info(gc_tocab t, int32_t* B, int64_t* P, int32_t* W, int32_t* k, int32
   if (k) *k = t->k;
   if (dir) *dir = t->dir;
   if (bytes) *bytes = t->bytes;
+  return GC_OK;
+}
+
+int tocab_layout(gc_tocab t, int32_t* stream_layout, int32_t* chunks, int64_t* table_bytes) {
+  if (!t) return fail(GC_EINVAL, "tocab_layout: NULL partition");
+  const bool st = t->col16 != nullptr;
+  if (stream_layout) *stream_layout = st ? 1 : 0;
+  if (chunks) *chunks = st ? t->n_chunks : 0;
+  if (table_bytes) *table_bytes = st ? static_cast<int64_t>(sizeof(int2)) * t->B * (t->R + 1) : 0;
   return GC_OK;
 }
 
