@@ -126,7 +126,7 @@ __device__ __forceinline__ int32_t seek_range(const int32_t* sb, int32_t j, int3
     if (adv < 4) return j;
   }
 }
-constexpr int kSegPad = 4;  // LDS entries past the position table read by seek_range
+constexpr int kSegPad = 4;  // LDS entries past the position table read by seek_range and the cursor
 
 // Buffer resource over the partial sums: a store whose offset lies past the
 // resource's size is dropped by the hardware, which lets every lane issue
@@ -156,17 +156,63 @@ __device__ __forceinline__ void seg_scan_step(double& A, int& F) {
 constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
 constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
 
-__device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, int32_t q, int lane, const float* slice,
-                                                 const uint16_t* __restrict__ col16,
-                                                 const gc_head_word* __restrict__ heads, const int32_t* sb,
-                                                 const int32_t* sd, int32_t ns, int32_t r0, int32_t r1, int32_t& jc,
-                                                 __amdgpu_buffer_rsrc_t out, float* __restrict__ partial) {
+// What a wave carries from one tile of its range to the next: the running
+// sum of the row still open at the tile's end (when that row is one the wave
+// must write) and a cursor into the chunk's position table with the next
+// boundaries and shifts cached in registers.
+struct PullCarry {
+  double open = 0.0;
+  int32_t open_row = -1;           // >= 0 when the wave owes that row's sum
+  int32_t jc = 0;                  // sb[jc] <= every row the wave still writes
+  int32_t b1, b2, b3, d0, d1, d2;  // sb[jc+1..jc+3], sd[jc..jc+2]
+};
+
+__device__ __forceinline__ void load_cursor(const int32_t* sb, const int32_t* sd, PullCarry& c) {
+  c.b1 = sb[c.jc + 1];
+  c.b2 = sb[c.jc + 2];
+  c.b3 = sb[c.jc + 3];
+  c.d0 = sd[c.jc];
+  c.d1 = sd[c.jc + 1];
+  c.d2 = sd[c.jc + 2];
+}
+
+// Sum over the tiles after tile q of the row open at q's end, up to its end
+// (the first head bit that follows).
+__device__ double finish_open_row(const uint16_t* __restrict__ col16, const gc_head_word* __restrict__ heads,
+                                  const float* slice, int32_t q, int lane) {
+  double acc = 0.0;
+  for (int32_t qq = q + 1;; ++qq) {
+    const WaveTile u = load_wave_tile(col16, heads, qq, lane);
+    const uint64_t hb = word_bits(u.hw);
+    // position of the tile's first head (kWaveTile if none): lowest lane group with a set bit
+    const uint64_t has = __ballot(hb != 0ull && (lane & 7) == 0);
+    const int32_t grp = has ? (__ffsll(static_cast<long long>(has)) - 1) >> 3 : 8;
+    const uint64_t gb = grp < 8 ? static_cast<uint64_t>(__shfl(static_cast<long long>(hb), grp * 8, kWave)) : 0ull;
+    const int32_t p = grp < 8 ? 64 * grp + __ffsll(static_cast<long long>(gb)) - 1 : kWaveTile;
+    double part = 0.0;
+#pragma unroll
+    for (int e = 0; e < kArcsPerLane; ++e)
+      if (kArcsPerLane * lane + e < p) part += static_cast<double>(slice[(u.cols[e >> 1] >> (16 * (e & 1))) & 0xFFFFu]);
+    acc += gcd::wave_sum(part);
+    if (p < kWaveTile) return acc;  // bits past the last arc are set, so this ends
+  }
+}
+
+__device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, int lane, const float* slice,
+                                                 const int32_t* sb, const int32_t* sd, int32_t r0, int32_t r1,
+                                                 PullCarry& cr, __amdgpu_buffer_rsrc_t out) {
   const uint32_t wlo = t.hw[0], whi = t.hw[1];
   const int32_t wrow = static_cast<int32_t>(t.hw[2]);
   const int32_t ta = __builtin_amdgcn_readfirstlane(wrow);
   const int32_t tz = __builtin_amdgcn_readlane(wrow + __popc(wlo) + __popc(whi), kWave - 1);
-  const int32_t ra = max(ta, r0), rz = min(tz, r1);  // rows of this chunk whose head is in the tile
-  if (ra < rz) jc = seek_range(sb, jc, ra);
+  // rows the wave writes from this tile: those whose head is here and that
+  // belong to the chunk, and the row left open by the previous tile
+  const int32_t rz = min(tz, r1);
+  const int32_t rmin = cr.open_row >= 0 ? cr.open_row : max(ta, r0);
+  if (rmin < rz && rmin >= cr.b1) {  // advance the range cursor
+    cr.jc = seek_range(sb, cr.jc, rmin);
+    load_cursor(sb, sd, cr);
+  }
   // this lane's 8 head bits, the bit after them, and the heads before them
   const int sub = lane & 7, sh = 8 * (sub & 3);
   const uint32_t half = sub < 4 ? wlo : whi;
@@ -193,35 +239,39 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, int32_t q, i
   seg_scan_step<kDppRowShr8, 0xF>(A, F);
   seg_scan_step<kDppRowBcast15, 0xA>(A, F);
   seg_scan_step<kDppRowBcast31, 0xC>(A, F);
-  const double carry = __hiloint2double(
+  double carry = __hiloint2double(
       __builtin_amdgcn_update_dpp(0, __double2hiint(A), kDppWaveShr1, 0xF, 0xF, false),
       __builtin_amdgcn_update_dpp(0, __double2loint(A), kDppWaveShr1, 0xF, 0xF, false));
-  // Range-major offsets. A lane's rows are consecutive, so while they stay in
-  // one merge range their offsets are consecutive too: look up the range of
-  // the lane's first row once and step from there; a lane whose rows reach
-  // the next range takes the slow path below.
-  const int32_t rlo = min(max(first - 1, ra), rz - 1);
-  int32_t jl = jc;
-  if (ra < rz) jl = seek_range(sb, jc, rlo);
-  const int32_t nb = sb[jl + 1];
-  const int32_t last = first - 1 + __popc(my8);  // row of the lane's last arc
+  const int Fx = __builtin_amdgcn_update_dpp(0, F, kDppWaveShr1, 0xF, 0xF, false);
+  if (!Fx) carry += cr.open;  // no head before this lane in the tile: the open row continues
+  // Range-major offsets: consecutive rows of one merge range have consecutive
+  // offsets; the lane's first row picks its range from the cached cursor and
+  // its rows step from there (a lane whose rows reach b3 or beyond takes the
+  // slow path below).
+  // (the selections are written as arithmetic on values so that they stay in registers)
+  const int32_t rl = max(first - 1, rmin);
+  const int32_t g1 = rl >= cr.b1, g2 = rl >= cr.b2;  // b1 <= b2
+  const int32_t dl = cr.d0 + g1 * (cr.d1 - cr.d0) + g2 * (cr.d2 - cr.d1);
+  const int32_t nl = cr.b1 + g1 * (cr.b2 - cr.b1) + g2 * (cr.b3 - cr.b2);
+  const int32_t last = first - 1 + __popc(my8);
   uint32_t off[kArcsPerLane];
-  uint32_t o = 4u * static_cast<uint32_t>(first - 1 + sd[jl]);  // offset of row first - 1
+  uint32_t o = 4u * static_cast<uint32_t>(first - 1 + dl);
   int32_t r = first - 1;
 #pragma unroll
   for (int e = 0; e < kArcsPerLane; ++e) {
     const uint32_t h = (my8 >> e) & 1u;
     r += static_cast<int32_t>(h);
     o += 4u * h;
-    if (!(my8 & ((2u << e) - 1u))) se[e] += carry;  // the row began in an earlier lane
-    off[e] = (((ends >> e) & 1u) && r >= ra && r < rz) ? o : kDropOffset;
+    if (!(my8 & ((2u << e) - 1u))) se[e] += carry;  // the row began before this lane
+    const bool mine = ((ends >> e) & 1u) && r >= rmin && r < rz;
+    off[e] = mine ? o : kDropOffset;
   }
-  if (__ballot(last >= nb && ra < rz)) {  // some lane's rows cross into another range
-    int32_t rr = first - 1, jj = jl;
+  if (__ballot(last >= nl && rmin < rz)) {  // some lane's rows reach the next merge range
+    int32_t rr = first - 1, jj = cr.jc;
 #pragma unroll
     for (int e = 0; e < kArcsPerLane; ++e) {
       rr += static_cast<int32_t>((my8 >> e) & 1u);
-      if (off[e] != kDropOffset && rr >= nb) {
+      if (off[e] != kDropOffset && rr >= nl) {
         jj = seek_range(sb, jj, rr);
         off[e] = 4u * static_cast<uint32_t>(rr + sd[jj]);
       }
@@ -230,32 +280,14 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, int32_t q, i
 #pragma unroll
   for (int e = 0; e < kArcsPerLane; ++e)
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(static_cast<float>(se[e])), out, off[e], 0, 0);
-  // the tile's last row continues into the next tile: the wave finishes it
-  const int32_t ro = tz - 1;
+  // the row open at the tile's end, if the wave writes it
   const uint32_t next_head = __builtin_amdgcn_readlane(static_cast<int32_t>(t.hw[3]), kWave - 1) & 1u;
-  if (!next_head && ro >= ra && ro < rz) {
-    double acc = __shfl(se[kArcsPerLane - 1], kWave - 1, kWave);
-    for (int32_t qq = q + 1;; ++qq) {
-      const WaveTile u = load_wave_tile(col16, heads, qq, lane);
-      const uint64_t hb = word_bits(u.hw);
-      // position of the tile's first head (kWaveTile if none): lowest lane group with a set bit
-      const uint64_t has = __ballot(hb != 0ull && (lane & 7) == 0);
-      const int32_t grp = has ? (__ffsll(static_cast<long long>(has)) - 1) >> 3 : 8;
-      const uint64_t gb = grp < 8 ? static_cast<uint64_t>(__shfl(static_cast<long long>(hb), grp * 8, kWave)) : 0ull;
-      const int32_t p = grp < 8 ? 64 * grp + __ffsll(static_cast<long long>(gb)) - 1 : kWaveTile;
-      double part = 0.0;
-#pragma unroll
-      for (int e = 0; e < kArcsPerLane; ++e)
-        if (kArcsPerLane * lane + e < p)
-          part += static_cast<double>(slice[(u.cols[e >> 1] >> (16 * (e & 1))) & 0xFFFFu]);
-      acc += gcd::wave_sum(part);
-      if (p < kWaveTile) break;  // bits past the last arc are set, so this ends
-    }
-    if (lane == 0) {
-      const int32_t j = seek_range(sb, jc, ro);
-      partial[ro + sd[j]] = static_cast<float>(acc);
-    }
-  }
+  const double tail = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(se[kArcsPerLane - 1]), kWave - 1),
+                                       __builtin_amdgcn_readlane(__double2loint(se[kArcsPerLane - 1]), kWave - 1));
+  const int32_t ro = tz - 1;  // the row of the tile's last arc
+  const bool owe = !next_head && (tz > ta ? (ro >= r0 && ro < r1) : cr.open_row >= 0);
+  cr.open_row = owe ? ro : -1;
+  cr.open = owe ? tail : 0.0;
 }
 
 __global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
@@ -274,7 +306,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
   const int32_t r0 = chunk_beg[ch], r1 = chunk_end[ch], b = chunk_blk[ch], j0 = chunk_j0[ch], ns = chunk_ns[ch];
   float* slice = lds;
   int32_t* sb = reinterpret_cast<int32_t*>(lds + W);  // ns + 1 boundaries, then kSegPad - 1 sentinels
-  int32_t* sd = sb + ns + kSegPad;                    // ns shifts, then one spare
+  int32_t* sd = sb + ns + kSegPad;                    // ns shifts, then spares
   {
     const int32_t v0 = b << log2W;
     const int32_t cnt = min(W, n - v0);
@@ -290,32 +322,44 @@ __global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
         sd[i] = e.y;  // i == ns: a spare, never used for a row of the chunk
       } else {
         sb[i] = INT32_MAX;
+        sd[i] = 0;
       }
     }
   }
   __syncthreads();
+  // each wave streams a contiguous range [qa, qz] of the chunk's tiles
   const int32_t q0 = row_ptr[r0] / kWaveTile, q1 = (row_ptr[r1] - 1) / kWaveTile;
-  int32_t q = q0 + wid;
-  if (q > q1) return;
-  constexpr int S = kLdsWaves;
-  int32_t jc = 0;  // sb[jc] <= first row of the current tile
+  const int32_t nt = q1 - q0 + 1;
+  const int32_t qa = q0 + static_cast<int32_t>(static_cast<int64_t>(nt) * wid / kLdsWaves);
+  const int32_t qz = q0 + static_cast<int32_t>(static_cast<int64_t>(nt) * (wid + 1) / kLdsWaves) - 1;
+  if (qa > qz) return;
+  PullCarry cr;
+  load_cursor(sb, sd, cr);
   // four tiles in registers: one is reduced while the next three load
+  int32_t q = qa;
   WaveTile t0 = load_wave_tile(col16, heads, q, lane);
-  WaveTile t1 = load_wave_tile(col16, heads, min(q + S, q1), lane);
-  WaveTile t2 = load_wave_tile(col16, heads, min(q + 2 * S, q1), lane);
+  WaveTile t1 = load_wave_tile(col16, heads, min(q + 1, qz), lane);
+  WaveTile t2 = load_wave_tile(col16, heads, min(q + 2, qz), lane);
   WaveTile t3;
-#define GC_PULL_STEP(cur, k, refill)                                                              \
-  refill = load_wave_tile(col16, heads, min(q + (k + 3) * S, q1), lane);                          \
-  reduce_wave_tile(cur, q + k * S, lane, slice, col16, heads, sb, sd, ns, r0, r1, jc, out, partial); \
-  if (q + (k + 1) * S > q1) break;
+#define GC_PULL_STEP(cur, k, refill)                                 \
+  refill = load_wave_tile(col16, heads, min(q + (k + 3), qz), lane); \
+  reduce_wave_tile(cur, lane, slice, sb, sd, r0, r1, cr, out);       \
+  if (q + (k + 1) > qz) break;
   for (;;) {
     GC_PULL_STEP(t0, 0, t3)
     GC_PULL_STEP(t1, 1, t0)
     GC_PULL_STEP(t2, 2, t1)
     GC_PULL_STEP(t3, 3, t2)
-    q += 4 * S;
+    q += 4;
   }
 #undef GC_PULL_STEP
+  if (cr.open_row >= 0) {  // the range's last row continues past it
+    const double v = cr.open + finish_open_row(col16, heads, slice, qz, lane);
+    if (lane == 0) {
+      const int32_t j = seek_range(sb, cr.jc, cr.open_row);
+      partial[cr.open_row + sd[j]] = static_cast<float>(v);
+    }
+  }
 }
 
 // Algorithm 1 with the update fused (same tiles over the transposed graph):
