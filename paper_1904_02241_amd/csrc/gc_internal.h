@@ -150,12 +150,14 @@ constexpr int32_t kLdsMaxWidth = 1 << 15;
 // Smallest number of arcs per chunk of an LDS-resident block (one work-group each).
 constexpr int32_t kLdsChunkArcs = 1 << 16;
 // LDS bytes one work-group of the LDS-resident pull may use: half a CU's
-// 160 KB (two resident work-groups) for slices up to 2^14 floats, all of it
-// for 2^15.
-inline int32_t lds_budget(int32_t W) { return W >= (1 << 15) ? 160 * 1024 - 512 : 80 * 1024 - 512; }
-// Largest range table (entries) that fits beside a W-float slice (with
-// 8 entries of padding).
-inline int32_t lds_seg_cap(int32_t W) { return ((lds_budget(W) - 4 * W) / 4 - 8) / 2; }
+// 160 KB (two resident work-groups) for slices up to 2^13 floats, all of it
+// for wider ones.
+inline int32_t lds_budget(int32_t W) { return W >= (1 << 14) ? 160 * 1024 - 512 : 80 * 1024 - 512; }
+// LDS bytes of the pull's per-wave output staging (16 waves x 256 floats).
+constexpr int32_t kLdsStageBytes = 16 * 256 * 4;
+// Largest range table (entries) that fits beside a W-float slice and the
+// staging (with 8 entries of padding).
+inline int32_t lds_seg_cap(int32_t W) { return ((lds_budget(W) - 4 * W - kLdsStageBytes) / 4 - 8) / 2; }
 hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int32_t dangling,
                         const float* rank_in, float* rank_out, int32_t iters, hipStream_t s);
 

@@ -95,6 +95,7 @@ constexpr int kLdsThreads = 1024;
 constexpr int kLdsWaves = kLdsThreads / kWave;
 constexpr int kArcsPerLane = 8;
 constexpr int kWaveTile = kArcsPerLane * kWave;  // 512 arcs, 8 head words
+constexpr int kStageRows = 256;                  // staged row sums per wave and pass
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -200,7 +201,7 @@ __device__ double finish_open_row(const uint16_t* __restrict__ col16, const gc_h
 
 __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, int lane, const float* slice,
                                                  const int32_t* sb, const int32_t* sd, int32_t r0, int32_t r1,
-                                                 PullCarry& cr, __amdgpu_buffer_rsrc_t out) {
+                                                 PullCarry& cr, __amdgpu_buffer_rsrc_t out, float* stage) {
   const uint32_t wlo = t.hw[0], whi = t.hw[1];
   const int32_t wrow = static_cast<int32_t>(t.hw[2]);
   const int32_t ta = __builtin_amdgcn_readfirstlane(wrow);
@@ -220,18 +221,18 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, int lane, co
   const uint32_t after = sub == 7 ? (t.hw[3] & 1u) : sub == 3 ? (whi & 1u) : (half >> (sh + 8)) & 1u;
   const uint32_t ends = (my8 >> 1) | (after << 7);  // bit e: arc e is its row's last
   const int32_t first = wrow + (sub < 4 ? 0 : __popc(wlo)) + __popc(half & ((1u << sh) - 1u));
-  float x[kArcsPerLane];
-#pragma unroll
-  for (int e = 0; e < kArcsPerLane; ++e) x[e] = slice[(t.cols[e >> 1] >> (16 * (e & 1))) & 0xFFFFu];
-  double se[kArcsPerLane];
-  double run = 0.0;
+  // Sums inside the lane's 8 arcs in FP32 (at most 8 terms, one rounding per
+  // add); everything that crosses lanes or tiles in FP64.
+  float sf[kArcsPerLane];
+  float run = 0.0f;
 #pragma unroll
   for (int e = 0; e < kArcsPerLane; ++e) {
-    run = ((my8 >> e) & 1u) ? static_cast<double>(x[e]) : run + static_cast<double>(x[e]);
-    se[e] = run;
+    const float x = slice[(t.cols[e >> 1] >> (16 * (e & 1))) & 0xFFFFu];
+    run = ((my8 >> e) & 1u) ? x : run + x;
+    sf[e] = run;
   }
   // segmented inclusive scan of the lanes' open sums (flag: lane holds a head)
-  double A = run;
+  double A = static_cast<double>(run);
   int F = my8 != 0u;
   seg_scan_step<kDppRowShr1, 0xF>(A, F);
   seg_scan_step<kDppRowShr2, 0xF>(A, F);
@@ -244,46 +245,61 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, int lane, co
       __builtin_amdgcn_update_dpp(0, __double2loint(A), kDppWaveShr1, 0xF, 0xF, false));
   const int Fx = __builtin_amdgcn_update_dpp(0, F, kDppWaveShr1, 0xF, 0xF, false);
   if (!Fx) carry += cr.open;  // no head before this lane in the tile: the open row continues
-  // Range-major offsets: consecutive rows of one merge range have consecutive
-  // offsets; the lane's first row picks its range from the cached cursor and
-  // its rows step from there (a lane whose rows reach b3 or beyond takes the
-  // slow path below).
-  // (the selections are written as arithmetic on values so that they stay in registers)
-  const int32_t rl = max(first - 1, rmin);
-  const int32_t g1 = rl >= cr.b1, g2 = rl >= cr.b2;  // b1 <= b2
-  const int32_t dl = cr.d0 + g1 * (cr.d1 - cr.d0) + g2 * (cr.d2 - cr.d1);
-  const int32_t nl = cr.b1 + g1 * (cr.b2 - cr.b1) + g2 * (cr.b3 - cr.b2);
-  const int32_t last = first - 1 + __popc(my8);
-  uint32_t off[kArcsPerLane];
-  uint32_t o = 4u * static_cast<uint32_t>(first - 1 + dl);
-  int32_t r = first - 1;
+  // The lane's arcs before its first head belong to a row begun earlier; only
+  // the last of them (just before that head, or the lane's last arc) can end
+  // it, and it gets the carried sum.
+  const int fh = my8 ? __builtin_ctz(my8) : kArcsPerLane;
+  float lead_sum = 0.0f;
 #pragma unroll
-  for (int e = 0; e < kArcsPerLane; ++e) {
-    const uint32_t h = (my8 >> e) & 1u;
-    r += static_cast<int32_t>(h);
-    o += 4u * h;
-    if (!(my8 & ((2u << e) - 1u))) se[e] += carry;  // the row began before this lane
-    const bool mine = ((ends >> e) & 1u) && r >= rmin && r < rz;
-    off[e] = mine ? o : kDropOffset;
-  }
-  if (__ballot(last >= nl && rmin < rz)) {  // some lane's rows reach the next merge range
-    int32_t rr = first - 1, jj = cr.jc;
-#pragma unroll
-    for (int e = 0; e < kArcsPerLane; ++e) {
-      rr += static_cast<int32_t>((my8 >> e) & 1u);
-      if (off[e] != kDropOffset && rr >= nl) {
-        jj = seek_range(sb, jj, rr);
-        off[e] = 4u * static_cast<uint32_t>(rr + sd[jj]);
-      }
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < kArcsPerLane; ++e)
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(static_cast<float>(se[e])), out, off[e], 0, 0);
-  // the row open at the tile's end, if the wave writes it
+  for (int e = 0; e < kArcsPerLane; ++e) lead_sum = e < fh ? sf[e] : lead_sum;
+  const float lead_val = static_cast<float>(static_cast<double>(lead_sum) + carry);
+  // The rows this tile completes form one run [rs, re): the open row (if
+  // the wave owes it) and every row of the chunk with its head here, except
+  // the last one when it continues into the next tile. Their sums are
+  // staged in LDS by row and written back so that store k of the wave holds
+  // rows rs + 64k .. rs + 64k + 63 (coalesced); the position table turns a
+  // row into its range-major index. Every lane always issues the same 8
+  // stores (unused ones get a dropped offset), so the compiler's count of
+  // outstanding memory operations stays exact.
   const uint32_t next_head = __builtin_amdgcn_readlane(static_cast<int32_t>(t.hw[3]), kWave - 1) & 1u;
-  const double tail = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(se[kArcsPerLane - 1]), kWave - 1),
-                                       __builtin_amdgcn_readlane(__double2loint(se[kArcsPerLane - 1]), kWave - 1));
+  const int32_t rs = rmin;
+  const int32_t re = min(rz, next_head ? tz : tz - 1);
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    const int32_t base = rs + pass * kStageRows;
+    if (pass == 0 || re - base > 0) {  // uniform: the second half only when the tile completes > 256 rows
+      int32_t r = first - 1;
+#pragma unroll
+      for (int e = 0; e < kArcsPerLane; ++e) {
+        r += static_cast<int32_t>((my8 >> e) & 1u);
+        const int32_t idx = r - base;
+        if (((ends >> e) & 1u) && r >= rs && r < re && idx >= 0 && idx < kStageRows)
+          stage[idx] = e < fh ? lead_val : sf[e];
+      }
+      wave_lds_fence();
+    }
+#pragma unroll
+    for (int k = 0; k < kStageRows / kWave; ++k) {
+      const int32_t i = k * kWave + lane;
+      const int32_t row = base + i;
+      const bool ok = row < re;
+      float v = 0.0f;
+      uint32_t off = kDropOffset;
+      if (ok) {
+        v = stage[i];
+        const int32_t g1 = row >= cr.b1, g2 = row >= cr.b2;  // b1 <= b2
+        int32_t d = cr.d0 + g1 * (cr.d1 - cr.d0) + g2 * (cr.d2 - cr.d1);
+        if (row >= cr.b3) d = sd[seek_range(sb, cr.jc, row)];  // rare: three or more boundaries in the tile
+        off = 4u * static_cast<uint32_t>(row + d);
+      }
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), out, off, 0, 0);
+    }
+    wave_lds_fence();  // the staging is rewritten next
+  }
+  // the row open at the tile's end, if the wave writes it
+  const double mytail = fh < kArcsPerLane ? static_cast<double>(run) : static_cast<double>(run) + carry;
+  const double tail = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(mytail), kWave - 1),
+                                       __builtin_amdgcn_readlane(__double2loint(mytail), kWave - 1));
   const int32_t ro = tz - 1;  // the row of the tile's last arc
   const bool owe = !next_head && (tz > ta ? (ro >= r0 && ro < r1) : cr.open_row >= 0);
   cr.open_row = owe ? ro : -1;
@@ -305,7 +321,8 @@ __global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
   const int32_t ch = blockIdx.x;
   const int32_t r0 = chunk_beg[ch], r1 = chunk_end[ch], b = chunk_blk[ch], j0 = chunk_j0[ch], ns = chunk_ns[ch];
   float* slice = lds;
-  int32_t* sb = reinterpret_cast<int32_t*>(lds + W);  // ns + 1 boundaries, then kSegPad - 1 sentinels
+  float* stage = lds + W + wid * kStageRows;          // this wave's output staging
+  int32_t* sb = reinterpret_cast<int32_t*>(lds + W + kLdsWaves * kStageRows);  // ns + 1 boundaries, then sentinels
   int32_t* sd = sb + ns + kSegPad;                    // ns shifts, then spares
   {
     const int32_t v0 = b << log2W;
@@ -335,22 +352,18 @@ __global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
   if (qa > qz) return;
   PullCarry cr;
   load_cursor(sb, sd, cr);
-  // four tiles in registers: one is reduced while the next three load
+  // two tiles in registers: one is reduced while the next loads
   int32_t q = qa;
   WaveTile t0 = load_wave_tile(col16, heads, q, lane);
-  WaveTile t1 = load_wave_tile(col16, heads, min(q + 1, qz), lane);
-  WaveTile t2 = load_wave_tile(col16, heads, min(q + 2, qz), lane);
-  WaveTile t3;
+  WaveTile t1;
 #define GC_PULL_STEP(cur, k, refill)                                 \
-  refill = load_wave_tile(col16, heads, min(q + (k + 3), qz), lane); \
-  reduce_wave_tile(cur, lane, slice, sb, sd, r0, r1, cr, out);       \
+  refill = load_wave_tile(col16, heads, min(q + (k + 1), qz), lane); \
+  reduce_wave_tile(cur, lane, slice, sb, sd, r0, r1, cr, out, stage); \
   if (q + (k + 1) > qz) break;
   for (;;) {
-    GC_PULL_STEP(t0, 0, t3)
+    GC_PULL_STEP(t0, 0, t1)
     GC_PULL_STEP(t1, 1, t0)
-    GC_PULL_STEP(t2, 2, t1)
-    GC_PULL_STEP(t3, 3, t2)
-    q += 4;
+    q += 2;
   }
 #undef GC_PULL_STEP
   if (cr.open_row >= 0) {  // the range's last row continues past it
@@ -569,7 +582,8 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
       if (t->col16) {
         {
           ProfScope prof("pr_tocab_pull", s);
-          const size_t lds = sizeof(float) * (static_cast<size_t>(t->W) + 2 * static_cast<size_t>(t->seg_max) + 2 * kSegPad);
+          const size_t lds = sizeof(float) * (static_cast<size_t>(t->W) + 2 * static_cast<size_t>(t->seg_max) + 2 * kSegPad) +
+                             kLdsStageBytes;
           if (t->n_chunks > 0)
             k_pr_tocab_pull_lds<<<t->n_chunks, kLdsThreads, lds, s>>>(
                 t->row_ptr, t->col16, t->heads, t->chunk_beg, t->chunk_end, t->chunk_blk, t->chunk_j0,
