@@ -111,15 +111,23 @@ def run_traversal(gc, torch, g, gh, part, sources, kind, policies):
     return out
 
 
-def traffic_from_profiles(kernel, src_file):
+def source_digest():
+    """SHA-256 over the sources that decide the PageRank kernels and their data layout."""
+    h = hashlib.sha256()
+    for f in ("gc_pagerank.hip", "gc_pr_device.h", "gc_build.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1904_02241_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_from_profiles(kernel):
     """HBM bytes per launch from a committed rocprofv3 --pmc summary, or None
-    when the kernel's source changed since the counters were taken."""
+    when the kernels' sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     want = re.search(r"source_sha256:\s*([0-9a-f]+)", text)
-    got = hashlib.sha256(open(src_file, "rb").read()).hexdigest()
+    got = source_digest()
     if not want or want.group(1) != got:
         return None
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
@@ -151,7 +159,7 @@ def suite_traversal(args, gc, gg, torch):
         log(f"generating {name}")
         gh = make().with_weights(11)
         g = gc.graph_load_csr(gh.rowptr, gh.colidx, gh.weights)
-        part = gc.tocab_partition(g, gc.GC_PULL, args.block_width, args.merge_range)
+        part = gc.tocab_partition(g, gc.GC_PULL, args.traversal_block_width, args.traversal_merge_range)
         srcs = gg.sources(gh, args.bfs_sources or 8, seed=5)
         pols = [("plain_pull", gc.GC_POLICY_PULL, False), ("tocab_pull", gc.GC_POLICY_PULL, True),
                 ("push", gc.GC_POLICY_PUSH, False), ("heuristic_tocab", gc.GC_POLICY_HEURISTIC, True)]
@@ -165,8 +173,8 @@ def suite_traversal(args, gc, gg, torch):
     return {"metric": METRIC, "value": round(best, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.bfs_sources or 8,
             "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "i32", "data": "synthetic",
-            "config": {"workload": "bfs_sssp_grid4096_uniform2^25", "block_width": args.block_width,
-                       "merge_range": args.merge_range, "sources": args.bfs_sources or 8},
+            "config": {"workload": "bfs_sssp_grid4096_uniform2^25", "block_width": args.traversal_block_width,
+                       "merge_range": args.traversal_merge_range, "sources": args.bfs_sources or 8},
             "traversal": out}
 
 
@@ -246,7 +254,7 @@ def suite_learned(args, gc, gg, torch):
 
     def load(gh):
         g = gc.graph_load_csr(gh.rowptr, gh.colidx, gh.weights)
-        return g, [gc.tocab_partition(g, gc.GC_PULL, w, args.merge_range) for w in widths]
+        return g, [gc.tocab_partition(g, gc.GC_PULL, w, args.traversal_merge_range) for w in widths]
 
     feats, times = [], []
     t0 = time.perf_counter()
@@ -350,8 +358,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--edge-factor", type=int, default=16)
-    ap.add_argument("--block-width", type=int, default=1 << 18)
-    ap.add_argument("--merge-range", type=int, default=4096)
+    ap.add_argument("--block-width", type=int, default=1 << 15, help="PageRank TOCAB block width")
+    ap.add_argument("--merge-range", type=int, default=16384, help="PageRank TOCAB merge range")
+    ap.add_argument("--traversal-block-width", type=int, default=1 << 18,
+                    help="TOCAB block width of BFS / SSSP partitions (last-level-cache sized)")
+    ap.add_argument("--traversal-merge-range", type=int, default=4096)
+    ap.add_argument("--push-block-width", type=int, default=1 << 18,
+                    help="TOCAB push block width (destination slices of FP64 sums in L2)")
     ap.add_argument("--forms", default="tocab_pull,plain_pull,tocab_push,plain_push",
                     help="comma list; the first is the headline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -401,7 +414,9 @@ def main():
             d = gc.GC_PULL if form == "tocab_pull" else gc.GC_PUSH
             if d not in parts:
                 t0 = time.perf_counter()
-                parts[d] = gc.tocab_partition(g, d, args.block_width, args.merge_range)
+                W, K = ((args.block_width, args.merge_range) if d == gc.GC_PULL
+                        else (args.push_block_width, args.traversal_merge_range))
+                parts[d] = gc.tocab_partition(g, d, W, K)
                 log(f"tocab_partition {form} {parts[d].info} {time.perf_counter() - t0:.2f} s")
             part = parts[d]
         elif form == "plain_push":
@@ -413,13 +428,14 @@ def main():
 
     traversal = None
     if args.bfs_sources > 0:
-        if gc.GC_PULL not in parts:
-            parts[gc.GC_PULL] = gc.tocab_partition(g, gc.GC_PULL, args.block_width, args.merge_range)
+        parts["traversal"] = gc.tocab_partition(g, gc.GC_PULL, args.traversal_block_width,
+                                                args.traversal_merge_range)
         srcs = gg.sources(gh, args.bfs_sources, seed=2)
         pols = [("plain_pull", gc.GC_POLICY_PULL, False), ("tocab_pull", gc.GC_POLICY_PULL, True),
                 ("push", gc.GC_POLICY_PUSH, False), ("heuristic_tocab", gc.GC_POLICY_HEURISTIC, True),
                 ("heuristic_plain", gc.GC_POLICY_HEURISTIC, False)]
-        traversal = {"bfs": run_traversal(gc, torch, g, gh, parts[gc.GC_PULL], srcs, "bfs", pols),
+        traversal = {"bfs": run_traversal(gc, torch, g, gh, parts["traversal"], srcs, "bfs", pols),
+                     "block_width": args.traversal_block_width,
                      "sources": [int(x) for x in srcs]}
 
     head = forms[0]
@@ -430,8 +446,7 @@ def main():
     dom_ms = kern[dom][0] / kern[dom][1]
     per_launch = kernel_bytes(dom, n, m, info)
     achieved = per_launch / (dom_ms * 1e-3) / 1e9
-    src = os.path.join(ROOT, "paper_1904_02241_amd", "csrc", "gc_pagerank.hip")
-    traffic = traffic_from_profiles(dom, src)
+    traffic = traffic_from_profiles(dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "kernel_ms": round(dom_ms, 4), "algorithmic_bytes_per_launch": per_launch}
@@ -455,6 +470,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"pagerank_{head}_rmat{args.scale}", "graph": "rmat", "scale": args.scale,
                    "edge_factor": args.edge_factor, "n": n, "m": m, "block_width": args.block_width,
+                   "push_block_width": args.push_block_width,
                    "merge_range": args.merge_range, "damping": 0.85, "dangling": "uniform",
                    "P": info.get("P"), "B": info.get("B")},
         "roofline": roofline,

@@ -113,7 +113,7 @@ hipError_t autotune(gc_graph g, int32_t dir, int32_t min_W, int32_t* W_out, int3
   }
   Candidate best = cand[0];
   if (best.ms == 0.0) GC_HIP_TRY(evaluate(best, iters));
-  for (int32_t k : {2048, 8192}) {
+  for (int32_t k : {2048, 8192, 16384}) {
     if (!allowed(n, best.W, k)) continue;
     Candidate c{best.W, k};
     GC_HIP_TRY(evaluate(c, iters));

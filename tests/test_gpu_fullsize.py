@@ -19,7 +19,9 @@ from tests.gpu_util import host, load, pagerank_gpu, torch
 pytestmark = pytest.mark.gpu
 
 L1_TOL = 1e-6
-BENCH_W, BENCH_K = 1 << 18, 4096
+BENCH_W, BENCH_K = 1 << 15, 16384          # PageRank pull partition the benchmark times
+TRAV_W, TRAV_K = 1 << 18, 4096             # BFS / SSSP partition the benchmark times
+PUSH_W = 1 << 18
 
 
 @pytest.fixture(scope="module")
@@ -38,9 +40,9 @@ def rmat24_pagerank(rmat24):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("form,W,k", [("tocab_pull", BENCH_W, BENCH_K), ("tocab_pull", 1 << 14, BENCH_K),
-                                      ("plain_pull", 1 << 10, 256), ("tocab_push", BENCH_W, BENCH_K),
-                                      ("plain_push", 1 << 10, 256)])
+@pytest.mark.parametrize("form,W,k", [("tocab_pull", BENCH_W, BENCH_K), ("tocab_pull", 1 << 14, 8192),
+                                      ("tocab_pull", 1 << 18, 4096), ("plain_pull", 1 << 10, 256),
+                                      ("tocab_push", PUSH_W, TRAV_K), ("plain_push", 1 << 10, 256)])
 def test_rmat24_pagerank_20_iterations(rmat24, rmat24_pagerank, form, W, k):
     g = rmat24
     r0, want = rmat24_pagerank
@@ -57,7 +59,7 @@ def test_rmat24_traversals_bit_exact(rmat24):
     import paper_1904_02241_amd as gc
     g = rmat24
     h = load(g, weights=True)
-    part = gc.tocab_partition(h, gc.GC_PULL, BENCH_W, BENCH_K)
+    part = gc.tocab_partition(h, gc.GC_PULL, TRAV_W, TRAV_K)
     d = torch().empty(g.n, dtype=torch().int32, device="cuda")
     srcs = gg.sources(g, 2, seed=2)
     for s in srcs:
@@ -85,7 +87,7 @@ def test_traversal_graphs_bit_exact(name):
     g = g.with_weights(11)
     print(f"{name} n={g.n} m={g.m}", flush=True)
     h = load(g, weights=True)
-    part = gc.tocab_partition(h, gc.GC_PULL, BENCH_W, BENCH_K)
+    part = gc.tocab_partition(h, gc.GC_PULL, TRAV_W, TRAV_K)
     d = torch().empty(g.n, dtype=torch().int32, device="cuda")
     s = int(gg.sources(g, 1, seed=5)[0])
     policies = (("plain_pull", None, gc.GC_POLICY_PULL), ("tocab_pull", part, gc.GC_POLICY_PULL),

@@ -33,7 +33,8 @@ def test_pagerank_rmat16_20_iterations(form, mode):
 
 
 @pytest.mark.parametrize("form", FORMS)
-@pytest.mark.parametrize("W,k", [(1 << 10, 256), (1 << 12, 4096), (1 << 14, 16384), (1 << 15, 2048), (1 << 17, 512)])
+@pytest.mark.parametrize("W,k", [(1 << 10, 256), (1 << 12, 4096), (1 << 14, 16384), (1 << 15, 2048),
+                                 (1 << 15, 16384), (1 << 13, 256), (1 << 17, 512)])
 def test_pagerank_ragged_grid_block_shapes(form, W, k):
     g = gg.grid(300, 301, 0.05, seed=3)  # n = 90300: ragged last block and range
     print(f"pagerank grid {form} W={W} k={k}", flush=True)
