@@ -95,7 +95,11 @@ constexpr int kLdsThreads = 1024;
 constexpr int kLdsWaves = kLdsThreads / kWave;
 constexpr int kArcsPerLane = 8;
 constexpr int kWaveTile = kArcsPerLane * kWave;  // 512 arcs, 8 head words
-constexpr int kStageRows = 256;                  // staged row sums per wave and pass
+constexpr int kStageRows = 320;                  // staged row sums per wave in the first pass
+constexpr int kTileRowsMax = 512;                // rows one tile can complete
+constexpr int kStageSpare = 16;                  // spare slots per wave for elements that end no staged row
+static_assert(kStageRows % kWave == 0 && (kTileRowsMax - kStageRows) % kWave == 0 &&
+              kTileRowsMax - kStageRows <= kStageRows, "staging passes of whole store instructions");
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -138,6 +142,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t partial_rsrc(float* partial, u
   return __builtin_amdgcn_make_buffer_rsrc(partial, 0, static_cast<int>(bytes), 0x00020000);
 }
 constexpr uint32_t kDropOffset = 0x80000000u;  // past any resource size below 2^31
+
+__device__ __forceinline__ void partial_store(__amdgpu_buffer_rsrc_t out, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), out, off, 0, 0);
+}
 
 // One step of a wave-wide segmented inclusive scan of (F, A) pairs, the
 // value moved between lanes by a DPP control (lanes with no source receive
@@ -264,37 +272,63 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, int lane, co
   const uint32_t next_head = __builtin_amdgcn_readlane(static_cast<int32_t>(t.hw[3]), kWave - 1) & 1u;
   const int32_t rs = rmin;
   const int32_t re = min(rz, next_head ? tz : tz - 1);
+  // Staging slot of each element, computed once: for an element that ends
+  // a row, the row's offset from rs (as unsigned: rows before rs wrap to
+  // huge values); otherwise none. Rows at or past re may land in slots that
+  // are never read back (the write-out stops at re), so only the row ends
+  // need testing here.
+  uint32_t slot[kArcsPerLane];
+  float val[kArcsPerLane];
+  {
+    int32_t r = first - 1;
+#pragma unroll
+    for (int e = 0; e < kArcsPerLane; ++e) {
+      r += static_cast<int32_t>((my8 >> e) & 1u);
+      slot[e] = ((ends >> e) & 1u) ? static_cast<uint32_t>(r - rs) : 0xFFFFFFFFu;
+      val[e] = e < fh ? lead_val : sf[e];
+    }
+  }
+  // rows at or past the cached boundary b3 (three or more ranges in one tile)
+  // are stored on the slow path below; the others index with the cursor
+  const int32_t i1 = cr.b1 - rs, i2 = cr.b2 - rs, iz = min(re, cr.b3) - rs;
+  // Two passes over the staging: rows [0, 320) of the run, then [320, 512)
+  // (a tile completes at most 512 rows; the second pass's LDS work is
+  // skipped when it has no rows, its 3 stores are then dropped).
 #pragma unroll
   for (int pass = 0; pass < 2; ++pass) {
-    const int32_t base = rs + pass * kStageRows;
-    if (pass == 0 || re - base > 0) {  // uniform: the second half only when the tile completes > 256 rows
-      int32_t r = first - 1;
+    const uint32_t lo = pass == 0 ? 0u : static_cast<uint32_t>(kStageRows);
+    const int n = pass == 0 ? kStageRows : kTileRowsMax - kStageRows;  // rows of this pass
+    if (pass == 0 || re - rs > kStageRows) {  // uniform
+      // every element writes (no branch): rows of this pass to their slot,
+      // the rest to one of the wave's spare slots
 #pragma unroll
       for (int e = 0; e < kArcsPerLane; ++e) {
-        r += static_cast<int32_t>((my8 >> e) & 1u);
-        const int32_t idx = r - base;
-        if (((ends >> e) & 1u) && r >= rs && r < re && idx >= 0 && idx < kStageRows)
-          stage[idx] = e < fh ? lead_val : sf[e];
+        const uint32_t k = slot[e] - lo;
+        stage[k < static_cast<uint32_t>(n) ? k : kStageRows + (lane & (kStageSpare - 1))] = val[e];
       }
       wave_lds_fence();
     }
+    float v[kStageRows / kWave];
 #pragma unroll
-    for (int k = 0; k < kStageRows / kWave; ++k) {
-      const int32_t i = k * kWave + lane;
-      const int32_t row = base + i;
-      const bool ok = row < re;
-      float v = 0.0f;
-      uint32_t off = kDropOffset;
-      if (ok) {
-        v = stage[i];
-        const int32_t g1 = row >= cr.b1, g2 = row >= cr.b2;  // b1 <= b2
-        int32_t d = cr.d0 + g1 * (cr.d1 - cr.d0) + g2 * (cr.d2 - cr.d1);
-        if (row >= cr.b3) d = sd[seek_range(sb, cr.jc, row)];  // rare: three or more boundaries in the tile
-        off = 4u * static_cast<uint32_t>(row + d);
-      }
-      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), out, off, 0, 0);
+    for (int k = 0; k < n / kWave; ++k) v[k] = stage[k * kWave + lane];
+#pragma unroll
+    for (int k = 0; k < n / kWave; ++k) {
+      const int32_t i = static_cast<int32_t>(lo) + k * kWave + lane;  // row rs + i
+      const int32_t d = cr.d0 + (i >= i1) * (cr.d1 - cr.d0) + (i >= i2) * (cr.d2 - cr.d1);  // arithmetic keeps cr in registers
+      const uint32_t off = i < iz ? 4u * static_cast<uint32_t>(rs + i + d) : kDropOffset;
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[k]), out, off, 0, 0);
     }
     wave_lds_fence();  // the staging is rewritten next
+  }
+  if (re > cr.b3) {  // uniform, rare: store the rows at or past b3
+#pragma unroll
+    for (int e = 0; e < kArcsPerLane; ++e) {
+      const int32_t r = rs + static_cast<int32_t>(slot[e]);
+      if (slot[e] < static_cast<uint32_t>(re - rs) && r >= cr.b3) {
+        const int32_t j = seek_range(sb, cr.jc, r);
+        partial_store(out, 4u * static_cast<uint32_t>(r + sd[j]), val[e]);
+      }
+    }
   }
   // the row open at the tile's end, if the wave writes it
   const double mytail = fh < kArcsPerLane ? static_cast<double>(run) : static_cast<double>(run) + carry;
@@ -321,8 +355,8 @@ __global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
   const int32_t ch = blockIdx.x;
   const int32_t r0 = chunk_beg[ch], r1 = chunk_end[ch], b = chunk_blk[ch], j0 = chunk_j0[ch], ns = chunk_ns[ch];
   float* slice = lds;
-  float* stage = lds + W + wid * kStageRows;          // this wave's output staging
-  int32_t* sb = reinterpret_cast<int32_t*>(lds + W + kLdsWaves * kStageRows);  // ns + 1 boundaries, then sentinels
+  float* stage = lds + W + wid * (kStageRows + kStageSpare);  // this wave's output staging and spare slots
+  int32_t* sb = reinterpret_cast<int32_t*>(lds + W + kLdsWaves * (kStageRows + kStageSpare));  // ns + 1 boundaries, then sentinels
   int32_t* sd = sb + ns + kSegPad;                    // ns shifts, then spares
   {
     const int32_t v0 = b << log2W;
@@ -415,9 +449,13 @@ __global__ __launch_bounds__(kThreads) void k_pr_merge(const int32_t* __restrict
 // partial sums of every block are one contiguous slice [rstart[j],
 // rstart[j+1]) of partial / id16s, read with 16-byte / 8-byte loads (4
 // entries per load) and added into an FP64 LDS accumulator per vertex.
-constexpr int kMergeThreads = 512;
-
+// Work-group size: an FP64 accumulator of 16384 entries (128 KB) leaves room
+// for one work-group per CU, which then runs 16 waves; smaller ranges run two
+// or more 512-thread work-groups per CU.
 template <int K>
+constexpr int merge_threads() { return K >= 16384 ? 1024 : 512; }
+
+template <int K, int kMergeThreads = merge_threads<K>()>
 __global__ __launch_bounds__(kMergeThreads) void k_pr_merge_stream(const int32_t* __restrict__ rstart,
                                                                    const uint16_t* __restrict__ id16s,
                                                                    const float* __restrict__ partial, Update u) {
@@ -593,14 +631,14 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
         u.contrib = g->contrib[0];
         ProfScope prof("pr_merge", s);
         switch (t->k) {
-          case 256: k_pr_merge_stream<256><<<t->R, kMergeThreads, 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
-          case 512: k_pr_merge_stream<512><<<t->R, kMergeThreads, 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
-          case 1024: k_pr_merge_stream<1024><<<t->R, kMergeThreads, 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
-          case 2048: k_pr_merge_stream<2048><<<t->R, kMergeThreads, 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
-          case 4096: k_pr_merge_stream<4096><<<t->R, kMergeThreads, 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
-          case 8192: k_pr_merge_stream<8192><<<t->R, kMergeThreads, 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
+          case 256: k_pr_merge_stream<256><<<t->R, merge_threads<256>(), 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
+          case 512: k_pr_merge_stream<512><<<t->R, merge_threads<512>(), 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
+          case 1024: k_pr_merge_stream<1024><<<t->R, merge_threads<1024>(), 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
+          case 2048: k_pr_merge_stream<2048><<<t->R, merge_threads<2048>(), 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
+          case 4096: k_pr_merge_stream<4096><<<t->R, merge_threads<4096>(), 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
+          case 8192: k_pr_merge_stream<8192><<<t->R, merge_threads<8192>(), 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
           case 16384:
-            k_pr_merge_stream<16384><<<t->R, kMergeThreads, 0, s>>>(t->rstart, t->id16s, t->partial, u);
+            k_pr_merge_stream<16384><<<t->R, merge_threads<16384>(), 0, s>>>(t->rstart, t->id16s, t->partial, u);
             break;
           default: return hipErrorInvalidValue;
         }
