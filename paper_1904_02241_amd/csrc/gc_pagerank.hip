@@ -255,12 +255,9 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, int lane, co
   if (!Fx) carry += cr.open;  // no head before this lane in the tile: the open row continues
   // The lane's arcs before its first head belong to a row begun earlier; only
   // the last of them (just before that head, or the lane's last arc) can end
-  // it, and it gets the carried sum.
+  // it, and it gets the carried sum (rounded to FP32 once, then one FP32 add).
   const int fh = my8 ? __builtin_ctz(my8) : kArcsPerLane;
-  float lead_sum = 0.0f;
-#pragma unroll
-  for (int e = 0; e < kArcsPerLane; ++e) lead_sum = e < fh ? sf[e] : lead_sum;
-  const float lead_val = static_cast<float>(static_cast<double>(lead_sum) + carry);
+  const float carry_f = static_cast<float>(carry);
   // The rows this tile completes form one run [rs, re): the open row (if
   // the wave owes it) and every row of the chunk with its head here, except
   // the last one when it continues into the next tile. Their sums are
@@ -285,7 +282,7 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, int lane, co
     for (int e = 0; e < kArcsPerLane; ++e) {
       r += static_cast<int32_t>((my8 >> e) & 1u);
       slot[e] = ((ends >> e) & 1u) ? static_cast<uint32_t>(r - rs) : 0xFFFFFFFFu;
-      val[e] = e < fh ? lead_val : sf[e];
+      val[e] = e < fh ? sf[e] + carry_f : sf[e];
     }
   }
   // rows at or past the cached boundary b3 (three or more ranges in one tile)
@@ -386,18 +383,20 @@ __global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
   if (qa > qz) return;
   PullCarry cr;
   load_cursor(sb, sd, cr);
-  // two tiles in registers: one is reduced while the next loads
+  // three tiles in registers: one is reduced while the next two load
   int32_t q = qa;
   WaveTile t0 = load_wave_tile(col16, heads, q, lane);
-  WaveTile t1;
+  WaveTile t1 = load_wave_tile(col16, heads, min(q + 1, qz), lane);
+  WaveTile t2;
 #define GC_PULL_STEP(cur, k, refill)                                 \
-  refill = load_wave_tile(col16, heads, min(q + (k + 1), qz), lane); \
+  refill = load_wave_tile(col16, heads, min(q + (k + 2), qz), lane); \
   reduce_wave_tile(cur, lane, slice, sb, sd, r0, r1, cr, out, stage); \
   if (q + (k + 1) > qz) break;
   for (;;) {
-    GC_PULL_STEP(t0, 0, t1)
+    GC_PULL_STEP(t0, 0, t2)
     GC_PULL_STEP(t1, 1, t0)
-    q += 2;
+    GC_PULL_STEP(t2, 2, t1)
+    q += 3;
   }
 #undef GC_PULL_STEP
   if (cr.open_row >= 0) {  // the range's last row continues past it
