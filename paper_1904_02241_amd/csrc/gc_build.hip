@@ -645,30 +645,45 @@ hipError_t build_lds_stream(gc_tocab t, hipStream_t s) {
   GC_HIP_TRY(hipMemcpyAsync(hseg.data(), t->seg, sizeof(int2) * entries, hipMemcpyDeviceToHost, s));
   GC_HIP_TRY(hipMemcpyAsync(harc.data(), arcs.p, sizeof(int32_t) * entries, hipMemcpyDeviceToHost, s));
   GC_HIP_TRY(hipStreamSynchronize(s));
+  // A block's ranges are cut into chunks of about equal arc counts (near
+  // `target`, at most `cap` ranges each); chunks are launched largest first,
+  // so the work-groups that start last are the short ones.
   const int64_t target = std::max<int64_t>(kLdsChunkArcs, m / 1024);
   const int32_t cap = lds_seg_cap(t->W);
-  std::vector<int32_t> beg, end, blk, j0v, nsv;
+  struct Chunk {
+    int32_t beg, end, blk, j0, ns;
+    int64_t arcs;
+  };
+  std::vector<Chunk> ch;
   int32_t seg_max = 1;
   for (int32_t b = 0; b < B; ++b) {
     const int64_t o = static_cast<int64_t>(b) * (R + 1);
+    const int64_t mb = harc[o + R] - harc[o];
+    const int64_t pieces = std::max<int64_t>(1, (mb + target - 1) / target);
+    const int64_t per = (mb + pieces - 1) / pieces;  // arcs per chunk of this block
     int32_t j = 0;
     while (j < R) {
       const int32_t ja = j;
       int64_t a = 0;
-      while (j < R && j - ja < cap && (j == ja || a < target)) {
+      while (j < R && j - ja < cap && (j == ja || a < per)) {
         a += harc[o + j + 1] - harc[o + j];
         ++j;
       }
       const int32_t r0 = hseg[o + ja].x, r1 = hseg[o + j].x;
       if (r1 > r0) {
-        beg.push_back(r0);
-        end.push_back(r1);
-        blk.push_back(b);
-        j0v.push_back(ja);
-        nsv.push_back(j - ja);
+        ch.push_back({r0, r1, b, ja, j - ja, a});
         seg_max = std::max(seg_max, j - ja);
       }
     }
+  }
+  std::stable_sort(ch.begin(), ch.end(), [](const Chunk& x, const Chunk& y) { return x.arcs > y.arcs; });
+  std::vector<int32_t> beg, end, blk, j0v, nsv;
+  for (const Chunk& c : ch) {
+    beg.push_back(c.beg);
+    end.push_back(c.end);
+    blk.push_back(c.blk);
+    j0v.push_back(c.j0);
+    nsv.push_back(c.ns);
   }
   const int32_t nch = static_cast<int32_t>(beg.size());
   t->n_chunks = nch;
@@ -723,7 +738,9 @@ hipError_t build_partition(gc_tocab t, const int32_t* a_rowptr, const int32_t* a
   const size_t mn = static_cast<size_t>(std::max<int64_t>(t->m, 1));
   t->id_map = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * Pn, s));
   t->row_ptr = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * (Pn + 1), s));
-  t->partial = static_cast<float*>(dev_alloc(sizeof(float) * (Pn + 8), s));  // padded for 4-wide reads
+  // padded for 4-wide reads, and past the pull's buffer resource (its range
+  // check leaves out a store's scalar offset, at most 512 floats)
+  t->partial = static_cast<float*>(dev_alloc(sizeof(float) * (Pn + 8 + 512), s));
   t->pmin = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * Pn, s));
   t->col = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * mn, s));
   if (t->weighted) t->w = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * mn, s));

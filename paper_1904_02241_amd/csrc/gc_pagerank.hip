@@ -141,22 +141,38 @@ constexpr int kSegPad = 4;  // LDS entries past the position table read by seek_
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t partial_rsrc(float* partial, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(partial, 0, static_cast<int>(bytes), 0x00020000);
 }
-constexpr uint32_t kDropOffset = 0x80000000u;  // past any resource size below 2^31
 
 __device__ __forceinline__ void partial_store(__amdgpu_buffer_rsrc_t out, uint32_t off, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), out, off, 0, 0);
 }
 
-// One step of a wave-wide segmented inclusive scan of (F, A) pairs, the
-// value moved between lanes by a DPP control (lanes with no source receive
-// the identity (0, 0)): (F1, A1) then (F2, A2) gives (F1 | F2, F2 ? A2 : A1 + A2).
+constexpr int kStoresPerTile = 8;  // 5 + 3 stores of the two staging passes
+
+// kStoresPerTile stores the hardware drops (offsets past any resource size
+// below 2^31, distinct so that none is a dead store of another).
+__device__ __forceinline__ void drop_stores(__amdgpu_buffer_rsrc_t out) {
+#pragma unroll
+  for (int i = 0; i < kStoresPerTile; ++i) __builtin_amdgcn_raw_buffer_store_b32(0u, out, 0x80000000u + 4u * i, 0, 0);
+}
+
+// Lanes of the wave selected by a mask held in scalar registers.
+__device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+
+// Value a DPP control moves into each lane (lanes with no source get 0).
 template <int kCtrl, int kRowMask>
-__device__ __forceinline__ void seg_scan_step(double& A, int& F) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(A), kCtrl, kRowMask, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(A), kCtrl, kRowMask, 0xF, false);
-  const int f = __builtin_amdgcn_update_dpp(0, F, kCtrl, kRowMask, 0xF, false);
-  if (!F) A += __hiloint2double(hi, lo);
-  F |= f;
+__device__ __forceinline__ float dpp_moved(float a) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(a), kCtrl, kRowMask, 0xF, false));
+}
+
+// One step of a wave-wide segmented inclusive scan: a lane that has met no
+// head yet within the reach of the steps so far (not in F) adds the value
+// the DPP control moves in. F itself is kept as a lane mask in scalar
+// registers and widened by the caller after each step.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ void seg_scan_step(float& A, uint64_t F) {
+  const float s = A + dpp_moved<kCtrl, kRowMask>(A);
+  A = lane_in(F) ? A : s;
 }
 
 // DPP controls (gfx9): shift right by n lanes inside each row of 16, copy
@@ -167,22 +183,50 @@ constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x1
 
 // What a wave carries from one tile of its range to the next: the running
 // sum of the row still open at the tile's end (when that row is one the wave
-// must write) and a cursor into the chunk's position table with the next
-// boundaries and shifts cached in registers.
+// must write), a window of 64 entries of the chunk's position table held one
+// per lane, and a cursor into it with the next boundaries and shifts in
+// scalar registers.
 struct PullCarry {
   double open = 0.0;
   int32_t open_row = -1;           // >= 0 when the wave owes that row's sum
-  int32_t jc = 0;                  // sb[jc] <= every row the wave still writes
+  int32_t jw = 0;                  // first table entry of the window
+  int32_t sbw, sdw;                // lane l: sb[jw + l], sd[jw + l] (past the table: its last spare)
+  int32_t jc = 0;                  // sb[jc] <= every row the wave still writes; jc - jw <= 60
   int32_t b1, b2, b3, d0, d1, d2;  // sb[jc+1..jc+3], sd[jc..jc+2]
 };
 
-__device__ __forceinline__ void load_cursor(const int32_t* sb, const int32_t* sd, PullCarry& c) {
-  c.b1 = sb[c.jc + 1];
-  c.b2 = sb[c.jc + 2];
-  c.b3 = sb[c.jc + 3];
-  c.d0 = sd[c.jc];
-  c.d1 = sd[c.jc + 1];
-  c.d2 = sd[c.jc + 2];
+__device__ __forceinline__ void load_window(const int32_t* sb, const int32_t* sd, int32_t ns, int lane,
+                                            PullCarry& c) {
+  const int32_t i = min(c.jw + lane, ns + kSegPad - 1);
+  c.sbw = sb[i];
+  c.sdw = sd[i];
+}
+
+__device__ __forceinline__ void cursor_from_window(PullCarry& c) {
+  const int32_t o = c.jc - c.jw;
+  c.b1 = __builtin_amdgcn_readlane(c.sbw, o + 1);
+  c.b2 = __builtin_amdgcn_readlane(c.sbw, o + 2);
+  c.b3 = __builtin_amdgcn_readlane(c.sbw, o + 3);
+  c.d0 = __builtin_amdgcn_readlane(c.sdw, o);
+  c.d1 = __builtin_amdgcn_readlane(c.sdw, o + 1);
+  c.d2 = __builtin_amdgcn_readlane(c.sdw, o + 2);
+}
+
+// Moves the cursor to the range holding row r (r >= sb[jc]): the count of
+// window entries at or below r, restarting the window when the cursor and
+// the three boundaries after it would not fit in it.
+__device__ __forceinline__ void seek_cursor(const int32_t* sb, const int32_t* sd, int32_t ns, int lane, int32_t r,
+                                            PullCarry& c) {
+  for (;;) {
+    const int32_t cnt = __popcll(__ballot(c.sbw <= r));  // >= 1: sb[jw] <= r
+    if (cnt <= kWave - 3) {
+      c.jc = c.jw + cnt - 1;
+      break;
+    }
+    c.jw += cnt - 1;  // advances by at least 61; entries past the table are INT32_MAX, so this ends
+    load_window(sb, sd, ns, lane, c);
+  }
+  cursor_from_window(c);
 }
 
 // Sum over the tiles after tile q of the row open at q's end, up to its end
@@ -207,57 +251,111 @@ __device__ double finish_open_row(const uint16_t* __restrict__ col16, const gc_h
   }
 }
 
-__device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, int lane, const float* slice,
-                                                 const int32_t* sb, const int32_t* sd, int32_t r0, int32_t r1,
-                                                 PullCarry& cr, __amdgpu_buffer_rsrc_t out, float* stage) {
+// Keeps a tile's registers and gathered values allocated up to this point.
+__device__ __forceinline__ void hold_live(const WaveTile& t, const float (&x)[kArcsPerLane]) {
+  asm volatile("" ::"v"(t.cols), "v"(t.hw));
+#pragma unroll
+  for (int e = 0; e < kArcsPerLane; ++e) asm volatile("" ::"v"(x[e]));
+}
+
+typedef __attribute__((address_space(3))) const float lds_float;
+
+// The contributions this lane's 8 arcs gather from the block's slice. The
+// kernel declares no static LDS, so its dynamic LDS (and the slice at its
+// start) begins at LDS address 0: a column's byte offset is its address.
+__device__ __forceinline__ void gather_tile(const WaveTile& t, float (&x)[kArcsPerLane]) {
+#pragma unroll
+  for (int e = 0; e < kArcsPerLane; ++e) {
+    const uint32_t col = (t.cols[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+    x[e] = *reinterpret_cast<lds_float*>(static_cast<uintptr_t>(col << 2));
+  }
+}
+
+constexpr uint32_t kPushOut = 1u << 23;  // moves the staging slot of an arc that ends no row past every pass
+
+// Byte offsets (past the store's base) of the stores k < nk of a staging
+// pass: store k holds rows rs + i, i = lo + 64k + lane, written to index
+// i + D0 / D1 / D2 below / from / past the range boundaries i1 and i2
+// (kTwo: i2 lies among the rows written), dropped from iz on. The lane is
+// compared with scalar thresholds; the store's base offset 4(lo + 64k)
+// travels in the scalar offset operand, which the hardware leaves out of
+// its range check, so a dropped lane's offset alone is past the resource.
+template <bool kTwo>
+__device__ __forceinline__ void row_offsets(uint32_t (&off)[kStageRows / kWave], int nk, int lane, int32_t lo,
+                                            int32_t i1, int32_t i2, int32_t iz, int32_t D0, int32_t D1, int32_t D2) {
+  constexpr int32_t kDropIndex = 1 << 29;  // (lane + kDropIndex) * 4 >= 2^31
+#pragma unroll
+  for (int k = 0; k < kStageRows / kWave; ++k) {
+    if (k < nk) {
+      const int32_t base = lo + k * kWave;
+      const bool p1 = lane >= i1 - base, pz = lane >= iz - base;
+      int32_t d = p1 ? D1 : D0;
+      if (kTwo) d = lane >= i2 - base ? D2 : d;
+      d = pz ? kDropIndex : d;
+      off[k] = static_cast<uint32_t>(lane + d) << 2;
+    }
+  }
+}
+
+__device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, const float (&x)[kArcsPerLane], int lane,
+                                                 const int32_t* sb, const int32_t* sd, int32_t ns, int32_t r0,
+                                                 int32_t r1, PullCarry& cr, __amdgpu_buffer_rsrc_t out,
+                                                 float* stage) {
   const uint32_t wlo = t.hw[0], whi = t.hw[1];
   const int32_t wrow = static_cast<int32_t>(t.hw[2]);
   const int32_t ta = __builtin_amdgcn_readfirstlane(wrow);
   const int32_t tz = __builtin_amdgcn_readlane(wrow + __popc(wlo) + __popc(whi), kWave - 1);
+  const uint32_t next_head = __builtin_amdgcn_readlane(static_cast<int32_t>(t.hw[3]), kWave - 1) & 1u;
   // rows the wave writes from this tile: those whose head is here and that
   // belong to the chunk, and the row left open by the previous tile
   const int32_t rz = min(tz, r1);
   const int32_t rmin = cr.open_row >= 0 ? cr.open_row : max(ta, r0);
-  if (rmin < rz && rmin >= cr.b1) {  // advance the range cursor
-    cr.jc = seek_range(sb, cr.jc, rmin);
-    load_cursor(sb, sd, cr);
-  }
-  // this lane's 8 head bits, the bit after them, and the heads before them
-  const int sub = lane & 7, sh = 8 * (sub & 3);
-  const uint32_t half = sub < 4 ? wlo : whi;
-  const uint32_t my8 = (half >> sh) & 0xFFu;
-  const uint32_t after = sub == 7 ? (t.hw[3] & 1u) : sub == 3 ? (whi & 1u) : (half >> (sh + 8)) & 1u;
-  const uint32_t ends = (my8 >> 1) | (after << 7);  // bit e: arc e is its row's last
-  const int32_t first = wrow + (sub < 4 ? 0 : __popc(wlo)) + __popc(half & ((1u << sh) - 1u));
-  // Sums inside the lane's 8 arcs in FP32 (at most 8 terms, one rounding per
-  // add); everything that crosses lanes or tiles in FP64.
-  float sf[kArcsPerLane];
-  float run = 0.0f;
+  if (rmin < rz && rmin >= cr.b1) seek_cursor(sb, sd, ns, lane, rmin, cr);
+  // this lane's 8 head bits and the head bit of the arc after them (bit 8)
+  const int sub = lane & 7;
+  const uint32_t wa = sub < 4 ? wlo : whi, wb = sub < 4 ? whi : t.hw[3];
+  const uint32_t my9 = __builtin_amdgcn_alignbit(wb, wa, 8 * (sub & 3)) & 0x1FFu;
+  const uint32_t my8 = my9 & 0xFFu;
+  const int32_t first = wrow + (sub < 4 ? 0 : __popc(wlo)) + __popc(wa & ((1u << (8 * (sub & 3))) - 1u));
+  // none[e]: all ones when arc e ends no row (the arc after it is no head)
+  uint32_t none[kArcsPerLane];
 #pragma unroll
-  for (int e = 0; e < kArcsPerLane; ++e) {
-    const float x = slice[(t.cols[e >> 1] >> (16 * (e & 1))) & 0xFFFFu];
-    run = ((my8 >> e) & 1u) ? x : run + x;
+  for (int e = 0; e < kArcsPerLane; ++e)
+    none[e] = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int32_t>(~my9), e + 1, 1));
+  // Sums inside the lane's 8 arcs in FP32: sf[e] runs from the row's start
+  // (or the lane's first arc) to arc e; the run carries over arc e - 1 (its
+  // bits masked to +0.0 otherwise) when that arc ends no row.
+  float sf[kArcsPerLane];
+  float run = x[0];
+  sf[0] = run;
+#pragma unroll
+  for (int e = 1; e < kArcsPerLane; ++e) {
+    run = x[e] + __uint_as_float(__float_as_uint(run) & none[e - 1]);
     sf[e] = run;
   }
-  // segmented inclusive scan of the lanes' open sums (flag: lane holds a head)
-  double A = static_cast<double>(run);
-  int F = my8 != 0u;
+  // Segmented inclusive scan of the lanes' open sums across the wave (FP32;
+  // the flag of a lane is whether it holds a head). The flags live in a
+  // scalar lane mask, widened after each step the way the DPP moves data.
+  const uint64_t H = __ballot(my8 != 0u);
+  float A = run;
+  uint64_t F = H;
   seg_scan_step<kDppRowShr1, 0xF>(A, F);
+  F |= (F << 1) & 0xFFFEFFFEFFFEFFFEull;
   seg_scan_step<kDppRowShr2, 0xF>(A, F);
+  F |= (F << 2) & 0xFFFCFFFCFFFCFFFCull;
   seg_scan_step<kDppRowShr4, 0xF>(A, F);
+  F |= (F << 4) & 0xFFF0FFF0FFF0FFF0ull;
   seg_scan_step<kDppRowShr8, 0xF>(A, F);
+  F |= (F << 8) & 0xFF00FF00FF00FF00ull;
   seg_scan_step<kDppRowBcast15, 0xA>(A, F);
+  F |= ((F & (1ull << 15)) ? 0x00000000FFFF0000ull : 0ull) | ((F & (1ull << 47)) ? 0xFFFF000000000000ull : 0ull);
   seg_scan_step<kDppRowBcast31, 0xC>(A, F);
-  double carry = __hiloint2double(
-      __builtin_amdgcn_update_dpp(0, __double2hiint(A), kDppWaveShr1, 0xF, 0xF, false),
-      __builtin_amdgcn_update_dpp(0, __double2loint(A), kDppWaveShr1, 0xF, 0xF, false));
-  const int Fx = __builtin_amdgcn_update_dpp(0, F, kDppWaveShr1, 0xF, 0xF, false);
-  if (!Fx) carry += cr.open;  // no head before this lane in the tile: the open row continues
-  // The lane's arcs before its first head belong to a row begun earlier; only
-  // the last of them (just before that head, or the lane's last arc) can end
-  // it, and it gets the carried sum (rounded to FP32 once, then one FP32 add).
-  const int fh = my8 ? __builtin_ctz(my8) : kArcsPerLane;
-  const float carry_f = static_cast<float>(carry);
+  // lane l: the open sum at the end of lane l - 1, plus (in FP64) the sum
+  // carried from earlier tiles when no lane before l holds a head
+  const float c = dpp_moved<kDppWaveShr1, 0xF>(A);
+  const uint64_t past_head = H ? ((~0ull << __builtin_ctzll(H)) << 1) : 0ull;
+  const float with_open = static_cast<float>(static_cast<double>(c) + cr.open);
+  const float carry = lane_in(past_head) ? c : with_open;
   // The rows this tile completes form one run [rs, re): the open row (if
   // the wave owes it) and every row of the chunk with its head here, except
   // the last one when it continues into the next tile. Their sums are
@@ -266,28 +364,30 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, int lane, co
   // row into its range-major index. Every lane always issues the same 8
   // stores (unused ones get a dropped offset), so the compiler's count of
   // outstanding memory operations stays exact.
-  const uint32_t next_head = __builtin_amdgcn_readlane(static_cast<int32_t>(t.hw[3]), kWave - 1) & 1u;
   const int32_t rs = rmin;
   const int32_t re = min(rz, next_head ? tz : tz - 1);
-  // Staging slot of each element, computed once: for an element that ends
-  // a row, the row's offset from rs (as unsigned: rows before rs wrap to
-  // huge values); otherwise none. Rows at or past re may land in slots that
-  // are never read back (the write-out stops at re), so only the row ends
-  // need testing here.
+  // Staging slot of each arc: its row's offset from rs (as unsigned: rows
+  // before rs wrap to huge values) when the arc ends its row, pushed out by
+  // kPushOut otherwise. Every arc writes its run to the staging; those with
+  // no row of the pass go to one of the wave's spare slots.
   uint32_t slot[kArcsPerLane];
-  float val[kArcsPerLane];
   {
-    int32_t r = first - 1;
+    uint32_t r = static_cast<uint32_t>(first - 1 - rs) + (my9 & 1u);  // offset of arc 0's row
 #pragma unroll
     for (int e = 0; e < kArcsPerLane; ++e) {
-      r += static_cast<int32_t>((my8 >> e) & 1u);
-      slot[e] = ((ends >> e) & 1u) ? static_cast<uint32_t>(r - rs) : 0xFFFFFFFFu;
-      val[e] = e < fh ? sf[e] + carry_f : sf[e];
+      slot[e] = (none[e] & kPushOut) | r;  // r < 512, or wrapped past 2^31: the OR acts as an add
+      r += 1u + none[e];
     }
   }
+  // The row carried into the lane (arc 0 is not a head) ends here when a
+  // later arc, or the next lane's first, is a head: its staged run then
+  // still lacks the carried sum, which one LDS add supplies.
+  const uint32_t cslot = ((my9 & 1u) == 0u && my9 != 0u) ? static_cast<uint32_t>(first - 1 - rs) : 0xFFFFFFFFu;
   // rows at or past the cached boundary b3 (three or more ranges in one tile)
   // are stored on the slow path below; the others index with the cursor
   const int32_t i1 = cr.b1 - rs, i2 = cr.b2 - rs, iz = min(re, cr.b3) - rs;
+  const int32_t D0 = rs + cr.d0, D1 = rs + cr.d1, D2 = rs + cr.d2;  // row rs + i goes to index i + D
+  const uint32_t spare = kStageRows + (lane & (kStageSpare - 1));
   // Two passes over the staging: rows [0, 320) of the run, then [320, 512)
   // (a tile completes at most 512 rows; the second pass's LDS work is
   // skipped when it has no rows, its 3 stores are then dropped).
@@ -295,42 +395,45 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, int lane, co
   for (int pass = 0; pass < 2; ++pass) {
     const uint32_t lo = pass == 0 ? 0u : static_cast<uint32_t>(kStageRows);
     const int n = pass == 0 ? kStageRows : kTileRowsMax - kStageRows;  // rows of this pass
+    // slots of the pass run [0, n); anything at or past n lands in [n, 336),
+    // which this pass does not read back
+    const uint32_t cap = pass == 0 ? spare : spare - static_cast<uint32_t>(kStageRows - n);
     if (pass == 0 || re - rs > kStageRows) {  // uniform
-      // every element writes (no branch): rows of this pass to their slot,
-      // the rest to one of the wave's spare slots
 #pragma unroll
-      for (int e = 0; e < kArcsPerLane; ++e) {
-        const uint32_t k = slot[e] - lo;
-        stage[k < static_cast<uint32_t>(n) ? k : kStageRows + (lane & (kStageSpare - 1))] = val[e];
-      }
+      for (int e = 0; e < kArcsPerLane; ++e) stage[min(slot[e] - lo, cap)] = sf[e];
+      __hip_atomic_fetch_add(stage + min(cslot - lo, cap), carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
       wave_lds_fence();
     }
     float v[kStageRows / kWave];
 #pragma unroll
     for (int k = 0; k < n / kWave; ++k) v[k] = stage[k * kWave + lane];
+    // the offsets take one of two branches; the stores follow unconditionally
+    // (stores inside the branches would leave the compiler unable to count
+    // them on every path)
+    uint32_t off[kStageRows / kWave];
+    if (i2 < iz) row_offsets<true>(off, n / kWave, lane, static_cast<int32_t>(lo), i1, i2, iz, D0, D1, D2);
+    else row_offsets<false>(off, n / kWave, lane, static_cast<int32_t>(lo), i1, i2, iz, D0, D1, D2);
 #pragma unroll
-    for (int k = 0; k < n / kWave; ++k) {
-      const int32_t i = static_cast<int32_t>(lo) + k * kWave + lane;  // row rs + i
-      const int32_t d = cr.d0 + (i >= i1) * (cr.d1 - cr.d0) + (i >= i2) * (cr.d2 - cr.d1);  // arithmetic keeps cr in registers
-      const uint32_t off = i < iz ? 4u * static_cast<uint32_t>(rs + i + d) : kDropOffset;
-      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[k]), out, off, 0, 0);
-    }
+    for (int k = 0; k < n / kWave; ++k)
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[k]), out, off[k], 4 * (static_cast<int32_t>(lo) + k * kWave), 0);
     wave_lds_fence();  // the staging is rewritten next
   }
   if (re > cr.b3) {  // uniform, rare: store the rows at or past b3
+    const int fh = my8 ? __builtin_ctz(my8) : kArcsPerLane;
 #pragma unroll
     for (int e = 0; e < kArcsPerLane; ++e) {
       const int32_t r = rs + static_cast<int32_t>(slot[e]);
       if (slot[e] < static_cast<uint32_t>(re - rs) && r >= cr.b3) {
         const int32_t j = seek_range(sb, cr.jc, r);
-        partial_store(out, 4u * static_cast<uint32_t>(r + sd[j]), val[e]);
+        partial_store(out, 4u * static_cast<uint32_t>(r + sd[j]), e < fh ? sf[e] + carry : sf[e]);
       }
     }
   }
-  // the row open at the tile's end, if the wave writes it
-  const double mytail = fh < kArcsPerLane ? static_cast<double>(run) : static_cast<double>(run) + carry;
-  const double tail = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(mytail), kWave - 1),
-                                       __builtin_amdgcn_readlane(__double2loint(mytail), kWave - 1));
+  // the row open at the tile's end, if the wave writes it (lane 63 holds its
+  // open sum; the earlier tiles' part joins in FP64)
+  const float run63 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(run), kWave - 1));
+  const float c63 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c), kWave - 1));
+  const double tail = static_cast<double>((H >> 63) ? run63 : run63 + c63) + (H ? 0.0 : cr.open);
   const int32_t ro = tz - 1;  // the row of the tile's last arc
   const bool owe = !next_head && (tz > ta ? (ro >= r0 && ro < r1) : cr.open_row >= 0);
   cr.open_row = owe ? ro : -1;
@@ -360,7 +463,20 @@ __global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
     const int32_t cnt = min(W, n - v0);
     const float4* c4 = reinterpret_cast<const float4*>(c + v0);  // v0 is a multiple of W >= 2^10
     float4* s4 = reinterpret_cast<float4*>(slice);
-    for (int32_t i = threadIdx.x; i < (cnt >> 2); i += kLdsThreads) s4[i] = c4[i];
+    // all of a thread's loads are issued before its first LDS write (one
+    // memory round trip for the whole slice)
+    constexpr int kFill = gcx::kLdsMaxWidth / 4 / kLdsThreads;
+    float4 f[kFill];
+#pragma unroll
+    for (int k = 0; k < kFill; ++k) {
+      const int32_t i = threadIdx.x + k * kLdsThreads;
+      if (i < (cnt >> 2)) f[k] = c4[i];
+    }
+#pragma unroll
+    for (int k = 0; k < kFill; ++k) {
+      const int32_t i = threadIdx.x + k * kLdsThreads;
+      if (i < (cnt >> 2)) s4[i] = f[k];
+    }
     for (int32_t i = (cnt & ~3) + threadIdx.x; i < cnt; i += kLdsThreads) slice[i] = c[v0 + i];
     const int2* sg = seg + static_cast<int64_t>(b) * (R + 1) + j0;
     for (int32_t i = threadIdx.x; i < ns + kSegPad; i += kLdsThreads) {
@@ -382,22 +498,55 @@ __global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
   const int32_t qz = q0 + static_cast<int32_t>(static_cast<int64_t>(nt) * (wid + 1) / kLdsWaves) - 1;
   if (qa > qz) return;
   PullCarry cr;
-  load_cursor(sb, sd, cr);
-  // three tiles in registers: one is reduced while the next two load
+  load_window(sb, sd, ns, lane, cr);
+  cursor_from_window(cr);
+  // Four tiles in registers: while one is reduced, the next one's gathers
+  // and the two after it's loads are in flight; the tile just reduced is
+  // refilled once its stores are issued, so the youngest memory operations
+  // at every wait are tile loads. Its registers (and its gathered values)
+  // are held live until then, so the compiler cannot hand them to the
+  // stores as temporaries (a load into a register a pending store still
+  // reads would wait for that store). Each tile issues exactly
+  // kStoresPerTile stores, and dropped stores after the prologue's loads
+  // give the compiler's count of memory operations after each load at
+  // least its steady-state value on entry.
   int32_t q = qa;
   WaveTile t0 = load_wave_tile(col16, heads, q, lane);
   WaveTile t1 = load_wave_tile(col16, heads, min(q + 1, qz), lane);
-  WaveTile t2;
-#define GC_PULL_STEP(cur, k, refill)                                 \
-  refill = load_wave_tile(col16, heads, min(q + (k + 2), qz), lane); \
-  reduce_wave_tile(cur, lane, slice, sb, sd, r0, r1, cr, out, stage); \
-  if (q + (k + 1) > qz) break;
-  for (;;) {
-    GC_PULL_STEP(t0, 0, t2)
-    GC_PULL_STEP(t1, 1, t0)
-    GC_PULL_STEP(t2, 2, t1)
-    q += 3;
+  WaveTile t2 = load_wave_tile(col16, heads, min(q + 2, qz), lane);
+  WaveTile t3 = load_wave_tile(col16, heads, min(q + 3, qz), lane);
+  drop_stores(out);
+  drop_stores(out);
+  drop_stores(out);
+  float x0[kArcsPerLane], x1[kArcsPerLane];
+  gather_tile(t0, x0);
+  // Whole rounds of four tiles run in a loop with no exit inside (an exit
+  // merged into the loop's back edge would make the compiler assume a path
+  // with fewer memory operations and wait longer); the last nt % 4 tiles
+  // follow it.
+#define GC_PULL_STEP(cur, xcur, nxt, xnxt, k)                           \
+  gather_tile(nxt, xnxt);                                               \
+  reduce_wave_tile(cur, xcur, lane, sb, sd, ns, r0, r1, cr, out, stage); \
+  hold_live(cur, xcur);                                                 \
+  cur = load_wave_tile(col16, heads, min(q + (k + 4), qz), lane);
+  const int32_t nw = qz - qa + 1;
+  for (int32_t round = 0; round < nw / 4; ++round) {
+    GC_PULL_STEP(t0, x0, t1, x1, 0)
+    GC_PULL_STEP(t1, x1, t2, x0, 1)
+    GC_PULL_STEP(t2, x0, t3, x1, 2)
+    GC_PULL_STEP(t3, x1, t0, x0, 3)
+    q += 4;
   }
+  const int32_t rest = nw % 4;
+  if (rest > 0) {
+    gather_tile(t1, x1);
+    reduce_wave_tile(t0, x0, lane, sb, sd, ns, r0, r1, cr, out, stage);
+  }
+  if (rest > 1) {
+    gather_tile(t2, x0);
+    reduce_wave_tile(t1, x1, lane, sb, sd, ns, r0, r1, cr, out, stage);
+  }
+  if (rest > 2) reduce_wave_tile(t2, x0, lane, sb, sd, ns, r0, r1, cr, out, stage);
 #undef GC_PULL_STEP
   if (cr.open_row >= 0) {  // the range's last row continues past it
     const double v = cr.open + finish_open_row(col16, heads, slice, qz, lane);
