@@ -322,17 +322,12 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, const float 
 #pragma unroll
   for (int e = 0; e < kArcsPerLane; ++e)
     none[e] = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int32_t>(~my9), e + 1, 1));
-  // Sums inside the lane's 8 arcs in FP32: sf[e] runs from the row's start
-  // (or the lane's first arc) to arc e; the run carries over arc e - 1 (its
-  // bits masked to +0.0 otherwise) when that arc ends no row.
-  float sf[kArcsPerLane];
+  // The lane's open sum in FP32: a run over its 8 arcs from the row's start
+  // (or the lane's first arc) that carries over arc e - 1 (its bits masked
+  // to +0.0 otherwise) when that arc ends no row.
   float run = x[0];
-  sf[0] = run;
 #pragma unroll
-  for (int e = 1; e < kArcsPerLane; ++e) {
-    run = x[e] + __uint_as_float(__float_as_uint(run) & none[e - 1]);
-    sf[e] = run;
-  }
+  for (int e = 1; e < kArcsPerLane; ++e) run = x[e] + __uint_as_float(__float_as_uint(run) & none[e - 1]);
   // Segmented inclusive scan of the lanes' open sums across the wave (FP32;
   // the flag of a lane is whether it holds a head). The flags live in a
   // scalar lane mask, widened after each step the way the DPP moves data.
@@ -379,10 +374,22 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, const float 
       r += 1u + none[e];
     }
   }
-  // The row carried into the lane (arc 0 is not a head) ends here when a
-  // later arc, or the next lane's first, is a head: its staged run then
-  // still lacks the carried sum, which one LDS add supplies.
-  const uint32_t cslot = ((my9 & 1u) == 0u && my9 != 0u) ? static_cast<uint32_t>(first - 1 - rs) : 0xFFFFFFFFu;
+  // The staged runs: the same masked run again, now starting from the
+  // carried sum unless arc 0 is a head (it reaches exactly the arcs before
+  // the lane's first head, i.e. the end of the row carried into the lane;
+  // an LDS atomic add of the carry to that row's slot costs more than these
+  // instructions).
+  float st[kArcsPerLane];
+  {
+    const uint32_t cont0 = static_cast<uint32_t>(__builtin_amdgcn_sbfe(static_cast<int32_t>(~my9), 0, 1));
+    float r = x[0] + __uint_as_float(__float_as_uint(carry) & cont0);
+    st[0] = r;
+#pragma unroll
+    for (int e = 1; e < kArcsPerLane; ++e) {
+      r = x[e] + __uint_as_float(__float_as_uint(r) & none[e - 1]);
+      st[e] = r;
+    }
+  }
   // rows at or past the cached boundary b3 (three or more ranges in one tile)
   // are stored on the slow path below; the others index with the cursor
   const int32_t i1 = cr.b1 - rs, i2 = cr.b2 - rs, iz = min(re, cr.b3) - rs;
@@ -400,8 +407,7 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, const float 
     const uint32_t cap = pass == 0 ? spare : spare - static_cast<uint32_t>(kStageRows - n);
     if (pass == 0 || re - rs > kStageRows) {  // uniform
 #pragma unroll
-      for (int e = 0; e < kArcsPerLane; ++e) stage[min(slot[e] - lo, cap)] = sf[e];
-      __hip_atomic_fetch_add(stage + min(cslot - lo, cap), carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+      for (int e = 0; e < kArcsPerLane; ++e) stage[min(slot[e] - lo, cap)] = st[e];
       wave_lds_fence();
     }
     float v[kStageRows / kWave];
@@ -419,13 +425,12 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, const float 
     wave_lds_fence();  // the staging is rewritten next
   }
   if (re > cr.b3) {  // uniform, rare: store the rows at or past b3
-    const int fh = my8 ? __builtin_ctz(my8) : kArcsPerLane;
 #pragma unroll
     for (int e = 0; e < kArcsPerLane; ++e) {
       const int32_t r = rs + static_cast<int32_t>(slot[e]);
       if (slot[e] < static_cast<uint32_t>(re - rs) && r >= cr.b3) {
         const int32_t j = seek_range(sb, cr.jc, r);
-        partial_store(out, 4u * static_cast<uint32_t>(r + sd[j]), e < fh ? sf[e] + carry : sf[e]);
+        partial_store(out, 4u * static_cast<uint32_t>(r + sd[j]), st[e]);
       }
     }
   }
@@ -463,21 +468,19 @@ __global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
     const int32_t cnt = min(W, n - v0);
     const float4* c4 = reinterpret_cast<const float4*>(c + v0);  // v0 is a multiple of W >= 2^10
     float4* s4 = reinterpret_cast<float4*>(slice);
-    // all of a thread's loads are issued before its first LDS write (one
-    // memory round trip for the whole slice)
     constexpr int kFill = gcx::kLdsMaxWidth / 4 / kLdsThreads;
-    float4 f[kFill];
+    if (cnt == gcx::kLdsMaxWidth) {  // uniform: a full block of the widest kind
+      // all of a thread's loads are issued before its first LDS write (one
+      // memory round trip for the whole slice)
+      float4 f[kFill];
 #pragma unroll
-    for (int k = 0; k < kFill; ++k) {
-      const int32_t i = threadIdx.x + k * kLdsThreads;
-      if (i < (cnt >> 2)) f[k] = c4[i];
-    }
+      for (int k = 0; k < kFill; ++k) f[k] = c4[threadIdx.x + k * kLdsThreads];
 #pragma unroll
-    for (int k = 0; k < kFill; ++k) {
-      const int32_t i = threadIdx.x + k * kLdsThreads;
-      if (i < (cnt >> 2)) s4[i] = f[k];
+      for (int k = 0; k < kFill; ++k) s4[threadIdx.x + k * kLdsThreads] = f[k];
+    } else {
+      for (int32_t i = threadIdx.x; i < (cnt >> 2); i += kLdsThreads) s4[i] = c4[i];
+      for (int32_t i = (cnt & ~3) + threadIdx.x; i < cnt; i += kLdsThreads) slice[i] = c[v0 + i];
     }
-    for (int32_t i = (cnt & ~3) + threadIdx.x; i < cnt; i += kLdsThreads) slice[i] = c[v0 + i];
     const int2* sg = seg + static_cast<int64_t>(b) * (R + 1) + j0;
     for (int32_t i = threadIdx.x; i < ns + kSegPad; i += kLdsThreads) {
       if (i <= ns) {
