@@ -153,9 +153,9 @@ constexpr int32_t kLdsChunkArcs = 1 << 16;
 // 160 KB (two resident work-groups) for slices up to 2^13 floats, all of it
 // for wider ones.
 inline int32_t lds_budget(int32_t W) { return W >= (1 << 14) ? 160 * 1024 - 512 : 80 * 1024 - 512; }
-// LDS bytes of the pull's per-wave output staging (16 waves x (320 rows +
+// LDS bytes of the pull's per-wave output staging (16 waves x (384 rows +
 // 16 spare slots) floats).
-constexpr int32_t kLdsStageBytes = 16 * (320 + 16) * 4;
+constexpr int32_t kLdsStageBytes = 16 * (384 + 16) * 4;
 // Largest range table (entries) that fits beside a W-float slice and the
 // staging (with 8 entries of padding).
 inline int32_t lds_seg_cap(int32_t W) { return ((lds_budget(W) - 4 * W - kLdsStageBytes) / 4 - 8) / 2; }

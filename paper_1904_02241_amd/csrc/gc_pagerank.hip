@@ -14,6 +14,8 @@
 
 #include <climits>
 
+#include <type_traits>
+
 #include "gc_device.h"
 #include "gc_internal.h"
 
@@ -95,7 +97,7 @@ constexpr int kLdsThreads = 1024;
 constexpr int kLdsWaves = kLdsThreads / kWave;
 constexpr int kArcsPerLane = 8;
 constexpr int kWaveTile = kArcsPerLane * kWave;  // 512 arcs, 8 head words
-constexpr int kStageRows = 320;                  // staged row sums per wave in the first pass
+constexpr int kStageRows = 384;                  // staged row sums per wave in the first pass
 constexpr int kTileRowsMax = 512;                // rows one tile can complete
 constexpr int kStageSpare = 16;                  // spare slots per wave for elements that end no staged row
 static_assert(kStageRows % kWave == 0 && (kTileRowsMax - kStageRows) % kWave == 0 &&
@@ -146,7 +148,7 @@ __device__ __forceinline__ void partial_store(__amdgpu_buffer_rsrc_t out, uint32
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), out, off, 0, 0);
 }
 
-constexpr int kStoresPerTile = 8;  // 5 + 3 stores of the two staging passes
+constexpr int kStoresPerTile = 6;  // stores of the first staging pass, issued by every tile
 
 // kStoresPerTile stores the hardware drops (offsets past any resource size
 // below 2^31, distinct so that none is a dead store of another).
@@ -356,8 +358,8 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, const float 
   // the last one when it continues into the next tile. Their sums are
   // staged in LDS by row and written back so that store k of the wave holds
   // rows rs + 64k .. rs + 64k + 63 (coalesced); the position table turns a
-  // row into its range-major index. Every lane always issues the same 8
-  // stores (unused ones get a dropped offset), so the compiler's count of
+  // row into its range-major index. Every lane issues the same stores
+  // (unused ones get a dropped offset), so the compiler's count of
   // outstanding memory operations stays exact.
   const int32_t rs = rmin;
   const int32_t re = min(rz, next_head ? tz : tz - 1);
@@ -395,22 +397,21 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, const float 
   const int32_t i1 = cr.b1 - rs, i2 = cr.b2 - rs, iz = min(re, cr.b3) - rs;
   const int32_t D0 = rs + cr.d0, D1 = rs + cr.d1, D2 = rs + cr.d2;  // row rs + i goes to index i + D
   const uint32_t spare = kStageRows + (lane & (kStageSpare - 1));
-  // Two passes over the staging: rows [0, 320) of the run, then [320, 512)
-  // (a tile completes at most 512 rows; the second pass's LDS work is
-  // skipped when it has no rows, its 3 stores are then dropped).
+  // Staging passes: rows [0, 384) of the run in every tile (6 stores),
+  // rows [384, 512) only in tiles that complete more rows (a tile completes
+  // at most 512). Every tile thus issues at least kStoresPerTile stores, the
+  // count the compiler's memory waits assume.
+  auto stage_pass = [&](auto pass_tag) {
+    constexpr int pass = decltype(pass_tag)::value;
+    constexpr uint32_t lo = pass == 0 ? 0u : static_cast<uint32_t>(kStageRows);
+    constexpr int n = pass == 0 ? kStageRows : kTileRowsMax - kStageRows;  // rows of this pass
+    // slots of the pass run [0, n); anything at or past n lands in
+    // [n, n + 16), which this pass does not read back
+    const uint32_t cap = spare - static_cast<uint32_t>(kStageRows - n);
 #pragma unroll
-  for (int pass = 0; pass < 2; ++pass) {
-    const uint32_t lo = pass == 0 ? 0u : static_cast<uint32_t>(kStageRows);
-    const int n = pass == 0 ? kStageRows : kTileRowsMax - kStageRows;  // rows of this pass
-    // slots of the pass run [0, n); anything at or past n lands in [n, 336),
-    // which this pass does not read back
-    const uint32_t cap = pass == 0 ? spare : spare - static_cast<uint32_t>(kStageRows - n);
-    if (pass == 0 || re - rs > kStageRows) {  // uniform
-#pragma unroll
-      for (int e = 0; e < kArcsPerLane; ++e) stage[min(slot[e] - lo, cap)] = st[e];
-      wave_lds_fence();
-    }
-    float v[kStageRows / kWave];
+    for (int e = 0; e < kArcsPerLane; ++e) stage[min(slot[e] - lo, cap)] = st[e];
+    wave_lds_fence();
+    float v[n / kWave];
 #pragma unroll
     for (int k = 0; k < n / kWave; ++k) v[k] = stage[k * kWave + lane];
     // the offsets take one of two branches; the stores follow unconditionally
@@ -423,7 +424,9 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, const float 
     for (int k = 0; k < n / kWave; ++k)
       __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[k]), out, off[k], 4 * (static_cast<int32_t>(lo) + k * kWave), 0);
     wave_lds_fence();  // the staging is rewritten next
-  }
+  };
+  stage_pass(std::integral_constant<int, 0>());
+  if (re - rs > kStageRows) stage_pass(std::integral_constant<int, 1>());  // uniform
   if (re > cr.b3) {  // uniform, rare: store the rows at or past b3
 #pragma unroll
     for (int e = 0; e < kArcsPerLane; ++e) {
@@ -618,16 +621,20 @@ __global__ __launch_bounds__(kMergeThreads) void k_pr_merge_stream(const int32_t
   typedef float f4 __attribute__((ext_vector_type(4)));
   const f4* p4 = reinterpret_cast<const f4*>(partial);
   const uint64_t* i4 = reinterpret_cast<const uint64_t*>(id16s);
+  // kU groups of 4 entries per thread and step; the next step's loads are
+  // issued before this step's LDS adds (two register sets in turn)
   constexpr int kU = 4;
-  for (int32_t g = g0 + static_cast<int32_t>(threadIdx.x); g < g1; g += kMergeThreads * kU) {
-    f4 p[kU];
-    uint64_t id[kU];
+  f4 pa[kU], pb[kU];
+  uint64_t ia[kU], ib[kU];
+  auto load = [&](int32_t g, f4 (&p)[kU], uint64_t (&id)[kU]) {
 #pragma unroll
     for (int k = 0; k < kU; ++k) {
       const int32_t gg = min(g + k * kMergeThreads, g1 - 1);  // clamped, masked below
       p[k] = gcd::ld_stream(p4 + gg);
       id[k] = gcd::ld_stream(i4 + gg);
     }
+  };
+  auto add = [&](int32_t g, const f4 (&p)[kU], const uint64_t (&id)[kU]) {
 #pragma unroll
     for (int k = 0; k < kU; ++k) {
       const int32_t e0 = 4 * (g + k * kMergeThreads);
@@ -637,6 +644,17 @@ __global__ __launch_bounds__(kMergeThreads) void k_pr_merge_stream(const int32_t
         if (e0 + e >= a && e0 + e < z)
           atomicAdd(&acc[(id[k] >> (16 * e)) & 0xFFFFu], static_cast<double>(pv[e]));
     }
+  };
+  // (loads are clamped to the last group, so they need no branch and the
+  // compiler's count of outstanding loads holds on every path)
+  constexpr int32_t kStep = kMergeThreads * kU;
+  int32_t g = g0 + static_cast<int32_t>(threadIdx.x);
+  if (g0 < g1) load(g, pa, ia);  // uniform
+  for (; g < g1; g += 2 * kStep) {
+    load(g + kStep, pb, ib);
+    add(g, pa, ia);
+    load(g + 2 * kStep, pa, ia);
+    add(g + kStep, pb, ib);
   }
   __syncthreads();
   const int32_t v0 = blockIdx.x * K;
