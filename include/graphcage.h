@@ -166,6 +166,24 @@ int tocab_free(gc_tocab t);
 int pagerank_iter(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, int32_t dangling,
                   const float* rank_in, float* rank_out, int32_t iters, hipStream_t stream);
 
+/* PageRank until the change between consecutive iterates is small (the
+ * "run until converged" protocol of Section 4; the paper leaves the test
+ * unstated, the reading taken is the L1 norm): iterates exactly like
+ * pagerank_iter and after iteration k computes
+ *   delta_k = sum_v |r_k[v] - r_{k-1}[v]|   (FP64 over the FP32 iterates,
+ *                                           fused into the update kernels)
+ * stopping after the first k with delta_k <= tol, or after max_iters.
+ * rank_in, rank_out: device float[n], must not overlap; rank_out receives
+ * the last iterate. *iters_out (host) = iterations run; *delta_out (host,
+ * NULL to skip) = the last delta. Synchronises `stream` once per iteration
+ * to read delta_k. The first call on a graph allocates its convergence
+ * buffers (an FP32 iterate and one FP64 slot per update work-group), freed
+ * by graph_free. Errors: GC_EINVAL for bad arguments (tol < 0 or NaN,
+ * max_iters < 1, NULL iters_out, plus pagerank_iter's checks), GC_ENOMEM. */
+int pagerank_converge(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, int32_t dangling,
+                      const float* rank_in, float* rank_out, double tol, int32_t max_iters, int32_t* iters_out,
+                      double* delta_out, hipStream_t stream);
+
 /* Breadth-first search from `source` over out-arcs. depth: device
  * int32[n] out, depth[source] = 0, GC_UNREACHED when unreachable. The pull
  * levels are topology driven with status arrays (Section 3.3): with a

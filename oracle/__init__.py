@@ -58,6 +58,23 @@ def pagerank(n, rowptr, colidx, d=0.85, iters=20, mode=UNIFORM, r0=None):
     return out
 
 
+def pagerank_converge(n, rowptr, colidx, tol, max_iters, d=0.85, mode=UNIFORM, r0=None):
+    """FP64 PageRank run until the L1 change between consecutive iterates,
+    sum_v |r_k[v] - r_{k-1}[v]|, is at most tol (Section 4 runs the methods
+    until they converge; the test itself is not stated there, the L1 norm is
+    the reading taken), or for max_iters iterations. One iteration is the
+    plain definition above. Returns (r_k, k, [delta_1 .. delta_k])."""
+    r = np.full(n, 1.0 / n) if r0 is None else np.ascontiguousarray(r0, dtype=np.float64)
+    deltas = []
+    for _ in range(max_iters):
+        nxt = pagerank(n, rowptr, colidx, d, 1, mode, r0=r)
+        deltas.append(float(np.abs(nxt - r).sum()))
+        r = nxt
+        if deltas[-1] <= tol:
+            break
+    return r, len(deltas), deltas
+
+
 def ppr(n, rowptr, colidx, p, d=0.85, iters=20):
     """FP64 personalised PageRank iterate `iters` from r0 = p."""
     rowptr, colidx = _i32(rowptr), _i32(colidx)

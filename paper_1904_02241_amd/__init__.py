@@ -44,6 +44,8 @@ SIGNATURES = {
     "tocab_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tocab_free": (ctypes.c_int, [_vp]),
     "pagerank_iter": (ctypes.c_int, [_vp, _vp, _i32, _f32, _i32, _vp, _vp, _i32, _vp]),
+    "pagerank_converge": (ctypes.c_int, [_vp, _vp, _i32, _f32, _i32, _vp, _vp, ctypes.c_double, _i32, _p_i32,
+                                         ctypes.POINTER(ctypes.c_double), _vp]),
     "bfs_pull": (ctypes.c_int, [_vp, _vp, _i32, _vp, _p_i32, _u32, _vp]),
     "sssp_pull": (ctypes.c_int, [_vp, _vp, _i32, _vp, _p_i32, _u32, _vp]),
     "gc_sync": (ctypes.c_int, [_vp]),
@@ -274,6 +276,15 @@ def tocab_free(t):
 def pagerank_iter(g, t, dir_if_plain, damping, dangling, rank_in, rank_out, iters, stream=None):
     _check(lib.pagerank_iter(_h(g), _h(t), dir_if_plain, damping, dangling, _ptr(rank_in), _ptr(rank_out), iters,
                              _stream(stream)), "pagerank_iter")
+
+
+def pagerank_converge(g, t, dir_if_plain, damping, dangling, rank_in, rank_out, tol, max_iters, stream=None):
+    """Returns (iterations run, last L1 change)."""
+    iters, delta = ctypes.c_int32(0), ctypes.c_double(0.0)
+    _check(lib.pagerank_converge(_h(g), _h(t), dir_if_plain, damping, dangling, _ptr(rank_in), _ptr(rank_out),
+                                 float(tol), int(max_iters), ctypes.byref(iters), ctypes.byref(delta),
+                                 _stream(stream)), "pagerank_converge")
+    return iters.value, delta.value
 
 
 def bfs_pull(g, t, source, depth, policy=GC_POLICY_PULL, stream=None):

@@ -34,6 +34,12 @@ struct gc_graph_s {
   double* dtotal = nullptr;   // [2] ping-pong dangling totals
   unsigned* counter = nullptr;
   int32_t dpart_slots = 0;
+  // convergence mode (allocated by the first pagerank_converge call): FP64
+  // partials of the L1 change per update work-group, their total, and a
+  // second FP32 iterate
+  double* lpart = nullptr;
+  double* ltotal = nullptr;
+  float* rank_tmp = nullptr;
   // traversal scratch
   uint8_t* front = nullptr;   // status arrays (Section 3.3)
   uint8_t* next = nullptr;
@@ -159,8 +165,18 @@ constexpr int32_t kLdsStageBytes = 16 * (384 + 16) * 4;
 // Largest range table (entries) that fits beside a W-float slice and the
 // staging (with 8 entries of padding).
 inline int32_t lds_seg_cap(int32_t W) { return ((lds_budget(W) - 4 * W - kLdsStageBytes) / 4 - 8) / 2; }
+// Convergence mode of pagerank_run: iterate until the L1 change between
+// consecutive iterates is at most tol (or max_iters); iters / delta report
+// the iterations run and the last change.
+struct Converge {
+  double tol = 0.0;
+  int32_t max_iters = 0;
+  int32_t iters = 0;
+  double delta = 0.0;
+};
 hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int32_t dangling,
-                        const float* rank_in, float* rank_out, int32_t iters, hipStream_t s);
+                        const float* rank_in, float* rank_out, int32_t iters, hipStream_t s,
+                        Converge* cv = nullptr);
 
 // ---- autotuner (gc_autotune.hip) ----
 // Candidate widths start at max(2^12, min_W).

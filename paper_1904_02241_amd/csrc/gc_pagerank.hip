@@ -25,18 +25,30 @@ namespace {
 
 // D for the next iteration: the partials summed in index order by one
 // work-group (deterministic).
-__global__ __launch_bounds__(1024) void k_reduce_dangling(const double* __restrict__ dpart, int32_t count,
-                                                          double* __restrict__ dtotal) {
-  __shared__ double part[1024 / kWave];
+__device__ __forceinline__ double reduce_slots(const double* __restrict__ slots, int32_t count, double* part) {
   double acc = 0.0;
-  for (int32_t i = threadIdx.x; i < count; i += 1024) acc += dpart[i];
+  for (int32_t i = threadIdx.x; i < count; i += 1024) acc += slots[i];
   acc = gcd::wave_sum(acc);
+  __syncthreads();  // part may still be read by a previous call
   if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < 1024 / kWave; ++w) t += part[w];
-    *dtotal = t;
+  double t = 0.0;
+  for (int w = 0; w < 1024 / kWave; ++w) t += part[w];
+  return t;
+}
+
+// Total of the per-work-group dangling partials (and, in convergence mode,
+// of the L1-change partials), in a fixed order.
+__global__ __launch_bounds__(1024) void k_reduce_dangling(const double* __restrict__ dpart, int32_t count,
+                                                          double* __restrict__ dtotal,
+                                                          const double* __restrict__ lpart,
+                                                          double* __restrict__ ltotal) {
+  __shared__ double part[1024 / kWave];
+  const double t = reduce_slots(dpart, count, part);
+  if (threadIdx.x == 0) *dtotal = t;
+  if (lpart) {
+    const double l = reduce_slots(lpart, count, part);
+    if (threadIdx.x == 0) *ltotal = l;
   }
 }
 
@@ -571,13 +583,13 @@ __global__ __launch_bounds__(kThreads) void k_pr_plain_pull(const int32_t* __res
                                                             const float* __restrict__ c_in, Update u) {
   __shared__ float vals[kStageCap];
   const int32_t r0 = tile_row[blockIdx.x], r1 = tile_row[blockIdx.x + 1];
-  double mine = 0.0;
+  double mine = 0.0, dl = 0.0;
   if (r0 < r1) {
     const double D = *u.dtotal_in;
     pull_tile(t_rowptr, t_col, c_in, r0, r1, vals,
-              [&](int32_t v, double s) { mine += update_vertex(u, v, s, D); });
+              [&](int32_t v, double s) { mine += update_vertex(u, v, s, D, dl); });
   }
-  publish_dangling(u, mine);
+  publish_update(u, mine, dl);
 }
 
 // Figure 5 merge fused with the update: work-group j owns vertices
@@ -591,12 +603,12 @@ __global__ __launch_bounds__(kThreads) void k_pr_merge(const int32_t* __restrict
   merge_accumulate<K, kFlat>(range_ptr, B, id16, partial, blockIdx.x, acc);
   const int32_t v0 = blockIdx.x * K;
   const double D = *u.dtotal_in;
-  double mine = 0.0;
+  double mine = 0.0, dl = 0.0;
   for (int i = threadIdx.x; i < K; i += kThreads) {
     const int32_t v = v0 + i;
-    if (v < u.n) mine += update_vertex(u, v, acc[i], D);
+    if (v < u.n) mine += update_vertex(u, v, acc[i], D, dl);
   }
-  publish_dangling(u, mine);
+  publish_update(u, mine, dl);
 }
 
 // Figure 5 merge over the stream layout, fused with the update: range j's
@@ -659,12 +671,12 @@ __global__ __launch_bounds__(kMergeThreads) void k_pr_merge_stream(const int32_t
   __syncthreads();
   const int32_t v0 = blockIdx.x * K;
   const double D = *u.dtotal_in;
-  double mine = 0.0;
+  double mine = 0.0, dl = 0.0;
   for (int i = threadIdx.x; i < K; i += kMergeThreads) {
     const int32_t v = v0 + i;
-    if (v < u.n) mine += update_vertex(u, v, acc[i], D);
+    if (v < u.n) mine += update_vertex(u, v, acc[i], D, dl);
   }
-  publish_dangling<kMergeThreads>(u, mine);
+  publish_update<kMergeThreads>(u, mine, dl);
 }
 
 // Push with thread+warp+CTA style fine-grained balancing (Section 2.1,
@@ -721,13 +733,13 @@ __global__ __launch_bounds__(kThreads) void k_pr_push(const int32_t* __restrict_
 __global__ __launch_bounds__(kThreads) void k_pr_apply(double* __restrict__ sums, Update u) {
   const int32_t v = blockIdx.x * kThreads + threadIdx.x;
   const double D = *u.dtotal_in;
-  double mine = 0.0;
+  double mine = 0.0, dl = 0.0;
   if (v < u.n) {
     const double s = sums[v];
     sums[v] = 0.0;
-    mine = update_vertex(u, v, s, D);
+    mine = update_vertex(u, v, s, D, dl);
   }
-  publish_dangling(u, mine);
+  publish_update(u, mine, dl);
 }
 
 template <int K>
@@ -752,8 +764,9 @@ hipError_t pagerank_setup() {
 }
 
 hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int32_t dangling,
-                        const float* rank_in, float* rank_out, int32_t iters, hipStream_t s) {
+                        const float* rank_in, float* rank_out, int32_t iters, hipStream_t s, Converge* cv) {
   const int32_t n = g->n;
+  if (cv) iters = cv->max_iters;
   if (iters == 0)
     return hipMemcpyAsync(rank_out, rank_in, sizeof(float) * n, hipMemcpyDeviceToDevice, s);
   static const hipError_t setup = pagerank_setup();
@@ -776,14 +789,22 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
     ProfScope prof("pr_init", s);
     k_pr_init<<<vgrid, kThreads, 0, s>>>(rank_in, u, push ? g->sums : nullptr);
   }
-  k_reduce_dangling<<<1, 1024, 0, s>>>(g->dpart, vgrid, g->dtotal);
+  k_reduce_dangling<<<1, 1024, 0, s>>>(g->dpart, vgrid, g->dtotal, nullptr, nullptr);
   GC_HIP_TRY(hipGetLastError());
 
+  // convergence mode: iterates alternate between rank_out and rank_tmp,
+  // each compared with the one before it
+  float* const iterate[2] = {rank_out, cv ? g->rank_tmp : nullptr};
+  if (cv) u.lpart = g->lpart;
   int cur = 0;
   for (int32_t it = 0; it < iters; ++it) {
     u.dtotal_in = g->dtotal + (it & 1);
     double* dtotal_out = g->dtotal + ((it + 1) & 1);
     u.rank_out = (it == iters - 1) ? rank_out : nullptr;
+    if (cv) {
+      u.rank_out = iterate[it & 1];
+      u.rank_prev = it == 0 ? rank_in : iterate[(it - 1) & 1];
+    }
     int32_t parts = vgrid;  // work-groups of the update kernel
     if (t && !push) {
       if (t->col16) {
@@ -857,10 +878,20 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
     }
     {
       ProfScope prof("pr_dangling", s);
-      k_reduce_dangling<<<1, 1024, 0, s>>>(g->dpart, parts, dtotal_out);
+      k_reduce_dangling<<<1, 1024, 0, s>>>(g->dpart, parts, dtotal_out, u.lpart, g->ltotal);
     }
     GC_HIP_TRY(hipGetLastError());
+    if (cv) {  // read this iteration's L1 change
+      double delta = 0.0;
+      GC_HIP_TRY(hipMemcpyAsync(&delta, g->ltotal, sizeof(double), hipMemcpyDeviceToHost, s));
+      GC_HIP_TRY(hipStreamSynchronize(s));
+      cv->iters = it + 1;
+      cv->delta = delta;
+      if (delta <= cv->tol) break;
+    }
   }
+  if (cv && (cv->iters & 1) == 0)  // the last iterate is in rank_tmp
+    GC_HIP_TRY(hipMemcpyAsync(rank_out, g->rank_tmp, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
   return hipSuccess;
 }
 

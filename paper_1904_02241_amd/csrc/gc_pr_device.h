@@ -32,18 +32,28 @@ struct Update {
   const int32_t* rowptr;  // out-arc CSR: outdeg(v) = rowptr[v+1] - rowptr[v]
   float* contrib;         // written for the next iteration
   float* rank_out;        // written on the last iteration only (else null)
+  const float* rank_prev = nullptr;  // convergence mode: the previous iterate
+  double* lpart = nullptr;           // convergence mode: L1 change per work-group
   int32_t n;
 };
 
 // r'[v] from the neighbour sum; writes c'[v] (and r'[v] on the last pass),
 // returns r'[v] when v has no out-arcs (its share of the next D), else 0.
-__device__ __forceinline__ double update_vertex(const Update& u, int32_t v, double sum, double D) {
+// In convergence mode also adds |r'[v] - r[v]| (FP64 over the FP32
+// iterates) to dl.
+__device__ __forceinline__ double update_vertex(const Update& u, int32_t v, double sum, double D, double& dl) {
   const double r = u.base + u.d * (sum + D * u.inv_n);
   const float r32 = static_cast<float>(r);
   const int32_t deg = u.rowptr[v + 1] - u.rowptr[v];
   u.contrib[v] = deg ? static_cast<float>(static_cast<double>(r32) / deg) : 0.0f;
   if (u.rank_out) u.rank_out[v] = r32;
+  if (u.rank_prev) dl += fabs(static_cast<double>(r32) - static_cast<double>(u.rank_prev[v]));
   return deg ? 0.0 : static_cast<double>(r32);
+}
+
+__device__ __forceinline__ double update_vertex(const Update& u, int32_t v, double sum, double D) {
+  double dl = 0.0;
+  return update_vertex(u, v, sum, D, dl);
 }
 
 // Orders LDS accesses between the lanes of one wave.
@@ -71,6 +81,16 @@ template <int NT = kThreads>
 __device__ __forceinline__ void publish_dangling(const Update& u, double mine) {
   const double t = wg_sum<NT>(mine);
   if (threadIdx.x == 0) u.dpart[blockIdx.x] = t;
+}
+
+// publish_dangling plus, in convergence mode, the work-group's L1 change.
+template <int NT = kThreads>
+__device__ __forceinline__ void publish_update(const Update& u, double mine, double dl) {
+  publish_dangling<NT>(u, mine);
+  if (u.lpart) {  // uniform
+    const double t = wg_sum<NT>(dl);
+    if (threadIdx.x == 0) u.lpart[blockIdx.x] = t;
+  }
 }
 
 // Gathers c[col[a0 + i]] for i < len (len <= kStageCap) into LDS: every lane

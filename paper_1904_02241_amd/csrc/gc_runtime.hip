@@ -70,7 +70,7 @@ void free_graph(gc_graph g) {
   if (!g) return;
   void* bufs[] = {g->rowptr, g->colidx, g->w, g->t_rowptr, g->t_colidx, g->t_w, g->contrib[0], g->contrib[1],
                   g->sums, g->dpart, g->dtotal, g->counter, g->front, g->next, g->queue[0], g->queue[1],
-                  g->stats, g->tile_row_in, g->visited, g->mark};
+                  g->stats, g->tile_row_in, g->visited, g->mark, g->lpart, g->ltotal, g->rank_tmp};
   for (void* p : bufs)
     if (p) gcx::dev_free(p, nullptr);
   if (g->stats_host) (void)hipHostFree(g->stats_host);
@@ -373,25 +373,69 @@ int tocab_free(gc_tocab t) {
   return GC_OK;
 }
 
-int pagerank_iter(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, int32_t dangling,
-                  const float* rank_in, float* rank_out, int32_t iters, hipStream_t stream) {
-  if (!g) return fail(GC_EINVAL, "pagerank_iter: NULL graph");
-  if (t && t->g != g) return fail(GC_EINVAL, "pagerank_iter: partition belongs to another graph");
+namespace {
+
+// Checks shared by pagerank_iter and pagerank_converge (`who` names the call).
+int check_pagerank(const char* who, gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping,
+                   int32_t dangling, const float* rank_in, float* rank_out) {
+  if (!g) return fail(GC_EINVAL, "%s: NULL graph", who);
+  if (t && t->g != g) return fail(GC_EINVAL, "%s: partition belongs to another graph", who);
   if (!t && dir_if_plain != GC_PULL && dir_if_plain != GC_PUSH)
-    return fail(GC_EINVAL, "pagerank_iter: dir_if_plain must be GC_PULL or GC_PUSH");
-  if (!(damping >= 0.0f && damping <= 1.0f)) return fail(GC_EINVAL, "pagerank_iter: damping outside [0, 1]");
+    return fail(GC_EINVAL, "%s: dir_if_plain must be GC_PULL or GC_PUSH", who);
+  if (!(damping >= 0.0f && damping <= 1.0f)) return fail(GC_EINVAL, "%s: damping outside [0, 1]", who);
   if (dangling != GC_DANGLING_UNIFORM && dangling != GC_DANGLING_LEAK)
-    return fail(GC_EINVAL, "pagerank_iter: unknown dangling mode %d", dangling);
-  if (!rank_in || !rank_out) return fail(GC_EINVAL, "pagerank_iter: NULL rank buffer");
-  if (iters < 0) return fail(GC_EINVAL, "pagerank_iter: iters < 0");
+    return fail(GC_EINVAL, "%s: unknown dangling mode %d", who, dangling);
+  if (!rank_in || !rank_out) return fail(GC_EINVAL, "%s: NULL rank buffer", who);
   if (!is_device_ptr(rank_in) || !is_device_ptr(rank_out))
-    return fail(GC_EINVAL, "pagerank_iter: rank buffers must be device memory");
+    return fail(GC_EINVAL, "%s: rank buffers must be device memory", who);
   const char* a = reinterpret_cast<const char*>(rank_in);
   const char* b = reinterpret_cast<const char*>(rank_out);
   const size_t bytes = sizeof(float) * static_cast<size_t>(g->n);
-  if (a < b + bytes && b < a + bytes) return fail(GC_EINVAL, "pagerank_iter: rank_in and rank_out overlap");
+  if (a < b + bytes && b < a + bytes) return fail(GC_EINVAL, "%s: rank_in and rank_out overlap", who);
+  return GC_OK;
+}
+
+}  // namespace
+
+int pagerank_iter(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, int32_t dangling,
+                  const float* rank_in, float* rank_out, int32_t iters, hipStream_t stream) {
+  const int rc = check_pagerank("pagerank_iter", g, t, dir_if_plain, damping, dangling, rank_in, rank_out);
+  if (rc != GC_OK) return rc;
+  if (iters < 0) return fail(GC_EINVAL, "pagerank_iter: iters < 0");
   const hipError_t e = gcx::pagerank_run(g, t, dir_if_plain, damping, dangling, rank_in, rank_out, iters, stream);
   return e == hipSuccess ? GC_OK : hip_fail(e, "pagerank_iter");
+}
+
+int pagerank_converge(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, int32_t dangling,
+                      const float* rank_in, float* rank_out, double tol, int32_t max_iters, int32_t* iters_out,
+                      double* delta_out, hipStream_t stream) {
+  const int rc = check_pagerank("pagerank_converge", g, t, dir_if_plain, damping, dangling, rank_in, rank_out);
+  if (rc != GC_OK) return rc;
+  if (!(tol >= 0.0)) return fail(GC_EINVAL, "pagerank_converge: tol must be >= 0");
+  if (max_iters < 1) return fail(GC_EINVAL, "pagerank_converge: max_iters < 1");
+  if (!iters_out) return fail(GC_EINVAL, "pagerank_converge: NULL iters_out");
+  if (!g->lpart) {  // first call on this graph: its convergence buffers
+    g->lpart = static_cast<double*>(gcx::dev_alloc(sizeof(double) * g->dpart_slots, stream));
+    g->ltotal = static_cast<double*>(gcx::dev_alloc(sizeof(double), stream));
+    g->rank_tmp = static_cast<float*>(gcx::dev_alloc(sizeof(float) * std::max<int32_t>(g->n, 1), stream));
+    if (!g->lpart || !g->ltotal || !g->rank_tmp) {
+      for (void* p : {static_cast<void*>(g->lpart), static_cast<void*>(g->ltotal), static_cast<void*>(g->rank_tmp)})
+        if (p) gcx::dev_free(p, stream);
+      g->lpart = nullptr;
+      g->ltotal = nullptr;
+      g->rank_tmp = nullptr;
+      return fail(GC_ENOMEM, "pagerank_converge: device allocation failed");
+    }
+  }
+  gcx::Converge cv;
+  cv.tol = tol;
+  cv.max_iters = max_iters;
+  const hipError_t e =
+      gcx::pagerank_run(g, t, dir_if_plain, damping, dangling, rank_in, rank_out, max_iters, stream, &cv);
+  if (e != hipSuccess) return hip_fail(e, "pagerank_converge");
+  *iters_out = cv.iters;
+  if (delta_out) *delta_out = cv.delta;
+  return GC_OK;
 }
 
 int bfs_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32_t* levels, uint32_t policy,

@@ -257,3 +257,47 @@ def test_transpose_matches_scipy(g):
     np.testing.assert_array_equal(tr, T.indptr)
     np.testing.assert_array_equal(tc, T.indices)
     np.testing.assert_array_equal(tw, T.data.astype(np.int32))
+
+
+# ---- convergence-driven PageRank (the stopping rule of Section 4, read as an
+# L1 test on the change between consecutive iterates) ----
+
+@pytest.mark.parametrize("g", graphs.all_small(), ids=lambda g: g.name)
+def test_converge_changes_shrink_by_the_damping(g):
+    """With UNIFORM dangling the iteration map is r -> G r, G column-stochastic
+    scaled by d plus a constant, so consecutive differences obey
+    ||G x||_1 <= d ||x||_1: each delta is at most d times the one before."""
+    _, k, deltas = oracle.pagerank_converge(g.n, g.rowptr, g.colidx, 0.0, 30, D)
+    assert k == 30 or deltas[-1] == 0.0
+    for a, b in zip(deltas, deltas[1:]):
+        assert b <= D * a + 1e-15
+
+
+@pytest.mark.parametrize("g", graphs.all_small(), ids=lambda g: g.name)
+def test_converge_stops_at_first_small_change_within_the_contraction_bound(g):
+    """Stops at the first k with delta_k <= tol, and the contraction bound
+    ||r_k - r*||_1 <= d/(1-d) delta_k holds against the dense linear solve."""
+    G, _ = google_matrix(g)
+    n = g.n
+    want = np.linalg.solve(np.eye(n) - (G - (1.0 - D) / n * np.ones((n, n))), np.full(n, (1.0 - D) / n))
+    tol = 1e-7
+    r, k, deltas = oracle.pagerank_converge(n, g.rowptr, g.colidx, tol, 1000, D)
+    assert deltas[-1] <= tol and all(x > tol for x in deltas[:-1])
+    assert np.abs(r - want).sum() <= D / (1.0 - D) * deltas[-1] + 1e-12
+    # the iterate itself is the plain fixed-count one
+    np.testing.assert_allclose(r, oracle.pagerank(n, g.rowptr, g.colidx, D, k), rtol=0, atol=1e-15)
+
+
+def test_converge_closed_forms_and_cap():
+    # a directed cycle keeps the uniform vector: the first change is exactly 0
+    n = 12
+    rowptr = np.arange(n + 1, dtype=np.int32)
+    colidx = ((np.arange(n) + 1) % n).astype(np.int32)
+    r, k, deltas = oracle.pagerank_converge(n, rowptr, colidx, 0.0, 50, D)
+    assert (k, deltas) == (1, [0.0])
+    np.testing.assert_allclose(r, np.full(n, 1.0 / n), rtol=0, atol=1e-16)
+    # a star (all arcs into vertex 0, which has none) needs many steps; the cap holds
+    rowptr = np.concatenate([[0, 0], np.arange(1, n, dtype=np.int32)]).astype(np.int32)
+    colidx = np.zeros(n - 1, dtype=np.int32)
+    _, k, deltas = oracle.pagerank_converge(n, rowptr, colidx, 0.0, 7, D)
+    assert k == 7 and len(deltas) == 7 and deltas[-1] > 0.0
