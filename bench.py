@@ -178,6 +178,57 @@ def suite_traversal(args, gc, gg, torch):
             "traversal": out}
 
 
+def suite_ladder(args, gc, gg, torch):
+    """Section 4's comparison on R-MAT: Base, VWC (8 and 64 lanes), conventional
+    cache blocking (CB, LLC-sized and LDS-sized blocks), plain pull with the
+    load balancing of the GraphCage kernels, and TOCAB pull; time per PageRank
+    iteration and speedup over Base."""
+    gh = gg.rmat(args.scale, args.edge_factor, seed=1)
+    n, m = gh.n, gh.m
+    g = gc.graph_load_csr(gh.rowptr, gh.colidx)
+    rin = torch.full((n,), 1.0 / n, dtype=torch.float32, device="cuda")
+    rout = torch.empty_like(rin)
+    steps = max(1, args.steps)
+    parts = {W: gc.tocab_partition(g, gc.GC_PULL, W, K) for W, K in
+             ((1 << 18, args.traversal_merge_range), (args.block_width, args.merge_range))}
+
+    def timed(fn):
+        fn(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(steps)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    runs = [("base", lambda k: gc.pagerank_ladder(g, None, gc.GC_LADDER_BASE, 0.85, 0, rin, rout, k)),
+            ("vwc8", lambda k: gc.pagerank_ladder(g, None, gc.GC_LADDER_VWC, 0.85, 0, rin, rout, k)),
+            ("vwc64", lambda k: gc.pagerank_ladder(g, None, gc.GC_LADDER_VWC64, 0.85, 0, rin, rout, k)),
+            ("cb_W2^18", lambda k: gc.pagerank_ladder(g, parts[1 << 18], gc.GC_LADDER_CB, 0.85, 0, rin, rout, k)),
+            (f"cb_W2^{args.block_width.bit_length() - 1}",
+             lambda k: gc.pagerank_ladder(g, parts[args.block_width], gc.GC_LADDER_CB, 0.85, 0, rin, rout, k)),
+            ("plain_pull", lambda k: gc.pagerank_iter(g, None, gc.GC_PULL, 0.85, 0, rin, rout, k)),
+            ("tocab_pull_W2^18", lambda k: gc.pagerank_iter(g, parts[1 << 18], gc.GC_PULL, 0.85, 0, rin, rout, k)),
+            (f"tocab_pull_W2^{args.block_width.bit_length() - 1}",
+             lambda k: gc.pagerank_iter(g, parts[args.block_width], gc.GC_PULL, 0.85, 0, rin, rout, k))]
+    out = {}
+    for name, fn in runs:
+        ms = timed(fn)
+        out[name] = {"ms_per_iter": round(ms, 4), "gteps": round(m / (ms * 1e-3) / 1e9, 2)}
+        log(f"{name}: {ms:.3f} ms/iter")
+    for v in out.values():
+        v["speedup_over_base"] = round(out["base"]["ms_per_iter"] / v["ms_per_iter"], 2)
+    for p in parts.values():
+        p.free()
+    g.free()
+    head = f"tocab_pull_W2^{args.block_width.bit_length() - 1}"
+    return {"metric": METRIC, "value": out[head]["gteps"], "unit": "GTEPS", "n_gpus": 1, "steps": steps,
+            "warmup": 1, "ms_per_step": out[head]["ms_per_iter"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"pagerank_ladder_rmat{args.scale}", "n": n, "m": m,
+                       "block_width": args.block_width, "merge_range": args.merge_range},
+            "ladder": out}
+
+
 def suite_batched(args, gc, gg, torch):
     """32 R-MAT graphs (scales 14-20) + 64 PPR seeds on R-MAT 22, 20
     iterations in one captured persistent launch, against the same work as
@@ -369,15 +420,18 @@ def main():
                     help="comma list; the first is the headline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--converge-tol", type=float, default=1e-6,
+                    help="L1 tolerance of the convergence-driven TOCAB pull run (0 = skip)")
     ap.add_argument("--bfs-sources", type=int, default=8, help="BFS sources on the same graph (0 = skip)")
-    ap.add_argument("--suite", default="pagerank", choices=["pagerank", "traversal", "batched", "learned"],
+    ap.add_argument("--suite", default="pagerank", choices=["pagerank", "traversal", "batched", "learned", "ladder"],
                     help="pagerank: RMAT-24 PageRank forms + BFS (default); traversal: grid / uniform BFS+SSSP; "
-                         "batched: 32 graphs + 64 PPR seeds in one launch; learned: level scheduler")
+                         "batched: 32 graphs + 64 PPR seeds in one launch; learned: level scheduler; "
+                         "ladder: Section 4's Base / VWC / CB baselines beside TOCAB")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 1 GiB torch copy first (counter scale reference)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures a single GPU only: --gpus above 1 is not supported by this build",
+        print("bench.py measures one GPU: --gpus above 1 is not supported (the multi-GPU path is design only)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -387,7 +441,8 @@ def main():
 
     torch.cuda.init()
     if args.suite != "pagerank":
-        fn = {"traversal": suite_traversal, "batched": suite_batched, "learned": suite_learned}[args.suite]
+        fn = {"traversal": suite_traversal, "batched": suite_batched, "learned": suite_learned,
+              "ladder": suite_ladder}[args.suite]
         print(json.dumps(fn(args, gc, gg, torch)), flush=True)
         return
     if args.traffic_probe:
@@ -425,6 +480,24 @@ def main():
         res["partition"] = part.info if part else None
         results[form] = res
         log(f"{form}: {res['ms_per_step']:.3f} ms/iter, {res['gteps']:.1f} GTEPS, {res['checks']}")
+
+    converge = None
+    if "tocab_pull" in results and args.converge_tol > 0:
+        # convergence-driven run of the headline partition (one stream
+        # synchronisation per iteration to read the L1 change)
+        rin = torch.full((n,), 1.0 / n, dtype=torch.float32, device="cuda")
+        rout = torch.empty_like(rin)
+        gc.pagerank_converge(g, parts[gc.GC_PULL], gc.GC_PULL, 0.85, gc.GC_DANGLING_UNIFORM, rin, rout,
+                             args.converge_tol, 3)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k, delta = gc.pagerank_converge(g, parts[gc.GC_PULL], gc.GC_PULL, 0.85, gc.GC_DANGLING_UNIFORM, rin, rout,
+                                        args.converge_tol, 1000)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        converge = {"form": "tocab_pull", "tol": args.converge_tol, "iterations": k, "last_delta": delta,
+                    "ms": round(ms, 3), "ms_per_iter": round(ms / k, 4), "gteps": round(m * k / (ms * 1e-3) / 1e9, 2)}
+        log(f"converge {converge}")
 
     traversal = None
     if args.bfs_sources > 0:
@@ -477,6 +550,7 @@ def main():
         "step_algorithmic_GBs": round(step_bytes / (hres["ms_per_step"] * 1e-3) / 1e9, 1),
         "cpu_baseline": cpu,
         "forms": forms_out,
+        "converge": converge,
         "traversal": traversal,
     }
     print(json.dumps(out), flush=True)

@@ -58,6 +58,13 @@ typedef enum {
 #define GC_DANGLING_UNIFORM 0 /* their rank is spread evenly (sum stays 1)     */
 #define GC_DANGLING_LEAK 1    /* their rank leaves the system                   */
 
+/* PageRank baselines of the paper's comparison (Section 4), pagerank_ladder */
+#define GC_LADDER_BASE 0  /* pull, one lane per destination, serial in-arcs     */
+#define GC_LADDER_VWC 1   /* pull, a virtual warp of 8 lanes per destination     */
+#define GC_LADDER_VWC64 2 /* pull, a whole 64-lane wave per destination          */
+#define GC_LADDER_CB 3    /* conventional column blocking: block after block,   */
+                          /* row sums added straight into global FP64 sums      */
+
 /* traversal policies (bfs_pull / sssp_pull) */
 #define GC_POLICY_PULL 0      /* every level: topology-driven pull             */
 #define GC_POLICY_PUSH 1      /* every level: data-driven push with a queue    */
@@ -183,6 +190,20 @@ int pagerank_iter(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, i
 int pagerank_converge(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, int32_t dangling,
                       const float* rank_in, float* rank_out, double tol, int32_t max_iters, int32_t* iters_out,
                       double* delta_out, hipStream_t stream);
+
+/* The baselines TOCAB is compared with in Section 4, same iteration and
+ * arguments as pagerank_iter: GC_LADDER_BASE (a straightforward pull, one
+ * lane per vertex), GC_LADDER_VWC / GC_LADDER_VWC64 (virtual-warp-centric
+ * mapping of Section 2.1 with 8 / 64 lanes per vertex), GC_LADDER_CB (the
+ * conventional cache blocking Section 3.1 starts from: the column blocks of
+ * t, which must be a GC_PULL partition, run one launch after another and
+ * add every local row's sum into the global sums; t is ignored otherwise).
+ * Sums are FP64 inside a row, ranks FP32. GC_LADDER_CB synchronises `stream` once
+ * per call to read the block row offsets; the others only queue work.
+ * Errors as pagerank_iter, plus GC_EINVAL for an unknown method or a
+ * missing / push partition with GC_LADDER_CB. */
+int pagerank_ladder(gc_graph g, gc_tocab t, int32_t method, float damping, int32_t dangling,
+                    const float* rank_in, float* rank_out, int32_t iters, hipStream_t stream);
 
 /* Breadth-first search from `source` over out-arcs. depth: device
  * int32[n] out, depth[source] = 0, GC_UNREACHED when unreachable. The pull

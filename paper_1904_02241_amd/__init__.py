@@ -23,6 +23,7 @@ GC_DEVICE_PTRS, GC_VALIDATE = 1, 2
 GC_PULL, GC_PUSH = 0, 1
 GC_DANGLING_UNIFORM, GC_DANGLING_LEAK = 0, 1
 GC_POLICY_PULL, GC_POLICY_PUSH, GC_POLICY_HEURISTIC, GC_POLICY_LEARNED = 0, 1, 2, 3
+GC_LADDER_BASE, GC_LADDER_VWC, GC_LADDER_VWC64, GC_LADDER_CB = 0, 1, 2, 3
 GC_SCHED_INPUTS, GC_SCHED_HIDDEN = 6, 64
 
 # every exported entry point, with (restype, argtypes)
@@ -44,6 +45,7 @@ SIGNATURES = {
     "tocab_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tocab_free": (ctypes.c_int, [_vp]),
     "pagerank_iter": (ctypes.c_int, [_vp, _vp, _i32, _f32, _i32, _vp, _vp, _i32, _vp]),
+    "pagerank_ladder": (ctypes.c_int, [_vp, _vp, _i32, _f32, _i32, _vp, _vp, _i32, _vp]),
     "pagerank_converge": (ctypes.c_int, [_vp, _vp, _i32, _f32, _i32, _vp, _vp, ctypes.c_double, _i32, _p_i32,
                                          ctypes.POINTER(ctypes.c_double), _vp]),
     "bfs_pull": (ctypes.c_int, [_vp, _vp, _i32, _vp, _p_i32, _u32, _vp]),
@@ -276,6 +278,11 @@ def tocab_free(t):
 def pagerank_iter(g, t, dir_if_plain, damping, dangling, rank_in, rank_out, iters, stream=None):
     _check(lib.pagerank_iter(_h(g), _h(t), dir_if_plain, damping, dangling, _ptr(rank_in), _ptr(rank_out), iters,
                              _stream(stream)), "pagerank_iter")
+
+
+def pagerank_ladder(g, t, method, damping, dangling, rank_in, rank_out, iters, stream=None):
+    _check(lib.pagerank_ladder(_h(g), _h(t), method, damping, dangling, _ptr(rank_in), _ptr(rank_out), iters,
+                               _stream(stream)), "pagerank_ladder")
 
 
 def pagerank_converge(g, t, dir_if_plain, damping, dangling, rank_in, rank_out, tol, max_iters, stream=None):

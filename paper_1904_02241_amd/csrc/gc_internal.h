@@ -176,7 +176,7 @@ struct Converge {
 };
 hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int32_t dangling,
                         const float* rank_in, float* rank_out, int32_t iters, hipStream_t s,
-                        Converge* cv = nullptr);
+                        Converge* cv = nullptr, int32_t ladder = -1);
 
 // ---- autotuner (gc_autotune.hip) ----
 // Candidate widths start at max(2^12, min_W).

@@ -15,6 +15,7 @@
 #include <climits>
 
 #include <type_traits>
+#include <vector>
 
 #include "gc_device.h"
 #include "gc_internal.h"
@@ -742,6 +743,68 @@ __global__ __launch_bounds__(kThreads) void k_pr_apply(double* __restrict__ sums
   publish_update(u, mine, dl);
 }
 
+// ---- the baselines of Section 4's comparison (Base, VWC, conventional
+// cache blocking), each with the same FP64 row sums and fused update ----
+
+// Base: a straightforward pull, one lane per destination summing its
+// in-arcs serially (Algorithm 1 as written).
+__global__ __launch_bounds__(kThreads) void k_pr_base(const int32_t* __restrict__ t_rowptr,
+                                                      const int32_t* __restrict__ t_col,
+                                                      const float* __restrict__ c_in, Update u) {
+  const int32_t v = blockIdx.x * kThreads + threadIdx.x;
+  double mine = 0.0, dl = 0.0;
+  if (v < u.n) {
+    const double D = *u.dtotal_in;
+    double s = 0.0;
+    for (int32_t i = t_rowptr[v]; i < t_rowptr[v + 1]; ++i) s += static_cast<double>(c_in[t_col[i]]);
+    mine = update_vertex(u, v, s, D, dl);
+  }
+  publish_update(u, mine, dl);
+}
+
+// VWC (the virtual-warp-centric mapping of Section 2.1): VW lanes per
+// destination stride over its in-arcs, then reduce by lane exchanges. Each
+// work-group walks vertex groups of 256 / VW with a uniform loop, so the grid
+// (and the number of dangling partials) matches Base's.
+template <int VW>
+__global__ __launch_bounds__(kThreads) void k_pr_vwc(const int32_t* __restrict__ t_rowptr,
+                                                     const int32_t* __restrict__ t_col,
+                                                     const float* __restrict__ c_in, Update u) {
+  constexpr int32_t kPerGroup = kThreads / VW;
+  const int lane = threadIdx.x & (VW - 1);
+  const double D = *u.dtotal_in;
+  double mine = 0.0, dl = 0.0;
+  for (int32_t v0 = blockIdx.x * kPerGroup; v0 < u.n; v0 += gridDim.x * kPerGroup) {
+    const int32_t v = v0 + static_cast<int32_t>(threadIdx.x) / VW;
+    double s = 0.0;
+    if (v < u.n)
+      for (int32_t i = t_rowptr[v] + lane; i < t_rowptr[v + 1]; i += VW) s += static_cast<double>(c_in[t_col[i]]);
+#pragma unroll
+    for (int o = VW / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, VW);
+    if (lane == 0 && v < u.n) mine += update_vertex(u, v, s, D, dl);
+  }
+  publish_update(u, mine, dl);
+}
+
+// Conventional column blocking (the naive scheme Section 3.1 starts from):
+// the blocks of a pull partition run one launch after another; a lane per
+// local row of the block adds the row's sum over the block's arcs straight
+// into sums[id_map[l]] (FP64 read-modify-write: a destination appears once
+// per block and blocks do not overlap in time). The scattered updates of
+// sums are the cost TOCAB's partials and merge avoid.
+__global__ __launch_bounds__(kThreads) void k_pr_cb_block(const int32_t* __restrict__ row_ptr,
+                                                          const int32_t* __restrict__ id_map,
+                                                          const int32_t* __restrict__ col,
+                                                          const float* __restrict__ c, double* __restrict__ sums,
+                                                          int32_t a, int32_t b) {
+  const int32_t l = a + static_cast<int32_t>(blockIdx.x) * kThreads + static_cast<int32_t>(threadIdx.x);
+  if (l < b) {
+    double s = 0.0;
+    for (int32_t i = row_ptr[l]; i < row_ptr[l + 1]; ++i) s += static_cast<double>(c[col[i]]);
+    sums[id_map[l]] += s;
+  }
+}
+
 template <int K>
 void launch_merge(int32_t R, hipStream_t s, const int32_t* rp, int32_t B, const uint16_t* id16,
                   const float* partial, const Update& u) {
@@ -763,14 +826,83 @@ hipError_t pagerank_setup() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_budget(kLdsMaxWidth));
 }
 
+// The comparison baselines (pagerank_ladder): Base and VWC gather over the
+// whole transposed graph with two contribution buffers in turn; CB runs its
+// block launches into the FP64 sums and then the push-side update.
+hipError_t ladder_run(gc_graph g, gc_tocab t, int32_t method, float damping, int32_t dangling,
+                      const float* rank_in, float* rank_out, int32_t iters, hipStream_t s) {
+  const int32_t n = g->n;
+  const bool cb = method == GC_LADDER_CB;
+  Update u;
+  u.d = damping;
+  u.base = (1.0 - static_cast<double>(damping)) / n;
+  u.inv_n = dangling == GC_DANGLING_UNIFORM ? 1.0 / n : 0.0;
+  u.dpart = g->dpart;
+  u.rowptr = g->rowptr;
+  u.n = n;
+  u.rank_out = nullptr;
+  const int vgrid = (n + kThreads - 1) / kThreads;
+  std::vector<int32_t> rows;  // CB: first local row of every block
+  if (cb) {
+    rows.resize(static_cast<size_t>(t->B) + 1);
+    GC_HIP_TRY(hipMemcpyAsync(rows.data(), t->blk_rowoff, sizeof(int32_t) * rows.size(), hipMemcpyDeviceToHost, s));
+    GC_HIP_TRY(hipStreamSynchronize(s));
+  }
+  u.dtotal_in = nullptr;
+  u.contrib = g->contrib[0];
+  k_pr_init<<<vgrid, kThreads, 0, s>>>(rank_in, u, cb ? g->sums : nullptr);
+  k_reduce_dangling<<<1, 1024, 0, s>>>(g->dpart, vgrid, g->dtotal, nullptr, nullptr);
+  GC_HIP_TRY(hipGetLastError());
+  int cur = 0;
+  for (int32_t it = 0; it < iters; ++it) {
+    u.dtotal_in = g->dtotal + (it & 1);
+    u.rank_out = (it == iters - 1) ? rank_out : nullptr;
+    if (cb) {
+      {
+        ProfScope prof("pr_cb_blocks", s);
+        for (int32_t b = 0; b < t->B; ++b) {
+          const int32_t a = rows[b], z = rows[b + 1];
+          if (z > a)
+            k_pr_cb_block<<<(z - a + kThreads - 1) / kThreads, kThreads, 0, s>>>(t->row_ptr, t->id_map, t->col,
+                                                                                g->contrib[0], g->sums, a, z);
+        }
+      }
+      u.contrib = g->contrib[0];
+      ProfScope prof("pr_apply", s);
+      k_pr_apply<<<vgrid, kThreads, 0, s>>>(g->sums, u);
+    } else {
+      u.contrib = g->contrib[cur ^ 1];
+      if (method == GC_LADDER_BASE) {
+        ProfScope prof("pr_base", s);
+        k_pr_base<<<vgrid, kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, g->contrib[cur], u);
+      } else if (method == GC_LADDER_VWC) {
+        ProfScope prof("pr_vwc", s);
+        k_pr_vwc<8><<<vgrid, kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, g->contrib[cur], u);
+      } else {
+        ProfScope prof("pr_vwc64", s);
+        k_pr_vwc<64><<<vgrid, kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, g->contrib[cur], u);
+      }
+      cur ^= 1;
+    }
+    {
+      ProfScope prof("pr_dangling", s);
+      k_reduce_dangling<<<1, 1024, 0, s>>>(g->dpart, vgrid, g->dtotal + ((it + 1) & 1), nullptr, nullptr);
+    }
+    GC_HIP_TRY(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
 hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int32_t dangling,
-                        const float* rank_in, float* rank_out, int32_t iters, hipStream_t s, Converge* cv) {
+                        const float* rank_in, float* rank_out, int32_t iters, hipStream_t s, Converge* cv,
+                        int32_t ladder) {
   const int32_t n = g->n;
   if (cv) iters = cv->max_iters;
   if (iters == 0)
     return hipMemcpyAsync(rank_out, rank_in, sizeof(float) * n, hipMemcpyDeviceToDevice, s);
   static const hipError_t setup = pagerank_setup();
   GC_HIP_TRY(setup);
+  if (ladder >= 0) return ladder_run(g, t, ladder, damping, dangling, rank_in, rank_out, iters, s);
   const bool push = t ? (t->dir == GC_PUSH) : (dir == GC_PUSH);
   Update u;
   u.d = damping;

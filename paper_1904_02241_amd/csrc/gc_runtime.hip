@@ -406,6 +406,21 @@ int pagerank_iter(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, i
   return e == hipSuccess ? GC_OK : hip_fail(e, "pagerank_iter");
 }
 
+int pagerank_ladder(gc_graph g, gc_tocab t, int32_t method, float damping, int32_t dangling,
+                    const float* rank_in, float* rank_out, int32_t iters, hipStream_t stream) {
+  if (method < GC_LADDER_BASE || method > GC_LADDER_CB)
+    return fail(GC_EINVAL, "pagerank_ladder: unknown method %d", method);
+  if (method == GC_LADDER_CB && (!t || t->dir != GC_PULL))
+    return fail(GC_EINVAL, "pagerank_ladder: GC_LADDER_CB needs a GC_PULL partition");
+  const int rc = check_pagerank("pagerank_ladder", g, method == GC_LADDER_CB ? t : nullptr, GC_PULL, damping,
+                                dangling, rank_in, rank_out);
+  if (rc != GC_OK) return rc;
+  if (iters < 0) return fail(GC_EINVAL, "pagerank_ladder: iters < 0");
+  const hipError_t e = gcx::pagerank_run(g, t, GC_PULL, damping, dangling, rank_in, rank_out, iters, stream,
+                                         nullptr, method);
+  return e == hipSuccess ? GC_OK : hip_fail(e, "pagerank_ladder");
+}
+
 int pagerank_converge(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, int32_t dangling,
                       const float* rank_in, float* rank_out, double tol, int32_t max_iters, int32_t* iters_out,
                       double* delta_out, hipStream_t stream) {
