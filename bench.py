@@ -229,6 +229,49 @@ def suite_ladder(args, gc, gg, torch):
             "ladder": out}
 
 
+def suite_spmv(args, gc, gg, torch):
+    """Section 4's SpMV on R-MAT with FP32 arc values: y[v] = sum over arcs
+    u -> v of val * x[u], plain pull and column-blocked pull (LLC-sized and
+    LDS-sized blocks through the tile kernel), time per product."""
+    gh = gg.rmat(args.scale, args.edge_factor, seed=1)
+    n, m = gh.n, gh.m
+    rng = np.random.default_rng(7)
+    vals = rng.random(m, dtype=np.float32)
+    g = gc.graph_load_csr(gh.rowptr, gh.colidx, values=vals)
+    del vals
+    x = torch.rand(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    steps = max(1, args.steps)
+    parts = {W: gc.tocab_partition(g, gc.GC_PULL, W, K) for W, K in
+             ((1 << 18, args.traversal_merge_range), (args.block_width, args.merge_range))}
+    out = {}
+    for name, part in (("plain_pull", None), ("tocab_pull_W2^18", parts[1 << 18]),
+                       (f"tocab_pull_W2^{args.block_width.bit_length() - 1}", parts[args.block_width])):
+        gc.spmv(g, part, x, y)
+        torch.cuda.synchronize()
+        gc.gc_profile(1)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            gc.spmv(g, part, x, y)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        gc.gc_profile(0)
+        prof = gc.gc_profile_read()
+        out[name] = {"ms": round(ms, 4), "gteps": round(m / (ms * 1e-3) / 1e9, 2),
+                     "kernels_ms_per_launch": {k: round(v[0] / v[1], 4) for k, v in prof.items()}}
+        log(f"spmv {name}: {ms:.3f} ms")
+    for p in parts.values():
+        p.free()
+    g.free()
+    best = max(out, key=lambda k: out[k]["gteps"])
+    return {"metric": METRIC, "value": out[best]["gteps"], "unit": "GTEPS", "n_gpus": 1, "steps": steps,
+            "warmup": 1, "ms_per_step": out[best]["ms"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"spmv_rmat{args.scale}", "n": n, "m": m, "values": "uniform [0, 1) FP32",
+                       "best": best},
+            "spmv": out}
+
+
 def suite_batched(args, gc, gg, torch):
     """32 R-MAT graphs (scales 14-20) + 64 PPR seeds on R-MAT 22, 20
     iterations in one captured persistent launch, against the same work as
@@ -423,10 +466,10 @@ def main():
     ap.add_argument("--converge-tol", type=float, default=1e-6,
                     help="L1 tolerance of the convergence-driven TOCAB pull run (0 = skip)")
     ap.add_argument("--bfs-sources", type=int, default=8, help="BFS sources on the same graph (0 = skip)")
-    ap.add_argument("--suite", default="pagerank", choices=["pagerank", "traversal", "batched", "learned", "ladder"],
+    ap.add_argument("--suite", default="pagerank", choices=["pagerank", "traversal", "batched", "learned", "ladder", "spmv"],
                     help="pagerank: RMAT-24 PageRank forms + BFS (default); traversal: grid / uniform BFS+SSSP; "
                          "batched: 32 graphs + 64 PPR seeds in one launch; learned: level scheduler; "
-                         "ladder: Section 4's Base / VWC / CB baselines beside TOCAB")
+                         "ladder: Section 4's Base / VWC / CB baselines beside TOCAB; spmv: SpMV plain and blocked")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 1 GiB torch copy first (counter scale reference)")
     args = ap.parse_args()
@@ -442,7 +485,7 @@ def main():
     torch.cuda.init()
     if args.suite != "pagerank":
         fn = {"traversal": suite_traversal, "batched": suite_batched, "learned": suite_learned,
-              "ladder": suite_ladder}[args.suite]
+              "ladder": suite_ladder, "spmv": suite_spmv}[args.suite]
         print(json.dumps(fn(args, gc, gg, torch)), flush=True)
         return
     if args.traffic_probe:

@@ -49,6 +49,8 @@ typedef enum {
 #define GC_DEVICE_PTRS 1u /* rowptr/colidx/weight are device pointers          */
 #define GC_VALIDATE 2u    /* check monotone rowptr, column range, sorted rows,  */
                           /* no self-loops and no duplicate arcs (host check)   */
+#define GC_VALUES_F32 4u  /* weight holds FP32 arc values (bit patterns) for   */
+                          /* spmv; such a graph has no integer weights          */
 
 /* directions */
 #define GC_PULL 0 /* gather over in-arcs (transposed graph); blocks by source  */
@@ -204,6 +206,19 @@ int pagerank_converge(gc_graph g, gc_tocab t, int32_t dir_if_plain, float dampin
  * missing / push partition with GC_LADDER_CB. */
 int pagerank_ladder(gc_graph g, gc_tocab t, int32_t method, float damping, int32_t dangling,
                     const float* rank_in, float* rank_out, int32_t iters, hipStream_t stream);
+
+/* Sparse matrix-vector product over the arcs in the pull direction (the
+ * SpMV benchmark of Section 4; the generalised SpMV that Algorithm 1
+ * follows): y[v] = sum over arcs u -> v of val(u -> v) * x[u], i.e.
+ * y = A^T x for the loaded out-arc CSR A. val is the arc's FP32 value for a
+ * graph loaded with GC_VALUES_F32, its integer weight converted to FP32 for
+ * other weighted graphs, 1 for unweighted ones. t == NULL: plain pull; t, a
+ * GC_PULL partition of g: column-blocked pull (Algorithm 4) into partial
+ * sums per (row, block), then the Figure 5 merge. Products are FP32, sums
+ * FP64, y FP32. x, y: device float[n], must not overlap. Queues work only.
+ * Errors: GC_EINVAL for bad arguments (NULL or overlapping vectors, host
+ * memory, a partition of another graph or a GC_PUSH partition). */
+int spmv(gc_graph g, gc_tocab t, const float* x, float* y, hipStream_t stream);
 
 /* Breadth-first search from `source` over out-arcs. depth: device
  * int32[n] out, depth[source] = 0, GC_UNREACHED when unreachable. The pull

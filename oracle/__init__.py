@@ -75,6 +75,20 @@ def pagerank_converge(n, rowptr, colidx, tol, max_iters, d=0.85, mode=UNIFORM, r
     return r, len(deltas), deltas
 
 
+def spmv(n, rowptr, colidx, values, x):
+    """FP64 sparse matrix-vector product over the out-arc CSR in the pull
+    direction: y[v] = sum over arcs u -> v of values[arc] * x[u] (values
+    None: every arc counts 1), accumulated in arc order."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    colidx = np.asarray(colidx, dtype=np.int64)
+    x = np.asarray(x, dtype=np.float64)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rowptr))
+    terms = x[src] if values is None else np.asarray(values, dtype=np.float64) * x[src]
+    y = np.zeros(n, dtype=np.float64)
+    np.add.at(y, colidx, terms)
+    return y
+
+
 def ppr(n, rowptr, colidx, p, d=0.85, iters=20):
     """FP64 personalised PageRank iterate `iters` from r0 = p."""
     rowptr, colidx = _i32(rowptr), _i32(colidx)

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libgraphcage.so")
 
 GC_OK, GC_EINVAL, GC_ENOMEM, GC_EHIP, GC_EUNSUPPORTED, GC_EOVERFLOW = 0, -1, -2, -3, -4, -5
 GC_UNREACHED = np.iinfo(np.int32).max
-GC_DEVICE_PTRS, GC_VALIDATE = 1, 2
+GC_DEVICE_PTRS, GC_VALIDATE, GC_VALUES_F32 = 1, 2, 4
 GC_PULL, GC_PUSH = 0, 1
 GC_DANGLING_UNIFORM, GC_DANGLING_LEAK = 0, 1
 GC_POLICY_PULL, GC_POLICY_PUSH, GC_POLICY_HEURISTIC, GC_POLICY_LEARNED = 0, 1, 2, 3
@@ -45,6 +45,7 @@ SIGNATURES = {
     "tocab_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tocab_free": (ctypes.c_int, [_vp]),
     "pagerank_iter": (ctypes.c_int, [_vp, _vp, _i32, _f32, _i32, _vp, _vp, _i32, _vp]),
+    "spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "pagerank_ladder": (ctypes.c_int, [_vp, _vp, _i32, _f32, _i32, _vp, _vp, _i32, _vp]),
     "pagerank_converge": (ctypes.c_int, [_vp, _vp, _i32, _f32, _i32, _vp, _vp, ctypes.c_double, _i32, _p_i32,
                                          ctypes.POINTER(ctypes.c_double), _vp]),
@@ -206,15 +207,25 @@ def gc_sync(stream=None):
     _check(lib.gc_sync(_stream(stream)), "gc_sync")
 
 
-def graph_load_csr(rowptr, colidx, weight=None, validate=False, stream=None):
-    """Out-arc CSR (numpy int32 arrays or CUDA int32 tensors) -> Graph."""
+def graph_load_csr(rowptr, colidx, weight=None, validate=False, stream=None, values=None):
+    """Out-arc CSR (numpy int32 arrays or CUDA int32 tensors) -> Graph.
+    `values` (float32, instead of `weight`) loads FP32 arc values for spmv."""
     n = int(rowptr.shape[0]) - 1
     m = int(colidx.shape[0])
+    f32 = values is not None
+    if f32:
+        if weight is not None:
+            raise ValueError("pass either weight or values")
+        if isinstance(values, np.ndarray):
+            weight = np.ascontiguousarray(values, dtype=np.float32).view(np.int32)
+        else:
+            import torch
+            weight = values.contiguous().view(torch.int32)
     dev = _is_device(rowptr)
     for a in (colidx, weight):
         if a is not None and _is_device(a) != dev:
             raise ValueError("rowptr, colidx and weight must all be host or all be device arrays")
-    flags = (GC_DEVICE_PTRS if dev else 0) | (GC_VALIDATE if validate else 0)
+    flags = (GC_DEVICE_PTRS if dev else 0) | (GC_VALIDATE if validate else 0) | (GC_VALUES_F32 if f32 else 0)
     out = ctypes.c_void_p()
     _check(lib.graph_load_csr(n, m, _ptr(rowptr), _ptr(colidx), _ptr(weight), flags, _stream(stream),
                               ctypes.byref(out)), "graph_load_csr")
@@ -278,6 +289,10 @@ def tocab_free(t):
 def pagerank_iter(g, t, dir_if_plain, damping, dangling, rank_in, rank_out, iters, stream=None):
     _check(lib.pagerank_iter(_h(g), _h(t), dir_if_plain, damping, dangling, _ptr(rank_in), _ptr(rank_out), iters,
                              _stream(stream)), "pagerank_iter")
+
+
+def spmv(g, t, x, y, stream=None):
+    _check(lib.spmv(_h(g), _h(t), _ptr(x), _ptr(y), _stream(stream)), "spmv")
 
 
 def pagerank_ladder(g, t, method, damping, dangling, rank_in, rank_out, iters, stream=None):

@@ -34,6 +34,7 @@ struct gc_graph_s {
   double* dtotal = nullptr;   // [2] ping-pong dangling totals
   unsigned* counter = nullptr;
   int32_t dpart_slots = 0;
+  bool values_f32 = false;  // the weight arrays hold FP32 values (GC_VALUES_F32)
   // convergence mode (allocated by the first pagerank_converge call): FP64
   // partials of the L1 change per update work-group, their total, and a
   // second FP32 iterate
@@ -165,6 +166,9 @@ constexpr int32_t kLdsStageBytes = 16 * (384 + 16) * 4;
 // Largest range table (entries) that fits beside a W-float slice and the
 // staging (with 8 entries of padding).
 inline int32_t lds_seg_cap(int32_t W) { return ((lds_budget(W) - 4 * W - kLdsStageBytes) / 4 - 8) / 2; }
+// ---- SpMV (gc_spmv.hip) ----
+hipError_t spmv_run(gc_graph g, gc_tocab t, const float* x, float* y, hipStream_t s);
+
 // Convergence mode of pagerank_run: iterate until the L1 change between
 // consecutive iterates is at most tol (or max_iters); iters / delta report
 // the iterations run and the last change.

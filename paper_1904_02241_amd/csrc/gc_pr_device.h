@@ -93,14 +93,32 @@ __device__ __forceinline__ void publish_update(const Update& u, double mine, dou
   }
 }
 
-// Gathers c[col[a0 + i]] for i < len (len <= kStageCap) into LDS: every lane
-// first issues its column loads (coalesced across the work-group, streamed
-// past the cache), then the gathers, so all loads of a tile are in flight
-// together. Indices past the end are clamped to the last arc instead of
-// branched around, which keeps the loads free of control flow (a branch per
-// load would make each one wait for the previous).
+// The value an arc contributes to its row's sum, given its index i in the
+// arc array and the gathered source value x: x itself (PageRank, where the
+// source value is already c[u] = r[u] / outdeg(u)), or x times the arc's
+// value (SpMV: FP32 values stored as their bits, or integer weights).
+struct PlainArc {
+  __device__ __forceinline__ float operator()(int32_t, float x) const { return x; }
+};
+struct ValuedArc {
+  const int32_t* val;  // null: every value is 1
+  bool f32;            // val holds FP32 bit patterns (else integers)
+  __device__ __forceinline__ float operator()(int32_t i, float x) const {
+    if (!val) return x;
+    const int32_t b = gcd::ld_stream(val + i);
+    return x * (f32 ? __int_as_float(b) : static_cast<float>(b));
+  }
+};
+
+// Gathers arc(i, c[col[i]]) for i = a0 + [0, len) (len <= kStageCap) into
+// LDS: every lane first issues its column loads (coalesced across the
+// work-group, streamed past the cache), then the gathers, so all loads of a
+// tile are in flight together. Indices past the end are clamped to the last
+// arc instead of branched around, which keeps the loads free of control flow
+// (a branch per load would make each one wait for the previous).
+template <class Arc = PlainArc>
 __device__ __forceinline__ void stage_gather(const int32_t* __restrict__ col, const float* __restrict__ c,
-                                             int32_t a0, int32_t len, float* vals) {
+                                             int32_t a0, int32_t len, float* vals, Arc arc = Arc()) {
   if (len <= 0) return;
   int32_t idx[kPerThread];
 #pragma unroll
@@ -114,12 +132,15 @@ __device__ __forceinline__ void stage_gather(const int32_t* __restrict__ col, co
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
     const int32_t i = threadIdx.x + k * kThreads;
-    if (i < len) vals[i] = x[k];
+    if (i < len) vals[i] = arc(a0 + i, x[k]);
   }
 }
 
-// Sum of c over columns [b, e) (b < e) by the whole work-group (hub rows).
-__device__ double wg_row_sum(const int32_t* __restrict__ col, const float* __restrict__ c, int32_t b, int32_t e) {
+// Sum of arc(i, c[col[i]]) over arcs [b, e) (b < e) by the whole
+// work-group (hub rows).
+template <class Arc = PlainArc>
+__device__ double wg_row_sum(const int32_t* __restrict__ col, const float* __restrict__ c, int32_t b, int32_t e,
+                             Arc arc = Arc()) {
   double s = 0.0;
   for (int32_t base = b; base < e; base += kStageCap) {
     int32_t idx[kPerThread];
@@ -130,8 +151,10 @@ __device__ double wg_row_sum(const int32_t* __restrict__ col, const float* __res
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) x[k] = c[idx[k]];
 #pragma unroll
-    for (int k = 0; k < kPerThread; ++k)
-      if (base + static_cast<int32_t>(threadIdx.x) + k * kThreads < e) s += static_cast<double>(x[k]);
+    for (int k = 0; k < kPerThread; ++k) {
+      const int32_t i = base + static_cast<int32_t>(threadIdx.x) + k * kThreads;
+      if (i < e) s += static_cast<double>(arc(i, x[k]));
+    }
   }
   return wg_sum(s);
 }
@@ -142,15 +165,15 @@ __device__ double wg_row_sum(const int32_t* __restrict__ col, const float* __res
 // together; then each thread sums whole short rows serially in FP64, and a
 // last row too long for the stage is summed by the whole work-group. No
 // atomics. emit(row, sum) is called once per owned row.
-template <class Emit>
+template <class Emit, class Arc = PlainArc>
 __device__ __forceinline__ void pull_tile(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                           const float* __restrict__ c, int32_t r0, int32_t r1, float* vals,
-                                          Emit&& emit) {
+                                          Emit&& emit, Arc arc = Arc()) {
   const int32_t a0 = row_ptr[r0];
   const int32_t last_b = row_ptr[r1 - 1];
   const int32_t a_end = row_ptr[r1];
   const bool long_last = (a_end - a0) > kStageCap;
-  stage_gather(col, c, a0, (long_last ? last_b : a_end) - a0, vals);
+  stage_gather(col, c, a0, (long_last ? last_b : a_end) - a0, vals, arc);
   __syncthreads();
   const int32_t r_short_end = long_last ? r1 - 1 : r1;
   for (int32_t r = r0 + threadIdx.x; r < r_short_end; r += kThreads) {
@@ -160,7 +183,7 @@ __device__ __forceinline__ void pull_tile(const int32_t* __restrict__ row_ptr, c
     emit(r, s);
   }
   if (long_last) {
-    const double s = wg_row_sum(col, c, last_b, a_end);
+    const double s = wg_row_sum(col, c, last_b, a_end, arc);
     if (threadIdx.x == 0) emit(r1 - 1, s);
   }
 }

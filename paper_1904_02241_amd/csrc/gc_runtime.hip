@@ -140,7 +140,9 @@ int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* c
   if (n > INT32_MAX - 1) return fail(GC_EINVAL, "graph_load_csr: n too large");
   if (m < 0 || m >= INT32_MAX) return fail(GC_EINVAL, "graph_load_csr: m = %lld outside [0, 2^31)", (long long)m);
   if (!rowptr || (m > 0 && !colidx)) return fail(GC_EINVAL, "graph_load_csr: NULL rowptr or colidx");
-  if (flags & ~(GC_DEVICE_PTRS | GC_VALIDATE)) return fail(GC_EINVAL, "graph_load_csr: unknown flags 0x%x", flags);
+  if (flags & ~(GC_DEVICE_PTRS | GC_VALIDATE | GC_VALUES_F32))
+    return fail(GC_EINVAL, "graph_load_csr: unknown flags 0x%x", flags);
+  if ((flags & GC_VALUES_F32) && !weight) return fail(GC_EINVAL, "graph_load_csr: GC_VALUES_F32 without values");
   const bool dev = (flags & GC_DEVICE_PTRS) != 0;
 
   if (flags & GC_VALIDATE) {
@@ -159,7 +161,7 @@ int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* c
       pc = hc.data();
       pw = weight ? hw.data() : nullptr;
     }
-    const int rc = validate_host(n, m, pr, pc, pw);
+    const int rc = validate_host(n, m, pr, pc, (flags & GC_VALUES_F32) ? nullptr : pw);
     if (rc != GC_OK) return rc;
   } else if (!dev) {
     if (rowptr[0] != 0 || rowptr[n] != m)
@@ -171,6 +173,7 @@ int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* c
   g->n = n;
   g->m = m;
   g->weighted = weight != nullptr;
+  g->values_f32 = (flags & GC_VALUES_F32) != 0;
   const size_t nb = sizeof(int32_t) * (static_cast<size_t>(n) + 1);
   const size_t mb = sizeof(int32_t) * static_cast<size_t>(m > 0 ? m : 1);
   g->dpart_slots = static_cast<int32_t>(std::max<int64_t>((n + 255) / 256, m / gcx::pull_tile_arcs() + 2));
@@ -421,6 +424,20 @@ int pagerank_ladder(gc_graph g, gc_tocab t, int32_t method, float damping, int32
   return e == hipSuccess ? GC_OK : hip_fail(e, "pagerank_ladder");
 }
 
+int spmv(gc_graph g, gc_tocab t, const float* x, float* y, hipStream_t stream) {
+  if (!g) return fail(GC_EINVAL, "spmv: NULL graph");
+  if (t && t->g != g) return fail(GC_EINVAL, "spmv: partition belongs to another graph");
+  if (t && t->dir != GC_PULL) return fail(GC_EINVAL, "spmv: partition must be GC_PULL");
+  if (!x || !y) return fail(GC_EINVAL, "spmv: NULL vector");
+  if (!is_device_ptr(x) || !is_device_ptr(y)) return fail(GC_EINVAL, "spmv: vectors must be device memory");
+  const char* a = reinterpret_cast<const char*>(x);
+  const char* b = reinterpret_cast<const char*>(y);
+  const size_t bytes = sizeof(float) * static_cast<size_t>(g->n);
+  if (a < b + bytes && b < a + bytes) return fail(GC_EINVAL, "spmv: x and y overlap");
+  const hipError_t e = gcx::spmv_run(g, t, x, y, stream);
+  return e == hipSuccess ? GC_OK : hip_fail(e, "spmv");
+}
+
 int pagerank_converge(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, int32_t dangling,
                       const float* rank_in, float* rank_out, double tol, int32_t max_iters, int32_t* iters_out,
                       double* delta_out, hipStream_t stream) {
@@ -471,7 +488,7 @@ int bfs_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32_t* le
 int sssp_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* dist, int32_t* rounds, uint32_t policy,
               hipStream_t stream) {
   if (!g) return fail(GC_EINVAL, "sssp_pull: NULL graph");
-  if (!g->weighted) return fail(GC_EINVAL, "sssp_pull: graph has no weights");
+  if (!g->weighted || g->values_f32) return fail(GC_EINVAL, "sssp_pull: graph has no integer weights");
   if (t && t->g != g) return fail(GC_EINVAL, "sssp_pull: partition belongs to another graph");
   if (t && t->dir != GC_PULL) return fail(GC_EINVAL, "sssp_pull: partition must be GC_PULL");
   if (source < 0 || source >= g->n) return fail(GC_EINVAL, "sssp_pull: source %d outside [0, %d)", source, g->n);

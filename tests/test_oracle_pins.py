@@ -301,3 +301,36 @@ def test_converge_closed_forms_and_cap():
     colidx = np.zeros(n - 1, dtype=np.int32)
     _, k, deltas = oracle.pagerank_converge(n, rowptr, colidx, 0.0, 7, D)
     assert k == 7 and len(deltas) == 7 and deltas[-1] > 0.0
+
+
+# ---- SpMV over the arcs in the pull direction (Section 4's SpMV benchmark) ----
+
+@pytest.mark.parametrize("g", graphs.all_small(), ids=lambda g: g.name)
+def test_spmv_matches_scipy_and_dense(g):
+    rng = np.random.default_rng(5)
+    vals = rng.uniform(-1.0, 1.0, g.m)
+    x = rng.uniform(-1.0, 1.0, g.n)
+    A = sp.csr_matrix((vals, g.colidx, g.rowptr), shape=(g.n, g.n))
+    got = oracle.spmv(g.n, g.rowptr, g.colidx, vals, x)
+    np.testing.assert_allclose(got, A.T @ x, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(got, A.toarray().T @ x, rtol=0, atol=1e-12)
+    # unit values: the pull neighbour sum
+    ones = oracle.spmv(g.n, g.rowptr, g.colidx, None, x)
+    np.testing.assert_allclose(ones, (dense_adj(g).T @ x), rtol=0, atol=1e-12)
+
+
+def test_spmv_linearity_and_pagerank_step():
+    g = gg.rmat(9, 8, seed=4)
+    rng = np.random.default_rng(6)
+    vals = rng.uniform(0.0, 2.0, g.m)
+    x, z = rng.uniform(-1, 1, g.n), rng.uniform(-1, 1, g.n)
+    lhs = oracle.spmv(g.n, g.rowptr, g.colidx, vals, 2.0 * x - 3.0 * z)
+    rhs = 2.0 * oracle.spmv(g.n, g.rowptr, g.colidx, vals, x) - 3.0 * oracle.spmv(g.n, g.rowptr, g.colidx, vals, z)
+    np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-12)
+    # with values 1 / outdeg(u) and x = r, one product is the neighbour sum of
+    # a PageRank step: r' = (1-d)/n + d (s + D/n) (leak mode: no D term)
+    deg = np.diff(g.rowptr)
+    r = np.full(g.n, 1.0 / g.n)
+    s = oracle.spmv(g.n, g.rowptr, g.colidx, np.repeat(1.0 / np.maximum(deg, 1), deg), r)
+    want = oracle.pagerank(g.n, g.rowptr, g.colidx, D, 1, mode=oracle.LEAK)
+    np.testing.assert_allclose((1.0 - D) / g.n + D * s, want, rtol=0, atol=1e-15)
