@@ -89,6 +89,55 @@ def spmv(n, rowptr, colidx, values, x):
     return y
 
 
+def bc_dependencies(n, rowptr, colidx, source):
+    """Brandes' single-source dependencies delta_s(v) over the out-arc CSR
+    (unweighted shortest paths): a BFS from s counting shortest paths sigma
+    level by level (a vertex at depth d+1 adds sigma of every in-neighbour at
+    depth d, Algorithm 3's update), then, deepest level first,
+    delta(v) = sum over arcs v -> w with depth(w) = depth(v) + 1 of
+    sigma(v) / sigma(w) * (1 + delta(w)). FP64. Returns (delta, sigma, depth)
+    with depth -1 for unreached vertices and delta(source) = 0."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    colidx = np.asarray(colidx, dtype=np.int64)
+    deg = np.diff(rowptr)
+    depth = np.full(n, -1, dtype=np.int64)
+    sigma = np.zeros(n, dtype=np.float64)
+    depth[source], sigma[source] = 0, 1.0
+    levels = [np.array([source], dtype=np.int64)]
+    d = 0
+    while True:
+        f = levels[-1]
+        src = np.repeat(f, deg[f])
+        dst = colidx[np.concatenate([np.arange(rowptr[u], rowptr[u + 1]) for u in f])] if len(f) else f
+        new = np.unique(dst[depth[dst] == -1])
+        depth[new] = d + 1
+        hit = depth[dst] == d + 1
+        np.add.at(sigma, dst[hit], sigma[src[hit]])
+        if len(new) == 0:
+            break
+        levels.append(new)
+        d += 1
+    delta = np.zeros(n, dtype=np.float64)
+    for lv in range(len(levels) - 2, 0, -1):
+        v = levels[lv]
+        src = np.repeat(v, deg[v])
+        w = colidx[np.concatenate([np.arange(rowptr[u], rowptr[u + 1]) for u in v])]
+        hit = depth[w] == lv + 1
+        np.add.at(delta, src[hit], sigma[src[hit]] / sigma[w[hit]] * (1.0 + delta[w[hit]]))
+    return delta, sigma, depth
+
+
+def bc(n, rowptr, colidx, sources):
+    """Betweenness centrality restricted to the given sources:
+    sum over s of delta_s(v) for v != s (FP64)."""
+    out = np.zeros(n, dtype=np.float64)
+    for s in sources:
+        delta, _, _ = bc_dependencies(n, rowptr, colidx, int(s))
+        delta[int(s)] = 0.0
+        out += delta
+    return out
+
+
 def ppr(n, rowptr, colidx, p, d=0.85, iters=20):
     """FP64 personalised PageRank iterate `iters` from r0 = p."""
     rowptr, colidx = _i32(rowptr), _i32(colidx)

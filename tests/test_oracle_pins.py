@@ -334,3 +334,77 @@ def test_spmv_linearity_and_pagerank_step():
     s = oracle.spmv(g.n, g.rowptr, g.colidx, np.repeat(1.0 / np.maximum(deg, 1), deg), r)
     want = oracle.pagerank(g.n, g.rowptr, g.colidx, D, 1, mode=oracle.LEAK)
     np.testing.assert_allclose((1.0 - D) / g.n + D * s, want, rtol=0, atol=1e-15)
+
+
+# ---- betweenness centrality (Section 4's BC benchmark, Brandes' dependencies) ----
+
+def _all_shortest_paths_bc(n, rowptr, colidx):
+    """BC by explicit enumeration of every shortest path (tiny graphs only):
+    for each (s, t) all simple s -> t paths are listed by depth-first search
+    and the shortest kept; v scores the fraction of them passing through it."""
+    adj = [list(colidx[rowptr[u]:rowptr[u + 1]]) for u in range(n)]
+    out = np.zeros(n)
+    for s in range(n):
+        paths = {t: [] for t in range(n)}
+        stack = [(s, [s])]
+        while stack:
+            u, p = stack.pop()
+            paths[u].append(p)
+            for v in adj[u]:
+                if v not in p:
+                    stack.append((v, p + [v]))
+        for t in range(n):
+            if t == s or not paths[t]:
+                continue
+            L = min(len(p) for p in paths[t])
+            short = [p for p in paths[t] if len(p) == L]
+            for p in short:
+                for v in p[1:-1]:
+                    out[v] += 1.0 / len(short)
+    return out
+
+
+@pytest.mark.parametrize("g", [graphs.random_small(9, 20, 3), graphs.random_small(8, 16, 11), graphs.dangling_mix(),
+                               graphs.two_components(), graphs.cycle(7)], ids=lambda g: g.name)
+def test_bc_matches_path_enumeration(g):
+    if g.n > 10:
+        pytest.skip("enumeration is for tiny graphs")
+    got = oracle.bc(g.n, g.rowptr, g.colidx, range(g.n))
+    np.testing.assert_allclose(got, _all_shortest_paths_bc(g.n, g.rowptr, g.colidx), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("g", [graphs.random_small(60, 240, 7), graphs.dangling_mix(), gg.rmat(8, 8, seed=9),
+                               graphs.two_components()], ids=lambda g: g.name)
+def test_bc_matches_networkx(g):
+    G = nx.DiGraph()
+    G.add_nodes_from(range(g.n))
+    src = np.repeat(np.arange(g.n), np.diff(g.rowptr))
+    G.add_edges_from(zip(src.tolist(), g.colidx.tolist()))
+    want = nx.betweenness_centrality(G, normalized=False)
+    got = oracle.bc(g.n, g.rowptr, g.colidx, range(g.n))
+    np.testing.assert_allclose(got, [want[v] for v in range(g.n)], rtol=1e-12, atol=1e-12)
+
+
+def test_bc_closed_forms():
+    # directed chain 0 -> 1 -> ... -> n-1: v lies on the one path of every
+    # pair s < v < t, so BC(v) = v (n - 1 - v)
+    n = 9
+    rowptr = np.concatenate([np.arange(n), [n - 1]]).astype(np.int32)
+    colidx = np.arange(1, n, dtype=np.int32)
+    np.testing.assert_allclose(oracle.bc(n, rowptr, colidx, range(n)), [v * (n - 1 - v) for v in range(n)])
+    # sigma on a 4 x 4 directed grid (right / down arcs) from the corner is
+    # the binomial count of monotone lattice paths
+    k = 4
+    rows, cols = [], []
+    for r in range(k):
+        for c in range(k):
+            u = r * k + c
+            nb = ([u + 1] if c + 1 < k else []) + ([u + k] if r + 1 < k else [])
+            rows.append(len(nb))
+            cols += nb
+    rowptr = np.concatenate([[0], np.cumsum(rows)]).astype(np.int32)
+    _, sigma, depth = oracle.bc_dependencies(k * k, rowptr, np.array(cols, np.int32), 0)
+    from math import comb
+    for r in range(k):
+        for c in range(k):
+            assert depth[r * k + c] == r + c and sigma[r * k + c] == comb(r + c, r)
