@@ -272,6 +272,57 @@ def suite_spmv(args, gc, gg, torch):
             "spmv": out}
 
 
+def suite_bc(args, gc, gg, torch):
+    """Section 4's BC on R-MAT: Brandes' accumulation from a set of sources,
+    forward levels by plain pull, TOCAB pull, push, or the per-level
+    heuristic. Rate per source = out-arcs of the reached vertices / time of
+    the source's forward and backward passes (the harmonic mean over sources
+    is reported), and the per-kernel times of the whole run."""
+    gh = gg.rmat(args.scale, args.edge_factor, seed=1)
+    n, m = gh.n, gh.m
+    outdeg = np.diff(gh.rowptr).astype(np.int64)
+    g = gc.graph_load_csr(gh.rowptr, gh.colidx)
+    part = gc.tocab_partition(g, gc.GC_PULL, args.traversal_block_width, args.traversal_merge_range)
+    srcs = [int(x) for x in gg.sources(gh, args.bfs_sources or 8, seed=5)]
+    depth = torch.empty(n, dtype=torch.int32, device="cuda")
+    reached_arcs = []
+    for s in srcs:
+        gc.bfs_pull(g, part, s, depth, gc.GC_POLICY_HEURISTIC)
+        reached_arcs.append(int(outdeg[depth.cpu().numpy() != gc.GC_UNREACHED].sum()))
+    bc = torch.zeros(n, dtype=torch.float64, device="cuda")
+    gc.bc_accumulate(g, part, srcs[:1], bc, gc.GC_POLICY_HEURISTIC)  # warm-up, allocates the BC buffers
+    out = {}
+    for name, policy, use_part in (("plain_pull", gc.GC_POLICY_PULL, False), ("tocab_pull", gc.GC_POLICY_PULL, True),
+                                   ("push", gc.GC_POLICY_PUSH, False),
+                                   ("heuristic_tocab", gc.GC_POLICY_HEURISTIC, True)):
+        rates, times = [], []
+        for s, arcs in zip(srcs, reached_arcs):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gc.bc_accumulate(g, part if use_part else None, [s], bc, policy)  # returns once complete
+            dt = time.perf_counter() - t0
+            rates.append(arcs / dt / 1e9)
+            times.append(dt * 1e3)
+        gc.gc_profile(1)  # a second pass with per-kernel events, kept out of the timing above
+        gc.bc_accumulate(g, part if use_part else None, srcs, bc, policy)
+        gc.gc_profile(0)
+        prof = gc.gc_profile_read()
+        hm = len(rates) / sum(1.0 / r for r in rates)
+        out[name] = {"gteps_hmean": round(hm, 3), "ms_mean": round(float(np.mean(times)), 3),
+                     "kernels_ms_per_source": {k: round(v[0] / len(srcs), 4) for k, v in prof.items()}}
+        log(f"bc {name}: {hm:.2f} GTEPS (harmonic mean), {np.mean(times):.2f} ms per source")
+    part.free()
+    g.free()
+    best = max(out, key=lambda k: out[k]["gteps_hmean"])
+    return {"metric": METRIC, "value": out[best]["gteps_hmean"], "unit": "GTEPS", "n_gpus": 1, "steps": len(srcs),
+            "warmup": 1, "ms_per_step": out[best]["ms_mean"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"bc_rmat{args.scale}", "n": n, "m": m, "sources": len(srcs),
+                       "block_width": args.traversal_block_width, "merge_range": args.traversal_merge_range,
+                       "best": best},
+            "bc": out}
+
+
 def suite_batched(args, gc, gg, torch):
     """32 R-MAT graphs (scales 14-20) + 64 PPR seeds on R-MAT 22, 20
     iterations in one captured persistent launch, against the same work as
@@ -466,10 +517,11 @@ def main():
     ap.add_argument("--converge-tol", type=float, default=1e-6,
                     help="L1 tolerance of the convergence-driven TOCAB pull run (0 = skip)")
     ap.add_argument("--bfs-sources", type=int, default=8, help="BFS sources on the same graph (0 = skip)")
-    ap.add_argument("--suite", default="pagerank", choices=["pagerank", "traversal", "batched", "learned", "ladder", "spmv"],
+    ap.add_argument("--suite", default="pagerank", choices=["pagerank", "traversal", "batched", "learned", "ladder", "spmv", "bc"],
                     help="pagerank: RMAT-24 PageRank forms + BFS (default); traversal: grid / uniform BFS+SSSP; "
                          "batched: 32 graphs + 64 PPR seeds in one launch; learned: level scheduler; "
-                         "ladder: Section 4's Base / VWC / CB baselines beside TOCAB; spmv: SpMV plain and blocked")
+                         "ladder: Section 4's Base / VWC / CB baselines beside TOCAB; spmv: SpMV plain and blocked; "
+                         "bc: betweenness centrality from sampled sources")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run a 1 GiB torch copy first (counter scale reference)")
     args = ap.parse_args()
@@ -485,7 +537,7 @@ def main():
     torch.cuda.init()
     if args.suite != "pagerank":
         fn = {"traversal": suite_traversal, "batched": suite_batched, "learned": suite_learned,
-              "ladder": suite_ladder, "spmv": suite_spmv}[args.suite]
+              "ladder": suite_ladder, "spmv": suite_spmv, "bc": suite_bc}[args.suite]
         print(json.dumps(fn(args, gc, gg, torch)), flush=True)
         return
     if args.traffic_probe:

@@ -243,6 +243,28 @@ int bfs_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32_t* le
 int sssp_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* dist, int32_t* rounds,
               uint32_t policy, hipStream_t stream);
 
+/* Betweenness centrality restricted to a source set (the BC benchmark of
+ * Section 4, Brandes' accumulation): for every source s in `sources` (host
+ * int32[n_sources], each in [0, n)), a BFS over out-arcs counts shortest
+ * paths sigma_s (a vertex one level down adds sigma_s of each in-neighbour on
+ * the level above, Algorithm 3's update), then the dependencies
+ * delta_s(v) = sum over arcs v -> w with depth(w) = depth(v) + 1 of
+ * sigma_s(v) / sigma_s(w) * (1 + delta_s(w)) are formed deepest level first
+ * and delta_s(v) is ADDED to bc[v] for every v != s. bc: device double[n],
+ * accumulated into (clear it first for a fresh sum). Path counts and
+ * dependencies are FP64; path counts stay exact below 2^53. Forward levels
+ * run as chosen by `policy` (GC_POLICY_PULL: TOCAB pull over the GC_PULL
+ * partition t with FP64 per-block partials and the Figure 5 merge, or plain
+ * pull with t == NULL; GC_POLICY_PUSH; GC_POLICY_HEURISTIC); GC_POLICY_LEARNED
+ * is refused. The first call allocates 20 bytes per vertex on g (and 8 per
+ * local row on t), freed with them. Synchronises `stream` once per level;
+ * returns after the last source's work is complete. The per-level record of
+ * traversal_trace covers the forward levels of every source in turn.
+ * Errors: GC_EINVAL for bad arguments (NULL or host bc, a source out of
+ * range, a partition of another graph or a GC_PUSH one, the learned policy). */
+int bc_accumulate(gc_graph g, gc_tocab t, const int32_t* sources, int32_t n_sources, double* bc,
+                  uint32_t policy, hipStream_t stream);
+
 /* Per-level record of the last bfs_pull / sssp_pull on g: actions[i] is the
  * way level i ran (0 push, 1 plain pull, 2 TOCAB pull with the call's
  * partition, or 2 + j for the j-th partition attached with sched_attach) and

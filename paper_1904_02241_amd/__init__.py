@@ -51,6 +51,7 @@ SIGNATURES = {
                                          ctypes.POINTER(ctypes.c_double), _vp]),
     "bfs_pull": (ctypes.c_int, [_vp, _vp, _i32, _vp, _p_i32, _u32, _vp]),
     "sssp_pull": (ctypes.c_int, [_vp, _vp, _i32, _vp, _p_i32, _u32, _vp]),
+    "bc_accumulate": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _u32, _vp]),
     "gc_sync": (ctypes.c_int, [_vp]),
     "traversal_trace": (ctypes.c_int, [_vp, _vp, _vp, _i32, _p_i32]),
     "sched_param_count": (ctypes.c_int, [_i32, _p_i64]),
@@ -323,6 +324,14 @@ def sssp_pull(g, t, source, dist, policy=GC_POLICY_PULL, stream=None):
     _check(lib.sssp_pull(_h(g), _h(t), int(source), _ptr(dist), ctypes.byref(rounds), policy, _stream(stream)),
            "sssp_pull")
     return rounds.value
+
+
+def bc_accumulate(g, t, sources, bc, policy=GC_POLICY_PULL, stream=None):
+    """Adds the dependencies of every source in `sources` (host ints) into
+    bc (device float64[n])."""
+    src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).reshape(-1))
+    _check(lib.bc_accumulate(_h(g), _h(t), src.ctypes.data if src.size else None, int(src.size), _ptr(bc), policy,
+                             _stream(stream)), "bc_accumulate")
 
 
 def gc_profile(enable):

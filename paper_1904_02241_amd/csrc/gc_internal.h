@@ -47,6 +47,11 @@ struct gc_graph_s {
   int32_t* queue[2] = {nullptr, nullptr};
   uint32_t* visited = nullptr;  // BFS: bitmap of vertices with a final depth
   int32_t* mark = nullptr;      // SSSP push: round in which a vertex was queued
+  // betweenness centrality (allocated by the first bc_accumulate call):
+  // path counts, dependencies and BFS depths of the current source
+  double* bc_sigma = nullptr;
+  double* bc_delta = nullptr;
+  int32_t* bc_depth = nullptr;
   int32_t* stats = nullptr;     // device counters read back once per level
   int32_t* stats_host = nullptr;  // pinned mirror
   int64_t bytes = 0;
@@ -106,6 +111,7 @@ struct gc_tocab_s {
   int32_t n_chunks = 0;
   int32_t seg_max = 0;            // largest chunk_ns (sizes the work-group's LDS table)
   int32_t* pmin = nullptr;        // [P] traversal partials (next flags / min)
+  double* bc_part = nullptr;      // [P] BC path-count partials (allocated on first use)
   int64_t bytes = 0;
 };
 
@@ -192,6 +198,8 @@ hipError_t bfs_run(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32
                    uint32_t policy, hipStream_t s);
 hipError_t sssp_run(gc_graph g, gc_tocab t, int32_t source, int32_t* dist, int32_t* rounds,
                     uint32_t policy, hipStream_t s, bool* overflow);
+hipError_t bc_run(gc_graph g, gc_tocab t, const int32_t* sources, int32_t n_src, double* bc, uint32_t policy,
+                  hipStream_t s);
 hipError_t collect(gc_graph g, gc_tocab* parts, int32_t n_parts, bool bfs, const int32_t* sources, int32_t n_src,
                    float* features, float* times, int32_t max_rows, int32_t* rows, hipStream_t s);
 void sched_features(int64_t n, int64_t m, int64_t n_f, int64_t m_f, int32_t level, double prior_ms, float* f);

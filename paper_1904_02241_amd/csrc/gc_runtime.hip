@@ -70,7 +70,8 @@ void free_graph(gc_graph g) {
   if (!g) return;
   void* bufs[] = {g->rowptr, g->colidx, g->w, g->t_rowptr, g->t_colidx, g->t_w, g->contrib[0], g->contrib[1],
                   g->sums, g->dpart, g->dtotal, g->counter, g->front, g->next, g->queue[0], g->queue[1],
-                  g->stats, g->tile_row_in, g->visited, g->mark, g->lpart, g->ltotal, g->rank_tmp};
+                  g->stats, g->tile_row_in, g->visited, g->mark, g->lpart, g->ltotal, g->rank_tmp, g->bc_sigma,
+                  g->bc_delta, g->bc_depth};
   for (void* p : bufs)
     if (p) gcx::dev_free(p, nullptr);
   if (g->stats_host) (void)hipHostFree(g->stats_host);
@@ -81,7 +82,7 @@ void free_tocab(gc_tocab t) {
   if (!t) return;
   void* bufs[] = {t->blk_rowoff, t->row_ptr, t->id_map, t->col, t->w, t->range_ptr, t->partial, t->pmin,
                   t->tile_row, t->col16, t->chunk_beg, t->chunk_end, t->chunk_blk, t->wtile_row, t->id16,
-                  t->heads, t->seg, t->rstart, t->id16s, t->chunk_j0, t->chunk_ns};
+                  t->heads, t->seg, t->rstart, t->id16s, t->chunk_j0, t->chunk_ns, t->bc_part};
   for (void* p : bufs)
     if (p) gcx::dev_free(p, nullptr);
   delete t;
@@ -502,6 +503,23 @@ int sssp_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* dist, int32_t* ro
   if (e != hipSuccess) return hip_fail(e, "sssp_pull");
   if (overflow) return fail(GC_EOVERFLOW, "sssp_pull: a distance reached INT32_MAX");
   return GC_OK;
+}
+
+int bc_accumulate(gc_graph g, gc_tocab t, const int32_t* sources, int32_t n_sources, double* bc, uint32_t policy,
+                  hipStream_t stream) {
+  if (!g) return fail(GC_EINVAL, "bc_accumulate: NULL graph");
+  if (t && t->g != g) return fail(GC_EINVAL, "bc_accumulate: partition belongs to another graph");
+  if (t && t->dir != GC_PULL) return fail(GC_EINVAL, "bc_accumulate: partition must be GC_PULL");
+  if (n_sources < 0 || (n_sources > 0 && !sources))
+    return fail(GC_EINVAL, "bc_accumulate: bad source list (%d sources)", n_sources);
+  for (int32_t i = 0; i < n_sources; ++i)
+    if (sources[i] < 0 || sources[i] >= g->n)
+      return fail(GC_EINVAL, "bc_accumulate: source %d outside [0, %d)", sources[i], g->n);
+  if (!bc) return fail(GC_EINVAL, "bc_accumulate: NULL bc");
+  if (!is_device_ptr(bc)) return fail(GC_EINVAL, "bc_accumulate: bc must be device memory");
+  if (policy > GC_POLICY_HEURISTIC) return fail(GC_EINVAL, "bc_accumulate: policy %u not supported", policy);
+  const hipError_t e = gcx::bc_run(g, t, sources, n_sources, bc, policy, stream);
+  return e == hipSuccess ? GC_OK : hip_fail(e, "bc_accumulate");
 }
 
 int traversal_trace(gc_graph g, int32_t* actions, float* ms, int32_t max, int32_t* count) {

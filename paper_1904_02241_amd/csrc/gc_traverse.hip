@@ -452,6 +452,243 @@ __global__ __launch_bounds__(kThreads) void k_sssp_push(const int32_t* __restric
 
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// Betweenness centrality (Section 4's BC benchmark): the BFS levels above
+// also count shortest paths, sigma[v] = sum of sigma[u] over in-neighbours u
+// one level up (Algorithm 3's update); then the dependencies are
+// accumulated level by level backwards (Brandes).
+
+__global__ void k_set_sigma(int32_t src, double* __restrict__ sigma) { sigma[src] = 1.0; }
+
+__global__ void k_fill_f64(double* __restrict__ a, int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = 0.0;
+}
+
+// Sum of sigma[u] over in-arcs [b, e) from active sources u (FP64); rows
+// longer than kHeavy are summed by the whole wave.
+__device__ __forceinline__ double scan_sigma(const int32_t* __restrict__ col, const uint8_t* __restrict__ front,
+                                             const double* __restrict__ sigma, bool active, int32_t b, int32_t e) {
+  const int lane = gcd::lane_id();
+  const bool heavy = active && (e - b) > kHeavy;
+  double s = 0.0;
+  if (active && !heavy)
+    for (int32_t i = b; i < e; ++i) {
+      const int32_t u = col[i];
+      if (front[u]) s += sigma[u];
+    }
+  uint64_t pending = __ballot(heavy);
+  while (pending) {
+    const int owner = __ffsll(static_cast<long long>(pending)) - 1;
+    pending &= pending - 1;
+    const int32_t hb = __shfl(b, owner, kWave), he = __shfl(e, owner, kWave);
+    double m = 0.0;
+    for (int32_t i = hb + lane; i < he; i += kWave) {
+      const int32_t u = col[i];
+      if (front[u]) m += sigma[u];
+    }
+    m = gcd::wave_sum(m);
+    if (lane == owner) s = m;
+  }
+  return s;
+}
+
+// Topology-driven pull: an unvisited vertex with an active in-neighbour
+// joins the next level with the sum of their path counts.
+__global__ __launch_bounds__(kThreads) void k_bc_pull(const int32_t* __restrict__ t_rowptr,
+                                                      const int32_t* __restrict__ t_col, int32_t n,
+                                                      const uint8_t* __restrict__ front, int32_t* __restrict__ depth,
+                                                      int32_t level, double* __restrict__ sigma,
+                                                      uint8_t* __restrict__ next, uint32_t* __restrict__ visited,
+                                                      int32_t* __restrict__ queue, int32_t* __restrict__ stats) {
+  const int32_t v = blockIdx.x * kThreads + threadIdx.x;
+  bool active = false;
+  int32_t b = 0, e = 0;
+  if (v < n && !bit_test(visited, v)) {
+    active = true;
+    b = t_rowptr[v];
+    e = t_rowptr[v + 1];
+  }
+  const double sum = scan_sigma(t_col, front, sigma, active, b, e);
+  const bool found = active && sum > 0.0;  // every active vertex has sigma >= 1
+  if (found) {
+    depth[v] = level + 1;
+    sigma[v] = sum;
+    next[v] = 1;
+    bit_set(visited, v);
+  }
+  wave_append(found, v, queue, stats + kQLen);
+}
+
+// TOCAB pull, per block: part[l] = sum of sigma over the active sources of
+// this block among the in-arcs of local row l (0 when its vertex is visited).
+__global__ __launch_bounds__(kThreads) void k_bc_tocab(const int32_t* __restrict__ row_ptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const int32_t* __restrict__ id_map, int64_t P,
+                                                       const uint32_t* __restrict__ visited,
+                                                       const uint8_t* __restrict__ front,
+                                                       const double* __restrict__ sigma, double* __restrict__ part) {
+  const int64_t l = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  bool active = false;
+  int32_t b = 0, e = 0;
+  if (l < P && !bit_test(visited, id_map[l])) {
+    active = true;
+    b = row_ptr[l];
+    e = row_ptr[l + 1];
+  }
+  const double sum = scan_sigma(col, front, sigma, active, b, e);
+  if (l < P) part[l] = sum;
+}
+
+// Merge of the per-block path counts over vertex range j (FP64 LDS sums),
+// fused with the depth / sigma update and the next frontier.
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_bc_merge(const int32_t* __restrict__ range_ptr, int32_t B,
+                                                       const int32_t* __restrict__ id_map,
+                                                       const double* __restrict__ part, int32_t n,
+                                                       int32_t* __restrict__ depth, int32_t level,
+                                                       double* __restrict__ sigma, uint8_t* __restrict__ next,
+                                                       uint32_t* __restrict__ visited, int32_t* __restrict__ queue,
+                                                       int32_t* __restrict__ stats) {
+  __shared__ double acc[K];
+  const int32_t v0 = blockIdx.x * K;
+  for (int i = threadIdx.x; i < K; i += kThreads) acc[i] = 0.0;
+  __syncthreads();
+  const int32_t* lo = range_ptr + static_cast<int64_t>(blockIdx.x) * B;
+  const int32_t* hi = lo + B;
+  for (int32_t s = 0; s < B; ++s) {
+    const int32_t a = lo[s], z = hi[s];
+    for (int32_t l = a + threadIdx.x; l < z; l += kThreads) {
+      const double x = part[l];
+      if (x != 0.0) atomicAdd(&acc[id_map[l] - v0], x);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < K; i += kThreads) {
+    const int32_t v = v0 + i;
+    const bool found = v < n && acc[i] > 0.0 && !bit_test(visited, v);
+    if (found) {
+      depth[v] = level + 1;
+      sigma[v] = acc[i];
+      next[v] = 1;
+      bit_set(visited, v);
+    }
+    wave_append(found, v, queue, stats + kQLen);
+  }
+}
+
+// Data-driven push (Algorithm 3): like the BFS push, plus sigma[v] +=
+// sigma[u] (FP64 atomic) for every arc u -> v that lands one level down.
+__global__ __launch_bounds__(kThreads) void k_bc_push(const int32_t* __restrict__ queue_in, int32_t qn,
+                                                      const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ colidx,
+                                                      int32_t* __restrict__ depth, int32_t level,
+                                                      double* __restrict__ sigma, uint8_t* __restrict__ next,
+                                                      uint32_t* __restrict__ visited, int32_t* __restrict__ queue,
+                                                      int32_t* __restrict__ stats) {
+  __shared__ int32_t start[kThreads];
+  __shared__ int32_t first[kThreads];
+  __shared__ double su[kThreads];
+  __shared__ int32_t wave_tot[kThreads / kWave];
+  const int32_t i = blockIdx.x * kThreads + threadIdx.x;
+  int32_t b = 0, len = 0;
+  double sg = 0.0;
+  if (i < qn) {
+    const int32_t u = queue_in[i];
+    b = rowptr[u];
+    len = rowptr[u + 1] - b;
+    sg = sigma[u];
+  }
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int incl = gcd::wave_incl_scan(len);
+  if (lane == kWave - 1) wave_tot[wid] = incl;
+  __syncthreads();
+  int off = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / kWave; ++w) {
+    off += (w < wid) ? wave_tot[w] : 0;
+    total += wave_tot[w];
+  }
+  start[threadIdx.x] = off + incl - len;
+  first[threadIdx.x] = b;
+  su[threadIdx.x] = sg;
+  __syncthreads();
+  // every wave runs the same number of rounds so that wave_append sees whole waves
+  const int32_t rounds = (total + kThreads - 1) / kThreads;
+  for (int32_t r = 0; r < rounds; ++r) {
+    const int32_t a = r * kThreads + threadIdx.x;
+    bool disc = false;
+    int32_t v = 0;
+    if (a < total) {
+      int lo = 0, hi = kThreads - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= a) lo = mid;
+        else hi = mid - 1;
+      }
+      v = colidx[first[lo] + (a - start[lo])];
+      int32_t old = depth[v];
+      if (old == kInf) {
+        old = atomicCAS(&depth[v], kInf, level + 1);
+        if (old == kInf) {
+          disc = true;
+          next[v] = 1;
+          bit_set(visited, v);
+        }
+      }
+      if (old == kInf || old == level + 1) atomicAdd(&sigma[v], su[lo]);
+    }
+    wave_append(disc, v, queue, stats + kQLen);
+  }
+}
+
+// Backward step for depth `level`: delta[v] = sigma[v] * sum over out-arcs
+// v -> w one level down of (1 + delta[w]) / sigma[w], added into bc[v];
+// rows longer than kHeavy are summed by the whole wave.
+__global__ __launch_bounds__(kThreads) void k_bc_back(const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ colidx, int32_t n,
+                                                      const int32_t* __restrict__ depth, int32_t level,
+                                                      const double* __restrict__ sigma, double* __restrict__ delta,
+                                                      double* __restrict__ bc) {
+  const int32_t v = blockIdx.x * kThreads + threadIdx.x;
+  const int lane = gcd::lane_id();
+  const bool active = v < n && depth[v] == level;
+  const int32_t b = active ? rowptr[v] : 0, e = active ? rowptr[v + 1] : 0;
+  const bool heavy = active && (e - b) > kHeavy;
+  double s = 0.0;
+  if (active && !heavy)
+    for (int32_t i = b; i < e; ++i) {
+      const int32_t w = colidx[i];
+      if (depth[w] == level + 1) s += (1.0 + delta[w]) / sigma[w];
+    }
+  uint64_t pending = __ballot(heavy);
+  while (pending) {
+    const int owner = __ffsll(static_cast<long long>(pending)) - 1;
+    pending &= pending - 1;
+    const int32_t hb = __shfl(b, owner, kWave), he = __shfl(e, owner, kWave);
+    double m = 0.0;
+    for (int32_t i = hb + lane; i < he; i += kWave) {
+      const int32_t w = colidx[i];
+      if (depth[w] == level + 1) m += (1.0 + delta[w]) / sigma[w];
+    }
+    m = gcd::wave_sum(m);
+    if (lane == owner) s = m;
+  }
+  if (active) {
+    const double d = sigma[v] * s;
+    delta[v] = d;
+    bc[v] += d;
+  }
+}
+
+template <int K>
+struct BcMerge {
+  template <class... A>
+  static void run(int32_t R, hipStream_t s, A... a) {
+    k_bc_merge<K><<<R, kThreads, 0, s>>>(a...);
+  }
+};
+
 inline int grid_for(int64_t items, int threads) {
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((items + threads - 1) / threads, 1 << 20)));
 }
@@ -640,6 +877,34 @@ void action_mode(int32_t a, gc_tocab* parts, Mode* mode, gc_tocab* t) {
 
 int32_t mode_action(Mode m) { return m == Mode::kPush ? 0 : (m == Mode::kPull ? 1 : 2); }
 
+// One forward BC level (depth `level` -> level+1): depth, sigma and the next
+// frontier, in the given mode.
+hipError_t run_bc_level(gc_graph g, Frontier& f, int32_t level, Mode mode, gc_tocab t, hipStream_t s) {
+  const int32_t n = g->n;
+  if (mode == Mode::kPush) {
+    ProfScope prof("bc_push", s);
+    k_bc_push<<<grid_for(f.n_f, kThreads), kThreads, 0, s>>>(f.queue(), f.n_f, g->rowptr, g->colidx, g->bc_depth,
+                                                              level, g->bc_sigma, f.next(), g->visited,
+                                                              f.queue_next(), g->stats);
+  } else if (mode == Mode::kPull) {
+    ProfScope prof("bc_pull", s);
+    k_bc_pull<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, n, f.front(), g->bc_depth, level,
+                                                          g->bc_sigma, f.next(), g->visited, f.queue_next(),
+                                                          g->stats);
+  } else {
+    {
+      ProfScope prof("bc_tocab", s);
+      k_bc_tocab<<<grid_for(t->P, kThreads), kThreads, 0, s>>>(t->row_ptr, t->col, t->id_map, t->P, g->visited,
+                                                                f.front(), g->bc_sigma, t->bc_part);
+    }
+    ProfScope prof("bc_merge", s);
+    GC_HIP_TRY((launch_by_k<BcMerge>(t->k, t->R, s, t->range_ptr, t->B, static_cast<const int32_t*>(t->id_map),
+                                     static_cast<const double*>(t->bc_part), n, g->bc_depth, level, g->bc_sigma,
+                                     f.next(), g->visited, f.queue_next(), g->stats)));
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
 namespace gcx {
@@ -726,6 +991,72 @@ hipError_t bfs_run(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32
 hipError_t sssp_run(gc_graph g, gc_tocab t, int32_t source, int32_t* dist, int32_t* rounds, uint32_t policy,
                     hipStream_t s, bool* overflow) {
   return traverse(g, t, source, dist, rounds, policy, s, false, overflow);
+}
+
+// Betweenness centrality from the given sources (Brandes): per source, the
+// forward levels count shortest paths (push, pull or TOCAB pull per level,
+// chosen as for BFS), then the backward steps accumulate the dependencies
+// deepest level first into bc. The per-graph sigma / delta / depth arrays
+// and the partition's FP64 partials are allocated by the first call.
+hipError_t bc_run(gc_graph g, gc_tocab t, const int32_t* sources, int32_t n_src, double* bc, uint32_t policy,
+                  hipStream_t s) {
+  const int32_t n = g->n;
+  if (!g->bc_sigma) {
+    g->bc_sigma = static_cast<double*>(dev_alloc(sizeof(double) * n, s));
+    g->bc_delta = static_cast<double*>(dev_alloc(sizeof(double) * n, s));
+    g->bc_depth = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * n, s));
+    if (!g->bc_sigma || !g->bc_delta || !g->bc_depth) {
+      for (void* p : {static_cast<void*>(g->bc_sigma), static_cast<void*>(g->bc_delta),
+                      static_cast<void*>(g->bc_depth)})
+        if (p) dev_free(p, s);
+      g->bc_sigma = g->bc_delta = nullptr;
+      g->bc_depth = nullptr;
+      return hipErrorOutOfMemory;
+    }
+  }
+  if (t && !t->bc_part) {
+    t->bc_part = static_cast<double*>(dev_alloc(sizeof(double) * std::max<int64_t>(t->P, 1), s));
+    if (!t->bc_part) return hipErrorOutOfMemory;
+  }
+  g->trace_action.clear();
+  g->trace_ms.clear();
+  for (int32_t si = 0; si < n_src; ++si) {
+    const int32_t src = sources[si];
+    GC_HIP_TRY(init_state(g, g->bc_depth, src, true, s));
+    k_fill_f64<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->bc_sigma, n);
+    k_fill_f64<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->bc_delta, n);
+    k_set_sigma<<<1, 1, 0, s>>>(src, g->bc_sigma);
+    GC_HIP_TRY(hipGetLastError());
+    Frontier f{g, s};
+    hipError_t e;
+    f.m_f = source_degree(g, src, s, &e);
+    GC_HIP_TRY(e);
+    int64_t m_u = g->m - f.m_f;
+    Heuristic h;
+    int32_t level = 0;
+    while (f.n_f > 0) {
+      Mode mode;
+      if (policy == GC_POLICY_PUSH) mode = Mode::kPush;
+      else if (policy == GC_POLICY_PULL) mode = t ? Mode::kTocab : Mode::kPull;
+      else mode = h.pick(n, f.n_f, f.m_f, m_u, t != nullptr);
+      const double t0 = now_ms();
+      GC_HIP_TRY(f.begin_level());
+      GC_HIP_TRY(run_bc_level(g, f, level, mode, t, s));
+      GC_HIP_TRY(f.end_level(nullptr));
+      g->trace_action.push_back(mode_action(mode));
+      g->trace_ms.push_back(static_cast<float>(now_ms() - t0));
+      m_u -= f.m_f;
+      ++level;
+    }
+    // depths run 0 .. level-1; delta is zero at the deepest level, and the
+    // source (depth 0) takes no share
+    ProfScope prof("bc_back", s);
+    for (int32_t d = level - 2; d >= 1; --d)
+      k_bc_back<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->rowptr, g->colidx, n, g->bc_depth, d, g->bc_sigma,
+                                                            g->bc_delta, bc);
+    GC_HIP_TRY(hipGetLastError());
+  }
+  return hipStreamSynchronize(s);
 }
 
 // Training data for the scheduler: at every level of a traversal from each
