@@ -48,10 +48,15 @@ struct gc_graph_s {
   uint32_t* visited = nullptr;  // BFS: bitmap of vertices with a final depth
   int32_t* mark = nullptr;      // SSSP push: round in which a vertex was queued
   // betweenness centrality (allocated by the first bc_accumulate call):
-  // path counts, dependencies and BFS depths of the current source
+  // path counts, two alternating arrays of (1 + delta) / sigma, BFS depths
+  // and the vertices in level order of the current source, with the scan of
+  // their out-degrees
   double* bc_sigma = nullptr;
-  double* bc_delta = nullptr;
+  double* bc_coef = nullptr;  // [2n]
   int32_t* bc_depth = nullptr;
+  int32_t* bc_order = nullptr;
+  int32_t* bc_pre = nullptr;  // [n+1] exclusive scan of out-degrees along bc_order (or a push level's queue)
+  int32_t* bc_deg = nullptr;  // [n] the out-degrees being scanned
   int32_t* stats = nullptr;     // device counters read back once per level
   int32_t* stats_host = nullptr;  // pinned mirror
   int64_t bytes = 0;

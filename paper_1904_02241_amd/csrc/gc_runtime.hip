@@ -71,7 +71,8 @@ void free_graph(gc_graph g) {
   void* bufs[] = {g->rowptr, g->colidx, g->w, g->t_rowptr, g->t_colidx, g->t_w, g->contrib[0], g->contrib[1],
                   g->sums, g->dpart, g->dtotal, g->counter, g->front, g->next, g->queue[0], g->queue[1],
                   g->stats, g->tile_row_in, g->visited, g->mark, g->lpart, g->ltotal, g->rank_tmp, g->bc_sigma,
-                  g->bc_delta, g->bc_depth};
+                  g->bc_coef, g->bc_depth, g->bc_order, g->bc_pre,
+                  g->bc_deg};
   for (void* p : bufs)
     if (p) gcx::dev_free(p, nullptr);
   if (g->stats_host) (void)hipHostFree(g->stats_host);

@@ -24,6 +24,7 @@
 
 #include "gc_device.h"
 #include "gc_internal.h"
+#include "gc_merge.h"
 
 namespace {
 
@@ -40,17 +41,30 @@ constexpr int kQLen = 0;       // vertices appended to the next queue
 constexpr int kOverflow = 1;   // SSSP: a path length reached INT32_MAX
 constexpr int kDegLo = 2;      // out-arcs of the next frontier (64-bit: lo, hi)
 
-// Appends v to queue for every lane with take set: one atomic per wave,
-// positions from the lane's rank among the taking lanes.
-__device__ __forceinline__ void wave_append(bool take, int32_t v, int32_t* __restrict__ queue,
-                                            int32_t* __restrict__ qlen) {
+// Appends v to queue for every thread with take set, with one atomic on the
+// queue length per work-group (per-wave atomics on the one counter
+// serialise in L2 when most waves of a large grid append); positions follow
+// the thread order inside the work-group. Synchronises the work-group: every
+// thread must reach each call.
+__device__ __forceinline__ void block_append(bool take, int32_t v, int32_t* __restrict__ queue,
+                                             int32_t* __restrict__ qlen) {
+  __shared__ int32_t wave_cnt[kThreads / kWave];
+  __shared__ int32_t wave_off[kThreads / kWave];
   const uint64_t mask = __ballot(take);
-  if (mask == 0) return;
-  const int leader = __ffsll(static_cast<long long>(mask)) - 1;
-  int32_t base = 0;
-  if (gcd::lane_id() == leader) base = atomicAdd(qlen, __popcll(mask));
-  base = __shfl(base, leader, kWave);
-  if (take) queue[base + __popcll(mask & gcd::lanemask_lt())] = v;
+  const int wid = threadIdx.x / kWave;
+  if (gcd::lane_id() == 0) wave_cnt[wid] = __popcll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t tot = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) {
+      wave_off[w] = tot;
+      tot += wave_cnt[w];
+    }
+    const int32_t base = tot ? atomicAdd(qlen, tot) : 0;
+    for (int w = 0; w < kThreads / kWave; ++w) wave_off[w] += base;
+  }
+  __syncthreads();
+  if (take) queue[wave_off[wid] + __popcll(mask & gcd::lanemask_lt())] = v;
 }
 
 __device__ __forceinline__ bool bit_test(const uint32_t* bits, int32_t v) {
@@ -153,7 +167,7 @@ __global__ __launch_bounds__(kThreads) void k_bfs_pull(const int32_t* __restrict
     next[v] = 1;
     bit_set(visited, v);
   }
-  wave_append(found, v, queue, stats + kQLen);
+  block_append(found, v, queue, stats + kQLen);
 }
 
 // TOCAB pull, per block: flag[l] = 1 when local row l (an unvisited vertex)
@@ -206,7 +220,7 @@ __global__ __launch_bounds__(kThreads) void k_bfs_merge(const int32_t* __restric
       next[v] = 1;
       bit_set(visited, v);
     }
-    wave_append(found, v, queue, stats + kQLen);
+    block_append(found, v, queue, stats + kQLen);
   }
 }
 
@@ -242,7 +256,7 @@ __global__ __launch_bounds__(kThreads) void k_bfs_push(const int32_t* __restrict
   start[threadIdx.x] = off + incl - len;
   first[threadIdx.x] = b;
   __syncthreads();
-  // every wave runs the same number of rounds so that wave_append sees whole waves
+  // every thread runs the same number of rounds (block_append synchronises the work-group)
   const int32_t rounds = (total + kThreads - 1) / kThreads;
   for (int32_t r = 0; r < rounds; ++r) {
     const int32_t a = r * kThreads + threadIdx.x;
@@ -262,7 +276,7 @@ __global__ __launch_bounds__(kThreads) void k_bfs_push(const int32_t* __restrict
         bit_set(visited, v);
       }
     }
-    wave_append(disc, v, queue, stats + kQLen);
+    block_append(disc, v, queue, stats + kQLen);
   }
 }
 
@@ -331,7 +345,7 @@ __global__ __launch_bounds__(kThreads) void k_sssp_pull(const int32_t* __restric
     next[v] = 1;
     improved = true;
   }
-  wave_append(improved, v, queue, stats + kQLen);
+  block_append(improved, v, queue, stats + kQLen);
 }
 
 // TOCAB pull, per block: pmin[l] = min over active sources of this block of
@@ -382,7 +396,7 @@ __global__ __launch_bounds__(kThreads) void k_sssp_merge(const int32_t* __restri
       next[v] = 1;
       improved = true;
     }
-    wave_append(improved, v, queue, stats + kQLen);
+    block_append(improved, v, queue, stats + kQLen);
   }
 }
 
@@ -446,7 +460,7 @@ __global__ __launch_bounds__(kThreads) void k_sssp_push(const int32_t* __restric
         }
       }
     }
-    wave_append(fresh, v, queue, stats + kQLen);
+    block_append(fresh, v, queue, stats + kQLen);
   }
 }
 
@@ -472,11 +486,23 @@ __device__ __forceinline__ double scan_sigma(const int32_t* __restrict__ col, co
   const int lane = gcd::lane_id();
   const bool heavy = active && (e - b) > kHeavy;
   double s = 0.0;
-  if (active && !heavy)
-    for (int32_t i = b; i < e; ++i) {
+  if (active && !heavy) {
+    int32_t i = b;
+    for (; i + 4 <= e; i += 4) {  // four arcs' loads in flight at a time
+      int32_t u[4];
+      bool on[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) u[k] = col[i + k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) on[k] = front[u[k]] != 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s += on[k] ? sigma[u[k]] : 0.0;
+    }
+    for (; i < e; ++i) {
       const int32_t u = col[i];
       if (front[u]) s += sigma[u];
     }
+  }
   uint64_t pending = __ballot(heavy);
   while (pending) {
     const int owner = __ffsll(static_cast<long long>(pending)) - 1;
@@ -517,7 +543,7 @@ __global__ __launch_bounds__(kThreads) void k_bc_pull(const int32_t* __restrict_
     next[v] = 1;
     bit_set(visited, v);
   }
-  wave_append(found, v, queue, stats + kQLen);
+  block_append(found, v, queue, stats + kQLen);
 }
 
 // TOCAB pull, per block: part[l] = sum of sigma over the active sources of
@@ -542,28 +568,17 @@ __global__ __launch_bounds__(kThreads) void k_bc_tocab(const int32_t* __restrict
 
 // Merge of the per-block path counts over vertex range j (FP64 LDS sums),
 // fused with the depth / sigma update and the next frontier.
-template <int K>
+template <int K, bool kFlat>
 __global__ __launch_bounds__(kThreads) void k_bc_merge(const int32_t* __restrict__ range_ptr, int32_t B,
-                                                       const int32_t* __restrict__ id_map,
+                                                       const uint16_t* __restrict__ id16,
                                                        const double* __restrict__ part, int32_t n,
                                                        int32_t* __restrict__ depth, int32_t level,
                                                        double* __restrict__ sigma, uint8_t* __restrict__ next,
                                                        uint32_t* __restrict__ visited, int32_t* __restrict__ queue,
                                                        int32_t* __restrict__ stats) {
   __shared__ double acc[K];
+  gcm::merge_accumulate<K, kFlat, kThreads>(range_ptr, B, id16, part, blockIdx.x, acc);
   const int32_t v0 = blockIdx.x * K;
-  for (int i = threadIdx.x; i < K; i += kThreads) acc[i] = 0.0;
-  __syncthreads();
-  const int32_t* lo = range_ptr + static_cast<int64_t>(blockIdx.x) * B;
-  const int32_t* hi = lo + B;
-  for (int32_t s = 0; s < B; ++s) {
-    const int32_t a = lo[s], z = hi[s];
-    for (int32_t l = a + threadIdx.x; l < z; l += kThreads) {
-      const double x = part[l];
-      if (x != 0.0) atomicAdd(&acc[id_map[l] - v0], x);
-    }
-  }
-  __syncthreads();
   for (int i = threadIdx.x; i < K; i += kThreads) {
     const int32_t v = v0 + i;
     const bool found = v < n && acc[i] > 0.0 && !bit_test(visited, v);
@@ -573,7 +588,7 @@ __global__ __launch_bounds__(kThreads) void k_bc_merge(const int32_t* __restrict
       next[v] = 1;
       bit_set(visited, v);
     }
-    wave_append(found, v, queue, stats + kQLen);
+    block_append(found, v, queue, stats + kQLen);
   }
 }
 
@@ -613,7 +628,7 @@ __global__ __launch_bounds__(kThreads) void k_bc_push(const int32_t* __restrict_
   first[threadIdx.x] = b;
   su[threadIdx.x] = sg;
   __syncthreads();
-  // every wave runs the same number of rounds so that wave_append sees whole waves
+  // every thread runs the same number of rounds (block_append synchronises the work-group)
   const int32_t rounds = (total + kThreads - 1) / kThreads;
   for (int32_t r = 0; r < rounds; ++r) {
     const int32_t a = r * kThreads + threadIdx.x;
@@ -638,54 +653,186 @@ __global__ __launch_bounds__(kThreads) void k_bc_push(const int32_t* __restrict_
       }
       if (old == kInf || old == level + 1) atomicAdd(&sigma[v], su[lo]);
     }
-    wave_append(disc, v, queue, stats + kQLen);
+    block_append(disc, v, queue, stats + kQLen);
   }
 }
 
-// Backward step for depth `level`: delta[v] = sigma[v] * sum over out-arcs
-// v -> w one level down of (1 + delta[w]) / sigma[w], added into bc[v];
-// rows longer than kHeavy are summed by the whole wave.
-__global__ __launch_bounds__(kThreads) void k_bc_back(const int32_t* __restrict__ rowptr,
-                                                      const int32_t* __restrict__ colidx, int32_t n,
-                                                      const int32_t* __restrict__ depth, int32_t level,
-                                                      const double* __restrict__ sigma, double* __restrict__ delta,
-                                                      double* __restrict__ bc) {
-  const int32_t v = blockIdx.x * kThreads + threadIdx.x;
-  const int lane = gcd::lane_id();
-  const bool active = v < n && depth[v] == level;
-  const int32_t b = active ? rowptr[v] : 0, e = active ? rowptr[v + 1] : 0;
-  const bool heavy = active && (e - b) > kHeavy;
-  double s = 0.0;
-  if (active && !heavy)
-    for (int32_t i = b; i < e; ++i) {
-      const int32_t w = colidx[i];
-      if (depth[w] == level + 1) s += (1.0 + delta[w]) / sigma[w];
+// The same push balanced over arcs for frontiers with many arcs: pre is the
+// exclusive scan of the queued vertices' out-degrees, and each lane takes
+// kPushArcs consecutive arcs of the concatenated out-arc lists (a hub's arcs
+// spread over many work-groups instead of one).
+constexpr int kPushArcs = 8;
+
+__global__ __launch_bounds__(kThreads) void k_bc_push_arcs(const int32_t* __restrict__ queue_in,
+                                                           const int32_t* __restrict__ pre, int32_t qn,
+                                                           const int32_t* __restrict__ rowptr,
+                                                           const int32_t* __restrict__ colidx,
+                                                           int32_t* __restrict__ depth, int32_t level,
+                                                           double* __restrict__ sigma, uint8_t* __restrict__ next,
+                                                           uint32_t* __restrict__ visited, int32_t* __restrict__ queue,
+                                                           int32_t* __restrict__ stats) {
+  const int64_t end = pre[qn];
+  const int64_t a0 = (static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x) * kPushArcs;
+  int32_t i = 0;
+  if (a0 < end) {  // the queued vertex whose arcs contain a0: the last i with pre[i] <= a0
+    int32_t h = qn - 1;
+    while (i < h) {
+      const int32_t mid = i + ((h - i + 1) >> 1);
+      if (pre[mid] <= a0) i = mid;
+      else h = mid - 1;
     }
-  uint64_t pending = __ballot(heavy);
-  while (pending) {
-    const int owner = __ffsll(static_cast<long long>(pending)) - 1;
-    pending &= pending - 1;
-    const int32_t hb = __shfl(b, owner, kWave), he = __shfl(e, owner, kWave);
-    double m = 0.0;
-    for (int32_t i = hb + lane; i < he; i += kWave) {
-      const int32_t w = colidx[i];
-      if (depth[w] == level + 1) m += (1.0 + delta[w]) / sigma[w];
-    }
-    m = gcd::wave_sum(m);
-    if (lane == owner) s = m;
   }
-  if (active) {
-    const double d = sigma[v] * s;
-    delta[v] = d;
+  int64_t ub = 0, ue = 0, rb = 0;
+  double su = 0.0;
+  if (a0 < end) {
+    const int32_t u = queue_in[i];
+    ub = pre[i];
+    ue = pre[i + 1];
+    rb = rowptr[u];
+    su = sigma[u];
+  }
+  // every thread runs the same kPushArcs steps (block_append synchronises the work-group)
+#pragma unroll 1
+  for (int k = 0; k < kPushArcs; ++k) {
+    const int64_t a = a0 + k;
+    bool disc = false;
+    int32_t v = 0;
+    if (a < end) {
+      while (a >= ue) {  // next queued vertex with an arc at a
+        ++i;
+        const int32_t u = queue_in[i];
+        ub = pre[i];
+        ue = pre[i + 1];
+        rb = rowptr[u];
+        su = sigma[u];
+      }
+      v = colidx[rb + (a - ub)];
+      int32_t old = depth[v];
+      if (old == kInf) {
+        old = atomicCAS(&depth[v], kInf, level + 1);
+        if (old == kInf) {
+          disc = true;
+          next[v] = 1;
+          bit_set(visited, v);
+        }
+      }
+      if (old == kInf || old == level + 1) atomicAdd(&sigma[v], su);
+    }
+    block_append(disc, v, queue, stats + kQLen);
+  }
+}
+
+// Backward sweep. coef[v] = (1 + delta[v]) / sigma[v]; two arrays alternate
+// from level to level. When depth d is processed, the array it reads holds
+// the coefficients of depth d + 1 and zero for depth d and every depth above
+// (an arc from depth d reaches depth d + 1 at most), so the sum over all
+// out-arcs of coef needs no depth test; the array it writes is zero at the
+// vertices of depth d.
+constexpr int kBackArcs = 8;  // consecutive arcs per lane
+
+__global__ void k_order_degree(const int32_t* __restrict__ order, int32_t cnt, const int32_t* __restrict__ rowptr,
+                               int32_t* __restrict__ deg) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) {
+    const int32_t v = order[i];
+    deg[i] = rowptr[v + 1] - rowptr[v];
+  }
+}
+
+// Sums for the vertices order[lo, hi) of one depth, balanced over arcs: the
+// level's out-arcs, concatenated in level order (pre = exclusive scan of the
+// degrees along order), are cut into kBackArcs-arc pieces, one per lane. A
+// lane adds the sum of coef_in over each vertex's arcs in its piece into
+// coef_out[v] (FP64 atomic), or stores it when the piece holds all of v's
+// arcs.
+__global__ __launch_bounds__(kThreads) void k_bc_back_arcs(const int32_t* __restrict__ rowptr,
+                                                           const int32_t* __restrict__ colidx,
+                                                           const int32_t* __restrict__ order,
+                                                           const int32_t* __restrict__ pre, int32_t lo, int32_t hi,
+                                                           const double* __restrict__ coef_in,
+                                                           double* __restrict__ coef_out) {
+  const int64_t end = pre[hi];
+  const int64_t a0 = pre[lo] + (static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x) * kBackArcs;
+  if (a0 >= end) return;
+  const int64_t a1 = a0 + kBackArcs < end ? a0 + kBackArcs : end;
+  // the vertex whose arcs contain a0: the last i in [lo, hi) with pre[i] <= a0
+  int32_t l = lo, h = hi - 1;
+  while (l < h) {
+    const int32_t mid = l + ((h - l + 1) >> 1);
+    if (pre[mid] <= a0) l = mid;
+    else h = mid - 1;
+  }
+  // owner and position of each of the lane's arcs, then all column loads,
+  // then all coefficient gathers, so that kBackArcs gathers are in flight
+  int64_t pos[kBackArcs];
+  int32_t vid[kBackArcs];
+  bool whole[kBackArcs];
+  {
+    int32_t i = l;
+    int32_t v = order[i];
+    int64_t vb = pre[i], ve = pre[i + 1];
+    int64_t rb = rowptr[v];
+#pragma unroll
+    for (int k = 0; k < kBackArcs; ++k) {
+      const int64_t a = a0 + k;
+      if (a < a1) {
+        while (a >= ve) {  // next vertex with an arc at a (vertices without out-arcs are skipped)
+          ++i;
+          vb = ve;
+          ve = pre[i + 1];
+          v = order[i];
+          rb = rowptr[v];
+        }
+        pos[k] = rb + (a - vb);
+        vid[k] = v;
+        whole[k] = vb >= a0 && ve <= a1;
+      } else {
+        pos[k] = pos[0];
+        vid[k] = -1;
+        whole[k] = false;
+      }
+    }
+  }
+  int32_t w[kBackArcs];
+#pragma unroll
+  for (int k = 0; k < kBackArcs; ++k) w[k] = colidx[pos[k]];
+  double c[kBackArcs];
+#pragma unroll
+  for (int k = 0; k < kBackArcs; ++k) c[k] = coef_in[w[k]];
+  // sums per vertex run: a plain store when the lane holds all of v's arcs
+  double sum = 0.0;
+#pragma unroll
+  for (int k = 0; k < kBackArcs; ++k) {
+    if (vid[k] < 0) break;
+    sum += c[k];
+    if (k == kBackArcs - 1 || vid[k + 1] != vid[k]) {
+      if (whole[k]) coef_out[vid[k]] = sum;
+      else if (sum != 0.0) atomicAdd(&coef_out[vid[k]], sum);
+      sum = 0.0;
+    }
+  }
+}
+
+// delta[v] = sigma[v] * (sum held in coef[v]) is added into bc[v], and
+// coef[v] becomes (1 + delta[v]) / sigma[v].
+__global__ void k_bc_finish(const int32_t* __restrict__ order, int32_t cnt, const double* __restrict__ sigma,
+                            double* __restrict__ coef, double* __restrict__ bc) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) {
+    const int32_t v = order[i];
+    const double sg = sigma[v];
+    const double d = sg * coef[v];
     bc[v] += d;
+    coef[v] = (1.0 + d) / sg;
   }
 }
 
 template <int K>
 struct BcMerge {
   template <class... A>
-  static void run(int32_t R, hipStream_t s, A... a) {
-    k_bc_merge<K><<<R, kThreads, 0, s>>>(a...);
+  static void run(int32_t R, hipStream_t s, const int32_t* range_ptr, int32_t B, A... a) {
+    if (B <= gcm::kFlatB) k_bc_merge<K, true><<<R, kThreads, 0, s>>>(range_ptr, B, a...);
+    else k_bc_merge<K, false><<<R, kThreads, 0, s>>>(range_ptr, B, a...);
   }
 };
 
@@ -881,7 +1028,16 @@ int32_t mode_action(Mode m) { return m == Mode::kPush ? 0 : (m == Mode::kPull ? 
 // frontier, in the given mode.
 hipError_t run_bc_level(gc_graph g, Frontier& f, int32_t level, Mode mode, gc_tocab t, hipStream_t s) {
   const int32_t n = g->n;
-  if (mode == Mode::kPush) {
+  if (mode == Mode::kPush && f.m_f > kThreads * kPushArcs) {
+    ProfScope prof("bc_push", s);
+    k_order_degree<<<grid_for(f.n_f, kThreads), kThreads, 0, s>>>(f.queue(), f.n_f, g->rowptr, g->bc_deg);
+    GC_HIP_TRY(hipGetLastError());
+    GC_HIP_TRY(gcx::scan_exclusive(g->bc_deg, g->bc_pre, f.n_f, s));
+    const int64_t pieces = (f.m_f + kPushArcs - 1) / kPushArcs;
+    k_bc_push_arcs<<<grid_for(pieces, kThreads), kThreads, 0, s>>>(f.queue(), g->bc_pre, f.n_f, g->rowptr,
+                                                                   g->colidx, g->bc_depth, level, g->bc_sigma,
+                                                                   f.next(), g->visited, f.queue_next(), g->stats);
+  } else if (mode == Mode::kPush) {
     ProfScope prof("bc_push", s);
     k_bc_push<<<grid_for(f.n_f, kThreads), kThreads, 0, s>>>(f.queue(), f.n_f, g->rowptr, g->colidx, g->bc_depth,
                                                               level, g->bc_sigma, f.next(), g->visited,
@@ -898,9 +1054,10 @@ hipError_t run_bc_level(gc_graph g, Frontier& f, int32_t level, Mode mode, gc_to
                                                                 f.front(), g->bc_sigma, t->bc_part);
     }
     ProfScope prof("bc_merge", s);
-    GC_HIP_TRY((launch_by_k<BcMerge>(t->k, t->R, s, t->range_ptr, t->B, static_cast<const int32_t*>(t->id_map),
-                                     static_cast<const double*>(t->bc_part), n, g->bc_depth, level, g->bc_sigma,
-                                     f.next(), g->visited, f.queue_next(), g->stats)));
+    GC_HIP_TRY((launch_by_k<BcMerge>(t->k, t->R, s, static_cast<const int32_t*>(t->range_ptr), t->B,
+                                     static_cast<const uint16_t*>(t->id16), static_cast<const double*>(t->bc_part),
+                                     n, g->bc_depth, level, g->bc_sigma, f.next(), g->visited, f.queue_next(),
+                                     g->stats)));
   }
   return hipGetLastError();
 }
@@ -1003,14 +1160,18 @@ hipError_t bc_run(gc_graph g, gc_tocab t, const int32_t* sources, int32_t n_src,
   const int32_t n = g->n;
   if (!g->bc_sigma) {
     g->bc_sigma = static_cast<double*>(dev_alloc(sizeof(double) * n, s));
-    g->bc_delta = static_cast<double*>(dev_alloc(sizeof(double) * n, s));
+    g->bc_coef = static_cast<double*>(dev_alloc(sizeof(double) * 2 * static_cast<size_t>(n), s));
     g->bc_depth = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * n, s));
-    if (!g->bc_sigma || !g->bc_delta || !g->bc_depth) {
-      for (void* p : {static_cast<void*>(g->bc_sigma), static_cast<void*>(g->bc_delta),
-                      static_cast<void*>(g->bc_depth)})
+    g->bc_order = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * n, s));
+    g->bc_pre = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * (static_cast<size_t>(n) + 1), s));
+    g->bc_deg = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * n, s));
+    if (!g->bc_sigma || !g->bc_coef || !g->bc_depth || !g->bc_order || !g->bc_pre || !g->bc_deg) {
+      for (void* p : {static_cast<void*>(g->bc_sigma), static_cast<void*>(g->bc_coef),
+                      static_cast<void*>(g->bc_depth), static_cast<void*>(g->bc_order),
+                      static_cast<void*>(g->bc_pre), static_cast<void*>(g->bc_deg)})
         if (p) dev_free(p, s);
-      g->bc_sigma = g->bc_delta = nullptr;
-      g->bc_depth = nullptr;
+      g->bc_sigma = g->bc_coef = nullptr;
+      g->bc_depth = g->bc_order = g->bc_pre = g->bc_deg = nullptr;
       return hipErrorOutOfMemory;
     }
   }
@@ -1024,14 +1185,21 @@ hipError_t bc_run(gc_graph g, gc_tocab t, const int32_t* sources, int32_t n_src,
     const int32_t src = sources[si];
     GC_HIP_TRY(init_state(g, g->bc_depth, src, true, s));
     k_fill_f64<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->bc_sigma, n);
-    k_fill_f64<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->bc_delta, n);
+    k_fill_f64<<<grid_for(2 * static_cast<int64_t>(n), kThreads), kThreads, 0, s>>>(g->bc_coef,
+                                                                                   2 * static_cast<int64_t>(n));
     k_set_sigma<<<1, 1, 0, s>>>(src, g->bc_sigma);
     GC_HIP_TRY(hipGetLastError());
+    // order holds the vertices level by level (the source first); level d
+    // occupies [lv_off[d], lv_off[d + 1])
+    std::vector<int32_t> lv_off{0, 1};
+    std::vector<int64_t> lv_arcs;  // out-arcs of each level's vertices
+    GC_HIP_TRY(hipMemcpyAsync(g->bc_order, g->queue[0], sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     Frontier f{g, s};
     hipError_t e;
     f.m_f = source_degree(g, src, s, &e);
     GC_HIP_TRY(e);
     int64_t m_u = g->m - f.m_f;
+    lv_arcs.push_back(f.m_f);
     Heuristic h;
     int32_t level = 0;
     while (f.n_f > 0) {
@@ -1045,15 +1213,34 @@ hipError_t bc_run(gc_graph g, gc_tocab t, const int32_t* sources, int32_t n_src,
       GC_HIP_TRY(f.end_level(nullptr));
       g->trace_action.push_back(mode_action(mode));
       g->trace_ms.push_back(static_cast<float>(now_ms() - t0));
+      if (f.n_f > 0) {
+        GC_HIP_TRY(hipMemcpyAsync(g->bc_order + lv_off.back(), f.queue(), sizeof(int32_t) * f.n_f,
+                                  hipMemcpyDeviceToDevice, s));
+        lv_off.push_back(lv_off.back() + f.n_f);
+        lv_arcs.push_back(f.m_f);
+      }
       m_u -= f.m_f;
       ++level;
     }
-    // depths run 0 .. level-1; delta is zero at the deepest level, and the
-    // source (depth 0) takes no share
+    // depths run 0 .. level-1 (level = lv_off.size() - 1); pre = exclusive
+    // scan of the out-degrees along order; the deepest level's arcs only
+    // reach zero coefficients, and the source (depth 0) takes no share
     ProfScope prof("bc_back", s);
-    for (int32_t d = level - 2; d >= 1; --d)
-      k_bc_back<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->rowptr, g->colidx, n, g->bc_depth, d, g->bc_sigma,
-                                                            g->bc_delta, bc);
+    const int32_t reached = lv_off.back();
+    k_order_degree<<<grid_for(reached, kThreads), kThreads, 0, s>>>(g->bc_order, reached, g->rowptr, g->bc_deg);
+    GC_HIP_TRY(hipGetLastError());
+    GC_HIP_TRY(scan_exclusive(g->bc_deg, g->bc_pre, reached, s));
+    for (int32_t d = level - 1; d >= 1; --d) {
+      const int32_t lo = lv_off[d], hi = lv_off[d + 1];
+      double* coef_out = g->bc_coef + static_cast<size_t>(d & 1) * n;
+      const double* coef_in = g->bc_coef + static_cast<size_t>((d + 1) & 1) * n;
+      const int64_t pieces = (lv_arcs[d] + kBackArcs - 1) / kBackArcs;
+      if (pieces > 0)
+        k_bc_back_arcs<<<grid_for(pieces, kThreads), kThreads, 0, s>>>(g->rowptr, g->colidx, g->bc_order, g->bc_pre,
+                                                                       lo, hi, coef_in, coef_out);
+      k_bc_finish<<<grid_for(hi - lo, kThreads), kThreads, 0, s>>>(g->bc_order + lo, hi - lo, g->bc_sigma, coef_out,
+                                                                    bc);
+    }
     GC_HIP_TRY(hipGetLastError());
   }
   return hipStreamSynchronize(s);
