@@ -47,16 +47,15 @@ struct gc_graph_s {
   int32_t* queue[2] = {nullptr, nullptr};
   uint32_t* visited = nullptr;  // BFS: bitmap of vertices with a final depth
   int32_t* mark = nullptr;      // SSSP push: round in which a vertex was queued
+  int32_t* arc_deg = nullptr;   // out-degrees of a vertex list (arc-balanced push, BC backward)
+  int32_t* arc_pre = nullptr;   // [n+1] their exclusive scan
   // betweenness centrality (allocated by the first bc_accumulate call):
   // path counts, two alternating arrays of (1 + delta) / sigma, BFS depths
-  // and the vertices in level order of the current source, with the scan of
-  // their out-degrees
+  // and the vertices in level order of the current source
   double* bc_sigma = nullptr;
   double* bc_coef = nullptr;  // [2n]
   int32_t* bc_depth = nullptr;
   int32_t* bc_order = nullptr;
-  int32_t* bc_pre = nullptr;  // [n+1] exclusive scan of out-degrees along bc_order (or a push level's queue)
-  int32_t* bc_deg = nullptr;  // [n] the out-degrees being scanned
   int32_t* stats = nullptr;     // device counters read back once per level
   int32_t* stats_host = nullptr;  // pinned mirror
   int64_t bytes = 0;

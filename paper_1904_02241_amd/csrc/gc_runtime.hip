@@ -71,8 +71,8 @@ void free_graph(gc_graph g) {
   void* bufs[] = {g->rowptr, g->colidx, g->w, g->t_rowptr, g->t_colidx, g->t_w, g->contrib[0], g->contrib[1],
                   g->sums, g->dpart, g->dtotal, g->counter, g->front, g->next, g->queue[0], g->queue[1],
                   g->stats, g->tile_row_in, g->visited, g->mark, g->lpart, g->ltotal, g->rank_tmp, g->bc_sigma,
-                  g->bc_coef, g->bc_depth, g->bc_order, g->bc_pre,
-                  g->bc_deg};
+                  g->bc_coef, g->bc_depth, g->bc_order, g->arc_deg,
+                  g->arc_pre};
   for (void* p : bufs)
     if (p) gcx::dev_free(p, nullptr);
   if (g->stats_host) (void)hipHostFree(g->stats_host);
@@ -200,7 +200,9 @@ int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* c
   g->stats = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * 16, stream));
   g->visited = static_cast<uint32_t*>(gcx::dev_alloc(sizeof(uint32_t) * ((static_cast<size_t>(n) + 31) / 32), stream));
   g->mark = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * n, stream));
-  bool ok = g->visited && g->mark && g->rowptr && g->colidx && g->t_rowptr && g->t_colidx && (!g->weighted || (g->w && g->t_w)) &&
+  g->arc_deg = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * n, stream));
+  g->arc_pre = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * (static_cast<size_t>(n) + 1), stream));
+  bool ok = g->visited && g->mark && g->arc_deg && g->arc_pre && g->rowptr && g->colidx && g->t_rowptr && g->t_colidx && (!g->weighted || (g->w && g->t_w)) &&
             g->contrib[0] && g->contrib[1] && g->sums && g->dpart && g->dtotal && g->counter && g->front &&
             g->next && g->queue[0] && g->queue[1] && g->stats;
   if (ok && hipHostMalloc(reinterpret_cast<void**>(&g->stats_host), sizeof(int32_t) * 16, hipHostMallocDefault) !=
@@ -213,7 +215,8 @@ int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* c
     return fail(GC_ENOMEM, "graph_load_csr: device allocation failed");
   }
   g->bytes = 2 * static_cast<int64_t>(nb) + 2 * static_cast<int64_t>(mb) * (g->weighted ? 2 : 1) +
-             12 * static_cast<int64_t>(n) + 2 * static_cast<int64_t>(n) + 8 * static_cast<int64_t>(n);
+             12 * static_cast<int64_t>(n) + 2 * static_cast<int64_t>(n) + 8 * static_cast<int64_t>(n) +
+             8 * static_cast<int64_t>(n) + 4;
 
   const hipMemcpyKind kind = hipMemcpyDefault;  // the runtime resolves host or device sources
   hipError_t e = hipMemcpyAsync(g->rowptr, rowptr, nb, kind, stream);

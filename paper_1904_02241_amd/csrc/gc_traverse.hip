@@ -657,20 +657,83 @@ __global__ __launch_bounds__(kThreads) void k_bc_push(const int32_t* __restrict_
   }
 }
 
-// The same push balanced over arcs for frontiers with many arcs: pre is the
-// exclusive scan of the queued vertices' out-degrees, and each lane takes
-// kPushArcs consecutive arcs of the concatenated out-arc lists (a hub's arcs
-// spread over many work-groups instead of one).
+// ---------------------------------------------------------------------------
+// Data-driven push balanced over arcs, for frontiers with many arcs: pre is
+// the exclusive scan of the queued vertices' out-degrees, and each lane takes
+// kPushArcs consecutive arcs of their concatenated out-arc lists, so a hub's
+// arcs spread over many work-groups instead of one. The relaxation is a
+// functor: src(u) loads what u passes along its arcs, relax(v, e, x)
+// handles arc e into v and returns true when v enters the next frontier.
 constexpr int kPushArcs = 8;
 
-__global__ __launch_bounds__(kThreads) void k_bc_push_arcs(const int32_t* __restrict__ queue_in,
-                                                           const int32_t* __restrict__ pre, int32_t qn,
-                                                           const int32_t* __restrict__ rowptr,
-                                                           const int32_t* __restrict__ colidx,
-                                                           int32_t* __restrict__ depth, int32_t level,
-                                                           double* __restrict__ sigma, uint8_t* __restrict__ next,
-                                                           uint32_t* __restrict__ visited, int32_t* __restrict__ queue,
-                                                           int32_t* __restrict__ stats) {
+struct BfsRelax {  // Algorithm 3's CAS on depth
+  int32_t* depth;
+  int32_t level;
+  uint8_t* next;
+  uint32_t* visited;
+  __device__ int32_t src(int32_t) const { return 0; }
+  __device__ bool relax(int32_t v, int64_t, int32_t) const {
+    if (depth[v] == kInf && atomicCAS(&depth[v], kInf, level + 1) == kInf) {
+      next[v] = 1;
+      bit_set(visited, v);
+      return true;
+    }
+    return false;
+  }
+};
+
+struct SsspRelax {  // atomicMin on dist; a vertex is queued once per round (stamp in mark)
+  const int32_t* w;
+  int32_t* dist;
+  int32_t round;
+  int32_t* mark;
+  uint8_t* next;
+  int32_t* stats;
+  __device__ int32_t src(int32_t u) const { return dist[u]; }
+  __device__ bool relax(int32_t v, int64_t e, int32_t du) const {
+    const int64_t nd = static_cast<int64_t>(du) + w[e];
+    if (nd >= kInf) {
+      stats[kOverflow] = 1;
+    } else if (static_cast<int32_t>(nd) < dist[v]) {
+      const int32_t old = atomicMin(&dist[v], static_cast<int32_t>(nd));
+      if (static_cast<int32_t>(nd) < old) {
+        next[v] = 1;
+        return atomicExch(&mark[v], round) != round;
+      }
+    }
+    return false;
+  }
+};
+
+struct BcRelax {  // the BFS CAS plus sigma[v] += sigma[u] for arcs that land one level down
+  int32_t* depth;
+  int32_t level;
+  double* sigma;
+  uint8_t* next;
+  uint32_t* visited;
+  __device__ double src(int32_t u) const { return sigma[u]; }
+  __device__ bool relax(int32_t v, int64_t, double su) const {
+    bool disc = false;
+    int32_t old = depth[v];
+    if (old == kInf) {
+      old = atomicCAS(&depth[v], kInf, level + 1);
+      if (old == kInf) {
+        disc = true;
+        next[v] = 1;
+        bit_set(visited, v);
+      }
+    }
+    if (old == kInf || old == level + 1) atomicAdd(&sigma[v], su);
+    return disc;
+  }
+};
+
+template <class Relax>
+__global__ __launch_bounds__(kThreads) void k_push_arcs(const int32_t* __restrict__ queue_in,
+                                                        const int32_t* __restrict__ pre, int32_t qn,
+                                                        const int32_t* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ colidx, Relax r,
+                                                        int32_t* __restrict__ queue, int32_t* __restrict__ stats) {
   const int64_t end = pre[qn];
   const int64_t a0 = (static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x) * kPushArcs;
   int32_t i = 0;
@@ -683,13 +746,13 @@ __global__ __launch_bounds__(kThreads) void k_bc_push_arcs(const int32_t* __rest
     }
   }
   int64_t ub = 0, ue = 0, rb = 0;
-  double su = 0.0;
+  auto x = r.src(0);
   if (a0 < end) {
     const int32_t u = queue_in[i];
     ub = pre[i];
     ue = pre[i + 1];
     rb = rowptr[u];
-    su = sigma[u];
+    x = r.src(u);
   }
   // every thread runs the same kPushArcs steps (block_append synchronises the work-group)
 #pragma unroll 1
@@ -701,24 +764,25 @@ __global__ __launch_bounds__(kThreads) void k_bc_push_arcs(const int32_t* __rest
       while (a >= ue) {  // next queued vertex with an arc at a
         ++i;
         const int32_t u = queue_in[i];
-        ub = pre[i];
+        ub = ue;
         ue = pre[i + 1];
         rb = rowptr[u];
-        su = sigma[u];
+        x = r.src(u);
       }
-      v = colidx[rb + (a - ub)];
-      int32_t old = depth[v];
-      if (old == kInf) {
-        old = atomicCAS(&depth[v], kInf, level + 1);
-        if (old == kInf) {
-          disc = true;
-          next[v] = 1;
-          bit_set(visited, v);
-        }
-      }
-      if (old == kInf || old == level + 1) atomicAdd(&sigma[v], su);
+      const int64_t e = rb + (a - ub);
+      v = colidx[e];
+      disc = r.relax(v, e, x);
     }
     block_append(disc, v, queue, stats + kQLen);
+  }
+}
+
+__global__ void k_order_degree(const int32_t* __restrict__ order, int32_t cnt, const int32_t* __restrict__ rowptr,
+                               int32_t* __restrict__ deg) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) {
+    const int32_t v = order[i];
+    deg[i] = rowptr[v + 1] - rowptr[v];
   }
 }
 
@@ -729,15 +793,6 @@ __global__ __launch_bounds__(kThreads) void k_bc_push_arcs(const int32_t* __rest
 // out-arcs of coef needs no depth test; the array it writes is zero at the
 // vertices of depth d.
 constexpr int kBackArcs = 8;  // consecutive arcs per lane
-
-__global__ void k_order_degree(const int32_t* __restrict__ order, int32_t cnt, const int32_t* __restrict__ rowptr,
-                               int32_t* __restrict__ deg) {
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt) {
-    const int32_t v = order[i];
-    deg[i] = rowptr[v + 1] - rowptr[v];
-  }
-}
 
 // Sums for the vertices order[lo, hi) of one depth, balanced over arcs: the
 // level's out-arcs, concatenated in level order (pre = exclusive scan of the
@@ -934,13 +989,31 @@ hipError_t init_state(gc_graph g, int32_t* value, int32_t source, bool bfs, hipS
   return hipGetLastError();
 }
 
+// Arc-balanced push of one level with relaxation r (frontiers with more
+// than one work-group's worth of arcs).
+template <class Relax>
+hipError_t push_arcs(gc_graph g, Frontier& f, Relax r, hipStream_t s) {
+  k_order_degree<<<grid_for(f.n_f, kThreads), kThreads, 0, s>>>(f.queue(), f.n_f, g->rowptr, g->arc_deg);
+  GC_HIP_TRY(hipGetLastError());
+  GC_HIP_TRY(gcx::scan_exclusive(g->arc_deg, g->arc_pre, f.n_f, s));
+  const int64_t pieces = (f.m_f + kPushArcs - 1) / kPushArcs;
+  k_push_arcs<<<grid_for(pieces, kThreads), kThreads, 0, s>>>(f.queue(), g->arc_pre, f.n_f, g->rowptr, g->colidx, r,
+                                                               f.queue_next(), g->stats);
+  return hipGetLastError();
+}
+
+bool arc_balanced(const Frontier& f) { return f.m_f > kThreads * kPushArcs; }
+
 // Enqueues one level (BFS depth `level` -> level+1, or SSSP round `level`)
 // in the given mode; t is the partition used by a TOCAB level.
 hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t level, Mode mode, gc_tocab t,
                      hipStream_t s) {
   const int32_t n = g->n;
   if (bfs) {
-    if (mode == Mode::kPush) {
+    if (mode == Mode::kPush && arc_balanced(f)) {
+      ProfScope prof("bfs_push", s);
+      GC_HIP_TRY(push_arcs(g, f, BfsRelax{value, level, f.next(), g->visited}, s));
+    } else if (mode == Mode::kPush) {
       ProfScope prof("bfs_push", s);
       k_bfs_push<<<grid_for(f.n_f, kThreads), kThreads, 0, s>>>(f.queue(), f.n_f, g->rowptr, g->colidx, value,
                                                                  level, f.next(), g->visited, f.queue_next(),
@@ -962,7 +1035,10 @@ hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t 
                                         f.queue_next(), g->stats)));
     }
   } else {
-    if (mode == Mode::kPush) {
+    if (mode == Mode::kPush && arc_balanced(f)) {
+      ProfScope prof("sssp_push", s);
+      GC_HIP_TRY(push_arcs(g, f, SsspRelax{g->w, value, level, g->mark, f.next(), g->stats}, s));
+    } else if (mode == Mode::kPush) {
       ProfScope prof("sssp_push", s);
       k_sssp_push<<<grid_for(f.n_f, kThreads), kThreads, 0, s>>>(f.queue(), f.n_f, g->rowptr, g->colidx, g->w,
                                                                   value, level, g->mark, f.next(), f.queue_next(),
@@ -1028,15 +1104,9 @@ int32_t mode_action(Mode m) { return m == Mode::kPush ? 0 : (m == Mode::kPull ? 
 // frontier, in the given mode.
 hipError_t run_bc_level(gc_graph g, Frontier& f, int32_t level, Mode mode, gc_tocab t, hipStream_t s) {
   const int32_t n = g->n;
-  if (mode == Mode::kPush && f.m_f > kThreads * kPushArcs) {
+  if (mode == Mode::kPush && arc_balanced(f)) {
     ProfScope prof("bc_push", s);
-    k_order_degree<<<grid_for(f.n_f, kThreads), kThreads, 0, s>>>(f.queue(), f.n_f, g->rowptr, g->bc_deg);
-    GC_HIP_TRY(hipGetLastError());
-    GC_HIP_TRY(gcx::scan_exclusive(g->bc_deg, g->bc_pre, f.n_f, s));
-    const int64_t pieces = (f.m_f + kPushArcs - 1) / kPushArcs;
-    k_bc_push_arcs<<<grid_for(pieces, kThreads), kThreads, 0, s>>>(f.queue(), g->bc_pre, f.n_f, g->rowptr,
-                                                                   g->colidx, g->bc_depth, level, g->bc_sigma,
-                                                                   f.next(), g->visited, f.queue_next(), g->stats);
+    GC_HIP_TRY(push_arcs(g, f, BcRelax{g->bc_depth, level, g->bc_sigma, f.next(), g->visited}, s));
   } else if (mode == Mode::kPush) {
     ProfScope prof("bc_push", s);
     k_bc_push<<<grid_for(f.n_f, kThreads), kThreads, 0, s>>>(f.queue(), f.n_f, g->rowptr, g->colidx, g->bc_depth,
@@ -1163,15 +1233,12 @@ hipError_t bc_run(gc_graph g, gc_tocab t, const int32_t* sources, int32_t n_src,
     g->bc_coef = static_cast<double*>(dev_alloc(sizeof(double) * 2 * static_cast<size_t>(n), s));
     g->bc_depth = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * n, s));
     g->bc_order = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * n, s));
-    g->bc_pre = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * (static_cast<size_t>(n) + 1), s));
-    g->bc_deg = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * n, s));
-    if (!g->bc_sigma || !g->bc_coef || !g->bc_depth || !g->bc_order || !g->bc_pre || !g->bc_deg) {
+    if (!g->bc_sigma || !g->bc_coef || !g->bc_depth || !g->bc_order) {
       for (void* p : {static_cast<void*>(g->bc_sigma), static_cast<void*>(g->bc_coef),
-                      static_cast<void*>(g->bc_depth), static_cast<void*>(g->bc_order),
-                      static_cast<void*>(g->bc_pre), static_cast<void*>(g->bc_deg)})
+                      static_cast<void*>(g->bc_depth), static_cast<void*>(g->bc_order)})
         if (p) dev_free(p, s);
       g->bc_sigma = g->bc_coef = nullptr;
-      g->bc_depth = g->bc_order = g->bc_pre = g->bc_deg = nullptr;
+      g->bc_depth = g->bc_order = nullptr;
       return hipErrorOutOfMemory;
     }
   }
@@ -1227,16 +1294,16 @@ hipError_t bc_run(gc_graph g, gc_tocab t, const int32_t* sources, int32_t n_src,
     // reach zero coefficients, and the source (depth 0) takes no share
     ProfScope prof("bc_back", s);
     const int32_t reached = lv_off.back();
-    k_order_degree<<<grid_for(reached, kThreads), kThreads, 0, s>>>(g->bc_order, reached, g->rowptr, g->bc_deg);
+    k_order_degree<<<grid_for(reached, kThreads), kThreads, 0, s>>>(g->bc_order, reached, g->rowptr, g->arc_deg);
     GC_HIP_TRY(hipGetLastError());
-    GC_HIP_TRY(scan_exclusive(g->bc_deg, g->bc_pre, reached, s));
+    GC_HIP_TRY(scan_exclusive(g->arc_deg, g->arc_pre, reached, s));
     for (int32_t d = level - 1; d >= 1; --d) {
       const int32_t lo = lv_off[d], hi = lv_off[d + 1];
       double* coef_out = g->bc_coef + static_cast<size_t>(d & 1) * n;
       const double* coef_in = g->bc_coef + static_cast<size_t>((d + 1) & 1) * n;
       const int64_t pieces = (lv_arcs[d] + kBackArcs - 1) / kBackArcs;
       if (pieces > 0)
-        k_bc_back_arcs<<<grid_for(pieces, kThreads), kThreads, 0, s>>>(g->rowptr, g->colidx, g->bc_order, g->bc_pre,
+        k_bc_back_arcs<<<grid_for(pieces, kThreads), kThreads, 0, s>>>(g->rowptr, g->colidx, g->bc_order, g->arc_pre,
                                                                        lo, hi, coef_in, coef_out);
       k_bc_finish<<<grid_for(hi - lo, kThreads), kThreads, 0, s>>>(g->bc_order + lo, hi - lo, g->bc_sigma, coef_out,
                                                                     bc);
