@@ -389,8 +389,8 @@ def suite_batched(args, gc, gg, torch):
 
 
 def suite_learned(args, gc, gg, torch):
-    """Level scheduler: trained on the GPU from per-level timings on R-MAT 16
-    and R-MAT 24 (BFS and SSSP), evaluated on R-MAT 25 and the rewired grid
+    """Level scheduler: trained on the GPU from per-level timings on R-MAT 16,
+    20, 22 and 24 (BFS and SSSP), evaluated on R-MAT 25 and the rewired grid
     against the working-set heuristic and fixed policies."""
     widths = [1 << s for s in range(16, 23)]
     K = 2 + len(widths)
@@ -403,7 +403,8 @@ def suite_learned(args, gc, gg, torch):
 
     feats, times = [], []
     t0 = time.perf_counter()
-    for scale in (16, 24):
+    train_scales = (16, 20, 22, 24)
+    for scale in train_scales:
         log(f"collecting levels on RMAT-{scale}")
         gh = gg.rmat(scale, 16, seed=1).with_weights(11)
         g, parts = load(gh)
@@ -418,10 +419,12 @@ def suite_learned(args, gc, gg, torch):
     collect_s = time.perf_counter() - t0
     X = np.concatenate(feats)
     Tms = np.maximum(np.concatenate(times), 1e-4)
-    T = np.log(Tms).astype(np.float32)
+    best = Tms.min(axis=1)
+    # targets: log of each action's time over the level's fastest (only the
+    # ranking decides, so the network need not learn each graph's scale);
     # rows weighted by the square root of their level's best time: the
     # decisions on long levels decide the total
-    best = Tms.min(axis=1)
+    T = np.log(Tms / best[:, None]).astype(np.float32)
     w = np.sqrt(best / best.mean())
     M = np.repeat(w[:, None], K, axis=1).astype(np.float32)
     theta = gc.sched_init_params(K, seed=1)
@@ -490,7 +493,7 @@ def suite_learned(args, gc, gg, torch):
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "learned_scheduler_rmat25_grid4096", "sources": n_src,
                        "actions": ["push", "pull"] + [f"tocab@2^{w.bit_length() - 1}" for w in widths],
-                       "heuristic_tocab_width": heur_w, "train_graphs": ["rmat16", "rmat24"],
+                       "heuristic_tocab_width": heur_w, "train_graphs": [f"rmat{s}" for s in train_scales],
                        "train_levels": int(X.shape[0]), "train_steps": steps, "collect_seconds": round(collect_s, 1),
                        "train_seconds": round(train_s, 2), "loss_first": float(h[0]), "loss_last": float(h[-1])},
             "learned": results}

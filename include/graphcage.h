@@ -277,8 +277,9 @@ int traversal_trace(gc_graph g, int32_t* actions, float* ms, int32_t max, int32_
  * data-driven push, plain topology-driven pull and TOCAB pull over one of
  * several block widths, trained on per-level timings the traversal itself
  * produces. Network: GC_SCHED_INPUTS -> GC_SCHED_HIDDEN -> GC_SCHED_HIDDEN ->
- * K, ReLU after the hidden layers, FP32; output k is the predicted log time
- * (ms) of action k and the arg-min is run. Parameters, row-major:
+ * K, ReLU after the hidden layers, FP32; output k scores action k (lower is
+ * faster: a predicted log time, or log time over the level's fastest action,
+ * as the training targets define) and the arg-min is run. Parameters, row-major:
  *   W1[64][6], b1[64], W2[64][64], b2[64], W3[K][64], b3[K].
  * Features of a level (sched_features): log1p(frontier size), log1p(frontier
  * out-arcs), log1p(m / n), log2(ceil(n / 2^18) + 1), level / 16,

@@ -1,6 +1,7 @@
 // Level scheduler network on the GPU: an MLP 6 -> 64 -> 64 -> K (ReLU after
-// the hidden layers, FP32) whose output k predicts the log run time of
-// action k for a traversal level; the scheduler runs the arg-min. Forward,
+// the hidden layers, FP32) whose output k scores action k for a traversal
+// level (a predicted log run time, absolute or relative to the level's
+// fastest action); the scheduler runs the arg-min. Forward,
 // backward, a deterministic gradient reduction and Adam (Kingma & Ba 2015)
 // are all hand-written kernels.
 //

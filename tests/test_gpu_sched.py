@@ -176,7 +176,7 @@ def test_trained_network_gains_over_heuristic():
     best = Tms.min(axis=1)
     M = np.repeat(np.sqrt(best / best.mean())[:, None], K, axis=1).astype(np.float32)
     m = gc.sched_create(K, mlp.init_params(K, seed=1).astype(np.float32))
-    gc.sched_train(m, dev(X), dev(np.log(Tms).astype(np.float32)), dev(M), 3000, 3e-3)
+    gc.sched_train(m, dev(X), dev(np.log(Tms / best[:, None]).astype(np.float32)), dev(M), 3000, 3e-3)
 
     g = gg.rmat(21, 16, seed=8).with_weights(11)
     h = load(g, weights=True)
