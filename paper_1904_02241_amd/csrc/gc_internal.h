@@ -116,6 +116,7 @@ struct gc_tocab_s {
   int32_t seg_max = 0;            // largest chunk_ns (sizes the work-group's LDS table)
   int32_t* pmin = nullptr;        // [P] traversal partials (next flags / min)
   double* bc_part = nullptr;      // [P] BC path-count partials (allocated on first use)
+  float* val32 = nullptr;         // [m_pad] FP32 arc values in stream order (first valued SpMV)
   int64_t bytes = 0;
 };
 
@@ -176,8 +177,10 @@ constexpr int32_t kLdsStageBytes = 16 * (384 + 16) * 4;
 // Largest range table (entries) that fits beside a W-float slice and the
 // staging (with 8 entries of padding).
 inline int32_t lds_seg_cap(int32_t W) { return ((lds_budget(W) - 4 * W - kLdsStageBytes) / 4 - 8) / 2; }
-// ---- SpMV (gc_spmv.hip) ----
+// ---- SpMV (gc_spmv.hip; the stream-layout form in gc_pagerank.hip) ----
 hipError_t spmv_run(gc_graph g, gc_tocab t, const float* x, float* y, hipStream_t s);
+hipError_t spmv_stream(gc_graph g, gc_tocab t, const float* x, const float* vals, float* y, hipStream_t s);
+hipError_t stream_values(gc_graph g, gc_tocab t, hipStream_t s);
 
 // Convergence mode of pagerank_run: iterate until the L1 change between
 // consecutive iterates is at most tol (or max_iters); iters / delta report

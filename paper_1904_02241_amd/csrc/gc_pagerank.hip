@@ -117,19 +117,35 @@ static_assert(kStageRows % kWave == 0 && (kTileRowsMax - kStageRows) % kWave == 
               kTileRowsMax - kStageRows <= kStageRows, "staging passes of whole store instructions");
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct WaveTile {
   u32x4 cols;  // this lane's 8 columns (16 bits each)
   u32x4 hw;    // head word holding this lane's arcs: bits lo, bits hi, row count, next word's bit 0
+  f32x4 va, vb;  // the 8 arcs' values (valued pull only)
 };
 
+// Arc values of the valued (SpMV) pull: FP32, in the partition's arc order,
+// padded like col16; null for PageRank, whose contributions are summed as they are.
+template <bool kVal>
 __device__ __forceinline__ WaveTile load_wave_tile(const uint16_t* __restrict__ col16,
-                                                   const gc_head_word* __restrict__ heads, int32_t q, int lane) {
+                                                   const gc_head_word* __restrict__ heads,
+                                                   const float* __restrict__ vals, int32_t q, int lane) {
   WaveTile t;
   const int64_t tb = static_cast<int64_t>(q) * kWaveTile;
   t.cols = gcd::ld_stream(reinterpret_cast<const u32x4*>(col16 + tb) + lane);
   t.hw = *reinterpret_cast<const u32x4*>(heads + (tb >> 6) + (lane >> 3));
+  if (kVal) {
+    const f32x4* v4 = reinterpret_cast<const f32x4*>(vals + tb) + 2 * lane;
+    t.va = gcd::ld_stream(v4);
+    t.vb = gcd::ld_stream(v4 + 1);
+  }
   return t;
+}
+
+template <bool kVal>
+__device__ __forceinline__ float arc_value(const WaveTile& t, int e) {
+  return kVal ? (e < 4 ? t.va[e] : t.vb[e - 4]) : 1.0f;
 }
 
 __device__ __forceinline__ uint64_t word_bits(const u32x4& w) {
@@ -246,11 +262,12 @@ __device__ __forceinline__ void seek_cursor(const int32_t* sb, const int32_t* sd
 
 // Sum over the tiles after tile q of the row open at q's end, up to its end
 // (the first head bit that follows).
+template <bool kVal>
 __device__ double finish_open_row(const uint16_t* __restrict__ col16, const gc_head_word* __restrict__ heads,
-                                  const float* slice, int32_t q, int lane) {
+                                  const float* __restrict__ vals, const float* slice, int32_t q, int lane) {
   double acc = 0.0;
   for (int32_t qq = q + 1;; ++qq) {
-    const WaveTile u = load_wave_tile(col16, heads, qq, lane);
+    const WaveTile u = load_wave_tile<kVal>(col16, heads, vals, qq, lane);
     const uint64_t hb = word_bits(u.hw);
     // position of the tile's first head (kWaveTile if none): lowest lane group with a set bit
     const uint64_t has = __ballot(hb != 0ull && (lane & 7) == 0);
@@ -260,29 +277,35 @@ __device__ double finish_open_row(const uint16_t* __restrict__ col16, const gc_h
     double part = 0.0;
 #pragma unroll
     for (int e = 0; e < kArcsPerLane; ++e)
-      if (kArcsPerLane * lane + e < p) part += static_cast<double>(slice[(u.cols[e >> 1] >> (16 * (e & 1))) & 0xFFFFu]);
+      if (kArcsPerLane * lane + e < p)
+        part += static_cast<double>(slice[(u.cols[e >> 1] >> (16 * (e & 1))) & 0xFFFFu] * arc_value<kVal>(u, e));
     acc += gcd::wave_sum(part);
     if (p < kWaveTile) return acc;  // bits past the last arc are set, so this ends
   }
 }
 
 // Keeps a tile's registers and gathered values allocated up to this point.
+template <bool kVal>
 __device__ __forceinline__ void hold_live(const WaveTile& t, const float (&x)[kArcsPerLane]) {
   asm volatile("" ::"v"(t.cols), "v"(t.hw));
+  if (kVal) asm volatile("" ::"v"(t.va), "v"(t.vb));
 #pragma unroll
   for (int e = 0; e < kArcsPerLane; ++e) asm volatile("" ::"v"(x[e]));
 }
 
 typedef __attribute__((address_space(3))) const float lds_float;
 
-// The contributions this lane's 8 arcs gather from the block's slice. The
-// kernel declares no static LDS, so its dynamic LDS (and the slice at its
-// start) begins at LDS address 0: a column's byte offset is its address.
+// The contributions this lane's 8 arcs gather from the block's slice (times
+// the arc values in the valued pull). The kernel declares no static LDS, so
+// its dynamic LDS (and the slice at its start) begins at LDS address 0: a
+// column's byte offset is its address.
+template <bool kVal>
 __device__ __forceinline__ void gather_tile(const WaveTile& t, float (&x)[kArcsPerLane]) {
 #pragma unroll
   for (int e = 0; e < kArcsPerLane; ++e) {
     const uint32_t col = (t.cols[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
     x[e] = *reinterpret_cast<lds_float*>(static_cast<uintptr_t>(col << 2));
+    if (kVal) x[e] *= arc_value<kVal>(t, e);
   }
 }
 
@@ -461,9 +484,10 @@ __device__ __forceinline__ void reduce_wave_tile(const WaveTile& t, const float 
   cr.open = owe ? tail : 0.0;
 }
 
+template <bool kVal>
 __global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
     const int32_t* __restrict__ row_ptr, const uint16_t* __restrict__ col16,
-    const gc_head_word* __restrict__ heads, const int32_t* __restrict__ chunk_beg,
+    const gc_head_word* __restrict__ heads, const float* __restrict__ vals, const int32_t* __restrict__ chunk_beg,
     const int32_t* __restrict__ chunk_end, const int32_t* __restrict__ chunk_blk,
     const int32_t* __restrict__ chunk_j0, const int32_t* __restrict__ chunk_ns, const int2* __restrict__ seg,
     int32_t R, int32_t log2W, int32_t n, const float* __restrict__ c, float* __restrict__ partial,
@@ -530,24 +554,24 @@ __global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
   // give the compiler's count of memory operations after each load at
   // least its steady-state value on entry.
   int32_t q = qa;
-  WaveTile t0 = load_wave_tile(col16, heads, q, lane);
-  WaveTile t1 = load_wave_tile(col16, heads, min(q + 1, qz), lane);
-  WaveTile t2 = load_wave_tile(col16, heads, min(q + 2, qz), lane);
-  WaveTile t3 = load_wave_tile(col16, heads, min(q + 3, qz), lane);
+  WaveTile t0 = load_wave_tile<kVal>(col16, heads, vals, q, lane);
+  WaveTile t1 = load_wave_tile<kVal>(col16, heads, vals, min(q + 1, qz), lane);
+  WaveTile t2 = load_wave_tile<kVal>(col16, heads, vals, min(q + 2, qz), lane);
+  WaveTile t3 = load_wave_tile<kVal>(col16, heads, vals, min(q + 3, qz), lane);
   drop_stores(out);
   drop_stores(out);
   drop_stores(out);
   float x0[kArcsPerLane], x1[kArcsPerLane];
-  gather_tile(t0, x0);
+  gather_tile<kVal>(t0, x0);
   // Whole rounds of four tiles run in a loop with no exit inside (an exit
   // merged into the loop's back edge would make the compiler assume a path
   // with fewer memory operations and wait longer); the last nt % 4 tiles
   // follow it.
 #define GC_PULL_STEP(cur, xcur, nxt, xnxt, k)                           \
-  gather_tile(nxt, xnxt);                                               \
+  gather_tile<kVal>(nxt, xnxt);                                         \
   reduce_wave_tile(cur, xcur, lane, sb, sd, ns, r0, r1, cr, out, stage); \
-  hold_live(cur, xcur);                                                 \
-  cur = load_wave_tile(col16, heads, min(q + (k + 4), qz), lane);
+  hold_live<kVal>(cur, xcur);                                           \
+  cur = load_wave_tile<kVal>(col16, heads, vals, min(q + (k + 4), qz), lane);
   const int32_t nw = qz - qa + 1;
   for (int32_t round = 0; round < nw / 4; ++round) {
     GC_PULL_STEP(t0, x0, t1, x1, 0)
@@ -558,17 +582,17 @@ __global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
   }
   const int32_t rest = nw % 4;
   if (rest > 0) {
-    gather_tile(t1, x1);
+    gather_tile<kVal>(t1, x1);
     reduce_wave_tile(t0, x0, lane, sb, sd, ns, r0, r1, cr, out, stage);
   }
   if (rest > 1) {
-    gather_tile(t2, x0);
+    gather_tile<kVal>(t2, x0);
     reduce_wave_tile(t1, x1, lane, sb, sd, ns, r0, r1, cr, out, stage);
   }
   if (rest > 2) reduce_wave_tile(t2, x0, lane, sb, sd, ns, r0, r1, cr, out, stage);
 #undef GC_PULL_STEP
   if (cr.open_row >= 0) {  // the range's last row continues past it
-    const double v = cr.open + finish_open_row(col16, heads, slice, qz, lane);
+    const double v = cr.open + finish_open_row<kVal>(col16, heads, vals, slice, qz, lane);
     if (lane == 0) {
       const int32_t j = seek_range(sb, cr.jc, cr.open_row);
       partial[cr.open_row + sd[j]] = static_cast<float>(v);
@@ -622,35 +646,35 @@ __global__ __launch_bounds__(kThreads) void k_pr_merge(const int32_t* __restrict
 template <int K>
 constexpr int merge_threads() { return K >= 16384 ? 1024 : 512; }
 
-template <int K, int kMergeThreads = merge_threads<K>()>
-__global__ __launch_bounds__(kMergeThreads) void k_pr_merge_stream(const int32_t* __restrict__ rstart,
-                                                                   const uint16_t* __restrict__ id16s,
-                                                                   const float* __restrict__ partial, Update u) {
-  __shared__ double acc[K];
-  for (int i = threadIdx.x; i < K; i += kMergeThreads) acc[i] = 0.0;
+// Accumulation part of the stream-layout merge for range blockIdx.x (NT
+// threads), into acc[K] (FP64, LDS).
+template <int K, int NT>
+__device__ __forceinline__ void stream_accumulate(const int32_t* __restrict__ rstart,
+                                                  const uint16_t* __restrict__ id16s,
+                                                  const float* __restrict__ partial, double* acc) {
+  for (int i = threadIdx.x; i < K; i += NT) acc[i] = 0.0;
   __syncthreads();
   const int32_t a = rstart[blockIdx.x], z = rstart[blockIdx.x + 1];
   const int32_t g0 = a >> 2, g1 = (z + 3) >> 2;  // 4-entry groups covering [a, z)
-  typedef float f4 __attribute__((ext_vector_type(4)));
-  const f4* p4 = reinterpret_cast<const f4*>(partial);
+  const f32x4* p4 = reinterpret_cast<const f32x4*>(partial);
   const uint64_t* i4 = reinterpret_cast<const uint64_t*>(id16s);
   // kU groups of 4 entries per thread and step; the next step's loads are
   // issued before this step's LDS adds (two register sets in turn)
   constexpr int kU = 4;
-  f4 pa[kU], pb[kU];
+  f32x4 pa[kU], pb[kU];
   uint64_t ia[kU], ib[kU];
-  auto load = [&](int32_t g, f4 (&p)[kU], uint64_t (&id)[kU]) {
+  auto load = [&](int32_t g, f32x4 (&p)[kU], uint64_t (&id)[kU]) {
 #pragma unroll
     for (int k = 0; k < kU; ++k) {
-      const int32_t gg = min(g + k * kMergeThreads, g1 - 1);  // clamped, masked below
+      const int32_t gg = min(g + k * NT, g1 - 1);  // clamped, masked below
       p[k] = gcd::ld_stream(p4 + gg);
       id[k] = gcd::ld_stream(i4 + gg);
     }
   };
-  auto add = [&](int32_t g, const f4 (&p)[kU], const uint64_t (&id)[kU]) {
+  auto add = [&](int32_t g, const f32x4 (&p)[kU], const uint64_t (&id)[kU]) {
 #pragma unroll
     for (int k = 0; k < kU; ++k) {
-      const int32_t e0 = 4 * (g + k * kMergeThreads);
+      const int32_t e0 = 4 * (g + k * NT);
       const float pv[4] = {p[k][0], p[k][1], p[k][2], p[k][3]};
 #pragma unroll
       for (int e = 0; e < 4; ++e)
@@ -660,7 +684,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_pr_merge_stream(const int32_t
   };
   // (loads are clamped to the last group, so they need no branch and the
   // compiler's count of outstanding loads holds on every path)
-  constexpr int32_t kStep = kMergeThreads * kU;
+  constexpr int32_t kStep = NT * kU;
   int32_t g = g0 + static_cast<int32_t>(threadIdx.x);
   if (g0 < g1) load(g, pa, ia);  // uniform
   for (; g < g1; g += 2 * kStep) {
@@ -670,6 +694,14 @@ __global__ __launch_bounds__(kMergeThreads) void k_pr_merge_stream(const int32_t
     add(g + kStep, pb, ib);
   }
   __syncthreads();
+}
+
+template <int K, int kMergeThreads = merge_threads<K>()>
+__global__ __launch_bounds__(kMergeThreads) void k_pr_merge_stream(const int32_t* __restrict__ rstart,
+                                                                   const uint16_t* __restrict__ id16s,
+                                                                   const float* __restrict__ partial, Update u) {
+  __shared__ double acc[K];
+  stream_accumulate<K, kMergeThreads>(rstart, id16s, partial, acc);
   const int32_t v0 = blockIdx.x * K;
   const double D = *u.dtotal_in;
   double mine = 0.0, dl = 0.0;
@@ -678,6 +710,31 @@ __global__ __launch_bounds__(kMergeThreads) void k_pr_merge_stream(const int32_t
     if (v < u.n) mine += update_vertex(u, v, acc[i], D, dl);
   }
   publish_update<kMergeThreads>(u, mine, dl);
+}
+
+// The same merge for SpMV: y[v] = the FP64 sum rounded to FP32.
+template <int K, int kMergeThreads = merge_threads<K>()>
+__global__ __launch_bounds__(kMergeThreads) void k_spmv_merge_stream(const int32_t* __restrict__ rstart,
+                                                                     const uint16_t* __restrict__ id16s,
+                                                                     const float* __restrict__ partial, int32_t n,
+                                                                     float* __restrict__ y) {
+  __shared__ double acc[K];
+  stream_accumulate<K, kMergeThreads>(rstart, id16s, partial, acc);
+  const int32_t v0 = blockIdx.x * K;
+  for (int i = threadIdx.x; i < K; i += kMergeThreads)
+    if (v0 + i < n) y[v0 + i] = static_cast<float>(acc[i]);
+}
+
+// Padded FP32 arc values in the partition's arc order: FP32 bit patterns or
+// integers converted, zero past the last arc.
+__global__ void k_stream_values(const int32_t* __restrict__ w, bool f32, int64_t m, int64_t m_pad,
+                                float* __restrict__ out) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < m_pad; i += stride) {
+    float v = 0.0f;
+    if (i < m) v = f32 ? __int_as_float(w[i]) : static_cast<float>(w[i]);
+    out[i] = v;
+  }
 }
 
 // Push with thread+warp+CTA style fine-grained balancing (Section 2.1,
@@ -822,8 +879,59 @@ int32_t wave_tile_arcs() { return kWaveTile; }
 
 hipError_t pagerank_setup() {
   // the LDS-resident pull holds a slice of up to kLdsMaxWidth floats plus its position table
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_tocab_pull_lds),
+  GC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_tocab_pull_lds<false>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds_budget(kLdsMaxWidth)));
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_tocab_pull_lds<true>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_budget(kLdsMaxWidth));
+}
+
+// Bytes of dynamic LDS the stream-layout pull takes for partition t.
+size_t pull_lds_bytes(gc_tocab t) {
+  return sizeof(float) * (static_cast<size_t>(t->W) + 2 * static_cast<size_t>(t->seg_max) + 2 * kSegPad) +
+         kLdsStageBytes;
+}
+
+// SpMV over a stream-layout partition: the LDS-resident pull (valued when
+// vals is given, unit values otherwise) and the range-major merge writing y.
+hipError_t spmv_stream(gc_graph g, gc_tocab t, const float* x, const float* vals, float* y, hipStream_t s) {
+  static const hipError_t setup = pagerank_setup();
+  GC_HIP_TRY(setup);
+  {
+    ProfScope prof("spmv_tocab", s);
+    if (t->n_chunks > 0) {
+      const uint32_t bytes = static_cast<uint32_t>(sizeof(float) * (t->P + 8));
+      if (vals)
+        k_pr_tocab_pull_lds<true><<<t->n_chunks, kLdsThreads, pull_lds_bytes(t), s>>>(
+            t->row_ptr, t->col16, t->heads, vals, t->chunk_beg, t->chunk_end, t->chunk_blk, t->chunk_j0,
+            t->chunk_ns, t->seg, t->R, t->log2W, g->n, x, t->partial, bytes);
+      else
+        k_pr_tocab_pull_lds<false><<<t->n_chunks, kLdsThreads, pull_lds_bytes(t), s>>>(
+            t->row_ptr, t->col16, t->heads, nullptr, t->chunk_beg, t->chunk_end, t->chunk_blk, t->chunk_j0,
+            t->chunk_ns, t->seg, t->R, t->log2W, g->n, x, t->partial, bytes);
+    }
+  }
+  ProfScope prof("spmv_merge", s);
+  switch (t->k) {
+    case 256: k_spmv_merge_stream<256><<<t->R, merge_threads<256>(), 0, s>>>(t->rstart, t->id16s, t->partial, g->n, y); break;
+    case 512: k_spmv_merge_stream<512><<<t->R, merge_threads<512>(), 0, s>>>(t->rstart, t->id16s, t->partial, g->n, y); break;
+    case 1024: k_spmv_merge_stream<1024><<<t->R, merge_threads<1024>(), 0, s>>>(t->rstart, t->id16s, t->partial, g->n, y); break;
+    case 2048: k_spmv_merge_stream<2048><<<t->R, merge_threads<2048>(), 0, s>>>(t->rstart, t->id16s, t->partial, g->n, y); break;
+    case 4096: k_spmv_merge_stream<4096><<<t->R, merge_threads<4096>(), 0, s>>>(t->rstart, t->id16s, t->partial, g->n, y); break;
+    case 8192: k_spmv_merge_stream<8192><<<t->R, merge_threads<8192>(), 0, s>>>(t->rstart, t->id16s, t->partial, g->n, y); break;
+    case 16384: k_spmv_merge_stream<16384><<<t->R, merge_threads<16384>(), 0, s>>>(t->rstart, t->id16s, t->partial, g->n, y); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// The padded FP32 arc values of a weighted stream-layout partition (t->val32),
+// built by the first valued SpMV over it.
+hipError_t stream_values(gc_graph g, gc_tocab t, hipStream_t s) {
+  if (t->val32) return hipSuccess;
+  t->val32 = static_cast<float*>(dev_alloc(sizeof(float) * static_cast<size_t>(t->m_pad), s));
+  if (!t->val32) return hipErrorOutOfMemory;
+  k_stream_values<<<4096, kThreads, 0, s>>>(t->w, g->values_f32, t->m, t->m_pad, t->val32);
+  return hipGetLastError();
 }
 
 // The comparison baselines (pagerank_ladder): Base and VWC gather over the
@@ -942,11 +1050,9 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
       if (t->col16) {
         {
           ProfScope prof("pr_tocab_pull", s);
-          const size_t lds = sizeof(float) * (static_cast<size_t>(t->W) + 2 * static_cast<size_t>(t->seg_max) + 2 * kSegPad) +
-                             kLdsStageBytes;
           if (t->n_chunks > 0)
-            k_pr_tocab_pull_lds<<<t->n_chunks, kLdsThreads, lds, s>>>(
-                t->row_ptr, t->col16, t->heads, t->chunk_beg, t->chunk_end, t->chunk_blk, t->chunk_j0,
+            k_pr_tocab_pull_lds<false><<<t->n_chunks, kLdsThreads, pull_lds_bytes(t), s>>>(
+                t->row_ptr, t->col16, t->heads, nullptr, t->chunk_beg, t->chunk_end, t->chunk_blk, t->chunk_j0,
                 t->chunk_ns, t->seg, t->R, t->log2W, n, g->contrib[0], t->partial,
                 static_cast<uint32_t>(sizeof(float) * (t->P + 8)));
         }

@@ -2,8 +2,11 @@
 // (the SpMV benchmark of Section 4): y[v] = sum over arcs u -> v of
 // val(u -> v) * x[u]. Plain: the pull tiles of the transposed graph.
 // Blocked: Algorithm 4's column-blocked pull over a GC_PULL partition into
-// per-(row, block) partial sums, then the Figure 5 merge writing y. Products
-// are FP32 (x times the arc's value), row and merge sums FP64, y FP32.
+// per-(row, block) partial sums, then the Figure 5 merge writing y; blocks
+// of at most 2^15 vertices go through the stream-layout kernels of PageRank
+// (x's slice in LDS, values streamed beside the 16-bit columns). Products
+// are FP32 (x times the arc's value), row and merge sums FP64 (inside a
+// stream-layout tile FP32, as for PageRank), y FP32.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -77,6 +80,14 @@ hipError_t spmv_run(gc_graph g, gc_tocab t, const float* x, float* y, hipStream_
     if (g->n_tiles_in > 0)
       k_spmv_plain<<<g->n_tiles_in, kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, g->tile_row_in, x, arc, y);
     return hipGetLastError();
+  }
+  if (t->col16) {  // stream layout: the LDS-resident pull of the PageRank kernels, valued
+    const float* vals = nullptr;
+    if (t->weighted) {
+      GC_HIP_TRY(stream_values(g, t, s));
+      vals = t->val32;
+    }
+    return spmv_stream(g, t, x, vals, y, s);
   }
   ValuedArc arc{t->weighted ? t->w : nullptr, g->values_f32};
   {
