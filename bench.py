@@ -114,7 +114,7 @@ def run_traversal(gc, torch, g, gh, part, sources, kind, policies):
 def source_digest():
     """SHA-256 over the sources that decide the PageRank kernels and their data layout."""
     h = hashlib.sha256()
-    for f in ("gc_pagerank.hip", "gc_pr_device.h", "gc_build.hip"):
+    for f in ("gc_pagerank.hip", "gc_pr_device.h", "gc_merge.h", "gc_device.h", "gc_internal.h", "gc_build.hip"):
         h.update(open(os.path.join(ROOT, "paper_1904_02241_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
