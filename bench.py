@@ -390,9 +390,10 @@ def suite_batched(args, gc, gg, torch):
 
 def suite_learned(args, gc, gg, torch):
     """Level scheduler: trained on the GPU from per-level timings on R-MAT 16,
-    20, 22 and 24 (BFS and SSSP), evaluated on R-MAT 25 and the rewired grid
-    against the working-set heuristic and fixed policies."""
-    widths = [1 << s for s in range(16, 23)]
+    20, 22 and 24 (BFS, SSSP, and PageRank iterations), evaluated on R-MAT 25
+    and the rewired grid against the working-set heuristic and fixed
+    policies."""
+    widths = [1 << s for s in range(15, 23)]
     K = 2 + len(widths)
     n_src = args.bfs_sources or 8
     heur_w = 1 << 18
@@ -413,6 +414,9 @@ def suite_learned(args, gc, gg, torch):
             f, t = gc.sched_collect(g, parts, kind, srcs)
             feats.append(f)
             times.append(t)
+        f, t = gc.sched_collect_pagerank(g, parts, rows=3)
+        feats.append(f)
+        times.append(t)
         for p in parts:
             p.free()
         g.free()
@@ -481,6 +485,32 @@ def suite_learned(args, gc, gg, torch):
             res[kind]["learned_gain_vs_best_fixed"] = round(min(others.values()) / res[kind]["learned"]["ms_total"], 3)
             log(f"{name} {kind}: " + ", ".join(f"{k2} {v['ms_total']:.1f} ms" for k2, v in res[kind].items()
                                                if isinstance(v, dict)))
+        # PageRank: one form per call (every iteration is alike), ms per iteration
+        rin = torch.full((gh.n,), 1.0 / gh.n, dtype=torch.float32, device="cuda")
+        rout = torch.empty_like(rin)
+
+        def per_iter(fn, iters=10):
+            fn(1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn(iters)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3 / iters, out
+
+        labels = ["push", "pull"] + [f"tocab@2^{w.bit_length() - 1}" for w in widths]
+        pr = {}
+        ms, act = per_iter(lambda k: gc.pagerank_learned(g, 0.85, 0, rin, rout, k))
+        pr["learned"] = {"ms_per_iter": round(ms, 4), "form": labels[act]}
+        pr["heuristic"] = {"ms_per_iter": round(per_iter(
+            lambda k: gc.pagerank_iter(g, mid, gc.GC_PULL, 0.85, 0, rin, rout, k))[0], 4), "form": "tocab@2^18"}
+        pr["always_pull"] = {"ms_per_iter": round(per_iter(
+            lambda k: gc.pagerank_iter(g, None, gc.GC_PULL, 0.85, 0, rin, rout, k))[0], 4), "form": "pull"}
+        pr["always_push"] = {"ms_per_iter": round(per_iter(
+            lambda k: gc.pagerank_iter(g, None, gc.GC_PUSH, 0.85, 0, rin, rout, k), 3)[0], 4), "form": "push"}
+        pr["learned_gain_vs_heuristic"] = round(pr["heuristic"]["ms_per_iter"] / pr["learned"]["ms_per_iter"], 3)
+        res["pagerank"] = pr
+        log(f"{name} pagerank: " + ", ".join(f"{k2} {v['ms_per_iter']:.3f} ms/iter ({v['form']})"
+                                             for k2, v in pr.items() if isinstance(v, dict)))
         results[name] = res
         gc.sched_attach(g, None)
         for p in parts:

@@ -310,14 +310,32 @@ int sched_features(int32_t n, int64_t m, int32_t frontier, int64_t frontier_arcs
 /* Training rows for a network with K = 2 + n_parts actions: traverses from
  * each source (kind 0 = BFS, 1 = SSSP) and at every level runs every action
  * from the same saved state, timing each with HIP events, then continues with
- * the fastest. Writes host features[rows][6] and times_ms[rows][K] (up to
- * max_rows) and *rows. parts must be GC_PULL partitions of g. */
+ * the fastest. kind 2 = PageRank: every vertex is active at every iteration,
+ * so a row is one all-active level: each action (0 plain push, 1 plain
+ * pull, 2 + i TOCAB pull over parts[i]) runs 4 iterations from the same
+ * ranks and times_ms holds its time per iteration; n_sources rows are
+ * collected (sources is unused and may be NULL), each from the previous
+ * row's fastest result. Writes host features[rows][6] and times_ms[rows][K]
+ * (up to max_rows) and *rows. parts must be GC_PULL partitions of g. */
 int sched_collect(gc_graph g, const gc_tocab* parts, int32_t n_parts, int32_t kind, const int32_t* sources,
                   int32_t n_sources, float* features, float* times_ms, int32_t max_rows, int32_t* rows,
                   hipStream_t stream);
 /* Attaches network m (K = 2 + n_parts) and its TOCAB partitions to g for
- * GC_POLICY_LEARNED; m = NULL detaches. The handles must outlive the use. */
+ * GC_POLICY_LEARNED and pagerank_learned; m = NULL detaches. The handles
+ * must outlive the use. */
 int sched_attach(gc_graph g, gc_sched m, const gc_tocab* parts, int32_t n_parts);
+/* PageRank (as pagerank_iter, `iters` iterations) in the form the attached
+ * network picks for an all-active level of g (frontier n vertices and m
+ * arcs, level 0, no prior time): 0 plain push, 1 plain pull, 2 + j TOCAB
+ * pull over the j-th attached partition. One decision per call (every
+ * iteration of PageRank is alike); synchronises `stream` once to read it.
+ * Without a finite network output the working-set rule decides: an
+ * all-active level's working set exceeds the cache, so TOCAB pull over the
+ * attached partition whose width is nearest 2^18, or plain pull when none
+ * is attached. *action (host, nullable) receives the form run. Errors as
+ * pagerank_iter, plus GC_EINVAL when no network is attached. */
+int pagerank_learned(gc_graph g, float damping, int32_t dangling, const float* rank_in, float* rank_out,
+                     int32_t iters, int32_t* action, hipStream_t stream);
 
 /* ---- batched persistent form ----------------------------------------------
  * Not in the paper: PageRank on many graphs of uneven size, each over its

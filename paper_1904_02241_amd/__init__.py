@@ -64,6 +64,7 @@ SIGNATURES = {
     "sched_features": (ctypes.c_int, [_i32, _i64, _i32, _i64, _i32, _f32, _vp]),
     "sched_collect": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _p_i32, _vp]),
     "sched_attach": (ctypes.c_int, [_vp, _vp, _vp, _i32]),
+    "pagerank_learned": (ctypes.c_int, [_vp, _f32, _i32, _vp, _vp, _i32, _p_i32, _vp]),
     "batch_create": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, ctypes.POINTER(_vp)]),
     "batch_info": (ctypes.c_int, [_vp, _vp, _vp, _p_i32, _p_i64]),
     "batch_run": (ctypes.c_int, [_vp, _f32, _i32, _vp, _vp, _vp, _vp]),
@@ -451,6 +452,26 @@ def sched_collect(g, parts, kind, sources, max_rows=100000, stream=None):
                              feats.ctypes.data, times.ctypes.data, max_rows, ctypes.byref(rows), _stream(stream)),
            "sched_collect")
     return feats[:rows.value], times[:rows.value]
+
+
+def sched_collect_pagerank(g, parts, rows=4, stream=None):
+    """(features [rows, 6], times_ms [rows, 2 + len(parts)]) of PageRank
+    iterations (sched_collect kind 2)."""
+    K = 2 + len(parts)
+    feats = np.zeros((rows, GC_SCHED_INPUTS), np.float32)
+    times = np.zeros((rows, K), np.float32)
+    got = ctypes.c_int32()
+    _check(lib.sched_collect(_h(g), _handles(parts), len(parts), 2, None, rows, feats.ctypes.data, times.ctypes.data,
+                             rows, ctypes.byref(got), _stream(stream)), "sched_collect")
+    return feats[:got.value], times[:got.value]
+
+
+def pagerank_learned(g, damping, dangling, rank_in, rank_out, iters, stream=None):
+    """Runs PageRank in the form the attached network picks; returns the action."""
+    action = ctypes.c_int32(-1)
+    _check(lib.pagerank_learned(_h(g), damping, dangling, _ptr(rank_in), _ptr(rank_out), iters,
+                                ctypes.byref(action), _stream(stream)), "pagerank_learned")
+    return action.value
 
 
 def sched_attach(g, m, parts=()):

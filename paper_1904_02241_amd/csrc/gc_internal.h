@@ -195,6 +195,10 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
                         const float* rank_in, float* rank_out, int32_t iters, hipStream_t s,
                         Converge* cv = nullptr, int32_t ladder = -1);
 
+// Scheduler training rows for PageRank (see sched_collect, kind 2).
+hipError_t collect_pagerank(gc_graph g, gc_tocab* parts, int32_t n_parts, int32_t n_rows, float* features,
+                            float* times, int32_t max_rows, int32_t* rows, hipStream_t s);
+
 // ---- autotuner (gc_autotune.hip) ----
 // Candidate widths start at max(2^12, min_W).
 hipError_t autotune(gc_graph g, int32_t dir, int32_t min_W, int32_t* W_out, int32_t* k_out, float* ms_out,

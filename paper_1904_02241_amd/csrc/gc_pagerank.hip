@@ -1001,6 +1001,58 @@ hipError_t ladder_run(gc_graph g, gc_tocab t, int32_t method, float damping, int
   return hipSuccess;
 }
 
+// Training rows of the level scheduler for PageRank, an all-active level
+// whose cost does not change from one iteration to the next: for each row,
+// every action runs kCollectIters iterations from the same ranks (0 plain
+// push, 1 plain pull, 2 + i TOCAB pull over parts[i]), timed with HIP
+// events (ms per iteration); the next row starts from the fastest action's
+// output. Features: frontier = all n vertices and m arcs, level = the row,
+// prior time = the previous row's best.
+hipError_t collect_pagerank(gc_graph g, gc_tocab* parts, int32_t n_parts, int32_t n_rows, float* features,
+                            float* times, int32_t max_rows, int32_t* rows, hipStream_t s) {
+  constexpr int32_t kCollectIters = 4;
+  const int32_t n = g->n;
+  const int32_t K = 2 + n_parts;
+  Buf ra(sizeof(float) * n, s), rb(sizeof(float) * n, s), rbest(sizeof(float) * n, s);
+  if (!ra.p || !rb.p || !rbest.p) return hipErrorOutOfMemory;
+  std::vector<float> init(static_cast<size_t>(n), 1.0f / static_cast<float>(n));
+  GC_HIP_TRY(hipMemcpyAsync(ra.p, init.data(), sizeof(float) * n, hipMemcpyHostToDevice, s));
+  GC_HIP_TRY(hipStreamSynchronize(s));
+  hipEvent_t e0, e1;
+  GC_HIP_TRY(hipEventCreate(&e0));
+  GC_HIP_TRY(hipEventCreate(&e1));
+  hipError_t err = hipSuccess;
+  int32_t r = 0;
+  double prior_ms = 0.0;
+  for (; r < n_rows && r < max_rows && err == hipSuccess; ++r) {
+    sched_features(n, g->m, n, g->m, r, prior_ms, features + static_cast<size_t>(r) * GC_SCHED_INPUTS);
+    float* row_t = times + static_cast<size_t>(r) * K;
+    int32_t best = 0;
+    for (int32_t a = 0; a < K && err == hipSuccess; ++a) {
+      gc_tocab t = a >= 2 ? parts[a - 2] : nullptr;
+      const int32_t dir = a == 0 ? GC_PUSH : GC_PULL;
+      err = hipEventRecord(e0, s);
+      if (err == hipSuccess)
+        err = pagerank_run(g, t, dir, 0.85f, GC_DANGLING_UNIFORM, ra.as<float>(), rb.as<float>(), kCollectIters, s);
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      row_t[a] = ms / kCollectIters;
+      if (row_t[a] < row_t[best]) best = a;
+      if (err == hipSuccess && best == a)
+        err = hipMemcpyAsync(rbest.p, rb.p, sizeof(float) * n, hipMemcpyDeviceToDevice, s);
+    }
+    if (err == hipSuccess) err = hipMemcpyAsync(ra.p, rbest.p, sizeof(float) * n, hipMemcpyDeviceToDevice, s);
+    prior_ms = row_t[best];
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *rows = r;
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  return err;
+}
+
 hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int32_t dangling,
                         const float* rank_in, float* rank_out, int32_t iters, hipStream_t s, Converge* cv,
                         int32_t ladder) {

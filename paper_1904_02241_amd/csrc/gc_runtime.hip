@@ -415,6 +415,35 @@ int pagerank_iter(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, i
   return e == hipSuccess ? GC_OK : hip_fail(e, "pagerank_iter");
 }
 
+int pagerank_learned(gc_graph g, float damping, int32_t dangling, const float* rank_in, float* rank_out,
+                     int32_t iters, int32_t* action, hipStream_t stream) {
+  const int rc = check_pagerank("pagerank_learned", g, nullptr, GC_PULL, damping, dangling, rank_in, rank_out);
+  if (rc != GC_OK) return rc;
+  if (iters < 0) return fail(GC_EINVAL, "pagerank_learned: iters < 0");
+  if (!g->sched) return fail(GC_EINVAL, "pagerank_learned: no scheduler attached");
+  float feats[GC_SCHED_INPUTS];
+  gcx::sched_features(g->n, g->m, g->n, g->m, 0, 0.0, feats);
+  int32_t a = -1;
+  hipError_t e = gcx::sched_decide(g->sched, feats, stream, &a);
+  if (e != hipSuccess) return hip_fail(e, "pagerank_learned");
+  const int32_t np = static_cast<int32_t>(g->sched_parts.size());
+  if (a < 0 || a >= 2 + np) {  // no finite output: the working-set rule (all active: block when a partition exists)
+    a = 1;
+    int32_t best = INT32_MAX;
+    for (int32_t j = 0; j < np; ++j) {
+      const int32_t d = std::abs(g->sched_parts[j]->log2W - 18);  // the paper's block width, 2^18
+      if (d < best) {
+        best = d;
+        a = 2 + j;
+      }
+    }
+  }
+  if (action) *action = a;
+  gc_tocab t = a >= 2 ? g->sched_parts[a - 2] : nullptr;
+  e = gcx::pagerank_run(g, t, a == 0 ? GC_PUSH : GC_PULL, damping, dangling, rank_in, rank_out, iters, stream);
+  return e == hipSuccess ? GC_OK : hip_fail(e, "pagerank_learned");
+}
+
 int pagerank_ladder(gc_graph g, gc_tocab t, int32_t method, float damping, int32_t dangling,
                     const float* rank_in, float* rank_out, int32_t iters, hipStream_t stream) {
   if (method < GC_LADDER_BASE || method > GC_LADDER_CB)
@@ -549,17 +578,22 @@ int sched_features(int32_t n, int64_t m, int32_t frontier, int64_t frontier_arcs
 int sched_collect(gc_graph g, const gc_tocab* parts, int32_t n_parts, int32_t kind, const int32_t* sources,
                   int32_t n_sources, float* features, float* times_ms, int32_t max_rows, int32_t* rows,
                   hipStream_t stream) {
-  if (!g || (n_parts > 0 && !parts) || n_parts < 0 || n_parts > 62 || !sources || n_sources < 0 || !features ||
-      !times_ms || max_rows < 0 || !rows)
+  if (!g || (n_parts > 0 && !parts) || n_parts < 0 || n_parts > 62 || (kind != 2 && !sources) || n_sources < 0 ||
+      !features || !times_ms || max_rows < 0 || !rows)
     return fail(GC_EINVAL, "sched_collect: bad argument");
-  if (kind != 0 && kind != 1) return fail(GC_EINVAL, "sched_collect: kind must be 0 (BFS) or 1 (SSSP)");
+  if (kind < 0 || kind > 2) return fail(GC_EINVAL, "sched_collect: kind must be 0 (BFS), 1 (SSSP) or 2 (PageRank)");
   if (kind == 1 && !g->weighted) return fail(GC_EINVAL, "sched_collect: SSSP needs a weighted graph");
   for (int32_t i = 0; i < n_parts; ++i)
     if (!parts[i] || parts[i]->g != g || parts[i]->dir != GC_PULL)
       return fail(GC_EINVAL, "sched_collect: partition %d is not a GC_PULL partition of this graph", i);
+  std::vector<gc_tocab> ps(parts, parts + n_parts);
+  if (kind == 2) {  // PageRank: n_sources rows, sources unused
+    const hipError_t e = gcx::collect_pagerank(g, ps.data(), n_parts, n_sources, features, times_ms, max_rows, rows,
+                                               stream);
+    return e == hipSuccess ? GC_OK : hip_fail(e, "sched_collect");
+  }
   for (int32_t i = 0; i < n_sources; ++i)
     if (sources[i] < 0 || sources[i] >= g->n) return fail(GC_EINVAL, "sched_collect: source %d out of range", i);
-  std::vector<gc_tocab> ps(parts, parts + n_parts);
   const hipError_t e = gcx::collect(g, ps.data(), n_parts, kind == 0, sources, n_sources, features, times_ms,
                                     max_rows, rows, stream);
   return e == hipSuccess ? GC_OK : hip_fail(e, "sched_collect");

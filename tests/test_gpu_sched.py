@@ -220,3 +220,84 @@ def test_trained_network_gains_over_heuristic():
     for kind, (vs_heur, vs_pull) in gains.items():
         assert vs_heur >= 0.8, (kind, vs_heur)
         assert vs_pull > 1.0, (kind, vs_pull)
+
+
+def _pagerank_l1(g, got):
+    r0 = np.full(g.n, 1.0 / g.n)
+    want = oracle.pagerank(g.n, g.rowptr, g.colidx, 0.85, 20, mode=oracle.UNIFORM, r0=r0)
+    return float(np.abs(got.astype(np.float64) - want).sum())
+
+
+def test_learned_pagerank_form():
+    """PageRank under the learned scheduler: rows collected on R-MAT 16 and
+    20 (every form timed from the same ranks), network trained on them, then
+    pagerank_learned on R-MAT 21. The form it picks gives ranks within L1
+    1e-6 of the oracle after 20 iterations, and its time per iteration is
+    within 1.5x of the fastest fixed form measured on the same graph (a wide
+    margin: the forms differ by up to 20x, and timings carry noise)."""
+    import time
+    import paper_1904_02241_amd as gc
+    widths = [1 << 15, 1 << 16, 1 << 18, 1 << 20]
+    K = 2 + len(widths)
+    X, T = [], []
+    for scale in (16, 20):
+        g = gg.rmat(scale, 16, seed=1)
+        h = load(g)
+        parts = [gc.tocab_partition(h, gc.GC_PULL, W, 4096) for W in widths]
+        f, t = gc.sched_collect_pagerank(h, parts, rows=3)
+        assert f.shape == (3, 6) and t.shape == (3, K) and (t > 0).all()
+        X.append(f)
+        T.append(t)
+        for p in parts:
+            p.free()
+        h.free()
+    X = np.concatenate(X)
+    Tms = np.maximum(np.concatenate(T), 1e-4)
+    best = Tms.min(axis=1)
+    M = np.ones_like(Tms, dtype=np.float32)
+    m = gc.sched_create(K, mlp.init_params(K, seed=1).astype(np.float32))
+    gc.sched_train(m, dev(X), dev(np.log(Tms / best[:, None]).astype(np.float32)), dev(M), 2000, 3e-3)
+
+    g = gg.rmat(21, 16, seed=8)
+    h = load(g)
+    parts = [gc.tocab_partition(h, gc.GC_PULL, W, 4096) for W in widths]
+    tt = torch()
+    rin = tt.full((g.n,), 1.0 / g.n, dtype=tt.float32, device="cuda")
+    rout = tt.empty_like(rin)
+    with pytest.raises(gc.GraphCageError):  # no network attached
+        gc.pagerank_learned(h, 0.85, gc.GC_DANGLING_UNIFORM, rin, rout, 1)
+    gc.sched_attach(h, m, parts)
+    a = gc.pagerank_learned(h, 0.85, gc.GC_DANGLING_UNIFORM, rin, rout, 20)
+    assert 0 <= a < K
+    err = _pagerank_l1(g, host(rout))
+    assert err <= 1e-6, err
+
+    def per_iter(fn):
+        fn(2)
+        tt.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(10)
+        tt.cuda.synchronize()
+        return (time.perf_counter() - t0) / 10
+
+    fixed = [per_iter(lambda k: gc.pagerank_iter(h, None, gc.GC_PUSH, 0.85, 0, rin, rout, k)),
+             per_iter(lambda k: gc.pagerank_iter(h, None, gc.GC_PULL, 0.85, 0, rin, rout, k))]
+    fixed += [per_iter(lambda k, p=p: gc.pagerank_iter(h, p, gc.GC_PULL, 0.85, 0, rin, rout, k)) for p in parts]
+    learned = per_iter(lambda k: gc.pagerank_learned(h, 0.85, 0, rin, rout, k))
+    print(f"learned form {a}: {learned * 1e3:.3f} ms/iter; fixed forms (push, pull, TOCAB@{widths}): "
+          f"{[round(x * 1e3, 3) for x in fixed]}")
+    assert learned <= 1.5 * min(fixed)
+
+    # a network without finite outputs: the working-set rule (TOCAB pull over
+    # the attached width nearest 2^18)
+    nan_net = gc.sched_create(K, np.full(gc.sched_param_count(K), np.nan, np.float32))
+    gc.sched_attach(h, nan_net, parts)
+    a = gc.pagerank_learned(h, 0.85, gc.GC_DANGLING_UNIFORM, rin, rout, 20)
+    assert a == 2 + widths.index(1 << 18)
+    assert _pagerank_l1(g, host(rout)) <= 1e-6
+    gc.sched_attach(h, None)
+    nan_net.free()
+    m.free()
+    for p in parts:
+        p.free()
+    h.free()
