@@ -42,8 +42,8 @@ struct gc_graph_s {
   double* ltotal = nullptr;
   float* rank_tmp = nullptr;
   // traversal scratch
-  uint8_t* front = nullptr;   // status arrays (Section 3.3)
-  uint8_t* next = nullptr;
+  uint32_t* front = nullptr;  // status arrays (Section 3.3), one bit per vertex
+  uint32_t* next = nullptr;
   int32_t* queue[2] = {nullptr, nullptr};
   uint32_t* visited = nullptr;  // BFS: bitmap of vertices with a final depth
   int32_t* mark = nullptr;      // SSSP push: round in which a vertex was queued

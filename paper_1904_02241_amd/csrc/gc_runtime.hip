@@ -194,8 +194,9 @@ int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* c
   g->dpart = static_cast<double*>(gcx::dev_alloc(sizeof(double) * g->dpart_slots, stream));
   g->dtotal = static_cast<double*>(gcx::dev_alloc(sizeof(double) * 2, stream));
   g->counter = static_cast<unsigned*>(gcx::dev_alloc(sizeof(unsigned) * 4, stream));
-  g->front = static_cast<uint8_t*>(gcx::dev_alloc(static_cast<size_t>(n), stream));
-  g->next = static_cast<uint8_t*>(gcx::dev_alloc(static_cast<size_t>(n), stream));
+  const size_t words = (static_cast<size_t>(n) + 31) / 32;
+  g->front = static_cast<uint32_t*>(gcx::dev_alloc(sizeof(uint32_t) * words, stream));
+  g->next = static_cast<uint32_t*>(gcx::dev_alloc(sizeof(uint32_t) * words, stream));
   g->queue[0] = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * n, stream));
   g->queue[1] = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * n, stream));
   g->stats = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * 16, stream));
@@ -216,7 +217,7 @@ int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* c
     return fail(GC_ENOMEM, "graph_load_csr: device allocation failed");
   }
   g->bytes = 2 * static_cast<int64_t>(nb) + 2 * static_cast<int64_t>(mb) * (g->weighted ? 2 : 1) +
-             12 * static_cast<int64_t>(n) + 2 * static_cast<int64_t>(n) + 8 * static_cast<int64_t>(n) +
+             12 * static_cast<int64_t>(n) + 8 * static_cast<int64_t>(words) + 8 * static_cast<int64_t>(n) +
              8 * static_cast<int64_t>(n) + 4;
 
   const hipMemcpyKind kind = hipMemcpyDefault;  // the runtime resolves host or device sources

@@ -1,9 +1,11 @@
 // Traversal on gfx950: BFS and SSSP level by level (Section 3.3).
 //
 // Frontier state kept by the library, per graph handle:
-//   front[v]   status array of the current frontier (1 = active), n bytes
-//   next[v]    status array being filled for the next level; all zero when a
-//              level starts (cleared through the old frontier's queue)
+//   front      status of the current frontier, one bit per vertex (the
+//              paper's status array, at n/8 bytes: 2 MB at 2^24 vertices,
+//              so the random tests of a pull level stay in one XCD's L2)
+//   next       the same for the next level; all zero when a level starts
+//              (cleared through the old frontier's queue)
 //   queue      list of the current frontier (size n_f), and the list being
 //              filled for the next level
 //   visited    bitmap of vertices with a final depth (BFS)
@@ -78,23 +80,19 @@ __global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t x) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = x;
 }
 
-__global__ void k_fill_u8(uint8_t* __restrict__ a, int64_t n) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = 0;
-}
-
-__global__ void k_set_source(int32_t src, int32_t* __restrict__ value, uint8_t* __restrict__ front,
+__global__ void k_set_source(int32_t src, int32_t* __restrict__ value, uint32_t* __restrict__ front,
                              int32_t* __restrict__ queue, uint32_t* __restrict__ visited) {
   value[src] = 0;
-  front[src] = 1;
+  front[src >> 5] |= 1u << (src & 31);
   queue[0] = src;
   if (visited) visited[src >> 5] |= 1u << (src & 31);
 }
 
-// front[q] = 0 for the entries of the old frontier's queue.
-__global__ void k_clear_front(uint8_t* __restrict__ front, const int32_t* __restrict__ queue, int32_t qn) {
+// Clears the old frontier's bitmap through its queue: every set bit belongs
+// to a queued vertex, so zeroing the words the queue touches clears it all.
+__global__ void k_clear_front(uint32_t* __restrict__ front, const int32_t* __restrict__ queue, int32_t qn) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < qn) front[queue[i]] = 0;
+  if (i < qn) front[queue[i] >> 5] = 0u;
 }
 
 // Out-arc count of the queued vertices (for the direction heuristic).
@@ -115,14 +113,14 @@ __global__ void k_queue_degree(const int32_t* __restrict__ queue, const int32_t*
 
 // Scans in-arcs [b, e) for an active source; rows longer than kHeavy are
 // taken by the whole wave, which stops as soon as any lane hits.
-__device__ __forceinline__ bool scan_front(const int32_t* __restrict__ col, const uint8_t* __restrict__ front,
+__device__ __forceinline__ bool scan_front(const int32_t* __restrict__ col, const uint32_t* __restrict__ front,
                                            bool active, int32_t b, int32_t e) {
   const int lane = gcd::lane_id();
   const bool heavy = active && (e - b) > kHeavy;
   bool found = false;
   if (active && !heavy) {
     for (int32_t i = b; i < e; ++i)
-      if (front[col[i]]) {
+      if (bit_test(front, col[i])) {
         found = true;
         break;
       }
@@ -135,7 +133,7 @@ __device__ __forceinline__ bool scan_front(const int32_t* __restrict__ col, cons
     bool hit = false;
     for (int32_t base = hb; base < he; base += kWave) {
       const int32_t i = base + lane;
-      const bool h = i < he && front[col[i]];
+      const bool h = i < he && bit_test(front, col[i]);
       if (__any(h)) {
         hit = true;
         break;
@@ -149,8 +147,8 @@ __device__ __forceinline__ bool scan_front(const int32_t* __restrict__ col, cons
 // Topology-driven pull over the whole transposed graph.
 __global__ __launch_bounds__(kThreads) void k_bfs_pull(const int32_t* __restrict__ t_rowptr,
                                                        const int32_t* __restrict__ t_col, int32_t n,
-                                                       const uint8_t* __restrict__ front, int32_t* __restrict__ depth,
-                                                       int32_t level, uint8_t* __restrict__ next,
+                                                       const uint32_t* __restrict__ front, int32_t* __restrict__ depth,
+                                                       int32_t level, uint32_t* __restrict__ next,
                                                        uint32_t* __restrict__ visited, int32_t* __restrict__ queue,
                                                        int32_t* __restrict__ stats) {
   const int32_t v = blockIdx.x * kThreads + threadIdx.x;
@@ -164,7 +162,7 @@ __global__ __launch_bounds__(kThreads) void k_bfs_pull(const int32_t* __restrict
   const bool found = scan_front(t_col, front, active, b, e);
   if (found) {
     depth[v] = level + 1;
-    next[v] = 1;
+    bit_set(next, v);
     bit_set(visited, v);
   }
   block_append(found, v, queue, stats + kQLen);
@@ -176,7 +174,7 @@ __global__ __launch_bounds__(kThreads) void k_bfs_tocab(const int32_t* __restric
                                                         const int32_t* __restrict__ col,
                                                         const int32_t* __restrict__ id_map, int64_t P,
                                                         const uint32_t* __restrict__ visited,
-                                                        const uint8_t* __restrict__ front,
+                                                        const uint32_t* __restrict__ front,
                                                         uint8_t* __restrict__ flag) {
   const int64_t l = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
   bool active = false;
@@ -198,7 +196,7 @@ __global__ __launch_bounds__(kThreads) void k_bfs_merge(const int32_t* __restric
                                                         const int32_t* __restrict__ id_map,
                                                         const uint8_t* __restrict__ flag, int32_t n,
                                                         int32_t* __restrict__ depth, int32_t level,
-                                                        uint8_t* __restrict__ next, uint32_t* __restrict__ visited,
+                                                        uint32_t* __restrict__ next, uint32_t* __restrict__ visited,
                                                         int32_t* __restrict__ queue, int32_t* __restrict__ stats) {
   __shared__ uint8_t hit[K];
   const int32_t v0 = blockIdx.x * K;
@@ -217,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void k_bfs_merge(const int32_t* __restric
     const bool found = v < n && hit[i] && !bit_test(visited, v);
     if (found) {
       depth[v] = level + 1;
-      next[v] = 1;
+      bit_set(next, v);
       bit_set(visited, v);
     }
     block_append(found, v, queue, stats + kQLen);
@@ -231,7 +229,7 @@ __global__ __launch_bounds__(kThreads) void k_bfs_push(const int32_t* __restrict
                                                        const int32_t* __restrict__ rowptr,
                                                        const int32_t* __restrict__ colidx,
                                                        int32_t* __restrict__ depth, int32_t level,
-                                                       uint8_t* __restrict__ next, uint32_t* __restrict__ visited,
+                                                       uint32_t* __restrict__ next, uint32_t* __restrict__ visited,
                                                        int32_t* __restrict__ queue, int32_t* __restrict__ stats) {
   __shared__ int32_t start[kThreads];
   __shared__ int32_t first[kThreads];
@@ -272,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void k_bfs_push(const int32_t* __restrict
       v = colidx[first[lo] + (a - start[lo])];
       if (depth[v] == kInf && atomicCAS(&depth[v], kInf, level + 1) == kInf) {
         disc = true;
-        next[v] = 1;
+        bit_set(next, v);
         bit_set(visited, v);
       }
     }
@@ -287,7 +285,7 @@ __global__ __launch_bounds__(kThreads) void k_bfs_push(const int32_t* __restrict
 // none); rows longer than kHeavy are reduced by the whole wave. *ovf is set
 // when a candidate path length reaches INT32_MAX.
 __device__ __forceinline__ int64_t scan_min(const int32_t* __restrict__ col, const int32_t* __restrict__ w,
-                                            const uint8_t* __restrict__ front, const int32_t* __restrict__ dist,
+                                            const uint32_t* __restrict__ front, const int32_t* __restrict__ dist,
                                             bool active, int32_t b, int32_t e, bool* ovf) {
   const int lane = gcd::lane_id();
   const bool heavy = active && (e - b) > kHeavy;
@@ -296,7 +294,7 @@ __device__ __forceinline__ int64_t scan_min(const int32_t* __restrict__ col, con
   if (active && !heavy) {
     for (int32_t i = b; i < e; ++i) {
       const int32_t u = col[i];
-      if (front[u]) {
+      if (bit_test(front, u)) {
         const int64_t cand = static_cast<int64_t>(dist[u]) + w[i];
         over |= cand >= kInf;
         best = min(best, cand);
@@ -311,7 +309,7 @@ __device__ __forceinline__ int64_t scan_min(const int32_t* __restrict__ col, con
     int64_t m = kInf;
     for (int32_t i = hb + lane; i < he; i += kWave) {
       const int32_t u = col[i];
-      if (front[u]) {
+      if (bit_test(front, u)) {
         const int64_t cand = static_cast<int64_t>(dist[u]) + w[i];
         over |= cand >= kInf;
         m = min(m, cand);
@@ -327,8 +325,8 @@ __device__ __forceinline__ int64_t scan_min(const int32_t* __restrict__ col, con
 __global__ __launch_bounds__(kThreads) void k_sssp_pull(const int32_t* __restrict__ t_rowptr,
                                                         const int32_t* __restrict__ t_col,
                                                         const int32_t* __restrict__ t_w, int32_t n,
-                                                        const uint8_t* __restrict__ front, int32_t* __restrict__ dist,
-                                                        uint8_t* __restrict__ next, int32_t* __restrict__ queue,
+                                                        const uint32_t* __restrict__ front, int32_t* __restrict__ dist,
+                                                        uint32_t* __restrict__ next, int32_t* __restrict__ queue,
                                                         int32_t* __restrict__ stats) {
   const int32_t v = blockIdx.x * kThreads + threadIdx.x;
   int32_t b = 0, e = 0;
@@ -342,7 +340,7 @@ __global__ __launch_bounds__(kThreads) void k_sssp_pull(const int32_t* __restric
   bool improved = false;
   if (v < n && best < dist[v]) {
     dist[v] = static_cast<int32_t>(best);
-    next[v] = 1;
+    bit_set(next, v);
     improved = true;
   }
   block_append(improved, v, queue, stats + kQLen);
@@ -353,7 +351,7 @@ __global__ __launch_bounds__(kThreads) void k_sssp_pull(const int32_t* __restric
 __global__ __launch_bounds__(kThreads) void k_sssp_tocab(const int32_t* __restrict__ row_ptr,
                                                          const int32_t* __restrict__ col,
                                                          const int32_t* __restrict__ w, int64_t P,
-                                                         const uint8_t* __restrict__ front,
+                                                         const uint32_t* __restrict__ front,
                                                          const int32_t* __restrict__ dist, int32_t* __restrict__ pmin,
                                                          int32_t* __restrict__ stats) {
   const int64_t l = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
@@ -372,7 +370,7 @@ template <int K>
 __global__ __launch_bounds__(kThreads) void k_sssp_merge(const int32_t* __restrict__ range_ptr, int32_t B,
                                                          const int32_t* __restrict__ id_map,
                                                          const int32_t* __restrict__ pmin, int32_t n,
-                                                         int32_t* __restrict__ dist, uint8_t* __restrict__ next,
+                                                         int32_t* __restrict__ dist, uint32_t* __restrict__ next,
                                                          int32_t* __restrict__ queue, int32_t* __restrict__ stats) {
   __shared__ int32_t best[K];
   const int32_t v0 = blockIdx.x * K;
@@ -393,7 +391,7 @@ __global__ __launch_bounds__(kThreads) void k_sssp_merge(const int32_t* __restri
     bool improved = false;
     if (v < n && best[i] < dist[v]) {
       dist[v] = best[i];
-      next[v] = 1;
+      bit_set(next, v);
       improved = true;
     }
     block_append(improved, v, queue, stats + kQLen);
@@ -407,7 +405,7 @@ __global__ __launch_bounds__(kThreads) void k_sssp_push(const int32_t* __restric
                                                         const int32_t* __restrict__ colidx,
                                                         const int32_t* __restrict__ w, int32_t* __restrict__ dist,
                                                         int32_t round, int32_t* __restrict__ mark,
-                                                        uint8_t* __restrict__ next, int32_t* __restrict__ queue,
+                                                        uint32_t* __restrict__ next, int32_t* __restrict__ queue,
                                                         int32_t* __restrict__ stats) {
   __shared__ int32_t start[kThreads];
   __shared__ int32_t first[kThreads];
@@ -455,7 +453,7 @@ __global__ __launch_bounds__(kThreads) void k_sssp_push(const int32_t* __restric
       } else if (static_cast<int32_t>(nd) < dist[v]) {
         const int32_t old = atomicMin(&dist[v], static_cast<int32_t>(nd));
         if (static_cast<int32_t>(nd) < old) {
-          next[v] = 1;
+          bit_set(next, v);
           fresh = atomicExch(&mark[v], round) != round;
         }
       }
@@ -481,7 +479,7 @@ __global__ void k_fill_f64(double* __restrict__ a, int64_t n) {
 
 // Sum of sigma[u] over in-arcs [b, e) from active sources u (FP64); rows
 // longer than kHeavy are summed by the whole wave.
-__device__ __forceinline__ double scan_sigma(const int32_t* __restrict__ col, const uint8_t* __restrict__ front,
+__device__ __forceinline__ double scan_sigma(const int32_t* __restrict__ col, const uint32_t* __restrict__ front,
                                              const double* __restrict__ sigma, bool active, int32_t b, int32_t e) {
   const int lane = gcd::lane_id();
   const bool heavy = active && (e - b) > kHeavy;
@@ -494,13 +492,13 @@ __device__ __forceinline__ double scan_sigma(const int32_t* __restrict__ col, co
 #pragma unroll
       for (int k = 0; k < 4; ++k) u[k] = col[i + k];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) on[k] = front[u[k]] != 0;
+      for (int k = 0; k < 4; ++k) on[k] = bit_test(front, u[k]);
 #pragma unroll
       for (int k = 0; k < 4; ++k) s += on[k] ? sigma[u[k]] : 0.0;
     }
     for (; i < e; ++i) {
       const int32_t u = col[i];
-      if (front[u]) s += sigma[u];
+      if (bit_test(front, u)) s += sigma[u];
     }
   }
   uint64_t pending = __ballot(heavy);
@@ -511,7 +509,7 @@ __device__ __forceinline__ double scan_sigma(const int32_t* __restrict__ col, co
     double m = 0.0;
     for (int32_t i = hb + lane; i < he; i += kWave) {
       const int32_t u = col[i];
-      if (front[u]) m += sigma[u];
+      if (bit_test(front, u)) m += sigma[u];
     }
     m = gcd::wave_sum(m);
     if (lane == owner) s = m;
@@ -523,9 +521,9 @@ __device__ __forceinline__ double scan_sigma(const int32_t* __restrict__ col, co
 // joins the next level with the sum of their path counts.
 __global__ __launch_bounds__(kThreads) void k_bc_pull(const int32_t* __restrict__ t_rowptr,
                                                       const int32_t* __restrict__ t_col, int32_t n,
-                                                      const uint8_t* __restrict__ front, int32_t* __restrict__ depth,
+                                                      const uint32_t* __restrict__ front, int32_t* __restrict__ depth,
                                                       int32_t level, double* __restrict__ sigma,
-                                                      uint8_t* __restrict__ next, uint32_t* __restrict__ visited,
+                                                      uint32_t* __restrict__ next, uint32_t* __restrict__ visited,
                                                       int32_t* __restrict__ queue, int32_t* __restrict__ stats) {
   const int32_t v = blockIdx.x * kThreads + threadIdx.x;
   bool active = false;
@@ -540,7 +538,7 @@ __global__ __launch_bounds__(kThreads) void k_bc_pull(const int32_t* __restrict_
   if (found) {
     depth[v] = level + 1;
     sigma[v] = sum;
-    next[v] = 1;
+    bit_set(next, v);
     bit_set(visited, v);
   }
   block_append(found, v, queue, stats + kQLen);
@@ -552,7 +550,7 @@ __global__ __launch_bounds__(kThreads) void k_bc_tocab(const int32_t* __restrict
                                                        const int32_t* __restrict__ col,
                                                        const int32_t* __restrict__ id_map, int64_t P,
                                                        const uint32_t* __restrict__ visited,
-                                                       const uint8_t* __restrict__ front,
+                                                       const uint32_t* __restrict__ front,
                                                        const double* __restrict__ sigma, double* __restrict__ part) {
   const int64_t l = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
   bool active = false;
@@ -573,7 +571,7 @@ __global__ __launch_bounds__(kThreads) void k_bc_merge(const int32_t* __restrict
                                                        const uint16_t* __restrict__ id16,
                                                        const double* __restrict__ part, int32_t n,
                                                        int32_t* __restrict__ depth, int32_t level,
-                                                       double* __restrict__ sigma, uint8_t* __restrict__ next,
+                                                       double* __restrict__ sigma, uint32_t* __restrict__ next,
                                                        uint32_t* __restrict__ visited, int32_t* __restrict__ queue,
                                                        int32_t* __restrict__ stats) {
   __shared__ double acc[K];
@@ -585,7 +583,7 @@ __global__ __launch_bounds__(kThreads) void k_bc_merge(const int32_t* __restrict
     if (found) {
       depth[v] = level + 1;
       sigma[v] = acc[i];
-      next[v] = 1;
+      bit_set(next, v);
       bit_set(visited, v);
     }
     block_append(found, v, queue, stats + kQLen);
@@ -598,7 +596,7 @@ __global__ __launch_bounds__(kThreads) void k_bc_push(const int32_t* __restrict_
                                                       const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ colidx,
                                                       int32_t* __restrict__ depth, int32_t level,
-                                                      double* __restrict__ sigma, uint8_t* __restrict__ next,
+                                                      double* __restrict__ sigma, uint32_t* __restrict__ next,
                                                       uint32_t* __restrict__ visited, int32_t* __restrict__ queue,
                                                       int32_t* __restrict__ stats) {
   __shared__ int32_t start[kThreads];
@@ -647,7 +645,7 @@ __global__ __launch_bounds__(kThreads) void k_bc_push(const int32_t* __restrict_
         old = atomicCAS(&depth[v], kInf, level + 1);
         if (old == kInf) {
           disc = true;
-          next[v] = 1;
+          bit_set(next, v);
           bit_set(visited, v);
         }
       }
@@ -669,12 +667,12 @@ constexpr int kPushArcs = 8;
 struct BfsRelax {  // Algorithm 3's CAS on depth
   int32_t* depth;
   int32_t level;
-  uint8_t* next;
+  uint32_t* next;
   uint32_t* visited;
   __device__ int32_t src(int32_t) const { return 0; }
   __device__ bool relax(int32_t v, int64_t, int32_t) const {
     if (depth[v] == kInf && atomicCAS(&depth[v], kInf, level + 1) == kInf) {
-      next[v] = 1;
+      bit_set(next, v);
       bit_set(visited, v);
       return true;
     }
@@ -687,7 +685,7 @@ struct SsspRelax {  // atomicMin on dist; a vertex is queued once per round (sta
   int32_t* dist;
   int32_t round;
   int32_t* mark;
-  uint8_t* next;
+  uint32_t* next;
   int32_t* stats;
   __device__ int32_t src(int32_t u) const { return dist[u]; }
   __device__ bool relax(int32_t v, int64_t e, int32_t du) const {
@@ -697,7 +695,7 @@ struct SsspRelax {  // atomicMin on dist; a vertex is queued once per round (sta
     } else if (static_cast<int32_t>(nd) < dist[v]) {
       const int32_t old = atomicMin(&dist[v], static_cast<int32_t>(nd));
       if (static_cast<int32_t>(nd) < old) {
-        next[v] = 1;
+        bit_set(next, v);
         return atomicExch(&mark[v], round) != round;
       }
     }
@@ -709,7 +707,7 @@ struct BcRelax {  // the BFS CAS plus sigma[v] += sigma[u] for arcs that land on
   int32_t* depth;
   int32_t level;
   double* sigma;
-  uint8_t* next;
+  uint32_t* next;
   uint32_t* visited;
   __device__ double src(int32_t u) const { return sigma[u]; }
   __device__ bool relax(int32_t v, int64_t, double su) const {
@@ -719,7 +717,7 @@ struct BcRelax {  // the BFS CAS plus sigma[v] += sigma[u] for arcs that land on
       old = atomicCAS(&depth[v], kInf, level + 1);
       if (old == kInf) {
         disc = true;
-        next[v] = 1;
+        bit_set(next, v);
         bit_set(visited, v);
       }
     }
@@ -954,8 +952,8 @@ struct Frontier {
   int cur = 0;
   int32_t n_f = 1;
   int64_t m_f = 0;
-  uint8_t* front() { return cur == 0 ? g->front : g->next; }
-  uint8_t* next() { return cur == 0 ? g->next : g->front; }
+  uint32_t* front() { return cur == 0 ? g->front : g->next; }
+  uint32_t* next() { return cur == 0 ? g->next : g->front; }
   int32_t* queue() { return g->queue[cur]; }
   int32_t* queue_next() { return g->queue[cur ^ 1]; }
 
@@ -980,9 +978,9 @@ struct Frontier {
 hipError_t init_state(gc_graph g, int32_t* value, int32_t source, bool bfs, hipStream_t s) {
   const int32_t n = g->n;
   k_fill_i32<<<grid_for(n, kThreads), kThreads, 0, s>>>(value, n, kInf);
-  k_fill_u8<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->front, n);
-  k_fill_u8<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->next, n);
   const int64_t words = (static_cast<int64_t>(n) + 31) / 32;
+  k_fill_i32<<<grid_for(words, kThreads), kThreads, 0, s>>>(reinterpret_cast<int32_t*>(g->front), words, 0);
+  k_fill_i32<<<grid_for(words, kThreads), kThreads, 0, s>>>(reinterpret_cast<int32_t*>(g->next), words, 0);
   k_fill_i32<<<grid_for(words, kThreads), kThreads, 0, s>>>(reinterpret_cast<int32_t*>(g->visited), words, 0);
   if (!bfs) k_fill_i32<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->mark, n, -1);
   k_set_source<<<1, 1, 0, s>>>(source, value, g->front, g->queue[0], bfs ? g->visited : nullptr);
@@ -1323,7 +1321,8 @@ hipError_t collect(gc_graph g, gc_tocab* parts, int32_t n_parts, bool bfs, const
   const int32_t n = g->n;
   const int32_t K = 2 + n_parts;
   const size_t words = (static_cast<size_t>(n) + 31) / 32;
-  Buf value(sizeof(int32_t) * n, s), sv(sizeof(int32_t) * n, s), sfront(n, s), snext(n, s),
+  Buf value(sizeof(int32_t) * n, s), sv(sizeof(int32_t) * n, s), sfront(sizeof(uint32_t) * words, s),
+      snext(sizeof(uint32_t) * words, s),
       svis(sizeof(uint32_t) * words, s), smark(sizeof(int32_t) * n, s), squeue(sizeof(int32_t) * n, s);
   if (!value.p || !sv.p || !sfront.p || !snext.p || !svis.p || !smark.p || !squeue.p) return hipErrorOutOfMemory;
   hipEvent_t e0, e1;
@@ -1344,8 +1343,8 @@ hipError_t collect(gc_graph g, gc_tocab* parts, int32_t n_parts, bool bfs, const
       // snapshot the state this level starts from
       const hipMemcpyKind dd = hipMemcpyDeviceToDevice;
       err = hipMemcpyAsync(sv.p, value.p, sizeof(int32_t) * n, dd, s);
-      if (err == hipSuccess) err = hipMemcpyAsync(sfront.p, f.front(), n, dd, s);
-      if (err == hipSuccess) err = hipMemcpyAsync(snext.p, f.next(), n, dd, s);
+      if (err == hipSuccess) err = hipMemcpyAsync(sfront.p, f.front(), sizeof(uint32_t) * words, dd, s);
+      if (err == hipSuccess) err = hipMemcpyAsync(snext.p, f.next(), sizeof(uint32_t) * words, dd, s);
       if (err == hipSuccess) err = hipMemcpyAsync(svis.p, g->visited, sizeof(uint32_t) * words, dd, s);
       if (err == hipSuccess && !bfs) err = hipMemcpyAsync(smark.p, g->mark, sizeof(int32_t) * n, dd, s);
       if (err == hipSuccess) err = hipMemcpyAsync(squeue.p, f.queue(), sizeof(int32_t) * f.n_f, dd, s);
@@ -1353,8 +1352,8 @@ hipError_t collect(gc_graph g, gc_tocab* parts, int32_t n_parts, bool bfs, const
       auto restore = [&]() -> hipError_t {
         f = start;
         GC_HIP_TRY(hipMemcpyAsync(value.p, sv.p, sizeof(int32_t) * n, dd, s));
-        GC_HIP_TRY(hipMemcpyAsync(f.front(), sfront.p, n, dd, s));
-        GC_HIP_TRY(hipMemcpyAsync(f.next(), snext.p, n, dd, s));
+        GC_HIP_TRY(hipMemcpyAsync(f.front(), sfront.p, sizeof(uint32_t) * words, dd, s));
+        GC_HIP_TRY(hipMemcpyAsync(f.next(), snext.p, sizeof(uint32_t) * words, dd, s));
         GC_HIP_TRY(hipMemcpyAsync(g->visited, svis.p, sizeof(uint32_t) * words, dd, s));
         if (!bfs) GC_HIP_TRY(hipMemcpyAsync(g->mark, smark.p, sizeof(int32_t) * n, dd, s));
         return hipMemcpyAsync(f.queue(), squeue.p, sizeof(int32_t) * f.n_f, dd, s);

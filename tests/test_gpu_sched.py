@@ -149,17 +149,21 @@ def test_network_without_finite_output_falls_back_to_heuristic():
 
 
 def test_trained_network_gains_over_heuristic():
-    """Trains the network on levels collected on R-MAT 16 and R-MAT 20 and
-    runs BFS and SSSP on R-MAT 21 under the learned policy, the working-set
-    heuristic and always-pull. Prints the gains; fails only if the learned
+    """Trains the network on levels collected on R-MAT 16 and R-MAT 22 (seed
+    1) and runs BFS and SSSP on R-MAT 21 of another seed under the learned
+    policy, the working-set heuristic and always-pull. Prints the gains; fails only if the learned
     policy is clearly worse than the heuristic or not better than always
-    pulling (timings on a shared GPU are noisy, the margins are wide)."""
+    pulling (timings carry noise, and the learned policy pays one more
+    synchronisation per level for its device-side decision, about 25 us, so
+    the graph is large enough that levels take far longer than that). The
+    held-out graph lies inside the trained range of sizes: the block-count
+    feature of a larger graph would lie outside what the network saw."""
     import time
     import paper_1904_02241_amd as gc
     widths = [1 << s for s in range(16, 21)]
     K = 2 + len(widths)
     X, T = [], []
-    for scale in (16, 20):
+    for scale in (16, 22):
         g = gg.rmat(scale, 16, seed=1).with_weights(11)
         h = load(g, weights=True)
         parts = [gc.tocab_partition(h, gc.GC_PULL, W, 4096) for W in widths]
