@@ -1,6 +1,6 @@
-// Figure 5 merge, accumulation part, shared by the PageRank, SpMV, batched
-// and BC merges: a work-group of NT threads sums, in FP64 LDS, every
-// block's partial results (float or double) of vertex range j.
+// Figure 5 merge, the walk over every block's partial results of one vertex
+// range by a work-group of NT threads, shared by the PageRank, SpMV, batched
+// and BC merges (FP64 LDS sums) and the BFS / SSSP merges (OR / min).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,18 +15,20 @@ using gcd::kWave;
 
 constexpr int kFlatB = 1024;  // merges over at most this many blocks flatten their slices
 
-// For every block s the local rows mapping into [j*K, (j+1)*K) form one
-// contiguous slice of partial / id16 (local ids ascend with global ids);
-// with B <= kFlatB the slices are walked as one flattened list so every
-// lane keeps several independent loads in flight. FP64 LDS accumulation;
-// zero partials are skipped.
-template <int K, bool kFlat, int NT, class T>
-__device__ __forceinline__ void merge_accumulate(const int32_t* __restrict__ range_ptr, int32_t B,
-                                                 const uint16_t* __restrict__ id16, const T* __restrict__ partial,
-                                                 int32_t j, double* acc) {
+// Walk of range j's entries: for every block s the local rows mapping into
+// [j*K, (j+1)*K) form one contiguous slice of the per-row arrays (local ids
+// ascend with global ids). visit(pos, value) is called once per entry with
+// its position inside the range (id16) and its value. With B <= kFlatB the
+// slices are walked as one flattened list so every lane keeps several
+// independent loads in flight. The walk synchronises the work-group before
+// its first visit and after its last, so LDS the visits update may be
+// initialised right before the call.
+template <bool kFlat, int NT, class T, class Visit>
+__device__ __forceinline__ void merge_slices(const int32_t* __restrict__ range_ptr, int32_t B,
+                                             const uint16_t* __restrict__ id16, const T* __restrict__ partial,
+                                             int32_t j, Visit&& visit) {
   __shared__ int32_t seg_lo[kFlat ? kFlatB : 1];
   __shared__ int32_t seg_pre[kFlat ? kFlatB + 1 : 1];
-  for (int i = threadIdx.x; i < K; i += NT) acc[i] = 0.0;
   const int32_t* lo = range_ptr + static_cast<int64_t>(j) * B;
   const int32_t* hi = lo + B;
   if (kFlat) {
@@ -87,20 +89,29 @@ __device__ __forceinline__ void merge_accumulate(const int32_t* __restrict__ ran
       }
 #pragma unroll
       for (int k = 0; k < kUnroll; ++k)
-        if (f0 + k * NT < total && p[k] != T(0)) atomicAdd(&acc[v[k]], static_cast<double>(p[k]));
+        if (f0 + k * NT < total) visit(static_cast<uint32_t>(v[k]), p[k]);
     }
   } else {
     __syncthreads();
     for (int32_t s = 0; s < B; ++s) {
       const int32_t a = lo[s], z = hi[s];
-      for (int32_t l = a + threadIdx.x; l < z; l += NT) {
-        const uint16_t v = gcd::ld_stream(id16 + l);
-        const T p = gcd::ld_stream(partial + l);
-        if (p != T(0)) atomicAdd(&acc[v], static_cast<double>(p));
-      }
+      for (int32_t l = a + threadIdx.x; l < z; l += NT)
+        visit(static_cast<uint32_t>(gcd::ld_stream(id16 + l)), gcd::ld_stream(partial + l));
     }
   }
   __syncthreads();
+}
+
+// FP64 sums of range j's partial results (float or double) into acc[K] in
+// LDS; zero partials are skipped.
+template <int K, bool kFlat, int NT, class T>
+__device__ __forceinline__ void merge_accumulate(const int32_t* __restrict__ range_ptr, int32_t B,
+                                                 const uint16_t* __restrict__ id16, const T* __restrict__ partial,
+                                                 int32_t j, double* acc) {
+  for (int i = threadIdx.x; i < K; i += NT) acc[i] = 0.0;
+  merge_slices<kFlat, NT>(range_ptr, B, id16, partial, j, [&](uint32_t v, T p) {
+    if (p != T(0)) atomicAdd(&acc[v], static_cast<double>(p));
+  });
 }
 
 }  // namespace gcm

@@ -191,9 +191,9 @@ __global__ __launch_bounds__(kThreads) void k_bfs_tocab(const int32_t* __restric
 // Merge of the per-block flags over vertex range j (OR), fused with the
 // depth update and the next frontier (Section 3.3: the reduction of next is
 // done in the same kernel as that of the partial results).
-template <int K>
+template <int K, bool kFlat>
 __global__ __launch_bounds__(kThreads) void k_bfs_merge(const int32_t* __restrict__ range_ptr, int32_t B,
-                                                        const int32_t* __restrict__ id_map,
+                                                        const uint16_t* __restrict__ id16,
                                                         const uint8_t* __restrict__ flag, int32_t n,
                                                         int32_t* __restrict__ depth, int32_t level,
                                                         uint32_t* __restrict__ next, uint32_t* __restrict__ visited,
@@ -201,15 +201,9 @@ __global__ __launch_bounds__(kThreads) void k_bfs_merge(const int32_t* __restric
   __shared__ uint8_t hit[K];
   const int32_t v0 = blockIdx.x * K;
   for (int i = threadIdx.x; i < K; i += kThreads) hit[i] = 0;
-  __syncthreads();
-  const int32_t* lo = range_ptr + static_cast<int64_t>(blockIdx.x) * B;
-  const int32_t* hi = lo + B;
-  for (int32_t s = 0; s < B; ++s) {
-    const int32_t a = lo[s], z = hi[s];
-    for (int32_t l = a + threadIdx.x; l < z; l += kThreads)
-      if (flag[l]) hit[id_map[l] - v0] = 1;
-  }
-  __syncthreads();
+  gcm::merge_slices<kFlat, kThreads>(range_ptr, B, id16, flag, blockIdx.x, [&](uint32_t v, uint8_t f) {
+    if (f) hit[v] = 1;
+  });
   for (int i = threadIdx.x; i < K; i += kThreads) {
     const int32_t v = v0 + i;
     const bool found = v < n && hit[i] && !bit_test(visited, v);
@@ -366,26 +360,18 @@ __global__ __launch_bounds__(kThreads) void k_sssp_tocab(const int32_t* __restri
   if (l < P) pmin[l] = static_cast<int32_t>(best);
 }
 
-template <int K>
+template <int K, bool kFlat>
 __global__ __launch_bounds__(kThreads) void k_sssp_merge(const int32_t* __restrict__ range_ptr, int32_t B,
-                                                         const int32_t* __restrict__ id_map,
+                                                         const uint16_t* __restrict__ id16,
                                                          const int32_t* __restrict__ pmin, int32_t n,
                                                          int32_t* __restrict__ dist, uint32_t* __restrict__ next,
                                                          int32_t* __restrict__ queue, int32_t* __restrict__ stats) {
   __shared__ int32_t best[K];
   const int32_t v0 = blockIdx.x * K;
   for (int i = threadIdx.x; i < K; i += kThreads) best[i] = kInf;
-  __syncthreads();
-  const int32_t* lo = range_ptr + static_cast<int64_t>(blockIdx.x) * B;
-  const int32_t* hi = lo + B;
-  for (int32_t s = 0; s < B; ++s) {
-    const int32_t a = lo[s], z = hi[s];
-    for (int32_t l = a + threadIdx.x; l < z; l += kThreads) {
-      const int32_t p = pmin[l];
-      if (p != kInf) atomicMin(&best[id_map[l] - v0], p);
-    }
-  }
-  __syncthreads();
+  gcm::merge_slices<kFlat, kThreads>(range_ptr, B, id16, pmin, blockIdx.x, [&](uint32_t v, int32_t p) {
+    if (p != kInf) atomicMin(&best[v], p);
+  });
   for (int i = threadIdx.x; i < K; i += kThreads) {
     const int32_t v = v0 + i;
     bool improved = false;
@@ -931,16 +917,18 @@ hipError_t launch_by_k(int32_t k, int32_t R, hipStream_t s, Args... args) {
 template <int K>
 struct BfsMerge {
   template <class... A>
-  static void run(int32_t R, hipStream_t s, A... a) {
-    k_bfs_merge<K><<<R, kThreads, 0, s>>>(a...);
+  static void run(int32_t R, hipStream_t s, const int32_t* range_ptr, int32_t B, A... a) {
+    if (B <= gcm::kFlatB) k_bfs_merge<K, true><<<R, kThreads, 0, s>>>(range_ptr, B, a...);
+    else k_bfs_merge<K, false><<<R, kThreads, 0, s>>>(range_ptr, B, a...);
   }
 };
 
 template <int K>
 struct SsspMerge {
   template <class... A>
-  static void run(int32_t R, hipStream_t s, A... a) {
-    k_sssp_merge<K><<<R, kThreads, 0, s>>>(a...);
+  static void run(int32_t R, hipStream_t s, const int32_t* range_ptr, int32_t B, A... a) {
+    if (B <= gcm::kFlatB) k_sssp_merge<K, true><<<R, kThreads, 0, s>>>(range_ptr, B, a...);
+    else k_sssp_merge<K, false><<<R, kThreads, 0, s>>>(range_ptr, B, a...);
   }
 };
 
@@ -1028,7 +1016,8 @@ hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t 
                                                                    f.front(), flag);
       }
       ProfScope prof("bfs_merge", s);
-      GC_HIP_TRY((launch_by_k<BfsMerge>(t->k, t->R, s, t->range_ptr, t->B, static_cast<const int32_t*>(t->id_map),
+      GC_HIP_TRY((launch_by_k<BfsMerge>(t->k, t->R, s, static_cast<const int32_t*>(t->range_ptr), t->B,
+                                        static_cast<const uint16_t*>(t->id16),
                                         static_cast<const uint8_t*>(flag), n, value, level, f.next(), g->visited,
                                         f.queue_next(), g->stats)));
     }
@@ -1052,7 +1041,8 @@ hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t 
                                                                     t->pmin, g->stats);
       }
       ProfScope prof("sssp_merge", s);
-      GC_HIP_TRY((launch_by_k<SsspMerge>(t->k, t->R, s, t->range_ptr, t->B, static_cast<const int32_t*>(t->id_map),
+      GC_HIP_TRY((launch_by_k<SsspMerge>(t->k, t->R, s, static_cast<const int32_t*>(t->range_ptr), t->B,
+                                         static_cast<const uint16_t*>(t->id16),
                                          static_cast<const int32_t*>(t->pmin), n, value, f.next(), f.queue_next(),
                                          g->stats)));
     }
