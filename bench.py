@@ -120,18 +120,20 @@ def source_digest():
 
 
 def traffic_from_profiles(kernel):
-    """HBM bytes per launch from a committed rocprofv3 --pmc summary, or None
-    when the kernels' sources changed since the counters were taken."""
+    """(HBM bytes per launch, L2 hit rate) from a committed rocprofv3 --pmc
+    summary, or (None, None) when the kernels' sources changed since the
+    counters were taken."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.md")
     if not os.path.exists(path):
-        return None
+        return None, None
     text = open(path).read()
     want = re.search(r"source_sha256:\s*([0-9a-f]+)", text)
     got = source_digest()
     if not want or want.group(1) != got:
-        return None
+        return None, None
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    return float(b.group(1)) if b else None
+    h = re.search(r"l2_hit_rate:\s*([0-9.]+)", text)
+    return (float(b.group(1)) if b else None), (float(h.group(1)) if h else None)
 
 
 def cpu_baseline(g, budget_s):
@@ -647,10 +649,14 @@ def main():
     dom_ms = kern[dom][0] / kern[dom][1]
     per_launch = kernel_bytes(dom, n, m, info)
     achieved = per_launch / (dom_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles(dom)
+    traffic, l2_hit = traffic_from_profiles(dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "kernel_ms": round(dom_ms, 4), "algorithmic_bytes_per_launch": per_launch}
+    if traffic:  # the measured HBM traffic over the same launch time, beside the algorithmic fraction
+        roofline["traffic_gbs"] = round(traffic / (dom_ms * 1e-3) / 1e9, 1)
+        roofline["traffic_frac"] = round(roofline["traffic_gbs"] / HBM_PEAK_GBS, 4)
+        roofline["l2_hit_rate"] = l2_hit
     step_bytes = sum(kernel_bytes(k, n, m, info) * v[1] for k, v in hres["kernels"].items()) / args.steps
     cpu = None
     if not args.no_cpu_baseline:
