@@ -277,7 +277,7 @@ def suite_spmv(args, gc, gg, torch):
 def suite_bc(args, gc, gg, torch):
     """Section 4's BC on R-MAT: Brandes' accumulation from a set of sources,
     forward levels by plain pull, TOCAB pull, push, or the per-level
-    heuristic. Rate per source = out-arcs of the reached vertices / time of
+    heuristic (with the partition, or with plain pull for its pull levels). Rate per source = out-arcs of the reached vertices / time of
     the source's forward and backward passes (the harmonic mean over sources
     is reported), and the per-kernel times of the whole run."""
     gh = gg.rmat(args.scale, args.edge_factor, seed=1)
@@ -296,7 +296,8 @@ def suite_bc(args, gc, gg, torch):
     out = {}
     for name, policy, use_part in (("plain_pull", gc.GC_POLICY_PULL, False), ("tocab_pull", gc.GC_POLICY_PULL, True),
                                    ("push", gc.GC_POLICY_PUSH, False),
-                                   ("heuristic_tocab", gc.GC_POLICY_HEURISTIC, True)):
+                                   ("heuristic_tocab", gc.GC_POLICY_HEURISTIC, True),
+                                   ("heuristic_plain", gc.GC_POLICY_HEURISTIC, False)):
         rates, times = [], []
         for s, arcs in zip(srcs, reached_arcs):
             torch.cuda.synchronize()

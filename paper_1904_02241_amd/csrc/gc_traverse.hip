@@ -852,6 +852,69 @@ __global__ __launch_bounds__(kThreads) void k_bc_back_arcs(const int32_t* __rest
   }
 }
 
+// The same step in the push direction, chosen when the next level's in-arcs
+// are fewer than this level's out-arcs: over the in-arcs v -> w of the
+// vertices w = order[lo, hi) of depth d + 1 (pre = exclusive scan of their
+// in-degrees along order), balanced like k_bc_back_arcs, coef_in[w] is
+// added into coef_out[v] for every v of depth d (FP64 atomic).
+__global__ __launch_bounds__(kThreads) void k_bc_back_push(const int32_t* __restrict__ t_rowptr,
+                                                           const int32_t* __restrict__ t_colidx,
+                                                           const int32_t* __restrict__ order,
+                                                           const int32_t* __restrict__ pre, int32_t lo, int32_t hi,
+                                                           const int32_t* __restrict__ depth, int32_t d,
+                                                           const double* __restrict__ coef_in,
+                                                           double* __restrict__ coef_out) {
+  const int64_t end = pre[hi];
+  const int64_t a0 = pre[lo] + (static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x) * kBackArcs;
+  if (a0 >= end) return;
+  const int64_t a1 = a0 + kBackArcs < end ? a0 + kBackArcs : end;
+  int32_t l = lo, h = hi - 1;  // the vertex whose in-arcs contain a0
+  while (l < h) {
+    const int32_t mid = l + ((h - l + 1) >> 1);
+    if (pre[mid] <= a0) l = mid;
+    else h = mid - 1;
+  }
+  // position and coefficient of each of the lane's arcs, then all column
+  // loads, then all depth gathers
+  int64_t pos[kBackArcs];
+  double cw[kBackArcs];
+  {
+    int32_t i = l;
+    int32_t w = order[i];
+    int64_t wb = pre[i], we = pre[i + 1];
+    int64_t rb = t_rowptr[w];
+    double c = coef_in[w];
+#pragma unroll
+    for (int k = 0; k < kBackArcs; ++k) {
+      const int64_t a = a0 + k;
+      if (a < a1) {
+        while (a >= we) {  // next vertex with an in-arc at a
+          ++i;
+          wb = we;
+          we = pre[i + 1];
+          w = order[i];
+          rb = t_rowptr[w];
+          c = coef_in[w];
+        }
+        pos[k] = rb + (a - wb);
+        cw[k] = c;
+      } else {
+        pos[k] = pos[0];
+        cw[k] = 0.0;
+      }
+    }
+  }
+  int32_t v[kBackArcs];
+#pragma unroll
+  for (int k = 0; k < kBackArcs; ++k) v[k] = t_colidx[pos[k]];
+  bool on[kBackArcs];
+#pragma unroll
+  for (int k = 0; k < kBackArcs; ++k) on[k] = a0 + k < a1 && depth[v[k]] == d;
+#pragma unroll
+  for (int k = 0; k < kBackArcs; ++k)
+    if (on[k]) atomicAdd(&coef_out[v[k]], cw[k]);
+}
+
 // delta[v] = sigma[v] * (sum held in coef[v]) is added into bc[v], and
 // coef[v] becomes (1 + delta[v]) / sigma[v].
 __global__ void k_bc_finish(const int32_t* __restrict__ order, int32_t cnt, const double* __restrict__ sigma,
@@ -1277,22 +1340,45 @@ hipError_t bc_run(gc_graph g, gc_tocab t, const int32_t* sources, int32_t n_src,
       m_u -= f.m_f;
       ++level;
     }
-    // depths run 0 .. level-1 (level = lv_off.size() - 1); pre = exclusive
-    // scan of the out-degrees along order; the deepest level's arcs only
-    // reach zero coefficients, and the source (depth 0) takes no share
+    // depths run 0 .. level-1 (level = lv_off.size() - 1). Each step d runs
+    // in the direction with fewer arcs: pull over the out-arcs of depth d
+    // (arc_pre = exclusive scan of out-degrees along order) or push over
+    // the in-arcs of depth d + 1 (pre_in, the same for in-degrees). The
+    // deepest level's step only sets coef = 1 / sigma; the source (depth 0)
+    // takes no share.
     ProfScope prof("bc_back", s);
     const int32_t reached = lv_off.back();
+    Buf pre_in(sizeof(int32_t) * (static_cast<size_t>(reached) + 1), s);
+    if (!pre_in.p) return hipErrorOutOfMemory;
     k_order_degree<<<grid_for(reached, kThreads), kThreads, 0, s>>>(g->bc_order, reached, g->rowptr, g->arc_deg);
     GC_HIP_TRY(hipGetLastError());
     GC_HIP_TRY(scan_exclusive(g->arc_deg, g->arc_pre, reached, s));
+    k_order_degree<<<grid_for(reached, kThreads), kThreads, 0, s>>>(g->bc_order, reached, g->t_rowptr, g->arc_deg);
+    GC_HIP_TRY(hipGetLastError());
+    GC_HIP_TRY(scan_exclusive(g->arc_deg, pre_in.as<int32_t>(), reached, s));
+    std::vector<int32_t> in_at(lv_off.size());  // in-arcs before each level's first vertex
+    for (size_t k = 0; k < lv_off.size(); ++k)
+      GC_HIP_TRY(hipMemcpyAsync(&in_at[k], pre_in.as<int32_t>() + lv_off[k], sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s));
+    GC_HIP_TRY(hipStreamSynchronize(s));
     for (int32_t d = level - 1; d >= 1; --d) {
       const int32_t lo = lv_off[d], hi = lv_off[d + 1];
       double* coef_out = g->bc_coef + static_cast<size_t>(d & 1) * n;
       const double* coef_in = g->bc_coef + static_cast<size_t>((d + 1) & 1) * n;
-      const int64_t pieces = (lv_arcs[d] + kBackArcs - 1) / kBackArcs;
-      if (pieces > 0)
-        k_bc_back_arcs<<<grid_for(pieces, kThreads), kThreads, 0, s>>>(g->rowptr, g->colidx, g->bc_order, g->arc_pre,
-                                                                       lo, hi, coef_in, coef_out);
+      const int64_t out_arcs = lv_arcs[d];
+      const int64_t in_next = d + 1 < level ? static_cast<int64_t>(in_at[d + 2]) - in_at[d + 1] : 0;
+      if (d + 1 < level && in_next < out_arcs) {
+        const int64_t pieces = (in_next + kBackArcs - 1) / kBackArcs;
+        if (pieces > 0)
+          k_bc_back_push<<<grid_for(pieces, kThreads), kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, g->bc_order,
+                                                                         pre_in.as<int32_t>(), hi, lv_off[d + 2],
+                                                                         g->bc_depth, d, coef_in, coef_out);
+      } else if (d + 1 < level) {
+        const int64_t pieces = (out_arcs + kBackArcs - 1) / kBackArcs;
+        if (pieces > 0)
+          k_bc_back_arcs<<<grid_for(pieces, kThreads), kThreads, 0, s>>>(g->rowptr, g->colidx, g->bc_order,
+                                                                         g->arc_pre, lo, hi, coef_in, coef_out);
+      }
       k_bc_finish<<<grid_for(hi - lo, kThreads), kThreads, 0, s>>>(g->bc_order + lo, hi - lo, g->bc_sigma, coef_out,
                                                                     bc);
     }
