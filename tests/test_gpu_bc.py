@@ -30,7 +30,18 @@ GRAPHS = {
     "two_components": graphs.two_components,
     "dangling_mix": graphs.dangling_mix,
     "dups_loops": graphs.with_dups_and_loops,
+    "dense_level": lambda: _dense_level(60),
 }
+
+
+def _dense_level(k):
+    """Source 0 -> 1..k (depth 1), every pair of 1..k joined both ways (arcs
+    inside the level), 1 -> k + 1 and k + 1 -> k + 2 (depths 2, 3): the step
+    of depth 1 has k(k - 1) + 1 out-arcs and the level below one in-arc, so
+    the backward pushes there; the other steps pull."""
+    src = [0] * k + [u for u in range(1, k + 1) for v in range(1, k + 1) if u != v] + [1, k + 1]
+    dst = list(range(1, k + 1)) + [v for u in range(1, k + 1) for v in range(1, k + 1) if u != v] + [k + 1, k + 2]
+    return gg.from_edges(k + 3, src, dst, name="dense_level")
 
 # (policy name, use a TOCAB partition)
 VARIANTS = [("pull", False), ("pull", True), ("push", False), ("heuristic", False), ("heuristic", True)]
