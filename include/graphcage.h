@@ -39,7 +39,7 @@ typedef enum {
   GC_EINVAL = -1,       /* bad argument or malformed graph                    */
   GC_ENOMEM = -2,       /* the allocator returned NULL                        */
   GC_EHIP = -3,         /* a HIP runtime call failed                          */
-  GC_EUNSUPPORTED = -4, /* valid request this build does not handle           */
+  GC_EUNSUPPORTED = -4, /* valid request the library does not handle         */
   GC_EOVERFLOW = -5     /* a result would not fit its integer type            */
 } gc_status;
 
