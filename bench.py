@@ -544,8 +544,8 @@ def main():
     ap.add_argument("--traversal-block-width", type=int, default=1 << 18,
                     help="TOCAB block width of BFS / SSSP partitions (last-level-cache sized)")
     ap.add_argument("--traversal-merge-range", type=int, default=4096)
-    ap.add_argument("--push-block-width", type=int, default=1 << 18,
-                    help="TOCAB push block width (destination slices of FP64 sums in L2)")
+    ap.add_argument("--push-block-width", type=int, default=1 << 13,
+                    help="TOCAB push block width (up to 2^14: the block's FP64 sums in LDS)")
     ap.add_argument("--forms", default="tocab_pull,plain_pull,tocab_push,plain_push",
                     help="comma list; the first is the headline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

@@ -788,6 +788,66 @@ __global__ __launch_bounds__(kThreads) void k_pr_push(const int32_t* __restrict_
 }
 
 // Update after a push pass; clears sums for the next pass.
+// Algorithm 5 with the destination block's sums in LDS: in a push partition
+// block s holds every arc into destinations [sW, (s+1)W), so work-group s
+// adds each of its local rows' contribution c[id_map[l]] into FP64 LDS sums
+// (W <= kPushLdsMaxWidth: 128 KB), then applies the update to its whole
+// range itself: no global atomics and no separate apply pass. A thread takes
+// whole rows (a (source, block) pair holds few arcs). c is read from one
+// buffer and the next iteration's contributions go to u.contrib, another.
+constexpr int32_t kPushLdsMaxWidth = 1 << 14;
+constexpr int kPushLdsThreads = 1024;
+
+__global__ __launch_bounds__(kPushLdsThreads) void k_pr_push_lds(const int32_t* __restrict__ blk_rowoff,
+                                                                 const int32_t* __restrict__ row_ptr,
+                                                                 const int32_t* __restrict__ id_map,
+                                                                 const int32_t* __restrict__ col, int32_t log2W,
+                                                                 const float* __restrict__ c, Update u) {
+  extern __shared__ double acc[];  // the block's W sums
+  const int32_t W = 1 << log2W;
+  const int32_t v0 = static_cast<int32_t>(blockIdx.x) << log2W;
+  for (int32_t i = threadIdx.x; i < W; i += kPushLdsThreads) acc[i] = 0.0;
+  __syncthreads();
+  const int32_t r0 = blk_rowoff[blockIdx.x], r1 = blk_rowoff[blockIdx.x + 1];
+  // kRows rows per thread and step, their loads issued together (row
+  // bounds and ids, then the contributions, then each row's first arc: a
+  // local row has at least one); rows past r1 reuse the last row, masked
+  constexpr int kRows = 4;
+  for (int32_t r = r0 + threadIdx.x; r < r1; r += kRows * kPushLdsThreads) {
+    int32_t b[kRows], e[kRows], id[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int32_t rk = min(r + k * kPushLdsThreads, r1 - 1);
+      b[k] = row_ptr[rk];
+      e[k] = row_ptr[rk + 1];
+      id[k] = id_map[rk];
+    }
+    float x[kRows];
+    int32_t c0[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      x[k] = c[id[k]];
+      c0[k] = col[b[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      if (r + k * kPushLdsThreads < r1) {
+        const double xk = static_cast<double>(x[k]);
+        atomicAdd(&acc[c0[k] - v0], xk);
+        for (int32_t a = b[k] + 1; a < e[k]; ++a) atomicAdd(&acc[col[a] - v0], xk);
+      }
+    }
+  }
+  __syncthreads();
+  const double D = *u.dtotal_in;
+  double mine = 0.0, dl = 0.0;
+  for (int32_t i = threadIdx.x; i < W; i += kPushLdsThreads) {
+    const int32_t v = v0 + i;
+    if (v < u.n) mine += update_vertex(u, v, acc[i], D, dl);
+  }
+  publish_update<kPushLdsThreads>(u, mine, dl);
+}
+
 __global__ __launch_bounds__(kThreads) void k_pr_apply(double* __restrict__ sums, Update u) {
   const int32_t v = blockIdx.x * kThreads + threadIdx.x;
   const double D = *u.dtotal_in;
@@ -878,7 +938,11 @@ int32_t pull_tile_arcs() { return kTileArcs; }
 int32_t wave_tile_arcs() { return kWaveTile; }
 
 hipError_t pagerank_setup() {
-  // the LDS-resident pull holds a slice of up to kLdsMaxWidth floats plus its position table
+  // the LDS-resident pull holds a slice of up to kLdsMaxWidth floats plus its
+  // position table; the LDS push a block's kPushLdsMaxWidth FP64 sums
+  GC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_push_lds),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 static_cast<int>(sizeof(double)) * kPushLdsMaxWidth));
   GC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_tocab_pull_lds<false>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds_budget(kLdsMaxWidth)));
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_tocab_pull_lds<true>),
@@ -1149,6 +1213,13 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
       ProfScope prof("pr_plain_pull", s);
       k_pr_plain_pull<<<g->n_tiles_in, kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, g->tile_row_in,
                                                          g->contrib[cur], u);
+      cur ^= 1;
+    } else if (t && t->W <= kPushLdsMaxWidth) {
+      u.contrib = g->contrib[cur ^ 1];
+      parts = t->B;
+      ProfScope prof("pr_tocab_push", s);
+      k_pr_push_lds<<<t->B, kPushLdsThreads, sizeof(double) * static_cast<size_t>(t->W), s>>>(
+          t->blk_rowoff, t->row_ptr, t->id_map, t->col, t->log2W, g->contrib[cur], u);
       cur ^= 1;
     } else {
       if (t) {
