@@ -119,11 +119,17 @@ __device__ __forceinline__ bool scan_front(const int32_t* __restrict__ col, cons
   const bool heavy = active && (e - b) > kHeavy;
   bool found = false;
   if (active && !heavy) {
-    for (int32_t i = b; i < e; ++i)
-      if (bit_test(front, col[i])) {
+    int32_t i = b;
+    for (; i + 4 <= e; i += 4) {  // four arcs' loads in flight at a time
+      int32_t u[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) u[k] = col[i + k];
+      if (bit_test(front, u[0]) | bit_test(front, u[1]) | bit_test(front, u[2]) | bit_test(front, u[3])) {
         found = true;
         break;
       }
+    }
+    for (; !found && i < e; ++i) found = bit_test(front, col[i]);
   }
   uint64_t pending = __ballot(heavy);
   while (pending) {
@@ -286,7 +292,25 @@ __device__ __forceinline__ int64_t scan_min(const int32_t* __restrict__ col, con
   int64_t best = kInf;
   bool over = false;
   if (active && !heavy) {
-    for (int32_t i = b; i < e; ++i) {
+    int32_t i = b;
+    for (; i + 4 <= e; i += 4) {  // four arcs' loads in flight at a time
+      int32_t u[4], wk[4];
+      bool on[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        u[k] = col[i + k];
+        wk[k] = w[i + k];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) on[k] = bit_test(front, u[k]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int64_t cand = on[k] ? static_cast<int64_t>(dist[u[k]]) + wk[k] : static_cast<int64_t>(kInf);
+        over |= on[k] && cand >= kInf;
+        best = min(best, cand);
+      }
+    }
+    for (; i < e; ++i) {
       const int32_t u = col[i];
       if (bit_test(front, u)) {
         const int64_t cand = static_cast<int64_t>(dist[u]) + w[i];
