@@ -517,7 +517,6 @@ int bfs_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32_t* le
   if (policy > GC_POLICY_LEARNED) return fail(GC_EINVAL, "bfs_pull: unknown policy %u", policy);
   if (policy == GC_POLICY_LEARNED && !g->sched) return fail(GC_EINVAL, "bfs_pull: no scheduler attached");
   const hipError_t e = gcx::bfs_run(g, t, source, depth, levels, policy, stream);
-  if (e == hipErrorNotSupported) return fail(GC_EUNSUPPORTED, "bfs_pull: not available in this library");
   return e == hipSuccess ? GC_OK : hip_fail(e, "bfs_pull");
 }
 
@@ -534,7 +533,6 @@ int sssp_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* dist, int32_t* ro
   if (policy == GC_POLICY_LEARNED && !g->sched) return fail(GC_EINVAL, "sssp_pull: no scheduler attached");
   bool overflow = false;
   const hipError_t e = gcx::sssp_run(g, t, source, dist, rounds, policy, stream, &overflow);
-  if (e == hipErrorNotSupported) return fail(GC_EUNSUPPORTED, "sssp_pull: not available in this library");
   if (e != hipSuccess) return hip_fail(e, "sssp_pull");
   if (overflow) return fail(GC_EOVERFLOW, "sssp_pull: a distance reached INT32_MAX");
   return GC_OK;
