@@ -305,3 +305,27 @@ def test_learned_pagerank_form():
     for p in parts:
         p.free()
     h.free()
+
+
+def test_learned_pagerank_edges():
+    """A network without finite outputs and no attached partition falls back
+    to plain pull (action 1); sched_collect refuses an unknown kind; PageRank
+    rows of a graph hold one time per action."""
+    import paper_1904_02241_amd as gc
+    g = gg.rmat(12, 16, seed=4)
+    h = load(g)
+    tt = torch()
+    rin = tt.full((g.n,), 1.0 / g.n, dtype=tt.float32, device="cuda")
+    rout = tt.empty_like(rin)
+    nan_net = gc.sched_create(2, np.full(gc.sched_param_count(2), np.nan, np.float32))
+    gc.sched_attach(h, nan_net, [])
+    assert gc.pagerank_learned(h, 0.85, gc.GC_DANGLING_UNIFORM, rin, rout, 20) == 1
+    assert _pagerank_l1(g, host(rout)) <= 1e-6
+    gc.sched_attach(h, None)
+    f, t = gc.sched_collect_pagerank(h, [], rows=2)
+    assert f.shape == (2, 6) and t.shape == (2, 2) and (t > 0).all()
+    np.testing.assert_allclose(f[0], gc.sched_features(g.n, g.m, g.n, g.m, 0, 0.0), rtol=1e-6)
+    with pytest.raises(gc.GraphCageError):
+        gc.sched_collect(h, [], 3, [0])
+    nan_net.free()
+    h.free()
