@@ -222,9 +222,9 @@ def test_trained_network_gains_over_heuristic():
         p.free()
     h.free()
     # the network learns from timings taken on this GPU, so its choices (and
-    # the gain) vary from box to box (on this small graph, measured 0.71-0.94
-    # of the heuristic's speed for BFS and 0.78-1.0 for SSSP, while it wins
-    # on R-MAT 25 in the benchmark); the bar only catches a policy that is
+    # the gain) vary from box to box (on this small graph, runs measured
+    # between 0.78 and 0.94 of the heuristic's speed, while it wins on R-MAT
+    # 25 in the benchmark); the bar only catches a policy that is
     # clearly worse than the heuristic or no better than always pulling
     for kind, (vs_heur, vs_pull) in gains.items():
         assert vs_heur >= 0.6, (kind, vs_heur)
