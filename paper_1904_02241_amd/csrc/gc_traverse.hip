@@ -124,7 +124,10 @@ __device__ __forceinline__ bool scan_front(const int32_t* __restrict__ col, cons
       int32_t u[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) u[k] = col[i + k];
-      if (bit_test(front, u[0]) | bit_test(front, u[1]) | bit_test(front, u[2]) | bit_test(front, u[3])) {
+      uint32_t any = 0;  // all four tests, no short circuit
+#pragma unroll
+      for (int k = 0; k < 4; ++k) any |= (front[u[k] >> 5] >> (u[k] & 31)) & 1u;
+      if (any) {
         found = true;
         break;
       }
