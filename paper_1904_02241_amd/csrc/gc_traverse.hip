@@ -105,7 +105,15 @@ __global__ void k_queue_degree(const int32_t* __restrict__ queue, const int32_t*
     sum += static_cast<uint64_t>(rowptr[v + 1] - rowptr[v]);
   }
   for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, kWave);
-  if (gcd::lane_id() == 0 && sum) atomicAdd(reinterpret_cast<unsigned long long*>(stats + kDegLo), sum);
+  // one atomic per work-group (per-wave atomics on the one counter serialise)
+  __shared__ uint64_t part[kThreads / kWave];
+  if (gcd::lane_id() == 0) part[threadIdx.x / kWave] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t total = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) total += part[w];
+    if (total) atomicAdd(reinterpret_cast<unsigned long long*>(stats + kDegLo), total);
+  }
 }
 
 // ---------------------------------------------------------------------------
