@@ -169,9 +169,15 @@ int tocab_free(gc_tocab t);
  *                                          without out-arcs; LEAK: no D/n)
  * rank_in, rank_out: device float[n], must not overlap; after the call
  * rank_out holds iterate k + iters given iterate k in rank_in (iters = 0
- * copies). dir_if_plain selects pull or push when t == NULL. Sums are
- * accumulated in FP64 inside a row; ranks are stored as FP32. Queues work
- * only: no host synchronisation and no allocation. */
+ * copies). dir_if_plain selects pull or push when t == NULL. Precision:
+ * ranks and contributions are stored as FP32. Plain pull, plain push, the
+ * wide-block TOCAB pull (block width above 2^15) and TOCAB push accumulate
+ * every row sum in FP64. The LDS-resident TOCAB pull (a GC_PULL partition
+ * with block width at most 2^15, the stream layout) sums in FP32 within one
+ * 512-arc tile (a lane's 8 arcs, then a wave-wide segmented scan), in FP64
+ * for the part of a row carried from one tile to the next, and stores each
+ * (row, block) partial sum as FP32; its merge adds the partials in FP64.
+ * Queues work only: no host synchronisation and no allocation. */
 int pagerank_iter(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, int32_t dangling,
                   const float* rank_in, float* rank_out, int32_t iters, hipStream_t stream);
 
@@ -214,8 +220,12 @@ int pagerank_ladder(gc_graph g, gc_tocab t, int32_t method, float damping, int32
  * graph loaded with GC_VALUES_F32, its integer weight converted to FP32 for
  * other weighted graphs, 1 for unweighted ones. t == NULL: plain pull; t, a
  * GC_PULL partition of g: column-blocked pull (Algorithm 4) into partial
- * sums per (row, block), then the Figure 5 merge. Products are FP32, sums
- * FP64, y FP32. x, y: device float[n], must not overlap. Queues work only.
+ * sums per (row, block), then the Figure 5 merge. Products are FP32 and y
+ * is FP32. Sums are FP64 inside a row for plain pull and for blocks wider
+ * than 2^15; for the stream layout (block width at most 2^15) they are FP32
+ * within one 512-arc tile and FP64 across tiles, the (row, block) partials
+ * are FP32, and the merge adds them in FP64. x, y: device float[n], must
+ * not overlap. Queues work only.
  * Errors: GC_EINVAL for bad arguments (NULL or overlapping vectors, host
  * memory, a partition of another graph or a GC_PUSH partition). */
 int spmv(gc_graph g, gc_tocab t, const float* x, float* y, hipStream_t stream);

@@ -46,12 +46,6 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
-    mb = os.path.join(HERE, "microbench", "gather_ceiling")
-    cmd = [HIPCC] + FLAGS + ["-Wno-unused-value", mb + ".hip", "-o", mb + ".tmp"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True, capture_output=not verbose)
-    os.replace(mb + ".tmp", mb)
     return LIB
 
 

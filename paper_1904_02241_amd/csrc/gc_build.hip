@@ -515,7 +515,8 @@ __global__ void k_id16_stream(const int32_t* __restrict__ id_map, int64_t P, con
   }
 }
 
-inline int grid_for(int64_t items, int threads, int cap = 1 << 20) {
+// cap: only for kernels that stride over their items; others get one thread per item.
+inline int grid_for(int64_t items, int threads, int cap = INT_MAX) {
   const int64_t g = (items + threads - 1) / threads;
   return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, cap)));
 }

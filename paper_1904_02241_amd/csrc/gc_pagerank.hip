@@ -1,7 +1,9 @@
 // PageRank iterations on gfx950: plain pull (Algorithm 1), plain push
 // (Algorithm 2), TOCAB pull (Algorithm 4 + the Figure 5 merge) and TOCAB push
-// (Algorithm 5), all with the same FP64 in-row accumulation and the same
-// fused update, so the comparison between them isolates the blocking.
+// (Algorithm 5), all with the same fused update and FP64 in-row
+// accumulation (except inside one 512-arc tile of the LDS-resident TOCAB
+// pull, which sums in FP32), so the comparison between them isolates the
+// blocking.
 //
 // Per iteration t (uniform dangling mode):
 //   c[u]  = r[u] / outdeg(u) (0 when outdeg(u) = 0)      [contributions]
@@ -100,9 +102,11 @@ __global__ __launch_bounds__(kThreads) void k_pr_tocab_pull(const int32_t* __res
 // tiles of the chunk. In a tile every lane holds 8 consecutive arcs (one
 // 16-byte load of columns), reads their contributions from the LDS slice
 // and takes the row boundaries from its head word; a segmented inclusive
-// scan across the wave (FP64) then gives the sum of every row whose head
-// lies in the tile. A row that runs past the tile end is finished by the
-// whole wave over the following tiles. Each row sum is stored at the row's
+// scan across the wave (FP32) then gives the sum of every row whose head
+// lies in the tile. A row that runs past the tile end is carried to the
+// wave's next tile as an FP64 sum, or finished by the whole wave over the
+// following tiles (FP64) when it runs past the wave's range. Row partials
+// are stored as FP32. Each row sum is stored at the row's
 // range-major index, so the merge reads every range as one stream. Loads
 // run two tiles ahead of the tile being reduced (all vector loads, which
 // complete in order, so waiting for one tile leaves the next in flight).

@@ -193,16 +193,21 @@ __global__ __launch_bounds__(kThreads) void k_bfs_tocab(const int32_t* __restric
                                                         const uint32_t* __restrict__ visited,
                                                         const uint32_t* __restrict__ front,
                                                         uint8_t* __restrict__ flag) {
-  const int64_t l = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-  bool active = false;
-  int32_t b = 0, e = 0;
-  if (l < P && !bit_test(visited, id_map[l])) {
-    active = true;
-    b = row_ptr[l];
-    e = row_ptr[l + 1];
+  // the stride is uniform over the work-group, so every wave of it runs the
+  // same passes and the wave-wide scans inside stay convergent
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kThreads; base < P;
+       base += static_cast<int64_t>(gridDim.x) * kThreads) {
+    const int64_t l = base + threadIdx.x;
+    bool active = false;
+    int32_t b = 0, e = 0;
+    if (l < P && !bit_test(visited, id_map[l])) {
+      active = true;
+      b = row_ptr[l];
+      e = row_ptr[l + 1];
+    }
+    const bool found = scan_front(col, front, active, b, e);
+    if (l < P) flag[l] = found ? 1 : 0;
   }
-  const bool found = scan_front(col, front, active, b, e);
-  if (l < P) flag[l] = found ? 1 : 0;
 }
 
 // Merge of the per-block flags over vertex range j (OR), fused with the
@@ -383,16 +388,19 @@ __global__ __launch_bounds__(kThreads) void k_sssp_tocab(const int32_t* __restri
                                                          const uint32_t* __restrict__ front,
                                                          const int32_t* __restrict__ dist, int32_t* __restrict__ pmin,
                                                          int32_t* __restrict__ stats) {
-  const int64_t l = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-  int32_t b = 0, e = 0;
-  if (l < P) {
-    b = row_ptr[l];
-    e = row_ptr[l + 1];
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kThreads; base < P;
+       base += static_cast<int64_t>(gridDim.x) * kThreads) {  // uniform per work-group
+    const int64_t l = base + threadIdx.x;
+    int32_t b = 0, e = 0;
+    if (l < P) {
+      b = row_ptr[l];
+      e = row_ptr[l + 1];
+    }
+    bool ovf;
+    const int64_t best = scan_min(col, w, front, dist, l < P, b, e, &ovf);
+    if (ovf) stats[kOverflow] = 1;
+    if (l < P) pmin[l] = static_cast<int32_t>(best);
   }
-  bool ovf;
-  const int64_t best = scan_min(col, w, front, dist, l < P, b, e, &ovf);
-  if (ovf) stats[kOverflow] = 1;
-  if (l < P) pmin[l] = static_cast<int32_t>(best);
 }
 
 template <int K, bool kFlat>
@@ -573,16 +581,19 @@ __global__ __launch_bounds__(kThreads) void k_bc_tocab(const int32_t* __restrict
                                                        const uint32_t* __restrict__ visited,
                                                        const uint32_t* __restrict__ front,
                                                        const double* __restrict__ sigma, double* __restrict__ part) {
-  const int64_t l = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-  bool active = false;
-  int32_t b = 0, e = 0;
-  if (l < P && !bit_test(visited, id_map[l])) {
-    active = true;
-    b = row_ptr[l];
-    e = row_ptr[l + 1];
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kThreads; base < P;
+       base += static_cast<int64_t>(gridDim.x) * kThreads) {  // uniform per work-group
+    const int64_t l = base + threadIdx.x;
+    bool active = false;
+    int32_t b = 0, e = 0;
+    if (l < P && !bit_test(visited, id_map[l])) {
+      active = true;
+      b = row_ptr[l];
+      e = row_ptr[l + 1];
+    }
+    const double sum = scan_sigma(col, front, sigma, active, b, e);
+    if (l < P) part[l] = sum;
   }
-  const double sum = scan_sigma(col, front, sigma, active, b, e);
-  if (l < P) part[l] = sum;
 }
 
 // Merge of the per-block path counts over vertex range j (FP64 LDS sums),
@@ -973,8 +984,18 @@ struct BcMerge {
   }
 };
 
+// Work-groups for one item per thread. Item counts here are vertex, queue
+// or arc counts below 2^31, so the grid never needs a cap.
 inline int grid_for(int64_t items, int threads) {
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((items + threads - 1) / threads, 1 << 20)));
+  return static_cast<int>(std::max<int64_t>(1, (items + threads - 1) / threads));
+}
+
+// Work-groups of the grid-stride TOCAB row kernels: at most kRowGrid, so
+// partitions with more than kRowGrid * kThreads local rows take several
+// passes (RMAT-24 partitions do).
+constexpr int64_t kRowGrid = 1 << 16;
+inline int row_grid(int64_t rows) {
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>((rows + kThreads - 1) / kThreads, kRowGrid)));
 }
 
 enum class Mode { kPull, kTocab, kPush };
@@ -1110,7 +1131,7 @@ hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t 
       uint8_t* flag = reinterpret_cast<uint8_t*>(t->pmin);
       {
         ProfScope prof("bfs_tocab", s);
-        k_bfs_tocab<<<grid_for(t->P, kThreads), kThreads, 0, s>>>(t->row_ptr, t->col, t->id_map, t->P, g->visited,
+        k_bfs_tocab<<<row_grid(t->P), kThreads, 0, s>>>(t->row_ptr, t->col, t->id_map, t->P, g->visited,
                                                                    f.front(), flag);
       }
       ProfScope prof("bfs_merge", s);
@@ -1135,7 +1156,7 @@ hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t 
     } else {
       {
         ProfScope prof("sssp_tocab", s);
-        k_sssp_tocab<<<grid_for(t->P, kThreads), kThreads, 0, s>>>(t->row_ptr, t->col, t->w, t->P, f.front(), value,
+        k_sssp_tocab<<<row_grid(t->P), kThreads, 0, s>>>(t->row_ptr, t->col, t->w, t->P, f.front(), value,
                                                                     t->pmin, g->stats);
       }
       ProfScope prof("sssp_merge", s);
@@ -1206,7 +1227,7 @@ hipError_t run_bc_level(gc_graph g, Frontier& f, int32_t level, Mode mode, gc_to
   } else {
     {
       ProfScope prof("bc_tocab", s);
-      k_bc_tocab<<<grid_for(t->P, kThreads), kThreads, 0, s>>>(t->row_ptr, t->col, t->id_map, t->P, g->visited,
+      k_bc_tocab<<<row_grid(t->P), kThreads, 0, s>>>(t->row_ptr, t->col, t->id_map, t->P, g->visited,
                                                                 f.front(), g->bc_sigma, t->bc_part);
     }
     ProfScope prof("bc_merge", s);

@@ -3,7 +3,8 @@ benchmark times.
 
 * R-MAT 24 (N = 2^24, about 263M arcs): 20 PageRank iterations of every
   form, L1 <= 1e-6 against the FP64 oracle run once for the whole module;
-  BFS depths from two sources and SSSP distances from one, bit-exact.
+  BFS depths from the benchmark's 8 sources and SSSP distances from 2 of
+  them, every policy, bit-exact.
 * The rewired 4096 x 4096 grid and the uniform graph with 2^25 vertices and
   2^28 arcs: BFS and SSSP from one source each, bit-exact, every policy.
 
@@ -55,27 +56,36 @@ def test_rmat24_pagerank_20_iterations(rmat24, rmat24_pagerank, form, W, k):
     assert abs(got.astype(np.float64).sum() - 1.0) < 1e-5
 
 
-@pytest.mark.timeout(600)
+@pytest.mark.timeout(900)
 def test_rmat24_traversals_bit_exact(rmat24):
+    """BFS from the 8 sources the benchmark times (seed 2) under every
+    policy it reports, and SSSP from 2 of them under every policy."""
+    import concurrent.futures
+    import os
     import paper_1904_02241_amd as gc
     g = rmat24
-    h = load(g, weights=True)
-    part = gc.tocab_partition(h, gc.GC_PULL, TRAV_W, TRAV_K)
-    d = torch().empty(g.n, dtype=torch().int32, device="cuda")
-    srcs = gg.sources(g, 2, seed=2)
-    for s in srcs:
-        want = oracle.bfs(g.n, g.rowptr, g.colidx, int(s))
-        for name, t, pol in (("plain_pull", None, gc.GC_POLICY_PULL), ("tocab_pull", part, gc.GC_POLICY_PULL),
-                             ("push", None, gc.GC_POLICY_PUSH), ("heuristic_tocab", part, gc.GC_POLICY_HEURISTIC)):
-            print(f"bfs rmat24 source {s} {name}", flush=True)
-            gc.bfs_pull(h, t, int(s), d, pol)
-            np.testing.assert_array_equal(host(d), want)
-    s = int(srcs[0])
-    want = oracle.dijkstra(g.n, g.rowptr, g.colidx, g.weights, s)
-    for name, t, pol in (("tocab_pull", part, gc.GC_POLICY_PULL), ("heuristic_tocab", part, gc.GC_POLICY_HEURISTIC)):
-        print(f"sssp rmat24 source {s} {name}", flush=True)
-        gc.sssp_pull(h, t, s, d, pol)
-        np.testing.assert_array_equal(host(d), want)
+    srcs = [int(x) for x in gg.sources(g, 8, seed=2)]
+    with concurrent.futures.ThreadPoolExecutor(max_workers=max(1, min(10, os.cpu_count() or 1))) as ex:
+        bfs_want = [ex.submit(oracle.bfs, g.n, g.rowptr, g.colidx, s) for s in srcs]
+        sssp_want = [ex.submit(oracle.dijkstra, g.n, g.rowptr, g.colidx, g.weights, s) for s in srcs[:2]]
+        h = load(g, weights=True)
+        part = gc.tocab_partition(h, gc.GC_PULL, TRAV_W, TRAV_K)
+        d = torch().empty(g.n, dtype=torch().int32, device="cuda")
+        policies = (("plain_pull", None, gc.GC_POLICY_PULL), ("tocab_pull", part, gc.GC_POLICY_PULL),
+                    ("push", None, gc.GC_POLICY_PUSH), ("heuristic_tocab", part, gc.GC_POLICY_HEURISTIC),
+                    ("heuristic_plain", None, gc.GC_POLICY_HEURISTIC))
+        for s, fw in zip(srcs, bfs_want):
+            want = fw.result()
+            for name, t, pol in policies:
+                print(f"bfs rmat24 source {s} {name}", flush=True)
+                gc.bfs_pull(h, t, s, d, pol)
+                np.testing.assert_array_equal(host(d), want)
+        for s, fw in zip(srcs[:2], sssp_want):
+            want = fw.result()
+            for name, t, pol in policies:
+                print(f"sssp rmat24 source {s} {name}", flush=True)
+                gc.sssp_pull(h, t, s, d, pol)
+                np.testing.assert_array_equal(host(d), want)
     part.free()
     h.free()
 
