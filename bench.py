@@ -61,11 +61,13 @@ def kernel_bytes(name, n, m, info):
 
 
 def run_form(gc, torch, g, part, plain_dir, n, m, steps, warmup):
+    """Times `steps` iterations as one call with per-kernel profiling off,
+    then repeats them with HIP-event timing of every kernel (on the
+    launching stream) for the per-kernel averages."""
     rin = torch.full((n,), 1.0 / n, dtype=torch.float32, device="cuda")
     rout = torch.empty_like(rin)
     gc.pagerank_iter(g, part, plain_dir, 0.85, gc.GC_DANGLING_UNIFORM, rin, rout, warmup)
     torch.cuda.synchronize()
-    gc.gc_profile(1)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -74,11 +76,15 @@ def run_form(gc, torch, g, part, plain_dir, n, m, steps, warmup):
     stop.record()
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3
-    gc.gc_profile(0)
-    prof = gc.gc_profile_read()
     ev_ms = start.elapsed_time(stop)
     ranks = rout.double()
     checks = {"sum": float(ranks.sum().item()), "min": float(ranks.min().item())}
+    # second pass: per-kernel HIP events
+    gc.gc_profile(1)
+    gc.pagerank_iter(g, part, plain_dir, 0.85, gc.GC_DANGLING_UNIFORM, rin, rout, steps)
+    torch.cuda.synchronize()
+    gc.gc_profile(0)
+    prof = gc.gc_profile_read()
     return {"ms_per_step": wall_ms / steps, "event_ms_per_step": ev_ms / steps,
             "gteps": m / (wall_ms / steps * 1e-3) / 1e9, "kernels": prof, "checks": checks}
 
@@ -91,8 +97,10 @@ def run_traversal(gc, torch, g, gh, part, sources, kind, policies):
     buf = torch.empty(gh.n, dtype=torch.int32, device="cuda")
     fn = gc.bfs_pull if kind == "bfs" else gc.sssp_pull
     out = {}
+    labels = {0: "push", 1: "pull", 2: "tocab"}
     for name, policy, use_part in policies:
         rates, times, levels = [], [], []
+        by_action = {}
         for src in sources:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -104,9 +112,15 @@ def run_traversal(gc, torch, g, gh, part, sources, kind, policies):
             rates.append(arcs / dt / 1e9)
             times.append(dt * 1e3)
             levels.append(lv)
+            acts, ms = gc.traversal_trace(g)
+            for a, t in zip(acts.tolist(), ms.tolist()):
+                e = by_action.setdefault(labels.get(a, f"action{a}"), [0, 0.0])
+                e[0] += 1
+                e[1] += t
         hm = len(rates) / sum(1.0 / r for r in rates)
         out[name] = {"gteps_hmean": round(hm, 3), "ms_mean": round(float(np.mean(times)), 3),
-                     "levels": levels}
+                     "levels": levels,
+                     "levels_by_action": {k: {"levels": v[0], "ms": round(v[1], 3)} for k, v in by_action.items()}}
         log(f"{kind} {name}: {hm:.2f} GTEPS (harmonic mean), {np.mean(times):.2f} ms mean, levels {levels}")
     return out
 
@@ -136,7 +150,42 @@ def traffic_from_profiles(kernel):
     return (float(b.group(1)) if b else None), (float(h.group(1)) if h else None)
 
 
+def mall_from_profiles():
+    """DRAM share of the L2's read requests per kernel from a committed
+    rocprofv3 counter summary (TCC_EA0_RDREQ_DRAM_sum / TCC_EA0_RDREQ_sum:
+    requests the memory fabric sent on to DRAM; the rest were served by the
+    Infinity Cache, MALL), or a note that it is unmeasured."""
+    path = os.path.join(ROOT, "profiles", "mall_requests.md")
+    if not os.path.exists(path):
+        return {"status": "unmeasured"}
+    text = open(path).read()
+    rows = re.findall(r"^mall:\s*(\S+)\s+([0-9.]+)\s+([0-9.]+)", text, re.M)
+    if not rows:
+        return {"status": "unmeasured"}
+    return {"status": "measured (profiles/mall_requests.md)",
+            "kernels": {k: {"dram_share_of_l2_reads": float(d), "mall_hit_rate": float(h)} for k, d, h in rows}}
+
+
+def host_cpu():
+    """(logical CPUs this process may use, CPU model name)."""
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return ncpu, model
+
+
 def cpu_baseline(g, budget_s):
+    """The FP64 oracle as it stands (single thread) on a bounded number of
+    PageRank iterations of the full graph."""
     import oracle
     r0 = np.full(g.n, 1.0 / g.n)
     t0 = time.perf_counter()
@@ -146,14 +195,50 @@ def cpu_baseline(g, budget_s):
     t0 = time.perf_counter()
     oracle.pagerank(g.n, g.rowptr, g.colidx, 0.85, iters, r0=r0)
     dt = time.perf_counter() - t0
+    ncpu, model = host_cpu()
     return {"value": g.m * iters / dt / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": f"FP64 single-thread oracle PageRank, {iters} of 20 iterations on the full graph "
-                      f"({dt:.1f} s)"}
+                      f"({dt:.1f} s)", "host_cpus": ncpu, "cpu_model": model}
 
 
-def suite_traversal(args, gc, gg, torch):
+def cpu_openmp_baseline(gh, sources, pr_iters=5):
+    """Multithreaded FP32 pull PageRank and direction-optimising BFS on all
+    host cores (cpubase: no code shared with the GPU path or the oracle);
+    median of 3 timed runs each, compute only (its in-arc CSR is built
+    first, untimed)."""
+    import cpubase
+    ncpu, model = host_cpu()
+    t0 = time.perf_counter()
+    cg = cpubase.Graph(gh.n, gh.rowptr, gh.colidx)
+    prep = time.perf_counter() - t0
+    pr = sorted(cg.pagerank(pr_iters)[1] for _ in range(3))[1]
+    outdeg = np.diff(gh.rowptr).astype(np.int64)
+    bfs = []
+    for s in sources:
+        runs = [cg.bfs(int(s)) for _ in range(3)]
+        dep, sec = sorted(runs, key=lambda x: x[1])[1]
+        reached = dep != np.iinfo(np.int32).max
+        bfs.append((int(outdeg[reached].sum()), sec))
+    hm = len(bfs) / sum(sec / arcs * 1e9 for arcs, sec in bfs)
+    return {"pagerank": {"value": round(gh.m * pr_iters / pr / 1e9, 3), "unit": "GTEPS",
+                         "ms_per_iter": round(pr / pr_iters * 1e3, 2), "iters_timed": pr_iters,
+                         "kind": "openmp_fp32_pull"},
+            "bfs": {"value": round(hm, 3), "unit": "GTEPS (harmonic mean)", "sources": len(bfs),
+                    "ms": [round(sec * 1e3, 2) for _, sec in bfs], "kind": "openmp_direction_optimising"},
+            "threads": cpubase.threads(), "host_cpus": ncpu, "cpu_model": model,
+            "transpose_s": round(prep, 2), "timing": "median of 3, compute only"}
+
+
+def traversal_policies(gc):
+    return [("plain_pull", gc.GC_POLICY_PULL, False), ("tocab_pull", gc.GC_POLICY_PULL, True),
+            ("push", gc.GC_POLICY_PUSH, False), ("heuristic_tocab", gc.GC_POLICY_HEURISTIC, True),
+            ("heuristic_plain", gc.GC_POLICY_HEURISTIC, False)]
+
+
+def traversal_c3(args, gc, gg, torch):
     """Blocked pull BFS and SSSP on the rewired 4096x4096 grid and the uniform
-    graph of 2^25 vertices (average degree 8), weights in [1, 255]."""
+    graph of 2^25 vertices (average degree 8), weights in [1, 255], every
+    policy, from 8 sources each (seed 5)."""
     graphs = [("grid4096", lambda: gg.grid(4096, 4096, 0.05, seed=3)),
               ("uniform2^25", lambda: gg.uniform(1 << 25, 1 << 27, seed=4))]
     out = {}
@@ -163,14 +248,20 @@ def suite_traversal(args, gc, gg, torch):
         g = gc.graph_load_csr(gh.rowptr, gh.colidx, gh.weights)
         part = gc.tocab_partition(g, gc.GC_PULL, args.traversal_block_width, args.traversal_merge_range)
         srcs = gg.sources(gh, args.bfs_sources or 8, seed=5)
-        pols = [("plain_pull", gc.GC_POLICY_PULL, False), ("tocab_pull", gc.GC_POLICY_PULL, True),
-                ("push", gc.GC_POLICY_PUSH, False), ("heuristic_tocab", gc.GC_POLICY_HEURISTIC, True)]
+        pols = traversal_policies(gc)
         out[name] = {"n": gh.n, "m": gh.m, "partition": part.info,
                      "bfs": run_traversal(gc, torch, g, gh, part, srcs, "bfs", pols),
                      "sssp": run_traversal(gc, torch, g, gh, part, srcs, "sssp", pols)}
         part.free()
         g.free()
         del gh
+    return out
+
+
+def suite_traversal(args, gc, gg, torch):
+    """Blocked pull BFS and SSSP on the rewired 4096x4096 grid and the uniform
+    graph of 2^25 vertices (average degree 8), weights in [1, 255]."""
+    out = traversal_c3(args, gc, gg, torch)
     best = max(v["gteps_hmean"] for v in out["uniform2^25"]["bfs"].values())
     return {"metric": METRIC, "value": round(best, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.bfs_sources or 8,
             "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -192,7 +283,7 @@ def suite_ladder(args, gc, gg, torch):
     rout = torch.empty_like(rin)
     steps = max(1, args.steps)
     parts = {W: gc.tocab_partition(g, gc.GC_PULL, W, K) for W, K in
-             ((1 << 18, args.traversal_merge_range), (args.block_width, args.merge_range))}
+             ((1 << 18, args.wide_merge_range), (args.block_width, args.merge_range))}
 
     def timed(fn):
         fn(1)
@@ -245,7 +336,7 @@ def suite_spmv(args, gc, gg, torch):
     y = torch.empty_like(x)
     steps = max(1, args.steps)
     parts = {W: gc.tocab_partition(g, gc.GC_PULL, W, K) for W, K in
-             ((1 << 18, args.traversal_merge_range), (args.block_width, args.merge_range))}
+             ((1 << 18, args.wide_merge_range), (args.block_width, args.merge_range))}
     out = {}
     for name, part in (("plain_pull", None), ("tocab_pull_W2^18", parts[1 << 18]),
                        (f"tocab_pull_W2^{args.block_width.bit_length() - 1}", parts[args.block_width])):
@@ -284,7 +375,7 @@ def suite_bc(args, gc, gg, torch):
     n, m = gh.n, gh.m
     outdeg = np.diff(gh.rowptr).astype(np.int64)
     g = gc.graph_load_csr(gh.rowptr, gh.colidx)
-    part = gc.tocab_partition(g, gc.GC_PULL, args.traversal_block_width, args.traversal_merge_range)
+    part = gc.tocab_partition(g, gc.GC_PULL, 1 << 18, args.wide_merge_range)
     srcs = [int(x) for x in gg.sources(gh, args.bfs_sources or 8, seed=5)]
     depth = torch.empty(n, dtype=torch.int32, device="cuda")
     reached_arcs = []
@@ -321,7 +412,7 @@ def suite_bc(args, gc, gg, torch):
             "warmup": 1, "ms_per_step": out[best]["ms_mean"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"bc_rmat{args.scale}", "n": n, "m": m, "sources": len(srcs),
-                       "block_width": args.traversal_block_width, "merge_range": args.traversal_merge_range,
+                       "block_width": 1 << 18, "merge_range": args.wide_merge_range,
                        "best": best},
             "bc": out}
 
@@ -392,10 +483,11 @@ def suite_batched(args, gc, gg, torch):
 
 
 def suite_learned(args, gc, gg, torch):
-    """Level scheduler: trained on the GPU from per-level timings on R-MAT 16,
-    20, 22 and 24 (BFS, SSSP, and PageRank iterations), evaluated on R-MAT 25
+    """Level scheduler: trained on the GPU from per-level timings on R-MAT 16
+    and R-MAT 24 (BFS, SSSP, and PageRank iterations), evaluated on R-MAT 25
     and the rewired grid against the working-set heuristic and fixed
-    policies."""
+    policies. Every policy's depths / distances from the first source are
+    compared with each other (exactness itself is the tests' job)."""
     widths = [1 << s for s in range(15, 23)]
     K = 2 + len(widths)
     n_src = args.bfs_sources or 8
@@ -403,11 +495,12 @@ def suite_learned(args, gc, gg, torch):
 
     def load(gh):
         g = gc.graph_load_csr(gh.rowptr, gh.colidx, gh.weights)
-        return g, [gc.tocab_partition(g, gc.GC_PULL, w, args.traversal_merge_range) for w in widths]
+        return g, [gc.tocab_partition(g, gc.GC_PULL, w, args.merge_range if w <= (1 << 15) else args.wide_merge_range)
+                   for w in widths]
 
     feats, times = [], []
     t0 = time.perf_counter()
-    train_scales = (16, 20, 22, 24)
+    train_scales = (16, 24)
     for scale in train_scales:
         log(f"collecting levels on RMAT-{scale}")
         gh = gg.rmat(scale, 16, seed=1).with_weights(11)
@@ -462,9 +555,16 @@ def suite_learned(args, gc, gg, torch):
         for kind, fn in (("bfs", gc.bfs_pull), ("sssp", gc.sssp_pull)):
             res[kind] = {}
             fn(g, None, int(srcs[0]), buf, gc.GC_POLICY_HEURISTIC)  # warm-up
+            first = None
             for pname, (pol, part) in pols.items():
                 total = 0.0
                 acts = []
+                fn(g, part, int(srcs[0]), buf, pol)
+                got = buf.cpu().numpy()
+                if first is None:
+                    first = got
+                elif not np.array_equal(got, first):
+                    raise RuntimeError(f"{name} {kind}: {pname} disagrees with the other policies")
                 for src in srcs:
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
@@ -541,9 +641,12 @@ def main():
     ap.add_argument("--edge-factor", type=int, default=16)
     ap.add_argument("--block-width", type=int, default=1 << 15, help="PageRank TOCAB block width")
     ap.add_argument("--merge-range", type=int, default=16384, help="PageRank TOCAB merge range")
-    ap.add_argument("--traversal-block-width", type=int, default=1 << 18,
-                    help="TOCAB block width of BFS / SSSP partitions (last-level-cache sized)")
-    ap.add_argument("--traversal-merge-range", type=int, default=4096)
+    ap.add_argument("--traversal-block-width", type=int, default=1 << 15,
+                    help="TOCAB block width of BFS / SSSP partitions (2^15: the stream layout, whose SSSP rounds "
+                         "keep a block's distances in LDS)")
+    ap.add_argument("--traversal-merge-range", type=int, default=16384)
+    ap.add_argument("--wide-merge-range", type=int, default=4096,
+                    help="merge range of partitions wider than 2^15 (push, sweep, ladder, SpMV, BC)")
     ap.add_argument("--push-block-width", type=int, default=1 << 13,
                     help="TOCAB push block width (up to 2^14: the block's FP64 sums in LDS)")
     ap.add_argument("--forms", default="tocab_pull,plain_pull,tocab_push,plain_push",
@@ -552,7 +655,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--converge-tol", type=float, default=1e-6,
                     help="L1 tolerance of the convergence-driven TOCAB pull run (0 = skip)")
-    ap.add_argument("--bfs-sources", type=int, default=8, help="BFS sources on the same graph (0 = skip)")
+    ap.add_argument("--bfs-sources", type=int, default=8,
+                    help="BFS / SSSP sources on the same graph and on each C3 graph (0 = skip)")
+    ap.add_argument("--no-sweep", dest="sweep", action="store_false",
+                    help="skip the TOCAB pull block-width sweep 2^15 .. 2^22")
+    ap.add_argument("--no-c3", dest="c3", action="store_false",
+                    help="skip BFS / SSSP on the rewired grid and the uniform 2^25 graph")
     ap.add_argument("--suite", default="pagerank", choices=["pagerank", "traversal", "batched", "learned", "ladder", "spmv", "bc"],
                     help="pagerank: RMAT-24 PageRank forms + BFS (default); traversal: grid / uniform BFS+SSSP; "
                          "batched: 32 graphs + 64 PPR seeds in one launch; learned: level scheduler; "
@@ -585,11 +693,11 @@ def main():
         del a, b
     log(f"generating RMAT scale {args.scale}")
     t0 = time.perf_counter()
-    gh = gg.rmat(args.scale, args.edge_factor, seed=1)
+    gh = gg.rmat(args.scale, args.edge_factor, seed=1).with_weights(11)  # weights for SSSP
     n, m = gh.n, gh.m
     log(f"n={n} m={m} ({time.perf_counter() - t0:.1f} s, {gg.threads()} threads)")
     t0 = time.perf_counter()
-    g = gc.graph_load_csr(gh.rowptr, gh.colidx)
+    g = gc.graph_load_csr(gh.rowptr, gh.colidx, gh.weights)
     log(f"graph_load_csr {time.perf_counter() - t0:.2f} s")
     parts = {}
     forms = args.forms.split(",")
@@ -601,7 +709,7 @@ def main():
             if d not in parts:
                 t0 = time.perf_counter()
                 W, K = ((args.block_width, args.merge_range) if d == gc.GC_PULL
-                        else (args.push_block_width, args.traversal_merge_range))
+                        else (args.push_block_width, args.wide_merge_range))
                 parts[d] = gc.tocab_partition(g, d, W, K)
                 log(f"tocab_partition {form} {parts[d].info} {time.perf_counter() - t0:.2f} s")
             part = parts[d]
@@ -630,15 +738,38 @@ def main():
                     "ms": round(ms, 3), "ms_per_iter": round(ms / k, 4), "gteps": round(m * k / (ms * 1e-3) / 1e9, 2)}
         log(f"converge {converge}")
 
+    sweep = None
+    if args.sweep and "tocab_pull" in results:
+        # Section 4.3's block-size sweep: TOCAB pull PageRank per block width
+        # (stream layout up to 2^15, LLC-sized blocks above), B and P per width
+        sweep = {}
+        rin = torch.full((n,), 1.0 / n, dtype=torch.float32, device="cuda")
+        rout = torch.empty_like(rin)
+        for lw in range(15, 23):
+            W = 1 << lw
+            k = args.merge_range if W <= (1 << 15) else args.wide_merge_range
+            p = parts[gc.GC_PULL] if W == args.block_width else gc.tocab_partition(g, gc.GC_PULL, W, k)
+            gc.pagerank_iter(g, p, gc.GC_PULL, 0.85, gc.GC_DANGLING_UNIFORM, rin, rout, 2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gc.pagerank_iter(g, p, gc.GC_PULL, 0.85, gc.GC_DANGLING_UNIFORM, rin, rout, args.steps)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            sweep[f"2^{lw}"] = {"ms_per_iter": round(ms, 4), "gteps": round(m / (ms * 1e-3) / 1e9, 2),
+                                "B": p.info["B"], "P": p.info["P"], "k": p.info["k"],
+                                "stream_layout": p.info["stream"]}
+            log(f"sweep W=2^{lw}: {ms:.3f} ms/iter, B={p.info['B']} P={p.info['P']}")
+            if p is not parts[gc.GC_PULL]:
+                p.free()
+
     traversal = None
     if args.bfs_sources > 0:
         parts["traversal"] = gc.tocab_partition(g, gc.GC_PULL, args.traversal_block_width,
                                                 args.traversal_merge_range)
         srcs = gg.sources(gh, args.bfs_sources, seed=2)
-        pols = [("plain_pull", gc.GC_POLICY_PULL, False), ("tocab_pull", gc.GC_POLICY_PULL, True),
-                ("push", gc.GC_POLICY_PUSH, False), ("heuristic_tocab", gc.GC_POLICY_HEURISTIC, True),
-                ("heuristic_plain", gc.GC_POLICY_HEURISTIC, False)]
+        pols = traversal_policies(gc)
         traversal = {"bfs": run_traversal(gc, torch, g, gh, parts["traversal"], srcs, "bfs", pols),
+                     "sssp": run_traversal(gc, torch, g, gh, parts["traversal"], srcs, "sssp", pols),
                      "block_width": args.traversal_block_width,
                      "sources": [int(x) for x in srcs]}
 
@@ -659,11 +790,20 @@ def main():
         roofline["traffic_frac"] = round(roofline["traffic_gbs"] / HBM_PEAK_GBS, 4)
         roofline["l2_hit_rate"] = l2_hit
     step_bytes = sum(kernel_bytes(k, n, m, info) * v[1] for k, v in hres["kernels"].items()) / args.steps
-    cpu = None
+    for p in parts.values():
+        p.free()
+    g.free()
+    c3 = None
+    if args.c3:
+        c3 = traversal_c3(args, gc, gg, torch)
+    cpu = cpu_omp = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         cpu = cpu_baseline(gh, args.cpu_seconds)
         log(f"cpu baseline {cpu}")
+        log("timing the multithreaded CPU baseline")
+        cpu_omp = cpu_openmp_baseline(gh, gg.sources(gh, 2, seed=2))
+        log(f"openmp baseline {cpu_omp}")
     forms_out = {}
     for f, r in results.items():
         forms_out[f] = {"gteps": round(r["gteps"], 2), "ms_per_iter": round(r["ms_per_step"], 4),
@@ -684,14 +824,15 @@ def main():
         "roofline": roofline,
         "step_algorithmic_GBs": round(step_bytes / (hres["ms_per_step"] * 1e-3) / 1e9, 1),
         "cpu_baseline": cpu,
+        "cpu_baseline_openmp": cpu_omp,
         "forms": forms_out,
         "converge": converge,
+        "block_width_sweep": sweep,
         "traversal": traversal,
+        "traversal_c3": c3,
+        "mall": mall_from_profiles(),
     }
     print(json.dumps(out), flush=True)
-    for p in parts.values():
-        p.free()
-    g.free()
 
 
 if __name__ == "__main__":

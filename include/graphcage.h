@@ -72,7 +72,7 @@ typedef enum {
 #define GC_POLICY_PUSH 1      /* every level: data-driven push with a queue    */
 #define GC_POLICY_HEURISTIC 2 /* per level: working-set rule of Section 3.3    */
 #define GC_POLICY_LEARNED 3   /* per level: attached scheduler network (below), */
-                              /* heuristic when it gives no finite answer       */
+                              /* gated by and falling back to the heuristic     */
 
 typedef struct gc_graph_s* gc_graph;
 typedef struct gc_tocab_s* gc_tocab;
@@ -289,11 +289,20 @@ int traversal_trace(gc_graph g, int32_t* actions, float* ms, int32_t max, int32_
  * produces. Network: GC_SCHED_INPUTS -> GC_SCHED_HIDDEN -> GC_SCHED_HIDDEN ->
  * K, ReLU after the hidden layers, FP32; output k scores action k (lower is
  * faster: a predicted log time, or log time over the level's fastest action,
- * as the training targets define) and the arg-min is run. Parameters, row-major:
+ * as the training targets define). The arg-min replaces the working-set
+ * heuristic's choice for the level only when its output is lower than the
+ * heuristic's action's output by more than 0.1 (about 10 % predicted gain
+ * with relative log-time targets); the heuristic alone decides when an
+ * output is not finite. For every traversal level after the first, the
+ * network runs on the device right after the previous level, on counters
+ * that never leave the device, and its answer returns with the level's
+ * counters (no synchronisation of its own). Parameters, row-major:
  *   W1[64][6], b1[64], W2[64][64], b2[64], W3[K][64], b3[K].
  * Features of a level (sched_features): log1p(frontier size), log1p(frontier
  * out-arcs), log1p(m / n), log2(ceil(n / 2^18) + 1), level / 16,
- * log1p(previous level's time in microseconds). */
+ * log1p(previous level's time per out-arc of its frontier, in ns; 0 at the
+ * first level). Level times are the device's own clock from a level's start
+ * to the end of its relaxation kernels. */
 #define GC_SCHED_INPUTS 6
 #define GC_SCHED_HIDDEN 64
 
@@ -314,18 +323,23 @@ int sched_loss_grad(gc_sched m, const float* x, const float* t, const float* mas
 int sched_train(gc_sched m, const float* x, const float* t, const float* mask, int32_t batch, int32_t steps, float lr,
                 float* loss_hist, hipStream_t stream);
 int sched_free(gc_sched m);
-/* The 6 features of a level (host arithmetic, also used internally). */
+/* The 6 features of a level (the library computes the same on the device
+ * for its per-level decisions). prior_ms = time of the previous level,
+ * prior_arcs = out-arcs of that level's frontier (both 0 at the first level). */
 int sched_features(int32_t n, int64_t m, int32_t frontier, int64_t frontier_arcs, int32_t level, float prior_ms,
-                   float* features);
+                   int64_t prior_arcs, float* features);
 /* Training rows for a network with K = 2 + n_parts actions: traverses from
  * each source (kind 0 = BFS, 1 = SSSP) and at every level runs every action
  * from the same saved state, timing each with HIP events, then continues with
  * the fastest. kind 2 = PageRank: every vertex is active at every iteration,
  * so a row is one all-active level: each action (0 plain push, 1 plain
  * pull, 2 + i TOCAB pull over parts[i]) runs 4 iterations from the same
- * ranks and times_ms holds its time per iteration; n_sources rows are
- * collected (sources is unused and may be NULL), each from the previous
- * row's fastest result. Writes host features[rows][6] and times_ms[rows][K]
+ * ranks and times_ms holds its time per iteration; the row's features are
+ * those pagerank_learned uses (level 1, prior time = the working-set form's
+ * time per iteration); n_sources rows are collected (sources is unused and
+ * may be NULL), each from the previous row's fastest result. BFS / SSSP
+ * rows give the prior-level input from the device clock stamps, as the
+ * learned traversal does. Writes host features[rows][6] and times_ms[rows][K]
  * (up to max_rows) and *rows. parts must be GC_PULL partitions of g. */
 int sched_collect(gc_graph g, const gc_tocab* parts, int32_t n_parts, int32_t kind, const int32_t* sources,
                   int32_t n_sources, float* features, float* times_ms, int32_t max_rows, int32_t* rows,
@@ -334,16 +348,20 @@ int sched_collect(gc_graph g, const gc_tocab* parts, int32_t n_parts, int32_t ki
  * GC_POLICY_LEARNED and pagerank_learned; m = NULL detaches. The handles
  * must outlive the use. */
 int sched_attach(gc_graph g, gc_sched m, const gc_tocab* parts, int32_t n_parts);
-/* PageRank (as pagerank_iter, `iters` iterations) in the form the attached
- * network picks for an all-active level of g (frontier n vertices and m
- * arcs, level 0, no prior time): 0 plain push, 1 plain pull, 2 + j TOCAB
- * pull over the j-th attached partition. One decision per call (every
- * iteration of PageRank is alike); synchronises `stream` once to read it.
- * Without a finite network output the working-set rule decides: an
- * all-active level's working set exceeds the cache, so TOCAB pull over the
- * attached partition whose width is nearest 2^18, or plain pull when none
- * is attached. *action (host, nullable) receives the form run. Errors as
- * pagerank_iter, plus GC_EINVAL when no network is attached. */
+/* PageRank (as pagerank_iter, `iters` iterations) in the form chosen for
+ * g: 0 plain push, 1 plain pull, 2 + j TOCAB pull over the j-th attached
+ * partition. The working-set rule's form for an all-active level is TOCAB
+ * pull over the attached partition whose width is nearest 2^18 (plain pull
+ * when none is attached). Every iteration is alike, so the choice is made
+ * once per attached network, by the first call: it runs that form for 3
+ * iterations from rank_in (1 warm-up, 2 timed with HIP events; their result
+ * is discarded), feeds the network an all-active level (frontier n vertices
+ * and m arcs, level 1, prior time = the timed iteration) and keeps the
+ * rule's form unless the network's pick is predicted faster by more than
+ * the gate above (or the rule's form when an output is not finite). That
+ * first call synchronises `stream` twice; later calls only queue work.
+ * *action (host, nullable) receives the form run. Errors as pagerank_iter,
+ * plus GC_EINVAL when no network is attached. */
 int pagerank_learned(gc_graph g, float damping, int32_t dangling, const float* rank_in, float* rank_out,
                      int32_t iters, int32_t* action, hipStream_t stream);
 

@@ -61,7 +61,7 @@ SIGNATURES = {
     "sched_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp]),
     "sched_train": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _f32, _vp, _vp]),
     "sched_free": (ctypes.c_int, [_vp]),
-    "sched_features": (ctypes.c_int, [_i32, _i64, _i32, _i64, _i32, _f32, _vp]),
+    "sched_features": (ctypes.c_int, [_i32, _i64, _i32, _i64, _i32, _f32, _i64, _vp]),
     "sched_collect": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _p_i32, _vp]),
     "sched_attach": (ctypes.c_int, [_vp, _vp, _vp, _i32]),
     "pagerank_learned": (ctypes.c_int, [_vp, _f32, _i32, _vp, _vp, _i32, _p_i32, _vp]),
@@ -428,9 +428,10 @@ def sched_free(m):
     m.free()
 
 
-def sched_features(n, m, frontier, frontier_arcs, level, prior_ms):
+def sched_features(n, m, frontier, frontier_arcs, level, prior_ms, prior_arcs=0):
     out = np.empty(GC_SCHED_INPUTS, np.float32)
-    _check(lib.sched_features(n, m, frontier, frontier_arcs, level, prior_ms, out.ctypes.data), "sched_features")
+    _check(lib.sched_features(n, m, frontier, frontier_arcs, level, prior_ms, prior_arcs, out.ctypes.data),
+           "sched_features")
     return out
 
 

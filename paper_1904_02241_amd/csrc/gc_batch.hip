@@ -23,7 +23,10 @@ namespace {
 
 constexpr int kBatchK = 1024;   // merge range of batched partitions
 constexpr int kPprLanes = 64;   // one lane per seed vector
-constexpr int kPprRows = 32;    // rows per PPR work item (8 per wave)
+constexpr int kPprRows = 32;    // rows per PPR start item (8 per wave)
+constexpr int32_t kPprChunk = 2048;  // in-arcs per PPR chunk (one wave each, kWaves chunks per item)
+constexpr int kWaves = kThreads / kWave;
+constexpr int kPprBatch = 16;   // 256-byte row gathers a wave keeps in flight
 constexpr unsigned long long kSpinLimit = 1ull << 21;
 
 struct BGraph {
@@ -41,14 +44,30 @@ struct BGraph {
   int64_t rank_off;
 };
 
+// Personalised PageRank of up to 64 seeds, lane q of a wave = seed q. An
+// iteration gathers, per in-arc u -> v, the 256-byte row c[u][0..64) of the
+// current contributions. The in-arcs are cut into chunks of kPprChunk arcs
+// (one wave each) rather than handed out by rows, so every wave keeps
+// kPprBatch gathers in flight and a hub row's arcs spread over many waves:
+// a row whose arcs lie in one chunk is finished by that chunk's wave; a row
+// whose arcs span chunks leaves one FP64 piece per chunk (the sum of its
+// arcs there: piece_tail of the chunk it starts in, piece_head of the
+// others), and the next phase adds the pieces and finishes it.
 struct BPpr {
-  int32_t n, S, items;
+  int32_t n, S;
+  int64_t m;
+  int32_t init_items;        // start items: kPprRows rows each
+  int32_t n_chunks, items;   // iteration items: kWaves chunks each
+  int32_t n_split, fix_items;  // rows spanning chunks; finishing items: kWaves rows each
   const int32_t* t_rowptr;
   const int32_t* t_col;
   const int32_t* rowptr;
   const int32_t* seeds;      // [S]
+  const int32_t* split;      // [n_split] rows spanning chunks
   float* c[2];               // [n][64]
-  double* dpart;             // [items][64]
+  double* piece_head;        // [n_chunks][64]
+  double* piece_tail;        // [n_chunks][64]
+  double* dpart;             // [max(init_items, items + fix_items)][64]
   double* dtotal;            // [2][64]
 };
 
@@ -130,50 +149,130 @@ __device__ __forceinline__ double sum_slots(const double* p, int32_t count, int3
   return wg_sum(acc);
 }
 
-// One PPR row group: each wave takes rows, lane q = seed q. Returns nothing;
-// writes c_next, the output on the last iteration and the item's dangling
-// partials (one per seed).
-__device__ void ppr_rows(const BPpr& p, int32_t item, int32_t it, double d, float* out) {
-  __shared__ double dp[kThreads / kWave][kPprLanes];
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+// Finishes row v of an iteration from its in-arc sum s (lane = seed):
+// writes its next contribution and, on the last iteration, its rank; returns
+// its dangling mass (its rank when it has no out-arc).
+__device__ __forceinline__ double ppr_finish(const BPpr& p, int32_t v, double s, int32_t it, double d, double D,
+                                             int32_t seed, float* out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const double pv = (v == seed) ? 1.0 : 0.0;
+  const double r = (1.0 - d) * pv + d * (s + D * pv);
+  const float r32 = static_cast<float>(r);
+  const int32_t deg = p.rowptr[v + 1] - p.rowptr[v];
+  p.c[(it + 1) & 1][static_cast<int64_t>(v) * kPprLanes + lane] =
+      deg ? static_cast<float>(static_cast<double>(r32) / deg) : 0.0f;
+  if (out && lane < p.S) out[static_cast<int64_t>(v) * p.S + lane] = r32;
+  return deg ? 0.0 : static_cast<double>(r32);
+}
+
+// One wave walks in-arc chunk c: arcs [c L, min(m, (c + 1) L)). It finishes
+// every row whose arcs all lie in the chunk (and the empty rows that start
+// in it; the last chunk also takes those starting at m), and leaves pieces
+// for rows that cross its ends. Returns the wave's dangling mass.
+__device__ double ppr_chunk(const BPpr& p, int32_t c, int32_t it, double d, double D, int32_t seed, float* out) {
+  const int lane = threadIdx.x & (kWave - 1);
   const float* cur = p.c[it & 1];
-  float* nxt = p.c[(it + 1) & 1];
-  const double D = p.dtotal[(it & 1) * kPprLanes + lane];
-  const int32_t seed = lane < p.S ? p.seeds[lane] : -1;
-  double mine = 0.0;
-  const int32_t r0 = item * kPprRows;
-  for (int32_t v = r0 + wid; v < min(p.n, r0 + kPprRows); v += kThreads / kWave) {
-    const int32_t b = p.t_rowptr[v], e = p.t_rowptr[v + 1];
-    double s = 0.0;
-    for (int32_t a = b; a < e; a += 8) {
-      int32_t u[8];
-      float x[8];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) u[k] = p.t_col[min(a + k, e - 1)];
-#pragma unroll
-      for (int k = 0; k < 8; ++k) x[k] = cur[static_cast<int64_t>(u[k]) * kPprLanes + lane];
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (a + k < e) s += static_cast<double>(x[k]);
+  const int64_t A0 = static_cast<int64_t>(c) * kPprChunk;
+  const int64_t A1 = min(p.m, A0 + kPprChunk);
+  const bool last_chunk = c == p.n_chunks - 1;
+  // rows starting in the chunk: [lo_row, hi_row); the row holding arc A0,
+  // if it started before A0, is the chunk's head row
+  const int32_t lo_row = gcd::lower_bound(p.t_rowptr, 0, p.n, static_cast<int32_t>(A0));
+  const int32_t hi_row = last_chunk ? p.n : gcd::lower_bound(p.t_rowptr, lo_row, p.n, static_cast<int32_t>(A1));
+  const bool head_split = A0 < A1 && lo_row > 0 && p.t_rowptr[lo_row] > A0;
+  int32_t v = head_split ? lo_row - 1 : lo_row;  // current row
+  // ends of rows base .. base + 63, one per lane
+  int32_t base = v;
+  int32_t ends = p.t_rowptr[min(base + 1 + lane, p.n)];
+  auto row_end = [&](int32_t r) {
+    if (r - base >= kWave) {
+      base = r;
+      ends = p.t_rowptr[min(base + 1 + lane, p.n)];
     }
-    const double pv = (v == seed) ? 1.0 : 0.0;
-    const double r = (1.0 - d) * pv + d * (s + D * pv);
-    const float r32 = static_cast<float>(r);
-    const int32_t deg = p.rowptr[v + 1] - p.rowptr[v];
-    nxt[static_cast<int64_t>(v) * kPprLanes + lane] =
-        deg ? static_cast<float>(static_cast<double>(r32) / deg) : 0.0f;
-    if (!deg) mine += r32;
-    if (out && lane < p.S) out[static_cast<int64_t>(v) * p.S + lane] = r32;
+    return __builtin_amdgcn_readlane(ends, r - base);
+  };
+  double s = 0.0, dang = 0.0;
+  int32_t vend = v < hi_row || head_split ? row_end(v) : 0;
+  // rows that end at or before arc a (empty ones included) are finished
+  auto flush_to = [&](int64_t a) {
+    while (v < hi_row && vend <= a) {
+      if (head_split && v == lo_row - 1) {
+        p.piece_head[static_cast<int64_t>(c) * kPprLanes + lane] = s;
+      } else {
+        dang += ppr_finish(p, v, s, it, d, D, seed, out);
+      }
+      s = 0.0;
+      ++v;
+      if (v < hi_row) vend = row_end(v);
+    }
+  };
+  for (int64_t a = A0; a < A1; a += kPprBatch) {
+    const int32_t nb = static_cast<int32_t>(min<int64_t>(kPprBatch, A1 - a));
+    const int32_t u = p.t_col[a + min(lane, nb - 1)];
+    float x[kPprBatch];
+#pragma unroll
+    for (int k = 0; k < kPprBatch; ++k)
+      x[k] = cur[static_cast<int64_t>(__builtin_amdgcn_readlane(u, min(k, nb - 1))) * kPprLanes + lane];
+#pragma unroll
+    for (int k = 0; k < kPprBatch; ++k) {
+      if (k < nb) {
+        flush_to(a + k);
+        s += static_cast<double>(x[k]);
+      }
+    }
   }
+  flush_to(A1);
+  // what is left open crosses the chunk's end: the head row (when the whole
+  // chunk lies inside it) or the last row that started here
+  if (A0 < A1 && v < p.n && (v < hi_row || (head_split && v == lo_row - 1)) && vend > A1) {
+    if (head_split && v == lo_row - 1) p.piece_head[static_cast<int64_t>(c) * kPprLanes + lane] = s;
+    else p.piece_tail[static_cast<int64_t>(c) * kPprLanes + lane] = s;
+  }
+  return dang;
+}
+
+// Writes the work-group's dangling partial of item `slot` (one per seed).
+__device__ __forceinline__ void ppr_dangling(const BPpr& p, int32_t slot, double mine) {
+  __shared__ double dp[kWaves][kPprLanes];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   dp[wid][lane] = mine;
   __syncthreads();
   if (wid == 0) {
     double t = 0.0;
 #pragma unroll
-    for (int w = 0; w < kThreads / kWave; ++w) t += dp[w][lane];
-    p.dpart[static_cast<int64_t>(item) * kPprLanes + lane] = t;
+    for (int w = 0; w < kWaves; ++w) t += dp[w][lane];
+    p.dpart[static_cast<int64_t>(slot) * kPprLanes + lane] = t;
   }
   __syncthreads();
+}
+
+// Iteration item: chunks kWaves * item + wave.
+__device__ void ppr_chunks(const BPpr& p, int32_t item, int32_t it, double d, float* out) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const double D = p.dtotal[(it & 1) * kPprLanes + lane];
+  const int32_t seed = lane < p.S ? p.seeds[lane] : -1;
+  const int32_t c = item * kWaves + wid;
+  double mine = 0.0;
+  if (c < p.n_chunks) mine = ppr_chunk(p, c, it, d, D, seed, out);
+  ppr_dangling(p, item, mine);
+}
+
+// Finishing item (the phase after the chunks): rows that span chunks,
+// kWaves * item + wave, from their pieces.
+__device__ void ppr_split_rows(const BPpr& p, int32_t item, int32_t it, double d, float* out) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const double D = p.dtotal[(it & 1) * kPprLanes + lane];
+  const int32_t seed = lane < p.S ? p.seeds[lane] : -1;
+  const int32_t i = item * kWaves + wid;
+  double mine = 0.0;
+  if (i < p.n_split) {
+    const int32_t v = p.split[i];
+    const int32_t c0 = p.t_rowptr[v] / kPprChunk, c1 = (p.t_rowptr[v + 1] - 1) / kPprChunk;
+    double s = p.piece_tail[static_cast<int64_t>(c0) * kPprLanes + lane];
+    for (int32_t c = c0 + 1; c <= c1; ++c) s += p.piece_head[static_cast<int64_t>(c) * kPprLanes + lane];
+    mine = ppr_finish(p, v, s, it, d, D, seed, out);
+  }
+  ppr_dangling(p, p.items + item, mine);
 }
 
 // PPR start: r0 = p (one-hot per seed), c0 = r0 / outdeg, dangling partials.
@@ -210,11 +309,13 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs a) {
   __shared__ double acc[kBatchK];
   const int32_t G = a.G;
   const int32_t tiles = G ? a.tile_pre[G] : 0, ranges = G ? a.range_pre[G] : 0, verts = G ? a.vert_pre[G] : 0;
+  const int32_t init_items = a.has_ppr ? a.ppr.init_items : 0;
   const int32_t pitems = a.has_ppr ? a.ppr.items : 0;
+  const int32_t fitems = a.has_ppr ? a.ppr.fix_items : 0;
   const int32_t red_items = G + (a.has_ppr ? kPprLanes : 0);
 
   // ---- start: contributions of the start vectors and their dangling mass
-  for (int32_t item = blockIdx.x; item < verts + pitems; item += gridDim.x) {
+  for (int32_t item = blockIdx.x; item < verts + init_items; item += gridDim.x) {
     if (item < verts) {
       const int32_t gi = which(a.vert_pre, G, item);
       const BGraph& g = a.graphs[gi];
@@ -240,7 +341,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs a) {
       if (threadIdx.x == 0) g.dtotal[0] = t;
     } else {
       const int32_t q = item - G;
-      const double t = sum_slots(a.ppr.dpart + q, a.ppr.items, kPprLanes);
+      const double t = sum_slots(a.ppr.dpart + q, init_items, kPprLanes);
       if (threadIdx.x == 0) a.ppr.dtotal[q] = t;
     }
   }
@@ -260,12 +361,17 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs a) {
                     [&](int32_t r, double s) { g.partial[r] = static_cast<float>(s); });
         __syncthreads();  // vals is reused by the next item
       } else {
-        ppr_rows(a.ppr, item - tiles, it, a.damping, last ? a.ppr_out : nullptr);
+        ppr_chunks(a.ppr, item - tiles, it, a.damping, last ? a.ppr_out : nullptr);
       }
     }
     if (!grid_sync(a)) return;
-    // ---- merge ranges fused with the update (Figure 5)
-    for (int32_t item = blockIdx.x; item < ranges; item += gridDim.x) {
+    // ---- merge ranges fused with the update (Figure 5), and the PPR rows
+    // whose arcs span chunks
+    for (int32_t item = blockIdx.x; item < ranges + fitems; item += gridDim.x) {
+      if (item >= ranges) {
+        ppr_split_rows(a.ppr, item - ranges, it, a.damping, last ? a.ppr_out : nullptr);
+        continue;
+      }
       const int32_t gi = which(a.range_pre, G, item);
       const BGraph& g = a.graphs[gi];
       const int32_t j = item - a.range_pre[gi];
@@ -290,7 +396,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchArgs a) {
         if (threadIdx.x == 0) g.dtotal[(it + 1) & 1] = t;
       } else {
         const int32_t q = item - G;
-        const double t = sum_slots(a.ppr.dpart + q, a.ppr.items, kPprLanes);
+        const double t = sum_slots(a.ppr.dpart + q, pitems + fitems, kPprLanes);
         if (threadIdx.x == 0) a.ppr.dtotal[((it + 1) & 1) * kPprLanes + q] = t;
       }
     }
@@ -425,25 +531,46 @@ int batch_create(const gc_graph* graphs, int32_t n_graphs, const int32_t* block_
     b->n_seeds = n_seeds;
     BPpr& p = a.ppr;
     p.n = pg->n;
+    p.m = pg->m;
     p.S = n_seeds;
-    p.items = (pg->n + kPprRows - 1) / kPprRows;
+    p.init_items = (pg->n + kPprRows - 1) / kPprRows;
+    p.n_chunks = static_cast<int32_t>(std::max<int64_t>(1, (pg->m + kPprChunk - 1) / kPprChunk));
+    p.items = (p.n_chunks + kWaves - 1) / kWaves;
     p.t_rowptr = pg->t_rowptr;
     p.t_col = pg->t_colidx;
     p.rowptr = pg->rowptr;
+    // rows whose in-arcs span chunks (finished from their pieces)
+    std::vector<int32_t> trp(static_cast<size_t>(pg->n) + 1), split;
+    if (hipMemcpy(trp.data(), pg->t_rowptr, sizeof(int32_t) * trp.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+      destroy(b);
+      return bfail(GC_EHIP, "batch_create: copy failed");
+    }
+    for (int32_t v = 0; v < pg->n; ++v)
+      if (trp[v + 1] > trp[v] && trp[v] / kPprChunk != (trp[v + 1] - 1) / kPprChunk) split.push_back(v);
+    p.n_split = static_cast<int32_t>(split.size());
+    p.fix_items = (p.n_split + kWaves - 1) / kWaves;
+    const size_t lanes = kPprLanes;
     int32_t* ds = static_cast<int32_t*>(own(b, sizeof(int32_t) * n_seeds));
-    p.c[0] = static_cast<float*>(own(b, sizeof(float) * kPprLanes * static_cast<size_t>(pg->n)));
-    p.c[1] = static_cast<float*>(own(b, sizeof(float) * kPprLanes * static_cast<size_t>(pg->n)));
-    p.dpart = static_cast<double*>(own(b, sizeof(double) * kPprLanes * static_cast<size_t>(p.items)));
-    p.dtotal = static_cast<double*>(own(b, sizeof(double) * 2 * kPprLanes));
-    if (!ds || !p.c[0] || !p.c[1] || !p.dpart || !p.dtotal) {
+    int32_t* sp = static_cast<int32_t*>(own(b, sizeof(int32_t) * std::max<size_t>(split.size(), 1)));
+    p.c[0] = static_cast<float*>(own(b, sizeof(float) * lanes * static_cast<size_t>(pg->n)));
+    p.c[1] = static_cast<float*>(own(b, sizeof(float) * lanes * static_cast<size_t>(pg->n)));
+    p.piece_head = static_cast<double*>(own(b, sizeof(double) * lanes * static_cast<size_t>(p.n_chunks)));
+    p.piece_tail = static_cast<double*>(own(b, sizeof(double) * lanes * static_cast<size_t>(p.n_chunks)));
+    const size_t slots = static_cast<size_t>(std::max(p.init_items, p.items + p.fix_items));
+    p.dpart = static_cast<double*>(own(b, sizeof(double) * lanes * slots));
+    p.dtotal = static_cast<double*>(own(b, sizeof(double) * 2 * lanes));
+    if (!ds || !sp || !p.c[0] || !p.c[1] || !p.piece_head || !p.piece_tail || !p.dpart || !p.dtotal) {
       destroy(b);
       return bfail(GC_ENOMEM, "batch_create: allocation failed");
     }
-    if (hipMemcpy(ds, seeds, sizeof(int32_t) * n_seeds, hipMemcpyDefault) != hipSuccess) {
+    if (hipMemcpy(ds, seeds, sizeof(int32_t) * n_seeds, hipMemcpyDefault) != hipSuccess ||
+        (!split.empty() && hipMemcpy(sp, split.data(), sizeof(int32_t) * split.size(), hipMemcpyHostToDevice) !=
+                               hipSuccess)) {
       destroy(b);
       return bfail(GC_EHIP, "batch_create: copy failed");
     }
     p.seeds = ds;
+    p.split = sp;
   }
   BGraph* dg = static_cast<BGraph*>(own(b, sizeof(BGraph) * std::max(1, n_graphs)));
   int32_t* pre = static_cast<int32_t*>(own(b, sizeof(int32_t) * 3 * (n_graphs + 1)));

@@ -677,15 +677,51 @@ hipError_t build_lds_stream(gc_tocab t, hipStream_t s) {
       }
     }
   }
+  // Dispatch order, XCD aware: the GPU hands consecutive work-groups to its
+  // kXcds XCDs in turn (work-group i to XCD i mod kXcds), and each XCD has
+  // its own L2. All chunks of a block go to one XCD, next to each other in
+  // its sequence, so the block's slice of c comes from memory once and
+  // from that L2 for the block's other chunks. Blocks are dealt largest
+  // first, each to the XCD with the fewest arcs so far; within a block the
+  // largest chunk runs first; shorter lists are padded with empty chunks.
+  constexpr int kXcds = 8;
+  std::vector<int64_t> blk_arcs(static_cast<size_t>(B), 0);
+  for (const Chunk& c : ch) blk_arcs[c.blk] += c.arcs;
+  std::vector<int32_t> order(static_cast<size_t>(B));
+  for (int32_t b = 0; b < B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return blk_arcs[x] > blk_arcs[y]; });
   std::stable_sort(ch.begin(), ch.end(), [](const Chunk& x, const Chunk& y) { return x.arcs > y.arcs; });
-  std::vector<int32_t> beg, end, blk, j0v, nsv;
-  for (const Chunk& c : ch) {
-    beg.push_back(c.beg);
-    end.push_back(c.end);
-    blk.push_back(c.blk);
-    j0v.push_back(c.j0);
-    nsv.push_back(c.ns);
+  std::vector<std::vector<int32_t>> blk_chunks(static_cast<size_t>(B));  // chunk ids per block, largest first
+  for (int32_t i = 0; i < static_cast<int32_t>(ch.size()); ++i) blk_chunks[ch[i].blk].push_back(i);
+  std::vector<std::vector<int32_t>> xcd(kXcds);
+  std::vector<int64_t> load(kXcds, 0);
+  for (int32_t b : order) {
+    if (blk_chunks[b].empty()) continue;
+    const int x = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+    load[x] += blk_arcs[b];
+    for (int32_t i : blk_chunks[b]) xcd[x].push_back(i);
   }
+  size_t longest = 0;
+  for (const auto& l : xcd) longest = std::max(longest, l.size());
+  std::vector<int32_t> beg, end, blk, j0v, nsv;
+  for (size_t pos = 0; pos < longest; ++pos)
+    for (int x = 0; x < kXcds; ++x) {
+      if (pos < xcd[x].size()) {
+        const Chunk& c = ch[xcd[x][pos]];
+        beg.push_back(c.beg);
+        end.push_back(c.end);
+        blk.push_back(c.blk);
+        j0v.push_back(c.j0);
+        nsv.push_back(c.ns);
+      } else {  // padding: no rows (the kernel returns at once)
+        beg.push_back(0);
+        end.push_back(0);
+        blk.push_back(0);
+        j0v.push_back(0);
+        nsv.push_back(1);
+      }
+    }
+  if (ch.empty()) beg.clear(), end.clear(), blk.clear(), j0v.clear(), nsv.clear();
   const int32_t nch = static_cast<int32_t>(beg.size());
   t->n_chunks = nch;
   t->seg_max = seg_max;

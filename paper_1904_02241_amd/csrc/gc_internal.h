@@ -56,12 +56,14 @@ struct gc_graph_s {
   double* bc_coef = nullptr;  // [2n]
   int32_t* bc_depth = nullptr;
   int32_t* bc_order = nullptr;
-  int32_t* stats = nullptr;     // device counters read back once per level
+  int32_t* stats = nullptr;     // device counters read back once per level (kStatSlots)
   int32_t* stats_host = nullptr;  // pinned mirror
+  int32_t clock_khz = 100000;   // rate of the device wall clock stamped into stats
   int64_t bytes = 0;
   // learned level scheduler attached to this graph (sched_attach)
   gc_sched sched = nullptr;
   std::vector<gc_tocab> sched_parts;
+  int32_t pr_learned_action = -1;  // pagerank_learned's form for the attached network (-1: not chosen yet)
   // per-level record of the last traversal: action and wall time (ms)
   std::vector<int32_t> trace_action;
   std::vector<float> trace_ms;
@@ -117,6 +119,7 @@ struct gc_tocab_s {
   int32_t* pmin = nullptr;        // [P] traversal partials (next flags / min)
   double* bc_part = nullptr;      // [P] BC path-count partials (allocated on first use)
   float* val32 = nullptr;         // [m_pad] FP32 arc values in stream order (first valued SpMV)
+  int32_t* w_pad = nullptr;       // [m_pad] integer weights in stream order, 0 past m (first SSSP over the stream layout)
   int64_t bytes = 0;
 };
 
@@ -191,10 +194,24 @@ struct Converge {
   int32_t iters = 0;
   double delta = 0.0;
 };
+// Device buffers an iteration writes besides rank_out: contributions (two,
+// used in turn by the forms that read one while writing the next), FP64
+// push sums (n), FP64 dangling partials (one per update work-group, at most
+// the graph's dpart_slots) and their two totals, and the pull partition's
+// partial sums (P + 8). By default the graph's and the partition's own.
+struct PrBuffers {
+  float* contrib[2];
+  double* sums;
+  double* dpart;
+  double* dtotal;
+  float* partial;
+};
 hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int32_t dangling,
                         const float* rank_in, float* rank_out, int32_t iters, hipStream_t s,
-                        Converge* cv = nullptr, int32_t ladder = -1);
+                        Converge* cv = nullptr, int32_t ladder = -1, const PrBuffers* bufs = nullptr);
 
+// PageRank's working-set action among 0 push, 1 pull, 2 + i TOCAB over parts[i].
+int32_t pagerank_fallback_action(const gc_tocab* parts, int32_t n_parts);
 // Scheduler training rows for PageRank (see sched_collect, kind 2).
 hipError_t collect_pagerank(gc_graph g, gc_tocab* parts, int32_t n_parts, int32_t n_rows, float* features,
                             float* times, int32_t max_rows, int32_t* rows, hipStream_t s);
@@ -213,11 +230,52 @@ hipError_t bc_run(gc_graph g, gc_tocab t, const int32_t* sources, int32_t n_src,
                   hipStream_t s);
 hipError_t collect(gc_graph g, gc_tocab* parts, int32_t n_parts, bool bfs, const int32_t* sources, int32_t n_src,
                    float* features, float* times, int32_t max_rows, int32_t* rows, hipStream_t s);
-void sched_features(int64_t n, int64_t m, int64_t n_f, int64_t m_f, int32_t level, double prior_ms, float* f);
+void sched_features(int64_t n, int64_t m, int64_t n_f, int64_t m_f, int32_t level, double prior_ms,
+                    int64_t prior_arcs, float* f);
+
+// The scheduler's 6 inputs for a level (the same arithmetic on the host and
+// in the device-side decision): log1p(frontier vertices), log1p(frontier
+// out-arcs), log1p(m / n), log2(ceil(n / 2^18) + 1), level / 16, and
+// log1p(the previous level's time per out-arc of its frontier, in ns), 0
+// before the first level.
+__host__ __device__ inline void level_features(int64_t n, int64_t m, int64_t n_f, int64_t m_f, int32_t level,
+                                               double prior_ms, int64_t prior_arcs, float* f) {
+  f[0] = static_cast<float>(log1p(static_cast<double>(n_f)));
+  f[1] = static_cast<float>(log1p(static_cast<double>(m_f)));
+  f[2] = static_cast<float>(log1p(static_cast<double>(m) / static_cast<double>(n > 1 ? n : 1)));
+  f[3] = static_cast<float>(log2(static_cast<double>((n + (1 << 18) - 1) >> 18) + 1.0));
+  f[4] = static_cast<float>(level) / 16.0f;
+  f[5] = static_cast<float>(log1p(prior_ms * 1e6 / static_cast<double>(prior_arcs > 1 ? prior_arcs : 1)));
+}
+
+// Device counters of one traversal level (int32 slots), copied once per
+// level to a pinned host mirror.
+constexpr int kStatQLen = 0;      // vertices appended to the next queue
+constexpr int kStatOverflow = 1;  // SSSP: a path length reached INT32_MAX
+constexpr int kStatDegLo = 2;     // out-arcs of the next frontier (64-bit: lo, hi)
+constexpr int kStatT0 = 4;        // device wall clock at the level's start (64-bit)
+constexpr int kStatT1 = 6;        // device wall clock when its relaxation kernels have finished (64-bit)
+constexpr int kStatChoice = 8;    // learned scheduler: action for the next level (-1: no finite output)
+constexpr int kStatOut = 16;      // learned scheduler: its K outputs (FP32 bit patterns)
+constexpr int kStatSlots = kStatOut + GC_SCHED_HIDDEN;
+
+// Learned policy: the working-set rule's choice is kept unless the network
+// predicts its own pick faster by more than this margin (its outputs are
+// log times relative to the fastest action, so 0.1 is about 10 %).
+constexpr float kLearnedGate = 0.1f;
 
 // ---- scheduler network (gc_sched.hip) ----
 int32_t sched_actions(gc_sched m);
-hipError_t sched_decide(gc_sched m, const float* features, hipStream_t s, int32_t* action);
+// Decision from host features: action (-1 when an output is not finite)
+// and, when out is given, the K outputs. Synchronises s.
+hipError_t sched_decide(gc_sched m, const float* features, hipStream_t s, int32_t* action, float* out = nullptr);
+// Decision for the next traversal level from the device counters of the
+// level just run (its frontier size and out-arcs, its start and end
+// clocks): queued on s, results in stats[kStatChoice] and stats[kStatOut..].
+// prior_arcs = out-arcs of the level just run; clock_khz = the device
+// wall-clock rate.
+hipError_t sched_decide_level(gc_sched m, int64_t n, int64_t m_arcs, int32_t level, int64_t prior_arcs,
+                              int32_t clock_khz, int32_t* stats, hipStream_t s);
 
 // Records HIP events around the launches made in its scope while
 // profiling is on (gc_profile); a no-op otherwise.

@@ -15,6 +15,7 @@
 // adds the partials in a fixed order, so D is reproducible.
 
 #include <climits>
+#include <cstdlib>
 
 #include <type_traits>
 #include <vector>
@@ -503,6 +504,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_pr_tocab_pull_lds(
   const __amdgpu_buffer_rsrc_t out = partial_rsrc(partial, partial_bytes);
   const int32_t ch = blockIdx.x;
   const int32_t r0 = chunk_beg[ch], r1 = chunk_end[ch], b = chunk_blk[ch], j0 = chunk_j0[ch], ns = chunk_ns[ch];
+  if (r0 >= r1) return;  // padding of the dispatch order (uniform)
   float* slice = lds;
   float* stage = lds + W + wid * (kStageRows + kStageSpare);  // this wave's output staging and spare slots
   int32_t* sb = reinterpret_cast<int32_t*>(lds + W + kLdsWaves * (kStageRows + kStageSpare));  // ns + 1 boundaries, then sentinels
@@ -1069,18 +1071,36 @@ hipError_t ladder_run(gc_graph g, gc_tocab t, int32_t method, float damping, int
   return hipSuccess;
 }
 
+// PageRank's working-set choice among the scheduler's actions (0 plain
+// push, 1 plain pull, 2 + i TOCAB pull over parts[i]): every vertex is
+// active, so the rule blocks whenever a partition is attached, over the
+// width nearest the paper's 2^18; plain pull otherwise.
+int32_t pagerank_fallback_action(const gc_tocab* parts, int32_t n_parts) {
+  int32_t a = 1, best = INT32_MAX;
+  for (int32_t j = 0; j < n_parts; ++j) {
+    const int32_t d = std::abs(parts[j]->log2W - 18);
+    if (d < best) {
+      best = d;
+      a = 2 + j;
+    }
+  }
+  return a;
+}
+
 // Training rows of the level scheduler for PageRank, an all-active level
 // whose cost does not change from one iteration to the next: for each row,
 // every action runs kCollectIters iterations from the same ranks (0 plain
 // push, 1 plain pull, 2 + i TOCAB pull over parts[i]), timed with HIP
 // events (ms per iteration); the next row starts from the fastest action's
-// output. Features: frontier = all n vertices and m arcs, level = the row,
-// prior time = the previous row's best.
+// output. Features: frontier = all n vertices and m arcs, level 1, prior
+// time = the working-set rule's form's time per iteration (over m arcs),
+// which is what pagerank_learned measures before it decides.
 hipError_t collect_pagerank(gc_graph g, gc_tocab* parts, int32_t n_parts, int32_t n_rows, float* features,
                             float* times, int32_t max_rows, int32_t* rows, hipStream_t s) {
   constexpr int32_t kCollectIters = 4;
   const int32_t n = g->n;
   const int32_t K = 2 + n_parts;
+  const int32_t fa = pagerank_fallback_action(parts, n_parts);
   Buf ra(sizeof(float) * n, s), rb(sizeof(float) * n, s), rbest(sizeof(float) * n, s);
   if (!ra.p || !rb.p || !rbest.p) return hipErrorOutOfMemory;
   std::vector<float> init(static_cast<size_t>(n), 1.0f / static_cast<float>(n));
@@ -1091,9 +1111,7 @@ hipError_t collect_pagerank(gc_graph g, gc_tocab* parts, int32_t n_parts, int32_
   GC_HIP_TRY(hipEventCreate(&e1));
   hipError_t err = hipSuccess;
   int32_t r = 0;
-  double prior_ms = 0.0;
   for (; r < n_rows && r < max_rows && err == hipSuccess; ++r) {
-    sched_features(n, g->m, n, g->m, r, prior_ms, features + static_cast<size_t>(r) * GC_SCHED_INPUTS);
     float* row_t = times + static_cast<size_t>(r) * K;
     int32_t best = 0;
     for (int32_t a = 0; a < K && err == hipSuccess; ++a) {
@@ -1111,8 +1129,8 @@ hipError_t collect_pagerank(gc_graph g, gc_tocab* parts, int32_t n_parts, int32_
       if (err == hipSuccess && best == a)
         err = hipMemcpyAsync(rbest.p, rb.p, sizeof(float) * n, hipMemcpyDeviceToDevice, s);
     }
+    sched_features(n, g->m, n, g->m, 1, row_t[fa], g->m, features + static_cast<size_t>(r) * GC_SCHED_INPUTS);
     if (err == hipSuccess) err = hipMemcpyAsync(ra.p, rbest.p, sizeof(float) * n, hipMemcpyDeviceToDevice, s);
-    prior_ms = row_t[best];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1123,8 +1141,10 @@ hipError_t collect_pagerank(gc_graph g, gc_tocab* parts, int32_t n_parts, int32_
 
 hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int32_t dangling,
                         const float* rank_in, float* rank_out, int32_t iters, hipStream_t s, Converge* cv,
-                        int32_t ladder) {
+                        int32_t ladder, const PrBuffers* bufs) {
   const int32_t n = g->n;
+  const PrBuffers buf = bufs ? *bufs : PrBuffers{{g->contrib[0], g->contrib[1]}, g->sums, g->dpart, g->dtotal,
+                                                 t ? t->partial : nullptr};
   if (cv) iters = cv->max_iters;
   if (iters == 0)
     return hipMemcpyAsync(rank_out, rank_in, sizeof(float) * n, hipMemcpyDeviceToDevice, s);
@@ -1136,7 +1156,7 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
   u.d = damping;
   u.base = (1.0 - static_cast<double>(damping)) / n;
   u.inv_n = dangling == GC_DANGLING_UNIFORM ? 1.0 / n : 0.0;
-  u.dpart = g->dpart;
+  u.dpart = buf.dpart;
   u.rowptr = g->rowptr;
   u.n = n;
   u.rank_out = nullptr;
@@ -1144,12 +1164,12 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
 
   // contributions of rank_in and D of iteration 0 -> dtotal[0]
   u.dtotal_in = nullptr;
-  u.contrib = g->contrib[0];
+  u.contrib = buf.contrib[0];
   {
     ProfScope prof("pr_init", s);
-    k_pr_init<<<vgrid, kThreads, 0, s>>>(rank_in, u, push ? g->sums : nullptr);
+    k_pr_init<<<vgrid, kThreads, 0, s>>>(rank_in, u, push ? buf.sums : nullptr);
   }
-  k_reduce_dangling<<<1, 1024, 0, s>>>(g->dpart, vgrid, g->dtotal, nullptr, nullptr);
+  k_reduce_dangling<<<1, 1024, 0, s>>>(buf.dpart, vgrid, buf.dtotal, nullptr, nullptr);
   GC_HIP_TRY(hipGetLastError());
 
   // convergence mode: iterates alternate between rank_out and rank_tmp,
@@ -1158,8 +1178,8 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
   if (cv) u.lpart = g->lpart;
   int cur = 0;
   for (int32_t it = 0; it < iters; ++it) {
-    u.dtotal_in = g->dtotal + (it & 1);
-    double* dtotal_out = g->dtotal + ((it + 1) & 1);
+    u.dtotal_in = buf.dtotal + (it & 1);
+    double* dtotal_out = buf.dtotal + ((it + 1) & 1);
     u.rank_out = (it == iters - 1) ? rank_out : nullptr;
     if (cv) {
       u.rank_out = iterate[it & 1];
@@ -1173,20 +1193,20 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
           if (t->n_chunks > 0)
             k_pr_tocab_pull_lds<false><<<t->n_chunks, kLdsThreads, pull_lds_bytes(t), s>>>(
                 t->row_ptr, t->col16, t->heads, nullptr, t->chunk_beg, t->chunk_end, t->chunk_blk, t->chunk_j0,
-                t->chunk_ns, t->seg, t->R, t->log2W, n, g->contrib[0], t->partial,
+                t->chunk_ns, t->seg, t->R, t->log2W, n, buf.contrib[0], buf.partial,
                 static_cast<uint32_t>(sizeof(float) * (t->P + 8)));
         }
-        u.contrib = g->contrib[0];
+        u.contrib = buf.contrib[0];
         ProfScope prof("pr_merge", s);
         switch (t->k) {
-          case 256: k_pr_merge_stream<256><<<t->R, merge_threads<256>(), 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
-          case 512: k_pr_merge_stream<512><<<t->R, merge_threads<512>(), 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
-          case 1024: k_pr_merge_stream<1024><<<t->R, merge_threads<1024>(), 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
-          case 2048: k_pr_merge_stream<2048><<<t->R, merge_threads<2048>(), 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
-          case 4096: k_pr_merge_stream<4096><<<t->R, merge_threads<4096>(), 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
-          case 8192: k_pr_merge_stream<8192><<<t->R, merge_threads<8192>(), 0, s>>>(t->rstart, t->id16s, t->partial, u); break;
+          case 256: k_pr_merge_stream<256><<<t->R, merge_threads<256>(), 0, s>>>(t->rstart, t->id16s, buf.partial, u); break;
+          case 512: k_pr_merge_stream<512><<<t->R, merge_threads<512>(), 0, s>>>(t->rstart, t->id16s, buf.partial, u); break;
+          case 1024: k_pr_merge_stream<1024><<<t->R, merge_threads<1024>(), 0, s>>>(t->rstart, t->id16s, buf.partial, u); break;
+          case 2048: k_pr_merge_stream<2048><<<t->R, merge_threads<2048>(), 0, s>>>(t->rstart, t->id16s, buf.partial, u); break;
+          case 4096: k_pr_merge_stream<4096><<<t->R, merge_threads<4096>(), 0, s>>>(t->rstart, t->id16s, buf.partial, u); break;
+          case 8192: k_pr_merge_stream<8192><<<t->R, merge_threads<8192>(), 0, s>>>(t->rstart, t->id16s, buf.partial, u); break;
           case 16384:
-            k_pr_merge_stream<16384><<<t->R, merge_threads<16384>(), 0, s>>>(t->rstart, t->id16s, t->partial, u);
+            k_pr_merge_stream<16384><<<t->R, merge_threads<16384>(), 0, s>>>(t->rstart, t->id16s, buf.partial, u);
             break;
           default: return hipErrorInvalidValue;
         }
@@ -1194,36 +1214,36 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
       } else {
         {
           ProfScope prof("pr_tocab_pull", s);
-          k_pr_tocab_pull<<<t->n_tiles, kThreads, 0, s>>>(t->row_ptr, t->col, t->tile_row, g->contrib[0],
-                                                          t->partial);
+          k_pr_tocab_pull<<<t->n_tiles, kThreads, 0, s>>>(t->row_ptr, t->col, t->tile_row, buf.contrib[0],
+                                                          buf.partial);
         }
-        u.contrib = g->contrib[0];  // safe in place: the pull pass has finished reading c
+        u.contrib = buf.contrib[0];  // safe in place: the pull pass has finished reading c
         parts = t->R;
         ProfScope prof("pr_merge", s);
         switch (t->k) {
-          case 256: launch_merge<256>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
-          case 512: launch_merge<512>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
-          case 1024: launch_merge<1024>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
-          case 2048: launch_merge<2048>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
-          case 4096: launch_merge<4096>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
-          case 8192: launch_merge<8192>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
-          case 16384: launch_merge<16384>(t->R, s, t->range_ptr, t->B, t->id16, t->partial, u); break;
+          case 256: launch_merge<256>(t->R, s, t->range_ptr, t->B, t->id16, buf.partial, u); break;
+          case 512: launch_merge<512>(t->R, s, t->range_ptr, t->B, t->id16, buf.partial, u); break;
+          case 1024: launch_merge<1024>(t->R, s, t->range_ptr, t->B, t->id16, buf.partial, u); break;
+          case 2048: launch_merge<2048>(t->R, s, t->range_ptr, t->B, t->id16, buf.partial, u); break;
+          case 4096: launch_merge<4096>(t->R, s, t->range_ptr, t->B, t->id16, buf.partial, u); break;
+          case 8192: launch_merge<8192>(t->R, s, t->range_ptr, t->B, t->id16, buf.partial, u); break;
+          case 16384: launch_merge<16384>(t->R, s, t->range_ptr, t->B, t->id16, buf.partial, u); break;
           default: return hipErrorInvalidValue;
         }
       }
     } else if (!push) {
-      u.contrib = g->contrib[cur ^ 1];
+      u.contrib = buf.contrib[cur ^ 1];
       parts = g->n_tiles_in;
       ProfScope prof("pr_plain_pull", s);
       k_pr_plain_pull<<<g->n_tiles_in, kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, g->tile_row_in,
-                                                         g->contrib[cur], u);
+                                                         buf.contrib[cur], u);
       cur ^= 1;
     } else if (t && t->W <= kPushLdsMaxWidth) {
-      u.contrib = g->contrib[cur ^ 1];
+      u.contrib = buf.contrib[cur ^ 1];
       parts = t->B;
       ProfScope prof("pr_tocab_push", s);
       k_pr_push_lds<<<t->B, kPushLdsThreads, sizeof(double) * static_cast<size_t>(t->W), s>>>(
-          t->blk_rowoff, t->row_ptr, t->id_map, t->col, t->log2W, g->contrib[cur], u);
+          t->blk_rowoff, t->row_ptr, t->id_map, t->col, t->log2W, buf.contrib[cur], u);
       cur ^= 1;
     } else {
       if (t) {
@@ -1231,19 +1251,19 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
         if (P > 0) {
           ProfScope prof("pr_tocab_push", s);
           k_pr_push<<<static_cast<uint32_t>((P + kThreads - 1) / kThreads), kThreads, 0, s>>>(
-              t->row_ptr, t->id_map, t->col, g->contrib[0], g->sums, P);
+              t->row_ptr, t->id_map, t->col, buf.contrib[0], buf.sums, P);
         }
       } else {
         ProfScope prof("pr_plain_push", s);
-        k_pr_push<<<vgrid, kThreads, 0, s>>>(g->rowptr, nullptr, g->colidx, g->contrib[0], g->sums, n);
+        k_pr_push<<<vgrid, kThreads, 0, s>>>(g->rowptr, nullptr, g->colidx, buf.contrib[0], buf.sums, n);
       }
-      u.contrib = g->contrib[0];
+      u.contrib = buf.contrib[0];
       ProfScope prof("pr_apply", s);
-      k_pr_apply<<<vgrid, kThreads, 0, s>>>(g->sums, u);
+      k_pr_apply<<<vgrid, kThreads, 0, s>>>(buf.sums, u);
     }
     {
       ProfScope prof("pr_dangling", s);
-      k_reduce_dangling<<<1, 1024, 0, s>>>(g->dpart, parts, dtotal_out, u.lpart, g->ltotal);
+      k_reduce_dangling<<<1, 1024, 0, s>>>(buf.dpart, parts, dtotal_out, u.lpart, g->ltotal);
     }
     GC_HIP_TRY(hipGetLastError());
     if (cv) {  // read this iteration's L1 change

@@ -84,7 +84,7 @@ void free_tocab(gc_tocab t) {
   void* bufs[] = {t->blk_rowoff, t->row_ptr, t->id_map, t->col, t->w, t->range_ptr, t->partial, t->pmin,
                   t->tile_row, t->col16, t->chunk_beg, t->chunk_end, t->chunk_blk, t->wtile_row, t->id16,
                   t->heads, t->seg, t->rstart, t->id16s, t->chunk_j0, t->chunk_ns, t->bc_part,
-                  t->val32};
+                  t->val32, t->w_pad};
   for (void* p : bufs)
     if (p) gcx::dev_free(p, nullptr);
   delete t;
@@ -199,7 +199,7 @@ int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* c
   g->next = static_cast<uint32_t*>(gcx::dev_alloc(sizeof(uint32_t) * words, stream));
   g->queue[0] = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * n, stream));
   g->queue[1] = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * n, stream));
-  g->stats = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * 16, stream));
+  g->stats = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * gcx::kStatSlots, stream));
   g->visited = static_cast<uint32_t*>(gcx::dev_alloc(sizeof(uint32_t) * ((static_cast<size_t>(n) + 31) / 32), stream));
   g->mark = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * n, stream));
   g->arc_deg = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * n, stream));
@@ -207,7 +207,8 @@ int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* c
   bool ok = g->visited && g->mark && g->arc_deg && g->arc_pre && g->rowptr && g->colidx && g->t_rowptr && g->t_colidx && (!g->weighted || (g->w && g->t_w)) &&
             g->contrib[0] && g->contrib[1] && g->sums && g->dpart && g->dtotal && g->counter && g->front &&
             g->next && g->queue[0] && g->queue[1] && g->stats;
-  if (ok && hipHostMalloc(reinterpret_cast<void**>(&g->stats_host), sizeof(int32_t) * 16, hipHostMallocDefault) !=
+  if (ok && hipHostMalloc(reinterpret_cast<void**>(&g->stats_host), sizeof(int32_t) * gcx::kStatSlots,
+                          hipHostMallocDefault) !=
                 hipSuccess) {
     g->stats_host = nullptr;
     ok = false;
@@ -215,6 +216,13 @@ int graph_load_csr(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* c
   if (!ok) {
     free_graph(g);
     return fail(GC_ENOMEM, "graph_load_csr: device allocation failed");
+  }
+  {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+      g->clock_khz = khz;
+    (void)hipGetLastError();
   }
   g->bytes = 2 * static_cast<int64_t>(nb) + 2 * static_cast<int64_t>(mb) * (g->weighted ? 2 : 1) +
              12 * static_cast<int64_t>(n) + 8 * static_cast<int64_t>(words) + 8 * static_cast<int64_t>(n) +
@@ -422,23 +430,41 @@ int pagerank_learned(gc_graph g, float damping, int32_t dangling, const float* r
   if (rc != GC_OK) return rc;
   if (iters < 0) return fail(GC_EINVAL, "pagerank_learned: iters < 0");
   if (!g->sched) return fail(GC_EINVAL, "pagerank_learned: no scheduler attached");
-  float feats[GC_SCHED_INPUTS];
-  gcx::sched_features(g->n, g->m, g->n, g->m, 0, 0.0, feats);
-  int32_t a = -1;
-  hipError_t e = gcx::sched_decide(g->sched, feats, stream, &a);
-  if (e != hipSuccess) return hip_fail(e, "pagerank_learned");
   const int32_t np = static_cast<int32_t>(g->sched_parts.size());
-  if (a < 0 || a >= 2 + np) {  // no finite output: the working-set rule (all active: block when a partition exists)
-    a = 1;
-    int32_t best = INT32_MAX;
-    for (int32_t j = 0; j < np; ++j) {
-      const int32_t d = std::abs(g->sched_parts[j]->log2W - 18);  // the paper's block width, 2^18
-      if (d < best) {
-        best = d;
-        a = 2 + j;
-      }
-    }
+  const int32_t K = gcx::sched_actions(g->sched);
+  const int32_t fa = gcx::pagerank_fallback_action(g->sched_parts.data(), np);
+  hipError_t e = hipSuccess;
+  if (g->pr_learned_action < 0) {
+    // Every iteration is alike, so the form is chosen once per attached
+    // network: time the working-set rule's form (one warm-up iteration,
+    // then two timed), give the network that time per arc as its prior-level
+    // input, and keep the rule's form unless the network predicts its own
+    // pick faster by more than the gate.
+    gc_tocab ft = fa >= 2 ? g->sched_parts[fa - 2] : nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float ms = 0.0f;
+    e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = gcx::pagerank_run(g, ft, GC_PULL, damping, dangling, rank_in, rank_out, 1, stream);
+    if (e == hipSuccess) e = hipEventRecord(e0, stream);
+    if (e == hipSuccess) e = gcx::pagerank_run(g, ft, GC_PULL, damping, dangling, rank_in, rank_out, 2, stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "pagerank_learned: timing the fallback form");
+    float feats[GC_SCHED_INPUTS];
+    gcx::sched_features(g->n, g->m, g->n, g->m, 1, ms / 2.0, g->m, feats);
+    std::vector<float> out(static_cast<size_t>(K));
+    int32_t a = -1;
+    e = gcx::sched_decide(g->sched, feats, stream, &a, out.data());
+    if (e != hipSuccess) return hip_fail(e, "pagerank_learned");
+    if (a < 0 || a >= 2 + np || a >= K) a = fa;  // no finite output: the working-set rule
+    else if (fa < K && out[fa] <= out[a] + gcx::kLearnedGate) a = fa;
+    g->pr_learned_action = a;
   }
+  const int32_t a = g->pr_learned_action;
   if (action) *action = a;
   gc_tocab t = a >= 2 ? g->sched_parts[a - 2] : nullptr;
   e = gcx::pagerank_run(g, t, a == 0 ? GC_PUSH : GC_PULL, damping, dangling, rank_in, rank_out, iters, stream);
@@ -567,10 +593,11 @@ int traversal_trace(gc_graph g, int32_t* actions, float* ms, int32_t max, int32_
 }
 
 int sched_features(int32_t n, int64_t m, int32_t frontier, int64_t frontier_arcs, int32_t level, float prior_ms,
-                   float* features) {
-  if (n <= 0 || m < 0 || frontier < 0 || frontier_arcs < 0 || level < 0 || !features)
+                   int64_t prior_arcs, float* features) {
+  if (n <= 0 || m < 0 || frontier < 0 || frontier_arcs < 0 || level < 0 || prior_arcs < 0 || !(prior_ms >= 0.0f) ||
+      !features)
     return fail(GC_EINVAL, "sched_features: bad argument");
-  gcx::sched_features(n, m, frontier, frontier_arcs, level, prior_ms, features);
+  gcx::sched_features(n, m, frontier, frontier_arcs, level, prior_ms, prior_arcs, features);
   return GC_OK;
 }
 
@@ -600,6 +627,7 @@ int sched_collect(gc_graph g, const gc_tocab* parts, int32_t n_parts, int32_t ki
 
 int sched_attach(gc_graph g, gc_sched m, const gc_tocab* parts, int32_t n_parts) {
   if (!g) return fail(GC_EINVAL, "sched_attach: NULL graph");
+  g->pr_learned_action = -1;  // pagerank_learned decides again for the new network
   if (!m) {
     g->sched = nullptr;
     g->sched_parts.clear();

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "gc_device.h"
@@ -163,14 +164,13 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   p[q] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-// Inference for one level: outputs for the given features, then the
-// arg-min action (or -1 if an output is not finite) into *choice.
-__global__ __launch_bounds__(kWave) void k_mlp_decide(const float* __restrict__ p, int32_t K, float f0, float f1,
-                                                      float f2, float f3, float f4, float f5,
-                                                      int32_t* __restrict__ choice) {
+// Inference for one level (one wave): the K outputs for features `in`
+// into out[k] (when given) and the arg-min action, or -1 if an output is
+// not finite, into *choice.
+__device__ __forceinline__ void mlp_decide(const float* __restrict__ p, int32_t K, const float (&in)[kIn],
+                                           int32_t* __restrict__ choice, float* __restrict__ out) {
   const Layout L(K);
   const int lane = threadIdx.x;
-  const float in[kIn] = {f0, f1, f2, f3, f4, f5};
   float z = p[L.b1 + lane];
 #pragma unroll
   for (int i = 0; i < kIn; ++i) z += p[L.W1 + lane * kIn + i] * in[i];
@@ -183,6 +183,7 @@ __global__ __launch_bounds__(kWave) void k_mlp_decide(const float* __restrict__ 
   bool bad = false;
   for (int k = 0; k < K; ++k) {
     const float o = p[L.b3 + k] + static_cast<float>(gcd::wave_sum(static_cast<double>(p[L.W3 + k * kHid + lane] * h2)));
+    if (out && lane == 0) out[k] = o;
     bad |= !isfinite(o);
     if (best < 0 || o < bv) {
       best = k;
@@ -190,6 +191,30 @@ __global__ __launch_bounds__(kWave) void k_mlp_decide(const float* __restrict__ 
     }
   }
   if (lane == 0) *choice = bad ? -1 : best;
+}
+
+__global__ __launch_bounds__(kWave) void k_mlp_decide(const float* __restrict__ p, int32_t K, float f0, float f1,
+                                                      float f2, float f3, float f4, float f5,
+                                                      int32_t* __restrict__ choice, float* __restrict__ out) {
+  const float in[kIn] = {f0, f1, f2, f3, f4, f5};
+  mlp_decide(p, K, in, choice, out);
+}
+
+// Decision for the next traversal level from the counters of the level
+// just run, read on the device: the next frontier's size and out-arcs, and
+// the level's time from its clock stamps.
+__global__ __launch_bounds__(kWave) void k_mlp_decide_level(const float* __restrict__ p, int32_t K, int64_t n,
+                                                            int64_t m, int32_t level, int64_t prior_arcs,
+                                                            int32_t clock_khz, int32_t* __restrict__ stats) {
+  const int64_t n_f = stats[gcx::kStatQLen];
+  const int64_t m_f = static_cast<int64_t>(static_cast<uint32_t>(stats[gcx::kStatDegLo])) |
+                      (static_cast<int64_t>(stats[gcx::kStatDegLo + 1]) << 32);
+  const uint64_t t0 = *reinterpret_cast<const uint64_t*>(stats + gcx::kStatT0);
+  const uint64_t t1 = *reinterpret_cast<const uint64_t*>(stats + gcx::kStatT1);
+  const double prior_ms = t1 > t0 ? static_cast<double>(t1 - t0) / clock_khz : 0.0;
+  float in[kIn];
+  gcx::level_features(n, m, n_f, m_f, level, prior_ms, prior_arcs, in);
+  mlp_decide(p, K, in, stats + gcx::kStatChoice, reinterpret_cast<float*>(stats + gcx::kStatOut));
 }
 
 }  // namespace
@@ -212,13 +237,22 @@ int32_t sched_actions(gc_sched m) { return m->K; }
 
 // Decision for one level from host-computed features; -1 when the network
 // gives no finite answer (the caller falls back to the heuristic).
-hipError_t sched_decide(gc_sched m, const float* f, hipStream_t s, int32_t* action) {
-  k_mlp_decide<<<1, kWave, 0, s>>>(m->params, m->K, f[0], f[1], f[2], f[3], f[4], f[5], m->choice);
+hipError_t sched_decide(gc_sched m, const float* f, hipStream_t s, int32_t* action, float* out) {
+  // m->choice holds the action, then the K outputs
+  k_mlp_decide<<<1, kWave, 0, s>>>(m->params, m->K, f[0], f[1], f[2], f[3], f[4], f[5], m->choice,
+                                   reinterpret_cast<float*>(m->choice + 1));
   GC_HIP_TRY(hipGetLastError());
-  GC_HIP_TRY(hipMemcpyAsync(m->choice_host, m->choice, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GC_HIP_TRY(hipMemcpyAsync(m->choice_host, m->choice, sizeof(int32_t) * (1 + m->K), hipMemcpyDeviceToHost, s));
   GC_HIP_TRY(hipStreamSynchronize(s));
-  *action = *m->choice_host;
+  *action = m->choice_host[0];
+  if (out) std::memcpy(out, m->choice_host + 1, sizeof(float) * m->K);
   return hipSuccess;
+}
+
+hipError_t sched_decide_level(gc_sched m, int64_t n, int64_t m_arcs, int32_t level, int64_t prior_arcs,
+                              int32_t clock_khz, int32_t* stats, hipStream_t s) {
+  k_mlp_decide_level<<<1, kWave, 0, s>>>(m->params, m->K, n, m_arcs, level, prior_arcs, clock_khz, stats);
+  return hipGetLastError();
 }
 
 }  // namespace gcx
@@ -282,8 +316,9 @@ int sched_create(int32_t n_actions, const float* params, gc_sched* out) {
   m->m = static_cast<float*>(gcx::dev_alloc(bytes, nullptr));
   m->v = static_cast<float*>(gcx::dev_alloc(bytes, nullptr));
   m->grad = static_cast<float*>(gcx::dev_alloc(bytes, nullptr));
-  m->choice = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t), nullptr));
-  if (hipHostMalloc(reinterpret_cast<void**>(&m->choice_host), sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+  m->choice = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * (1 + kHid), nullptr));
+  if (hipHostMalloc(reinterpret_cast<void**>(&m->choice_host), sizeof(int32_t) * (1 + kHid), hipHostMallocDefault) !=
+      hipSuccess)
     m->choice_host = nullptr;
   if (!m->params || !m->m || !m->v || !m->grad || !m->choice || !m->choice_host) {
     sched_free(m);

@@ -23,6 +23,8 @@
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "gc_device.h"
 #include "gc_internal.h"
@@ -38,10 +40,10 @@ constexpr int kThreads = 256;
 constexpr int32_t kInf = INT32_MAX;
 constexpr int kHeavy = 32;  // rows longer than this are scanned by the whole wave
 
-// stats slots (device int32[16], copied to the pinned mirror once per level)
-constexpr int kQLen = 0;       // vertices appended to the next queue
-constexpr int kOverflow = 1;   // SSSP: a path length reached INT32_MAX
-constexpr int kDegLo = 2;      // out-arcs of the next frontier (64-bit: lo, hi)
+// stats slots (device int32[gcx::kStatSlots], copied to the pinned mirror once per level)
+constexpr int kQLen = gcx::kStatQLen;
+constexpr int kOverflow = gcx::kStatOverflow;
+constexpr int kDegLo = gcx::kStatDegLo;
 
 // Appends v to queue for every thread with take set, with one atomic on the
 // queue length per work-group (per-wave atomics on the one counter
@@ -95,9 +97,19 @@ __global__ void k_clear_front(uint32_t* __restrict__ front, const int32_t* __res
   if (i < qn) front[queue[i] >> 5] = 0u;
 }
 
-// Out-arc count of the queued vertices (for the direction heuristic).
+// Start of a level: clears the counters the level accumulates and stamps
+// the device wall clock.
+__global__ void k_level_begin(int32_t* __restrict__ stats) {
+  if (threadIdx.x < gcx::kStatT0) stats[threadIdx.x] = 0;
+  if (threadIdx.x == 0) *reinterpret_cast<uint64_t*>(stats + gcx::kStatT0) = wall_clock64();
+}
+
+// Out-arc count of the queued vertices (for the direction heuristic). The
+// kernel runs right after the level's relaxation kernels on the same
+// stream, so its start stamps the end of the level.
 __global__ void k_queue_degree(const int32_t* __restrict__ queue, const int32_t* __restrict__ qlen,
                                const int32_t* __restrict__ rowptr, int32_t* __restrict__ stats) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *reinterpret_cast<uint64_t*>(stats + gcx::kStatT1) = wall_clock64();
   const int32_t qn = *qlen;
   uint64_t sum = 0;
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < qn; i += gridDim.x * blockDim.x) {
@@ -401,6 +413,149 @@ __global__ __launch_bounds__(kThreads) void k_sssp_tocab(const int32_t* __restri
     if (ovf) stats[kOverflow] = 1;
     if (l < P) pmin[l] = static_cast<int32_t>(best);
   }
+}
+
+// TOCAB pull for SSSP over the stream layout (blocks up to 2^15 wide, the
+// layout the PageRank pull reads): the block's slice of the frontier's
+// distances lives in LDS, so the random reads of a round never leave the
+// CU. One work-group per chunk of the partition (rows [r0, r1) of block b);
+// it first stores ad[i] = dist[bW + i] for sources in the frontier and
+// INT32_MAX for the others, then each wave walks a contiguous range of
+// 512-arc tiles: a lane holds 8 consecutive arcs (16-bit columns, their
+// weights, the head bits of its head word), takes their candidates ad[col]
+// + w, and a segmented minimum (lane-local runs, then a wave-wide
+// segmented scan) gives the minimum of every row whose head lies in the
+// wave's range; the row open at a tile's end carries into the next tile,
+// and the one open at the range's end is finished by reading on. pmin[l]
+// (block-major, as the wide-block kernel writes it) is the minimum over
+// local row l's arcs, INT32_MAX when no source of the row is active.
+constexpr int kLdsRowThreads = 1024;
+constexpr int kLdsRowWaves = kLdsRowThreads / kWave;
+constexpr int kRowTile = 512;  // arcs per wave tile: 8 per lane
+
+typedef uint32_t tu32x4 __attribute__((ext_vector_type(4)));
+typedef int32_t ti32x4 __attribute__((ext_vector_type(4)));
+
+struct MinTile {
+  int32_t x[8];     // candidates of the lane's 8 arcs
+  uint32_t my9;     // head bits of the lane's arcs, bit 8: the arc after them
+  int32_t row0;     // local row holding the lane's arc 0 when it is no head (row before the first head)
+};
+
+__device__ __forceinline__ MinTile load_min_tile(const uint16_t* __restrict__ col16,
+                                                 const gc_head_word* __restrict__ heads,
+                                                 const int32_t* __restrict__ w_pad, const int32_t* ad, int64_t q,
+                                                 int lane, bool* ovf) {
+  MinTile t;
+  const int64_t tb = q * kRowTile;
+  const tu32x4 cols = gcd::ld_stream(reinterpret_cast<const tu32x4*>(col16 + tb) + lane);
+  const ti32x4 wa = gcd::ld_stream(reinterpret_cast<const ti32x4*>(w_pad + tb) + 2 * lane);
+  const ti32x4 wb = gcd::ld_stream(reinterpret_cast<const ti32x4*>(w_pad + tb) + 2 * lane + 1);
+  const tu32x4 hw = *reinterpret_cast<const tu32x4*>(heads + (tb >> 6) + (lane >> 3));
+  const uint64_t bits = static_cast<uint64_t>(hw[0]) | (static_cast<uint64_t>(hw[1]) << 32);
+  const int sub = lane & 7;
+  const uint32_t after = sub < 7 ? static_cast<uint32_t>(bits >> (8 * sub + 8)) & 1u : hw[3] & 1u;
+  t.my9 = (static_cast<uint32_t>(bits >> (8 * sub)) & 0xFFu) | (after << 8);
+  const uint64_t below = sub ? (bits & ((1ull << (8 * sub)) - 1ull)) : 0ull;
+  t.row0 = static_cast<int32_t>(hw[2]) + __popcll(below) - 1;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const uint32_t c = (cols[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+    const int32_t a = ad[c];
+    const int32_t w = e < 4 ? wa[e] : wb[e - 4];
+    const int64_t cand = static_cast<int64_t>(a) + w;
+    *ovf |= a != kInf && cand >= kInf;
+    t.x[e] = (a == kInf || cand >= kInf) ? kInf : static_cast<int32_t>(cand);
+  }
+  return t;
+}
+
+__global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
+    const int32_t* __restrict__ row_ptr, const uint16_t* __restrict__ col16, const gc_head_word* __restrict__ heads,
+    const int32_t* __restrict__ w_pad, const int32_t* __restrict__ chunk_beg, const int32_t* __restrict__ chunk_end,
+    const int32_t* __restrict__ chunk_blk, int32_t log2W, int32_t n, const uint32_t* __restrict__ front,
+    const int32_t* __restrict__ dist, int32_t* __restrict__ pmin, int32_t* __restrict__ stats) {
+  extern __shared__ int32_t ad[];
+  const int32_t ch = blockIdx.x;
+  const int32_t r0 = chunk_beg[ch], r1 = chunk_end[ch], b = chunk_blk[ch];
+  if (r0 >= r1) return;  // padding of the dispatch order (uniform)
+  const int32_t W = 1 << log2W, v0 = b << log2W, cnt = min(W, n - v0);
+  for (int32_t i = threadIdx.x; i < W; i += kLdsRowThreads) {
+    int32_t a = kInf;
+    if (i < cnt && bit_test(front, v0 + i)) a = dist[v0 + i];
+    ad[i] = a;
+  }
+  __syncthreads();
+  const int lane = gcd::lane_id();
+  const int wid = static_cast<int>(threadIdx.x) / kWave;
+  const int32_t q0 = row_ptr[r0] / kRowTile, q1 = (row_ptr[r1] - 1) / kRowTile;
+  const int32_t nt = q1 - q0 + 1;
+  const int32_t qa = q0 + static_cast<int32_t>(static_cast<int64_t>(nt) * wid / kLdsRowWaves);
+  const int32_t qz = q0 + static_cast<int32_t>(static_cast<int64_t>(nt) * (wid + 1) / kLdsRowWaves) - 1;
+  if (qa > qz) return;  // no barrier follows
+  // rows this wave writes: heads at or after its first arc, inside the chunk
+  const int32_t own0 = max(heads[static_cast<int64_t>(qa) * (kRowTile / 64)].row, r0);
+  bool ovf = false;
+  int32_t carry = kInf;  // minimum so far of the row open at the previous tile's end
+  int32_t open_row = -1;
+  for (int32_t q = qa; q <= qz; ++q) {
+    const MinTile t = load_min_tile(col16, heads, w_pad, ad, q, lane, &ovf);
+    // lane-local runs: reset at every head; lane 0 starts from the carry
+    int32_t run = (lane == 0) ? carry : kInf;
+    int32_t rv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      run = ((t.my9 >> e) & 1u) ? t.x[e] : min(run, t.x[e]);
+      rv[e] = run;
+    }
+    // wave-wide segmented inclusive minimum of the lanes' open runs
+    int32_t A = run;
+    int F = (t.my9 & 0xFFu) != 0u;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int32_t ta = __shfl_up(A, o, kWave);
+      const int tf = __shfl_up(F, o, kWave);
+      if (lane >= o) {
+        if (!F) A = min(A, ta);
+        F |= tf;
+      }
+    }
+    const int32_t in = __shfl_up(A, 1, kWave);  // the row flowing into this lane
+    const int32_t lin = lane == 0 ? kInf : in;
+    int32_t row = t.row0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const bool head = (t.my9 >> e) & 1u;
+      row += head ? 1 : 0;
+      if ((t.my9 >> (e + 1)) & 1u) {  // arc e ends its row
+        const bool started_here = (t.my9 & ((2u << e) - 1u)) != 0u;
+        const int32_t v = started_here ? rv[e] : min(rv[e], lin);
+        if (row >= own0 && row < r1) pmin[row] = v;
+      }
+    }
+    carry = __builtin_amdgcn_readlane(A, kWave - 1);
+    open_row = __builtin_amdgcn_readlane(row, kWave - 1);
+  }
+  // the row open at the range's end, if the wave owns it: read on to its end
+  const int64_t end_arc = static_cast<int64_t>(qz + 1) * kRowTile;
+  const bool continues = !((heads[end_arc >> 6].bits) & 1ull);
+  if (continues && open_row >= own0 && open_row < r1) {
+    for (int64_t q = qz + 1;; ++q) {
+      const MinTile t = load_min_tile(col16, heads, w_pad, ad, q, lane, &ovf);
+      // arcs before the tile's first head belong to the open row
+      const int fh = (t.my9 & 0xFFu) ? __ffs(t.my9 & 0xFFu) - 1 : 8;  // first head in the lane
+      const uint64_t hl = __ballot(fh < 8);
+      const int first_lane = hl ? __ffsll(static_cast<long long>(hl)) - 1 : kWave;
+      int32_t mine = kInf;
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (lane < first_lane || (lane == first_lane && e < fh)) mine = min(mine, t.x[e]);
+      carry = min(carry, gcd::wave_min(mine));
+      if (first_lane < kWave) break;  // bits past the last arc are set, so this ends
+    }
+    if (lane == 0) pmin[open_row] = carry;
+  }
+  if (__any(ovf) && lane == 0) stats[kOverflow] = 1;
 }
 
 template <int K, bool kFlat>
@@ -1003,20 +1158,29 @@ enum class Mode { kPull, kTocab, kPush };
 // Direction choice (Section 3.3): with the direction-optimising rule of
 // Beamer et al. (the paper's [Direction] reference; alpha = 14, beta = 24)
 // a level pulls when the frontier's out-arcs exceed the unexplored arcs /
-// alpha and returns to push when the frontier shrinks below n / beta; pull
-// levels use TOCAB only when the frontier's working set, proportional to
-// its out-arc count, exceeds the last-level cache.
+// alpha and returns to push when the frontier shrinks below n / beta. A
+// pull level is blocked (TOCAB) when its working set exceeds the cache: the
+// frontier must be large (4 bytes per frontier out-arc above one XCD's L2,
+// the paper's test) and the array its random reads land in must not fit in
+// that L2 either. With one status bit per vertex a BFS pull reads only the
+// bitmap (n / 8 bytes: 2 MB at 2^24 vertices, so plain pull's reads already
+// hit L2 and blocking only adds its local rows); an SSSP pull also gathers
+// the 4-byte distances of active sources.
 struct Heuristic {
   static constexpr double kAlpha = 14.0, kBeta = 24.0;
   static constexpr double kCacheBytes = 4.0 * 1024 * 1024;  // one XCD's L2
   bool pulling = false;
-  Mode pick(int64_t n, int64_t n_f, int64_t m_f, int64_t m_u, bool have_tocab) {
+  Mode pick(int64_t n, int64_t n_f, int64_t m_f, int64_t m_u, bool have_tocab, bool bfs) {
     if (!pulling && static_cast<double>(m_f) > static_cast<double>(m_u) / kAlpha) pulling = true;
     else if (pulling && static_cast<double>(n_f) < static_cast<double>(n) / kBeta) pulling = false;
     if (!pulling) return Mode::kPush;
-    return (have_tocab && 4.0 * static_cast<double>(m_f) > kCacheBytes) ? Mode::kTocab : Mode::kPull;
+    const double gathered = static_cast<double>(n) / 8.0 + (bfs ? 0.0 : 4.0 * static_cast<double>(n));
+    const bool large = 4.0 * static_cast<double>(m_f) > kCacheBytes && gathered > kCacheBytes;
+    return (have_tocab && large) ? Mode::kTocab : Mode::kPull;
   }
 };
+
+using gcx::kLearnedGate;
 
 template <template <int> class Kern, class... Args>
 hipError_t launch_by_k(int32_t k, int32_t R, hipStream_t s, Args... args) {
@@ -1051,6 +1215,23 @@ struct SsspMerge {
   }
 };
 
+// Integer weights of a stream-layout partition in its arc order, padded with
+// zeros to the layout's length (built by the first SSSP round over it), and
+// the LDS limit of the kernel that reads them.
+hipError_t stream_weights(gc_tocab t, hipStream_t s) {
+  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sssp_tocab_lds),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     static_cast<int>(sizeof(int32_t)) * gcx::kLdsMaxWidth);
+  GC_HIP_TRY(attr);
+  if (t->w_pad) return hipSuccess;
+  if (!t->w) return hipErrorInvalidValue;
+  t->w_pad = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * static_cast<size_t>(t->m_pad), s));
+  if (!t->w_pad) return hipErrorOutOfMemory;
+  t->bytes += static_cast<int64_t>(sizeof(int32_t)) * t->m_pad;
+  if (t->m > 0) GC_HIP_TRY(hipMemcpyAsync(t->w_pad, t->w, sizeof(int32_t) * t->m, hipMemcpyDeviceToDevice, s));
+  return hipMemsetAsync(t->w_pad + t->m, 0, sizeof(int32_t) * (t->m_pad - t->m), s);
+}
+
 // Per-level bookkeeping: reads the next frontier's size and out-arc count,
 // clears the old frontier's status bytes, and swaps the buffers.
 struct Frontier {
@@ -1064,12 +1245,28 @@ struct Frontier {
   int32_t* queue() { return g->queue[cur]; }
   int32_t* queue_next() { return g->queue[cur ^ 1]; }
 
-  hipError_t begin_level() { return hipMemsetAsync(g->stats, 0, sizeof(int32_t) * 16, s); }
+  hipError_t begin_level() {
+    k_level_begin<<<1, kWave, 0, s>>>(g->stats);
+    return hipGetLastError();
+  }
 
-  hipError_t end_level(bool* overflow) {
+  // Device time of the level just ended (its relaxation kernels), in ms,
+  // from the clock stamps in the host mirror.
+  double level_ms() const {
+    const uint64_t t0 = *reinterpret_cast<const uint64_t*>(g->stats_host + gcx::kStatT0);
+    const uint64_t t1 = *reinterpret_cast<const uint64_t*>(g->stats_host + gcx::kStatT1);
+    return t1 > t0 ? static_cast<double>(t1 - t0) / g->clock_khz : 0.0;
+  }
+
+  // Ends a level: counts the next frontier's out-arcs, queues the learned
+  // scheduler's decision for the next level when `decide` is given (read
+  // back with the counters, so it costs no synchronisation of its own),
+  // and reads the counters.
+  hipError_t end_level(bool* overflow, gc_sched decide = nullptr, int32_t next_level = 0) {
     k_queue_degree<<<256, kThreads, 0, s>>>(queue_next(), g->stats + kQLen, g->rowptr, g->stats);
     GC_HIP_TRY(hipGetLastError());
-    GC_HIP_TRY(hipMemcpyAsync(g->stats_host, g->stats, sizeof(int32_t) * 16, hipMemcpyDeviceToHost, s));
+    if (decide) GC_HIP_TRY(gcx::sched_decide_level(decide, g->n, g->m, next_level, m_f, g->clock_khz, g->stats, s));
+    GC_HIP_TRY(hipMemcpyAsync(g->stats_host, g->stats, sizeof(int32_t) * gcx::kStatSlots, hipMemcpyDeviceToHost, s));
     if (n_f > 0) k_clear_front<<<grid_for(n_f, kThreads), kThreads, 0, s>>>(front(), queue(), n_f);
     GC_HIP_TRY(hipGetLastError());
     GC_HIP_TRY(hipStreamSynchronize(s));
@@ -1154,10 +1351,17 @@ hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t 
       k_sssp_pull<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, g->t_w, n, f.front(), value,
                                                               f.next(), f.queue_next(), g->stats);
     } else {
-      {
+      if (t->col16) {  // stream layout: the block's distances in LDS
+        GC_HIP_TRY(stream_weights(t, s));
+        ProfScope prof("sssp_tocab", s);
+        if (t->n_chunks > 0)
+          k_sssp_tocab_lds<<<t->n_chunks, kLdsRowThreads, sizeof(int32_t) * static_cast<size_t>(t->W), s>>>(
+              t->row_ptr, t->col16, t->heads, t->w_pad, t->chunk_beg, t->chunk_end, t->chunk_blk, t->log2W, n,
+              f.front(), value, t->pmin, g->stats);
+      } else {
         ProfScope prof("sssp_tocab", s);
         k_sssp_tocab<<<row_grid(t->P), kThreads, 0, s>>>(t->row_ptr, t->col, t->w, t->P, f.front(), value,
-                                                                    t->pmin, g->stats);
+                                                         t->pmin, g->stats);
       }
       ProfScope prof("sssp_merge", s);
       GC_HIP_TRY((launch_by_k<SsspMerge>(t->k, t->R, s, static_cast<const int32_t*>(t->range_ptr), t->B,
@@ -1243,13 +1447,9 @@ hipError_t run_bc_level(gc_graph g, Frontier& f, int32_t level, Mode mode, gc_to
 
 namespace gcx {
 
-void sched_features(int64_t n, int64_t m, int64_t n_f, int64_t m_f, int32_t level, double prior_ms, float* f) {
-  f[0] = static_cast<float>(std::log1p(static_cast<double>(n_f)));
-  f[1] = static_cast<float>(std::log1p(static_cast<double>(m_f)));
-  f[2] = static_cast<float>(std::log1p(static_cast<double>(m) / static_cast<double>(std::max<int64_t>(n, 1))));
-  f[3] = static_cast<float>(std::log2(static_cast<double>((n + (1 << 18) - 1) >> 18) + 1.0));
-  f[4] = static_cast<float>(level) / 16.0f;
-  f[5] = static_cast<float>(std::log1p(prior_ms * 1000.0));
+void sched_features(int64_t n, int64_t m, int64_t n_f, int64_t m_f, int32_t level, double prior_ms,
+                    int64_t prior_arcs, float* f) {
+  level_features(n, m, n_f, m_f, level, prior_ms, prior_arcs, f);
 }
 
 hipError_t traverse(gc_graph g, gc_tocab t, int32_t source, int32_t* value, int32_t* count, uint32_t policy,
@@ -1263,50 +1463,75 @@ hipError_t traverse(gc_graph g, gc_tocab t, int32_t source, int32_t* value, int3
   int64_t m_u = g->m - f.m_f;
   Heuristic h;
   int32_t level = 0;
-  double prior_ms = 0.0;
   g->trace_action.clear();
   g->trace_ms.clear();
   if (overflow) *overflow = false;
-  // Under the learned policy the prior-level time fed to the network is the
-  // level's kernel time from HIP events, the measure its training rows hold.
+  // Learned policy: the network's decision for every level after the first
+  // is computed on the device from the level counters at the end of the
+  // previous level and read back with them; the first level's from host
+  // features. Its working-set fallback uses the attached partition nearest
+  // the paper's 2^18 when the call gives none.
   const bool learned = policy == GC_POLICY_LEARNED && g->sched;
-  EventPair ev;
-  if (learned) GC_HIP_TRY(ev.create());
+  const int32_t K = learned ? sched_actions(g->sched) : 0;
+  gc_tocab fall_t = t;
+  int32_t fall_action = -1;  // action index of TOCAB over fall_t
+  if (learned) {
+    const int32_t np = static_cast<int32_t>(g->sched_parts.size());
+    int32_t best = INT32_MAX;
+    for (int32_t j = 0; j < np && 2 + j < K; ++j) {
+      const int32_t d = std::abs(g->sched_parts[j]->log2W - 18);
+      if (d < best) {
+        best = d;
+        fall_action = 2 + j;
+      }
+    }
+    if (!t && fall_action >= 0) fall_t = g->sched_parts[fall_action - 2];
+    if (t) fall_action = -1;  // the caller's partition is not among the network's actions
+  }
+  std::vector<float> outs(static_cast<size_t>(std::max(K, 1)));
   while (f.n_f > 0) {
     if (!bfs && level > n) return hipErrorInvalidValue;  // cannot happen with positive weights
     // SSSP revisits vertices, so the unexplored-arc count of BFS does not
     // apply; the whole arc set stands in for it.
     const int64_t unexplored = bfs ? m_u : g->m;
-    Mode mode = Mode::kPush;
-    gc_tocab lt = t;
+    // the working-set rule's choice: the policy itself, the fallback of the
+    // learned one, and the reference its decision is gated against
+    Mode hmode;
+    if (policy == GC_POLICY_PUSH) hmode = Mode::kPush;
+    else if (policy == GC_POLICY_PULL) hmode = t ? Mode::kTocab : Mode::kPull;
+    else hmode = h.pick(n, f.n_f, f.m_f, unexplored, fall_t != nullptr, bfs);
+    Mode mode = hmode;
+    gc_tocab lt = fall_t;
     int32_t action = -1;
     if (learned) {
-      float feats[GC_SCHED_INPUTS];
-      sched_features(n, g->m, f.n_f, f.m_f, level, prior_ms, feats);
-      GC_HIP_TRY(sched_decide(g->sched, feats, s, &action));
-      if (action >= 0 && action < sched_actions(g->sched)) action_mode(action, g->sched_parts.data(), &mode, &lt);
-      else action = -1;
+      int32_t a = -1;
+      if (level == 0) {
+        float feats[GC_SCHED_INPUTS];
+        sched_features(n, g->m, f.n_f, f.m_f, level, 0.0, 0, feats);
+        GC_HIP_TRY(sched_decide(g->sched, feats, s, &a, outs.data()));
+      } else {
+        a = g->stats_host[gcx::kStatChoice];
+        std::memcpy(outs.data(), g->stats_host + gcx::kStatOut, sizeof(float) * K);
+      }
+      if (a >= 0 && a < K) {
+        // the rule's own choice as an action, kept unless the network
+        // predicts its pick faster by more than the gate
+        const int32_t ha = hmode == Mode::kPush ? 0 : (hmode == Mode::kPull ? 1 : fall_action);
+        if (ha >= 0 && ha < K && outs[ha] <= outs[a] + kLearnedGate) a = ha;
+        action_mode(a, g->sched_parts.data(), &mode, &lt);
+        action = a;
+      }
     }
     if (action < 0) {
-      if (policy == GC_POLICY_PUSH) mode = Mode::kPush;
-      else if (policy == GC_POLICY_PULL) mode = t ? Mode::kTocab : Mode::kPull;
-      else mode = h.pick(n, f.n_f, f.m_f, unexplored, t != nullptr);  // heuristic, or learned fallback
-      lt = t;
+      mode = hmode;
+      lt = mode == Mode::kTocab ? fall_t : t;
       action = mode_action(mode);
     }
     const double t0 = now_ms();
     GC_HIP_TRY(f.begin_level());
-    if (learned) GC_HIP_TRY(hipEventRecord(ev.e[0], s));
     GC_HIP_TRY(run_level(g, f, bfs, value, level, mode, lt, s));
-    if (learned) GC_HIP_TRY(hipEventRecord(ev.e[1], s));
-    GC_HIP_TRY(f.end_level(overflow));
+    GC_HIP_TRY(f.end_level(overflow, learned ? g->sched : nullptr, level + 1));
     const double wall_ms = now_ms() - t0;
-    prior_ms = wall_ms;
-    if (learned) {
-      float ms = 0.0f;
-      GC_HIP_TRY(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
-      prior_ms = ms;
-    }
     g->trace_action.push_back(action);
     g->trace_ms.push_back(static_cast<float>(wall_ms));
     if (overflow && *overflow) break;
@@ -1380,7 +1605,7 @@ hipError_t bc_run(gc_graph g, gc_tocab t, const int32_t* sources, int32_t n_src,
       Mode mode;
       if (policy == GC_POLICY_PUSH) mode = Mode::kPush;
       else if (policy == GC_POLICY_PULL) mode = t ? Mode::kTocab : Mode::kPull;
-      else mode = h.pick(n, f.n_f, f.m_f, m_u, t != nullptr);
+      else mode = h.pick(n, f.n_f, f.m_f, m_u, t != nullptr, true);
       const double t0 = now_ms();
       GC_HIP_TRY(f.begin_level());
       GC_HIP_TRY(run_bc_level(g, f, level, mode, t, s));
@@ -1468,10 +1693,13 @@ hipError_t collect(gc_graph g, gc_tocab* parts, int32_t n_parts, bool bfs, const
     Frontier f{g, s};
     f.m_f = source_degree(g, sources[si], s, &err);
     int32_t level = 0;
-    double prior_ms = 0.0;
+    double prior_ms = 0.0;  // device time of the previous level (its fastest action), from the clock stamps
+    int64_t prior_arcs = 0;
     bool overflow = false;
+    std::vector<double> stamp_ms(static_cast<size_t>(K));
     while (err == hipSuccess && f.n_f > 0 && r < max_rows && !overflow) {
-      sched_features(n, g->m, f.n_f, f.m_f, level, prior_ms, features + static_cast<size_t>(r) * GC_SCHED_INPUTS);
+      sched_features(n, g->m, f.n_f, f.m_f, level, prior_ms, prior_arcs,
+                     features + static_cast<size_t>(r) * GC_SCHED_INPUTS);
       // snapshot the state this level starts from
       const hipMemcpyKind dd = hipMemcpyDeviceToDevice;
       err = hipMemcpyAsync(sv.p, value.p, sizeof(int32_t) * n, dd, s);
@@ -1505,6 +1733,7 @@ hipError_t collect(gc_graph g, gc_tocab* parts, int32_t n_parts, bool bfs, const
         float ms = 0.0f;
         if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
         row_t[a] = ms;
+        stamp_ms[a] = f.level_ms();
         if (ms < row_t[best]) best = a;
       }
       if (err != hipSuccess) break;
@@ -1518,7 +1747,8 @@ hipError_t collect(gc_graph g, gc_tocab* parts, int32_t n_parts, bool bfs, const
         if (err == hipSuccess) err = run_level(g, f, bfs, value.as<int32_t>(), level, mode, lt, s);
         if (err == hipSuccess) err = f.end_level(&overflow);
       }
-      prior_ms = row_t[best];
+      prior_ms = stamp_ms[best];
+      prior_arcs = start.m_f;
       ++r;
       ++level;
     }

@@ -21,7 +21,8 @@ pytestmark = pytest.mark.gpu
 
 L1_TOL = 1e-6
 BENCH_W, BENCH_K = 1 << 15, 16384          # PageRank pull partition the benchmark times
-TRAV_W, TRAV_K = 1 << 18, 4096             # BFS / SSSP partition the benchmark times
+TRAV_W, TRAV_K = 1 << 15, 16384            # BFS / SSSP partition the benchmark times (stream layout)
+WIDE_W, WIDE_K = 1 << 18, 4096             # the paper's LLC-sized blocks (wide-block kernels)
 PUSH_W = 1 << 18
 
 
@@ -70,10 +71,11 @@ def test_rmat24_traversals_bit_exact(rmat24):
         sssp_want = [ex.submit(oracle.dijkstra, g.n, g.rowptr, g.colidx, g.weights, s) for s in srcs[:2]]
         h = load(g, weights=True)
         part = gc.tocab_partition(h, gc.GC_PULL, TRAV_W, TRAV_K)
+        wide = gc.tocab_partition(h, gc.GC_PULL, WIDE_W, WIDE_K)
         d = torch().empty(g.n, dtype=torch().int32, device="cuda")
         policies = (("plain_pull", None, gc.GC_POLICY_PULL), ("tocab_pull", part, gc.GC_POLICY_PULL),
                     ("push", None, gc.GC_POLICY_PUSH), ("heuristic_tocab", part, gc.GC_POLICY_HEURISTIC),
-                    ("heuristic_plain", None, gc.GC_POLICY_HEURISTIC))
+                    ("heuristic_plain", None, gc.GC_POLICY_HEURISTIC), ("tocab_pull_2^18", wide, gc.GC_POLICY_PULL))
         for s, fw in zip(srcs, bfs_want):
             want = fw.result()
             for name, t, pol in policies:
@@ -86,6 +88,7 @@ def test_rmat24_traversals_bit_exact(rmat24):
                 print(f"sssp rmat24 source {s} {name}", flush=True)
                 gc.sssp_pull(h, t, s, d, pol)
                 np.testing.assert_array_equal(host(d), want)
+    wide.free()
     part.free()
     h.free()
 
@@ -99,10 +102,12 @@ def test_traversal_graphs_bit_exact(name):
     print(f"{name} n={g.n} m={g.m}", flush=True)
     h = load(g, weights=True)
     part = gc.tocab_partition(h, gc.GC_PULL, TRAV_W, TRAV_K)
+    wide = gc.tocab_partition(h, gc.GC_PULL, WIDE_W, WIDE_K)
     d = torch().empty(g.n, dtype=torch().int32, device="cuda")
     s = int(gg.sources(g, 1, seed=5)[0])
     policies = (("plain_pull", None, gc.GC_POLICY_PULL), ("tocab_pull", part, gc.GC_POLICY_PULL),
-                ("push", None, gc.GC_POLICY_PUSH), ("heuristic_tocab", part, gc.GC_POLICY_HEURISTIC))
+                ("push", None, gc.GC_POLICY_PUSH), ("heuristic_tocab", part, gc.GC_POLICY_HEURISTIC),
+                ("heuristic_plain", None, gc.GC_POLICY_HEURISTIC), ("tocab_pull_2^18", wide, gc.GC_POLICY_PULL))
     want = oracle.bfs(g.n, g.rowptr, g.colidx, s)
     for pname, t, pol in policies:
         print(f"bfs {name} source {s} {pname}", flush=True)
@@ -113,5 +118,31 @@ def test_traversal_graphs_bit_exact(name):
         print(f"sssp {name} source {s} {pname}", flush=True)
         gc.sssp_pull(h, t, s, d, pol)
         np.testing.assert_array_equal(host(d), want)
+    wide.free()
+    part.free()
+    h.free()
+
+
+@pytest.mark.timeout(900)
+def test_rmat25_partition_beyond_2p28_rows():
+    """R-MAT 25 (seed 8, the learned scheduler's evaluation graph) at W =
+    2^15 has more than 2^28 local rows, more than one row per thread of any
+    grid the TOCAB row kernels launch: BFS and SSSP under TOCAB pull must
+    still match the oracle bit for bit."""
+    import paper_1904_02241_amd as gc
+    g = gg.rmat(25, 16, seed=8).with_weights(11)
+    print(f"rmat25 n={g.n} m={g.m}", flush=True)
+    h = load(g, weights=True)
+    part = gc.tocab_partition(h, gc.GC_PULL, 1 << 15, 16384)
+    print(f"partition {part.info}", flush=True)
+    assert part.info["P"] > 1 << 28
+    d = torch().empty(g.n, dtype=torch().int32, device="cuda")
+    s = int(gg.sources(g, 1, seed=8)[0])
+    print(f"bfs rmat25 source {s} tocab_pull", flush=True)
+    gc.bfs_pull(h, part, s, d, gc.GC_POLICY_PULL)
+    np.testing.assert_array_equal(host(d), oracle.bfs(g.n, g.rowptr, g.colidx, s))
+    print(f"sssp rmat25 source {s} tocab_pull", flush=True)
+    gc.sssp_pull(h, part, s, d, gc.GC_POLICY_PULL)
+    np.testing.assert_array_equal(host(d), oracle.dijkstra(g.n, g.rowptr, g.colidx, g.weights, s))
     part.free()
     h.free()

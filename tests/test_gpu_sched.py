@@ -80,8 +80,9 @@ def test_adam_training_matches_oracle():
 
 def test_features_are_the_documented_transform():
     import paper_1904_02241_amd as gc
-    f = gc.sched_features(1 << 20, 16 << 20, 1000, 50000, 3, 0.25)
-    want = [np.log1p(1000), np.log1p(50000), np.log1p(16.0), np.log2(4 + 1), 3 / 16, np.log1p(250.0)]
+    # prior level: 0.25 ms over 50,000 frontier out-arcs = 5 ns per arc
+    f = gc.sched_features(1 << 20, 16 << 20, 1000, 60000, 3, 0.25, 50000)
+    want = [np.log1p(1000), np.log1p(60000), np.log1p(16.0), np.log2(4 + 1), 3 / 16, np.log1p(5.0)]
     np.testing.assert_allclose(f, want, rtol=1e-6)
 
 
@@ -331,7 +332,9 @@ def test_learned_pagerank_edges():
     gc.sched_attach(h, None)
     f, t = gc.sched_collect_pagerank(h, [], rows=2)
     assert f.shape == (2, 6) and t.shape == (2, 2) and (t > 0).all()
-    np.testing.assert_allclose(f[0], gc.sched_features(g.n, g.m, g.n, g.m, 0, 0.0), rtol=1e-6)
+    # a PageRank row: an all-active level 1 whose prior time is the working-set
+    # form's (plain pull here: no partition) time per iteration over m arcs
+    np.testing.assert_allclose(f[0], gc.sched_features(g.n, g.m, g.n, g.m, 1, float(t[0][1]), g.m), rtol=1e-6)
     with pytest.raises(gc.GraphCageError):
         gc.sched_collect(h, [], 3, [0])
     nan_net.free()
