@@ -181,6 +181,27 @@ int tocab_free(gc_tocab t);
 int pagerank_iter(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, int32_t dangling,
                   const float* rank_in, float* rank_out, int32_t iters, hipStream_t stream);
 
+/* pagerank_iter for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels and results, but the per-call scratch
+ * (contributions, dangling partials and totals, push accumulators, pull
+ * partial sums) lives in a static device array of the library, 64 MiB per
+ * GPU, held from library load until the process ends, instead of the
+ * graph's and the partition's buffers. Needs, in bytes, each term rounded up
+ * to 256:
+ *   4n + 4n + 8 * max(ceil(n / 256), m / 2048 + 2) + 16
+ *   + 8n               (push: plain push or a GC_PUSH partition)
+ *   + 4(P + 520)       (a GC_PULL partition with P local rows)
+ * and returns GC_EINVAL, queueing nothing, when that exceeds 64 MiB (a
+ * plain pull of a graph with 16 arcs per vertex fits up to about 8.3
+ * million vertices). Calls no allocator (hipMalloc, the gc_set_allocator
+ * hook, or any library routine that allocates). Every call on one GPU shares that GPU's array, and the
+ * array keeps the last call's contents: calls that overlap on one GPU (on
+ * different streams or from different host threads) race and give wrong
+ * results; serialise them. Errors otherwise as pagerank_iter. */
+int pagerank_iter_noalloc(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, int32_t dangling,
+                          const float* rank_in, float* rank_out, int32_t iters, hipStream_t stream);
+
 /* PageRank until the change between consecutive iterates is small (the
  * "run until converged" protocol of Section 4; the paper leaves the test
  * unstated, the reading taken is the L1 norm): iterates exactly like

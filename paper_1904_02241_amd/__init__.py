@@ -45,6 +45,7 @@ SIGNATURES = {
     "tocab_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "tocab_free": (ctypes.c_int, [_vp]),
     "pagerank_iter": (ctypes.c_int, [_vp, _vp, _i32, _f32, _i32, _vp, _vp, _i32, _vp]),
+    "pagerank_iter_noalloc": (ctypes.c_int, [_vp, _vp, _i32, _f32, _i32, _vp, _vp, _i32, _vp]),
     "spmv": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "pagerank_ladder": (ctypes.c_int, [_vp, _vp, _i32, _f32, _i32, _vp, _vp, _i32, _vp]),
     "pagerank_converge": (ctypes.c_int, [_vp, _vp, _i32, _f32, _i32, _vp, _vp, ctypes.c_double, _i32, _p_i32,
@@ -291,6 +292,11 @@ def tocab_free(t):
 def pagerank_iter(g, t, dir_if_plain, damping, dangling, rank_in, rank_out, iters, stream=None):
     _check(lib.pagerank_iter(_h(g), _h(t), dir_if_plain, damping, dangling, _ptr(rank_in), _ptr(rank_out), iters,
                              _stream(stream)), "pagerank_iter")
+
+
+def pagerank_iter_noalloc(g, t, dir_if_plain, damping, dangling, rank_in, rank_out, iters, stream=None):
+    _check(lib.pagerank_iter_noalloc(_h(g), _h(t), dir_if_plain, damping, dangling, _ptr(rank_in), _ptr(rank_out),
+                                     iters, _stream(stream)), "pagerank_iter_noalloc")
 
 
 def spmv(g, t, x, y, stream=None):

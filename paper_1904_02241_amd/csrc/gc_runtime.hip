@@ -4,7 +4,9 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "gc_internal.h"
@@ -119,6 +121,76 @@ void dev_free(void* p, hipStream_t s) {
 }
 
 }  // namespace gcx
+
+// ---- pagerank_iter_noalloc: the same iterations with the library's static scratch
+
+namespace {
+
+// Device scratch of pagerank_iter_noalloc (contributions, dangling partials
+// and totals, push accumulators, pull partial sums). Each GPU holds its own
+// copy for the life of the process; host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Address of the current device's scratch (looked up on the first call on
+// that device, with it current).
+hipError_t scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Byte offsets of the buffers pagerank_run needs for this graph / form inside
+// the scratch; returns the total.
+struct NoAllocLayout {
+  size_t contrib0, contrib1, dpart, dtotal, sums, partial, total;
+};
+NoAllocLayout noalloc_layout(gc_graph g, gc_tocab t, int32_t dir_if_plain) {
+  const bool push = t ? (t->dir == GC_PUSH) : (dir_if_plain == GC_PUSH);
+  const size_t n = static_cast<size_t>(g->n);
+  NoAllocLayout l{};
+  size_t off = 0;
+  l.contrib0 = off;
+  off += align256(sizeof(float) * n);
+  l.contrib1 = off;
+  off += align256(sizeof(float) * n);
+  l.dpart = off;
+  off += align256(sizeof(double) * static_cast<size_t>(g->dpart_slots));
+  l.dtotal = off;
+  off += align256(sizeof(double) * 2);
+  l.sums = SIZE_MAX;
+  if (push) {
+    l.sums = off;
+    off += align256(sizeof(double) * n);
+  }
+  l.partial = SIZE_MAX;
+  if (t && !push) {  // the same slack as the partition's own partial buffer
+    l.partial = off;
+    off += align256(sizeof(float) * (static_cast<size_t>(t->P) + 8 + 512));
+  }
+  l.total = off;
+  return l;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -394,7 +466,7 @@ int tocab_free(gc_tocab t) {
 namespace {
 
 // Checks shared by pagerank_iter and pagerank_converge (`who` names the call).
-int check_pagerank(const char* who, gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping,
+static int check_pagerank(const char* who, gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping,
                    int32_t dangling, const float* rank_in, float* rank_out) {
   if (!g) return fail(GC_EINVAL, "%s: NULL graph", who);
   if (t && t->g != g) return fail(GC_EINVAL, "%s: partition belongs to another graph", who);
@@ -422,6 +494,30 @@ int pagerank_iter(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, i
   if (iters < 0) return fail(GC_EINVAL, "pagerank_iter: iters < 0");
   const hipError_t e = gcx::pagerank_run(g, t, dir_if_plain, damping, dangling, rank_in, rank_out, iters, stream);
   return e == hipSuccess ? GC_OK : hip_fail(e, "pagerank_iter");
+}
+
+int pagerank_iter_noalloc(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, int32_t dangling,
+                          const float* rank_in, float* rank_out, int32_t iters, hipStream_t stream) {
+  const int rc = check_pagerank("pagerank_iter_noalloc", g, t, dir_if_plain, damping, dangling, rank_in, rank_out);
+  if (rc != GC_OK) return rc;
+  if (iters < 0) return fail(GC_EINVAL, "pagerank_iter_noalloc: iters < 0");
+  const NoAllocLayout l = noalloc_layout(g, t, dir_if_plain);
+  if (l.total > kNoAllocScratchBytes)
+    return fail(GC_EINVAL, "pagerank_iter_noalloc: needs %zu bytes of scratch, more than its %zu-byte maximum",
+                l.total, kNoAllocScratchBytes);
+  void* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) return hip_fail(e, "pagerank_iter_noalloc (scratch address)");
+  char* b = static_cast<char*>(base);
+  gcx::PrBuffers buf;
+  buf.contrib[0] = reinterpret_cast<float*>(b + l.contrib0);
+  buf.contrib[1] = reinterpret_cast<float*>(b + l.contrib1);
+  buf.dpart = reinterpret_cast<double*>(b + l.dpart);
+  buf.dtotal = reinterpret_cast<double*>(b + l.dtotal);
+  buf.sums = l.sums == SIZE_MAX ? nullptr : reinterpret_cast<double*>(b + l.sums);
+  buf.partial = l.partial == SIZE_MAX ? nullptr : reinterpret_cast<float*>(b + l.partial);
+  e = gcx::pagerank_run(g, t, dir_if_plain, damping, dangling, rank_in, rank_out, iters, stream, nullptr, -1, &buf);
+  return e == hipSuccess ? GC_OK : hip_fail(e, "pagerank_iter_noalloc");
 }
 
 int pagerank_learned(gc_graph g, float damping, int32_t dangling, const float* rank_in, float* rank_out,
