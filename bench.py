@@ -647,7 +647,7 @@ def main():
     ap.add_argument("--traversal-merge-range", type=int, default=16384)
     ap.add_argument("--wide-merge-range", type=int, default=4096,
                     help="merge range of partitions wider than 2^15 (push, sweep, ladder, SpMV, BC)")
-    ap.add_argument("--push-block-width", type=int, default=1 << 13,
+    ap.add_argument("--push-block-width", type=int, default=1 << 14,
                     help="TOCAB push block width (up to 2^14: the block's FP64 sums in LDS)")
     ap.add_argument("--forms", default="tocab_pull,plain_pull,tocab_push,plain_push",
                     help="comma list; the first is the headline")

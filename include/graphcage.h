@@ -117,6 +117,12 @@ int graph_free(gc_graph g);
  * merge_range k: power of two in [256, 16384], width of the merge ranges of
  * Figure 5 (0 = 4096, or the autotuned value when W = 0). Inside block s only rows with at least one arc there
  * get a local id, in ascending global order; id_map maps local to global.
+ * A GC_PUSH partition with W <= 2^14 and k <= W (its block sums fit in LDS)
+ * also holds the expanded-contribution form its PageRank iterations use:
+ * the local rows in source-major order (int32 + uint16 per row), two FP32
+ * buffers of one contribution per local row (written each iteration by the
+ * work-group that updates the row's source), and the arcs as streams (16-bit
+ * destination offsets, one head bit per arc): about 14P + 2.25m more bytes.
  * Synchronises `stream` once (it sizes its buffers). Free with tocab_free. */
 int tocab_partition(gc_graph g, int32_t dir, int32_t block_width, int32_t merge_range,
                     hipStream_t stream, gc_tocab* out);
@@ -198,7 +204,10 @@ int pagerank_iter(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, i
  * hook, or any library routine that allocates). Every call on one GPU shares that GPU's array, and the
  * array keeps the last call's contents: calls that overlap on one GPU (on
  * different streams or from different host threads) race and give wrong
- * results; serialise them. Errors otherwise as pagerank_iter. */
+ * results; serialise them. A GC_PUSH partition's expanded contributions
+ * (see tocab_partition) stay in the partition, which holds them from its
+ * construction: calls over one partition also race with each other.
+ * Errors otherwise as pagerank_iter. */
 int pagerank_iter_noalloc(gc_graph g, gc_tocab t, int32_t dir_if_plain, float damping, int32_t dangling,
                           const float* rank_in, float* rank_out, int32_t iters, hipStream_t stream);
 

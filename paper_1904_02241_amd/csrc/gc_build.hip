@@ -743,6 +743,90 @@ hipError_t build_lds_stream(gc_tocab t, hipStream_t s) {
   return hipStreamSynchronize(s);  // host vectors and Bufs are released on return
 }
 
+// ---- expanded contributions of the TOCAB push ----
+// A push block's local rows (source u, block b) are ordered by source, so
+// the rows of every block whose source lies in source block s (the W
+// sources [sW, (s+1)W)) form one run per block, bounded by the range table
+// at the merge ranges s W/k and (s+1) W/k. Listing those runs block after
+// block gives the source-major order of all local rows: the work-group
+// that has just updated the vertices of source block s holds their new
+// contributions and writes them to every local row of theirs with one pass
+// over that list.
+
+// cnt[s*B + b] = local rows of block b whose source lies in source block s.
+__global__ void k_push_run_counts(const int32_t* __restrict__ range_ptr, int32_t B, int32_t R, int32_t S,
+                                  int32_t shift, int32_t* __restrict__ cnt) {
+  const int64_t total = static_cast<int64_t>(S) * B;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int64_t s = i / B, b = i - s * B;
+    const int64_t j0 = s << shift, j1 = min<int64_t>(R, (s + 1) << shift);
+    cnt[i] = range_ptr[j1 * B + b] - range_ptr[j0 * B + b];
+  }
+}
+
+// Source-major position q of every local row: xperm[q] = the row, xid16[q]
+// = its source's offset inside the source block; xstart[s] = base[s*B].
+__global__ void k_push_perm(const int32_t* __restrict__ range_ptr, const int32_t* __restrict__ base,
+                            const int32_t* __restrict__ id_map, int32_t B, int32_t S, int32_t shift,
+                            int32_t wmask, int32_t* __restrict__ xperm, uint16_t* __restrict__ xid16,
+                            int32_t* __restrict__ xstart) {
+  const int64_t total = static_cast<int64_t>(S) * B;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int64_t s = i / B, b = i - s * B;
+    const int32_t st = range_ptr[(s << shift) * B + b];
+    const int32_t q0 = base[i], len = base[i + 1] - q0;
+    for (int32_t k = 0; k < len; ++k) {
+      xperm[q0 + k] = st + k;
+      xid16[q0 + k] = static_cast<uint16_t>(id_map[st + k] & wmask);
+    }
+    if (b == 0) xstart[s] = q0;
+    if (i == 0) xstart[S] = base[total];
+  }
+}
+
+// Builds t's source-major order and its two buffers of expanded
+// contributions (GC_PUSH partitions whose block sums fit in LDS).
+hipError_t build_push_expand(gc_tocab t, hipStream_t s) {
+  const int32_t B = t->B, R = t->R;
+  const int32_t S = static_cast<int32_t>((static_cast<int64_t>(t->n_rows) + t->W - 1) >> t->log2W);
+  const int32_t shift = t->log2W - t->log2k;
+  const int64_t SB = static_cast<int64_t>(S) * B;
+  const size_t Pn = static_cast<size_t>(std::max<int64_t>(t->P, 1));
+  Buf cnt(sizeof(int32_t) * SB, s), base(sizeof(int32_t) * (SB + 1), s);
+  if (!cnt.p || !base.p) return hipErrorOutOfMemory;
+  k_push_run_counts<<<grid_for(SB, 256, 65536), 256, 0, s>>>(t->range_ptr, B, R, S, shift, cnt.as<int32_t>());
+  GC_HIP_TRY(hipGetLastError());
+  GC_HIP_TRY(scan_exclusive(cnt.as<int32_t>(), base.as<int32_t>(), SB, s));
+  t->xperm = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * Pn, s));
+  t->xid16 = static_cast<uint16_t*>(dev_alloc(sizeof(uint16_t) * Pn, s));
+  t->xstart = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * (S + 1), s));
+  t->xc = static_cast<float*>(dev_alloc(sizeof(float) * 2 * Pn, s));
+  if (!t->xperm || !t->xid16 || !t->xstart || !t->xc) return hipErrorOutOfMemory;
+  t->n_sblk = S;
+  t->bytes += static_cast<int64_t>(Pn) * (4 + 2 + 8) + 4 * (S + 1);
+  k_push_perm<<<grid_for(SB, 256, 65536), 256, 0, s>>>(t->range_ptr, base.as<int32_t>(), t->id_map, B, S, shift,
+                                                       t->W - 1, t->xperm, t->xid16, t->xstart);
+  GC_HIP_TRY(hipGetLastError());
+  // the arc streams: destination offsets and head bits
+  const int64_t m = t->m, tile = wave_tile_arcs();
+  t->pm_pad = (m / tile + 2) * tile;
+  const int64_t words = t->pm_pad / 64 + 1;
+  t->pcol16 = static_cast<uint16_t*>(dev_alloc(sizeof(uint16_t) * t->pm_pad, s));
+  t->pheads = static_cast<gc_head_word*>(dev_alloc(sizeof(gc_head_word) * words, s));
+  if (!t->pcol16 || !t->pheads) return hipErrorOutOfMemory;
+  t->bytes += static_cast<int64_t>(sizeof(uint16_t)) * t->pm_pad + 16 * words;
+  GC_HIP_TRY(hipMemsetAsync(t->pcol16, 0, sizeof(uint16_t) * t->pm_pad, s));
+  GC_HIP_TRY(hipMemsetAsync(t->pheads, 0, sizeof(gc_head_word) * words, s));
+  if (m > 0) k_col16<<<grid_for(m, 256, 65536), 256, 0, s>>>(t->col, m, t->W - 1, t->pcol16);
+  k_heads_set<<<grid_for(t->P, 256, 65536), 256, 0, s>>>(t->row_ptr, t->P, t->pheads);
+  k_heads_finish<<<grid_for(words, 256, 65536), 256, 0, s>>>(t->row_ptr, t->P, m, words, t->pheads);
+  k_heads_next<<<grid_for(words, 256, 65536), 256, 0, s>>>(words, t->pheads);
+  GC_HIP_TRY(hipGetLastError());
+  return hipStreamSynchronize(s);  // the Bufs are released on return
+}
+
 hipError_t build_partition(gc_tocab t, const int32_t* a_rowptr, const int32_t* a_col, const int32_t* a_w,
                            hipStream_t s) {
   const int32_t B = t->B, R = t->R;
@@ -806,6 +890,9 @@ hipError_t build_partition(gc_tocab t, const int32_t* a_rowptr, const int32_t* a
   if (t->dir == GC_PULL && t->W <= kLdsMaxWidth && static_cast<int64_t>(B) * (R + 1) <= (int64_t(1) << 25) &&
       t->m + 1024 < INT32_MAX && 4 * (P + 8) < (int64_t(1) << 31))
     GC_HIP_TRY(build_lds_stream(t, s));
+  if (t->dir == GC_PUSH && t->W <= kPushLdsMaxWidth && t->k <= t->W && P > 0 && t->m + 1024 < INT32_MAX &&
+      static_cast<int64_t>(B) * ((static_cast<int64_t>(t->n_rows) + t->W - 1) >> t->log2W) <= (int64_t(1) << 26))
+    GC_HIP_TRY(build_push_expand(t, s));
   return hipStreamSynchronize(s);
 }
 

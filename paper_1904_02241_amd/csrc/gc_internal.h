@@ -120,6 +120,23 @@ struct gc_tocab_s {
   double* bc_part = nullptr;      // [P] BC path-count partials (allocated on first use)
   float* val32 = nullptr;         // [m_pad] FP32 arc values in stream order (first valued SpMV)
   int32_t* w_pad = nullptr;       // [m_pad] integer weights in stream order, 0 past m (first SSSP over the stream layout)
+  // Expanded contributions of a GC_PUSH partition with block sums in LDS
+  // (W <= kPushLdsMaxWidth): its local rows in source-major order (source
+  // block, then block, then source), so that the work-group updating source
+  // block s writes the new contribution of each of its rows to xc with one
+  // pass over [xstart[s], xstart[s+1]).
+  int32_t* xperm = nullptr;       // [P] local row at each source-major position
+  uint16_t* xid16 = nullptr;      // [P] that row's source, offset inside its source block
+  int32_t* xstart = nullptr;      // [n_sblk+1] first source-major position of each source block
+  float* xc = nullptr;            // [2P] contribution of each local row's source, two iterates in turn
+  int32_t n_sblk = 0;             // source blocks (ceil(rows / W)); 0 without the expanded form
+  // ... and its arcs as streams: destination offsets inside the block (16
+  // bits) and one head bit per arc marking the first arc of each local row
+  // (the head word layout of the pull's stream layout), padded to whole
+  // 512-arc tiles.
+  uint16_t* pcol16 = nullptr;     // [pm_pad], zero past m
+  gc_head_word* pheads = nullptr; // [pm_pad/64 + 1], bits at and past m set
+  int64_t pm_pad = 0;
   int64_t bytes = 0;
 };
 
@@ -168,6 +185,8 @@ int32_t pull_tile_arcs();
 int32_t wave_tile_arcs();
 // Largest block width whose FP32 contribution slice is staged in LDS.
 constexpr int32_t kLdsMaxWidth = 1 << 15;
+// Largest block width of a TOCAB push whose block sums (FP64) sit in LDS.
+constexpr int32_t kPushLdsMaxWidth = 1 << 14;
 // Smallest number of arcs per chunk of an LDS-resident block (one work-group each).
 constexpr int32_t kLdsChunkArcs = 1 << 16;
 // LDS bytes one work-group of the LDS-resident pull may use: half a CU's

@@ -793,7 +793,6 @@ __global__ __launch_bounds__(kThreads) void k_pr_push(const int32_t* __restrict_
   }
 }
 
-// Update after a push pass; clears sums for the next pass.
 // Algorithm 5 with the destination block's sums in LDS: in a push partition
 // block s holds every arc into destinations [sW, (s+1)W), so work-group s
 // adds each of its local rows' contribution c[id_map[l]] into FP64 LDS sums
@@ -801,7 +800,8 @@ __global__ __launch_bounds__(kThreads) void k_pr_push(const int32_t* __restrict_
 // range itself: no global atomics and no separate apply pass. A thread takes
 // whole rows (a (source, block) pair holds few arcs). c is read from one
 // buffer and the next iteration's contributions go to u.contrib, another.
-constexpr int32_t kPushLdsMaxWidth = 1 << 14;
+// (Form used for partitions without the expanded contributions below.)
+using gcx::kPushLdsMaxWidth;
 constexpr int kPushLdsThreads = 1024;
 
 __global__ __launch_bounds__(kPushLdsThreads) void k_pr_push_lds(const int32_t* __restrict__ blk_rowoff,
@@ -852,6 +852,130 @@ __global__ __launch_bounds__(kPushLdsThreads) void k_pr_push_lds(const int32_t* 
     if (v < u.n) mine += update_vertex(u, v, acc[i], D, dl);
   }
   publish_update<kPushLdsThreads>(u, mine, dl);
+}
+
+// The TOCAB push with expanded contributions. Reading c[id_map[l]] for
+// every local row l is a random 4-byte read per row, and on this GPU each
+// one moves a whole cache line from the Infinity Cache or HBM (about 120
+// bytes per row measured at R-MAT 24): the push spent its time there, not
+// in its LDS atomics. Instead every row's contribution sits at xc[l], in row
+// order, written by the work-group that produced it: after updating the
+// vertices of its block (source block s = destination block s), a
+// work-group keeps their new contributions in LDS and walks the
+// source-major list of the rows whose source lies in the block, writing
+// each row's value (runs of consecutive rows per destination block).
+
+// xc_out[xperm[q]] = cs[xid16[q]] for the source-major positions q of
+// source block s (cs: that block's contributions, in LDS).
+template <int NT>
+__device__ __forceinline__ void push_expand(const int32_t* __restrict__ xstart, const int32_t* __restrict__ xperm,
+                                            const uint16_t* __restrict__ xid16, int32_t s, const float* cs,
+                                            float* __restrict__ xc_out) {
+  const int32_t q0 = xstart[s], q1 = xstart[s + 1];
+  constexpr int kU = 4;  // positions per thread and step, loads issued together
+  for (int32_t q = q0 + static_cast<int32_t>(threadIdx.x); q < q1; q += kU * NT) {
+    int32_t r[kU];
+    uint32_t o[kU];
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      const int32_t qq = min(q + k * NT, q1 - 1);
+      r[k] = gcd::ld_stream(xperm + qq);
+      o[k] = gcd::ld_stream(xid16 + qq);
+    }
+#pragma unroll
+    for (int k = 0; k < kU; ++k)
+      if (q + k * NT < q1) xc_out[r[k]] = cs[o[k]];
+  }
+}
+
+// The expanded contributions of the starting vector: work-group s stages
+// c[sW, sW + W) in LDS and writes them to the rows of source block s.
+__global__ __launch_bounds__(kPushLdsThreads) void k_pr_push_expand(const int32_t* __restrict__ xstart,
+                                                                    const int32_t* __restrict__ xperm,
+                                                                    const uint16_t* __restrict__ xid16,
+                                                                    int32_t log2W, int32_t n,
+                                                                    const float* __restrict__ c,
+                                                                    float* __restrict__ xc_out) {
+  extern __shared__ float cs[];
+  const int32_t v0 = static_cast<int32_t>(blockIdx.x) << log2W;
+  const int32_t cnt = min(1 << log2W, n - v0);
+  for (int32_t i = threadIdx.x; i < cnt; i += kPushLdsThreads) cs[i] = c[v0 + i];
+  __syncthreads();
+  push_expand<kPushLdsThreads>(xstart, xperm, xid16, blockIdx.x, cs, xc_out);
+}
+
+// One iteration of the TOCAB push over expanded contributions: block s's
+// sums in FP64 LDS, then the update of its W vertices, then their
+// contributions expanded into xc_out. The sums walk the block's arcs as
+// streams, 512-arc tiles per wave (8 consecutive arcs per lane): an arc's
+// destination offset comes from the 16-bit column stream, its local row from
+// the head bits (rows starting before the arc, counted with popcounts of the
+// tile's head words), and the row's contribution from xc_in (neighbouring
+// arcs read neighbouring rows, so these loads stay in cache). One thread per
+// local row instead would serialise the arcs of long rows (a source with
+// many arcs into the block) behind one lane while the rest of its wave waits.
+__global__ __launch_bounds__(kPushLdsThreads) void k_pr_push_lds_x(
+    const int32_t* __restrict__ blk_rowoff, const int32_t* __restrict__ row_ptr,
+    const uint16_t* __restrict__ pcol16, const gc_head_word* __restrict__ pheads, int32_t log2W,
+    const float* __restrict__ xc_in, const int32_t* __restrict__ xstart, const int32_t* __restrict__ xperm,
+    const uint16_t* __restrict__ xid16, float* __restrict__ xc_out, Update u) {
+  extern __shared__ double acc[];  // the block's W sums, then (as FP32) its W new contributions
+  constexpr int kPer = kPushLdsMaxWidth / kPushLdsThreads;
+  constexpr int kWaves = kPushLdsThreads / kWave;
+  const int32_t W = 1 << log2W;
+  const int32_t v0 = static_cast<int32_t>(blockIdx.x) << log2W;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t wid = __builtin_amdgcn_readfirstlane(static_cast<int32_t>(threadIdx.x) / kWave);
+  for (int32_t i = threadIdx.x; i < W; i += kPushLdsThreads) acc[i] = 0.0;
+  __syncthreads();
+  const int32_t r0 = blk_rowoff[blockIdx.x], r1 = blk_rowoff[blockIdx.x + 1];
+  const int32_t A0 = row_ptr[r0], A1 = row_ptr[r1];  // the block's arcs
+  if (A1 > A0) {  // uniform
+    const int32_t q1 = (A1 - 1) / kWaveTile;
+    const int sub = lane & 7;  // this lane's 8 arcs are bits 8 sub .. 8 sub + 7 of its head word
+    int32_t q = A0 / kWaveTile + wid;
+    WaveTile cur = load_wave_tile<false>(pcol16, pheads, nullptr, min(q, q1), lane);
+    for (; q <= q1; q += kWaves) {
+      const uint64_t bits = word_bits(cur.hw);
+      const uint32_t my8 = static_cast<uint32_t>(bits >> (8 * sub)) & 0xFFu;
+      // the row of arc e: rows starting at or before it, minus one
+      const int32_t base = static_cast<int32_t>(cur.hw[2]) - 1 + __popcll(bits & ((1ull << (8 * sub)) - 1ull));
+      const int32_t a0 = q * kWaveTile + kArcsPerLane * lane;
+      float x[kArcsPerLane];
+      uint32_t d[kArcsPerLane];
+#pragma unroll
+      for (int e = 0; e < kArcsPerLane; ++e) {
+        const bool ok = a0 + e >= A0 && a0 + e < A1;
+        const int32_t row = ok ? base + __popc(my8 & ((2u << e) - 1u)) : r0;
+        x[e] = xc_in[row];
+        d[e] = ok ? (cur.cols[e >> 1] >> (16 * (e & 1))) & 0xFFFFu : 0xFFFFFFFFu;
+      }
+      cur = load_wave_tile<false>(pcol16, pheads, nullptr, min(q + kWaves, q1), lane);
+#pragma unroll
+      for (int e = 0; e < kArcsPerLane; ++e)
+        if (d[e] != 0xFFFFFFFFu) atomicAdd(&acc[d[e]], static_cast<double>(x[e]));
+    }
+  }
+  __syncthreads();
+  const double D = *u.dtotal_in;
+  double mine = 0.0, dl = 0.0;
+  float cv[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int32_t i = threadIdx.x + k * kPushLdsThreads;
+    cv[k] = 0.0f;
+    if (i < W && v0 + i < u.n) mine += update_vertex(u, v0 + i, acc[i], D, dl, cv[k]);
+  }
+  __syncthreads();  // every sum has been read: the LDS now holds the contributions
+  float* cs = reinterpret_cast<float*>(acc);
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int32_t i = threadIdx.x + k * kPushLdsThreads;
+    if (i < W) cs[i] = cv[k];
+  }
+  __syncthreads();
+  publish_update<kPushLdsThreads>(u, mine, dl);
+  push_expand<kPushLdsThreads>(xstart, xperm, xid16, blockIdx.x, cs, xc_out);
 }
 
 __global__ __launch_bounds__(kThreads) void k_pr_apply(double* __restrict__ sums, Update u) {
@@ -949,6 +1073,12 @@ hipError_t pagerank_setup() {
   GC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_push_lds),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  static_cast<int>(sizeof(double)) * kPushLdsMaxWidth));
+  GC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_push_lds_x),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 static_cast<int>(sizeof(double)) * kPushLdsMaxWidth));
+  GC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_push_expand),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 static_cast<int>(sizeof(float)) * kPushLdsMaxWidth));
   GC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_tocab_pull_lds<false>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds_budget(kLdsMaxWidth)));
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_tocab_pull_lds<true>),
@@ -1165,9 +1295,13 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
   // contributions of rank_in and D of iteration 0 -> dtotal[0]
   u.dtotal_in = nullptr;
   u.contrib = buf.contrib[0];
+  const bool expanded = push && t && t->W <= kPushLdsMaxWidth && t->xc;
   {
     ProfScope prof("pr_init", s);
-    k_pr_init<<<vgrid, kThreads, 0, s>>>(rank_in, u, push ? buf.sums : nullptr);
+    k_pr_init<<<vgrid, kThreads, 0, s>>>(rank_in, u, push && !expanded ? buf.sums : nullptr);
+    if (expanded)
+      k_pr_push_expand<<<t->n_sblk, kPushLdsThreads, sizeof(float) * static_cast<size_t>(t->W), s>>>(
+          t->xstart, t->xperm, t->xid16, t->log2W, n, buf.contrib[0], t->xc);
   }
   k_reduce_dangling<<<1, 1024, 0, s>>>(buf.dpart, vgrid, buf.dtotal, nullptr, nullptr);
   GC_HIP_TRY(hipGetLastError());
@@ -1238,6 +1372,14 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
       k_pr_plain_pull<<<g->n_tiles_in, kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, g->tile_row_in,
                                                          buf.contrib[cur], u);
       cur ^= 1;
+    } else if (expanded) {
+      u.contrib = nullptr;  // the contributions go to the rows' expanded copies only
+      parts = t->B;
+      ProfScope prof("pr_tocab_push", s);
+      const int64_t P = t->P;
+      k_pr_push_lds_x<<<t->B, kPushLdsThreads, sizeof(double) * static_cast<size_t>(t->W), s>>>(
+          t->blk_rowoff, t->row_ptr, t->pcol16, t->pheads, t->log2W, t->xc + (it & 1) * P, t->xstart, t->xperm,
+          t->xid16, t->xc + ((it + 1) & 1) * P, u);
     } else if (t && t->W <= kPushLdsMaxWidth) {
       u.contrib = buf.contrib[cur ^ 1];
       parts = t->B;

@@ -42,14 +42,23 @@ struct Update {
 // returns r'[v] when v has no out-arcs (its share of the next D), else 0.
 // In convergence mode also adds |r'[v] - r[v]| (FP64 over the FP32
 // iterates) to dl.
-__device__ __forceinline__ double update_vertex(const Update& u, int32_t v, double sum, double D, double& dl) {
+// The new contribution is also returned in cv (u.contrib may be null when
+// the caller keeps it elsewhere).
+__device__ __forceinline__ double update_vertex(const Update& u, int32_t v, double sum, double D, double& dl,
+                                                float& cv) {
   const double r = u.base + u.d * (sum + D * u.inv_n);
   const float r32 = static_cast<float>(r);
   const int32_t deg = u.rowptr[v + 1] - u.rowptr[v];
-  u.contrib[v] = deg ? static_cast<float>(static_cast<double>(r32) / deg) : 0.0f;
+  cv = deg ? static_cast<float>(static_cast<double>(r32) / deg) : 0.0f;
+  if (u.contrib) u.contrib[v] = cv;
   if (u.rank_out) u.rank_out[v] = r32;
   if (u.rank_prev) dl += fabs(static_cast<double>(r32) - static_cast<double>(u.rank_prev[v]));
   return deg ? 0.0 : static_cast<double>(r32);
+}
+
+__device__ __forceinline__ double update_vertex(const Update& u, int32_t v, double sum, double D, double& dl) {
+  float cv;
+  return update_vertex(u, v, sum, D, dl, cv);
 }
 
 __device__ __forceinline__ double update_vertex(const Update& u, int32_t v, double sum, double D) {

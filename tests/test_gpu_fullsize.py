@@ -45,6 +45,7 @@ def rmat24_pagerank(rmat24):
 @pytest.mark.parametrize("form,W,k", [("tocab_pull", BENCH_W, BENCH_K), ("tocab_pull", 1 << 14, 8192),
                                       ("tocab_pull", 1 << 18, 4096), ("plain_pull", 1 << 10, 256),
                                       ("tocab_push", PUSH_W, TRAV_K), ("tocab_push", 1 << 14, 16384),
+                                      ("tocab_push", 1 << 13, 4096),
                                       ("plain_push", 1 << 10, 256)])
 def test_rmat24_pagerank_20_iterations(rmat24, rmat24_pagerank, form, W, k):
     g = rmat24
