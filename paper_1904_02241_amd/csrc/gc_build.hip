@@ -745,13 +745,16 @@ hipError_t build_lds_stream(gc_tocab t, hipStream_t s) {
 
 // ---- expanded contributions of the TOCAB push ----
 // A push block's local rows (source u, block b) are ordered by source, so
-// the rows of every block whose source lies in source block s (the W
-// sources [sW, (s+1)W)) form one run per block, bounded by the range table
-// at the merge ranges s W/k and (s+1) W/k. Listing those runs block after
-// block gives the source-major order of all local rows: the work-group
-// that has just updated the vertices of source block s holds their new
-// contributions and writes them to every local row of theirs with one pass
-// over that list.
+// the rows of block b whose source lies in source block s (the W sources
+// [sW, (s+1)W)) are one run, bounded by the range table at the merge
+// ranges s W/k and (s+1) W/k. The work-group that has just updated the
+// vertices of source block s holds their new contributions and writes them
+// to each of those B runs. Long runs (128 rows or more on average) are
+// walked in place, with xid16[l] = the source of row l as an offset inside
+// its source block. Short ones are listed block after block per source
+// block (the source-major order): xperm[q] is the row at position q,
+// xid16[q] its source offset, xstart[s] the first position of source
+// block s.
 
 // cnt[s*B + b] = local rows of block b whose source lies in source block s.
 __global__ void k_push_run_counts(const int32_t* __restrict__ range_ptr, int32_t B, int32_t R, int32_t S,
@@ -765,8 +768,7 @@ __global__ void k_push_run_counts(const int32_t* __restrict__ range_ptr, int32_t
   }
 }
 
-// Source-major position q of every local row: xperm[q] = the row, xid16[q]
-// = its source's offset inside the source block; xstart[s] = base[s*B].
+// Source-major position of every local row (base: exclusive scan of cnt).
 __global__ void k_push_perm(const int32_t* __restrict__ range_ptr, const int32_t* __restrict__ base,
                             const int32_t* __restrict__ id_map, int32_t B, int32_t S, int32_t shift,
                             int32_t wmask, int32_t* __restrict__ xperm, uint16_t* __restrict__ xid16,
@@ -786,29 +788,39 @@ __global__ void k_push_perm(const int32_t* __restrict__ range_ptr, const int32_t
   }
 }
 
-// Builds t's source-major order and its two buffers of expanded
-// contributions (GC_PUSH partitions whose block sums fit in LDS).
+// Builds t's expanded-contribution form (GC_PUSH partitions whose block
+// sums fit in LDS).
 hipError_t build_push_expand(gc_tocab t, hipStream_t s) {
   const int32_t B = t->B, R = t->R;
   const int32_t S = static_cast<int32_t>((static_cast<int64_t>(t->n_rows) + t->W - 1) >> t->log2W);
-  const int32_t shift = t->log2W - t->log2k;
   const int64_t SB = static_cast<int64_t>(S) * B;
   const size_t Pn = static_cast<size_t>(std::max<int64_t>(t->P, 1));
-  Buf cnt(sizeof(int32_t) * SB, s), base(sizeof(int32_t) * (SB + 1), s);
-  if (!cnt.p || !base.p) return hipErrorOutOfMemory;
-  k_push_run_counts<<<grid_for(SB, 256, 65536), 256, 0, s>>>(t->range_ptr, B, R, S, shift, cnt.as<int32_t>());
-  GC_HIP_TRY(hipGetLastError());
-  GC_HIP_TRY(scan_exclusive(cnt.as<int32_t>(), base.as<int32_t>(), SB, s));
-  t->xperm = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * Pn, s));
-  t->xid16 = static_cast<uint16_t*>(dev_alloc(sizeof(uint16_t) * Pn, s));
-  t->xstart = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * (S + 1), s));
-  t->xc = static_cast<float*>(dev_alloc(sizeof(float) * 2 * Pn, s));
-  if (!t->xperm || !t->xid16 || !t->xstart || !t->xc) return hipErrorOutOfMemory;
   t->n_sblk = S;
-  t->bytes += static_cast<int64_t>(Pn) * (4 + 2 + 8) + 4 * (S + 1);
-  k_push_perm<<<grid_for(SB, 256, 65536), 256, 0, s>>>(t->range_ptr, base.as<int32_t>(), t->id_map, B, S, shift,
-                                                       t->W - 1, t->xperm, t->xid16, t->xstart);
-  GC_HIP_TRY(hipGetLastError());
+  // padded so that the 8-byte read of the last group of four rows stays inside
+  t->xid16 = static_cast<uint16_t*>(dev_alloc(sizeof(uint16_t) * (Pn + 8), s));
+  t->xc = static_cast<float*>(dev_alloc(sizeof(float) * 2 * push_xc_stride(t->P), s));
+  if (!t->xid16 || !t->xc) return hipErrorOutOfMemory;
+  t->bytes += static_cast<int64_t>(Pn) * 2 + 16 + 8 * push_xc_stride(t->P);
+  GC_HIP_TRY(hipMemsetAsync(t->xid16, 0, sizeof(uint16_t) * (Pn + 8), s));
+  if (t->P >= kPushLongRun * SB) {
+    k_col16<<<grid_for(t->P, 256, 65536), 256, 0, s>>>(t->id_map, t->P, t->W - 1, t->xid16);
+    GC_HIP_TRY(hipGetLastError());
+  } else {
+    const int32_t shift = t->log2W - t->log2k;
+    Buf cnt(sizeof(int32_t) * SB, s), base(sizeof(int32_t) * (SB + 1), s);
+    if (!cnt.p || !base.p) return hipErrorOutOfMemory;
+    k_push_run_counts<<<grid_for(SB, 256, 65536), 256, 0, s>>>(t->range_ptr, B, R, S, shift, cnt.as<int32_t>());
+    GC_HIP_TRY(hipGetLastError());
+    GC_HIP_TRY(scan_exclusive(cnt.as<int32_t>(), base.as<int32_t>(), SB, s));
+    t->xperm = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * Pn, s));
+    t->xstart = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * (S + 1), s));
+    if (!t->xperm || !t->xstart) return hipErrorOutOfMemory;
+    t->bytes += static_cast<int64_t>(Pn) * 4 + 4 * (S + 1);
+    k_push_perm<<<grid_for(SB, 256, 65536), 256, 0, s>>>(t->range_ptr, base.as<int32_t>(), t->id_map, B, S, shift,
+                                                         t->W - 1, t->xperm, t->xid16, t->xstart);
+    GC_HIP_TRY(hipGetLastError());
+    GC_HIP_TRY(hipStreamSynchronize(s));  // before the Bufs are released
+  }
   // the arc streams: destination offsets and head bits
   const int64_t m = t->m, tile = wave_tile_arcs();
   t->pm_pad = (m / tile + 2) * tile;
@@ -891,7 +903,7 @@ hipError_t build_partition(gc_tocab t, const int32_t* a_rowptr, const int32_t* a
       t->m + 1024 < INT32_MAX && 4 * (P + 8) < (int64_t(1) << 31))
     GC_HIP_TRY(build_lds_stream(t, s));
   if (t->dir == GC_PUSH && t->W <= kPushLdsMaxWidth && t->k <= t->W && P > 0 && t->m + 1024 < INT32_MAX &&
-      static_cast<int64_t>(B) * ((static_cast<int64_t>(t->n_rows) + t->W - 1) >> t->log2W) <= (int64_t(1) << 26))
+      B <= kPushExpandMaxBlocks)
     GC_HIP_TRY(build_push_expand(t, s));
   return hipStreamSynchronize(s);
 }

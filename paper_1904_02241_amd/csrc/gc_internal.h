@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -121,13 +122,13 @@ struct gc_tocab_s {
   float* val32 = nullptr;         // [m_pad] FP32 arc values in stream order (first valued SpMV)
   int32_t* w_pad = nullptr;       // [m_pad] integer weights in stream order, 0 past m (first SSSP over the stream layout)
   // Expanded contributions of a GC_PUSH partition with block sums in LDS
-  // (W <= kPushLdsMaxWidth): its local rows in source-major order (source
-  // block, then block, then source), so that the work-group updating source
-  // block s writes the new contribution of each of its rows to xc with one
-  // pass over [xstart[s], xstart[s+1]).
-  int32_t* xperm = nullptr;       // [P] local row at each source-major position
-  uint16_t* xid16 = nullptr;      // [P] that row's source, offset inside its source block
-  int32_t* xstart = nullptr;      // [n_sblk+1] first source-major position of each source block
+  // (W <= kPushLdsMaxWidth, B <= kPushExpandMaxBlocks): the work-group that
+  // updates source block s writes the new contribution of each local row
+  // whose source lies in it (block b's rows [range_ptr[j0 B + b],
+  // range_ptr[j1 B + b]) for the merge ranges j0 .. j1 of the block) to xc.
+  uint16_t* xid16 = nullptr;      // [P + 8] source of each local row (source-major when xperm is set), offset inside its source block
+  int32_t* xperm = nullptr;       // [P] short runs only: the local row at each source-major position
+  int32_t* xstart = nullptr;      // [n_sblk + 1] short runs only: first source-major position of each source block
   float* xc = nullptr;            // [2P] contribution of each local row's source, two iterates in turn
   int32_t n_sblk = 0;             // source blocks (ceil(rows / W)); 0 without the expanded form
   // ... and its arcs as streams: destination offsets inside the block (16
@@ -187,6 +188,15 @@ int32_t wave_tile_arcs();
 constexpr int32_t kLdsMaxWidth = 1 << 15;
 // Largest block width of a TOCAB push whose block sums (FP64) sit in LDS.
 constexpr int32_t kPushLdsMaxWidth = 1 << 14;
+// Most blocks of a push partition with expanded contributions (a work-group
+// keeps two run bounds per block in LDS).
+constexpr int32_t kPushExpandMaxBlocks = 4096;
+// Average run length (local rows per (source block, block) pair) from which
+// the expanded push walks its runs in place rather than through a
+// source-major list.
+constexpr int64_t kPushLongRun = 128;
+// Offset of the second buffer of expanded contributions (16-byte aligned).
+inline int64_t push_xc_stride(int64_t P) { return (std::max<int64_t>(P, 1) + 3) & ~int64_t(3); }
 // Smallest number of arcs per chunk of an LDS-resident block (one work-group each).
 constexpr int32_t kLdsChunkArcs = 1 << 16;
 // LDS bytes one work-group of the LDS-resident pull may use: half a CU's

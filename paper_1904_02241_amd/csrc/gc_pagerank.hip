@@ -861,47 +861,126 @@ __global__ __launch_bounds__(kPushLdsThreads) void k_pr_push_lds(const int32_t* 
 // in its LDS atomics. Instead every row's contribution sits at xc[l], in row
 // order, written by the work-group that produced it: after updating the
 // vertices of its block (source block s = destination block s), a
-// work-group keeps their new contributions in LDS and walks the
-// source-major list of the rows whose source lies in the block, writing
-// each row's value (runs of consecutive rows per destination block).
+// work-group keeps their new contributions in LDS and writes them to the
+// run of rows in every block whose source lies in block s.
 
-// xc_out[xperm[q]] = cs[xid16[q]] for the source-major positions q of
-// source block s (cs: that block's contributions, in LDS).
-template <int NT>
-__device__ __forceinline__ void push_expand(const int32_t* __restrict__ xstart, const int32_t* __restrict__ xperm,
-                                            const uint16_t* __restrict__ xid16, int32_t s, const float* cs,
-                                            float* __restrict__ xc_out) {
-  const int32_t q0 = xstart[s], q1 = xstart[s + 1];
-  constexpr int kU = 4;  // positions per thread and step, loads issued together
-  for (int32_t q = q0 + static_cast<int32_t>(threadIdx.x); q < q1; q += kU * NT) {
-    int32_t r[kU];
-    uint32_t o[kU];
+// Where the expanded contributions go (see gc_tocab_s): the range table,
+// the rows' source offsets and, for short runs, the source-major list.
+struct PushX {
+  const int32_t* range_ptr;
+  int32_t B, R, shift;  // shift = log2(W / k)
+  const uint16_t* xid16;
+  const int32_t* xperm;   // null: long runs, walked in place
+  const int32_t* xstart;
+};
+
+// Contributions of rows r .. r + 3 (a group of four, 16-byte aligned)
+// inside the run [st, en): one 16-byte store when the group lies inside it.
+__device__ __forceinline__ void push_store4(float* __restrict__ xc_out, int32_t r, int32_t st, int32_t en,
+                                            uint64_t id, const float* cs) {
+  if (r >= st && r + 3 < en) {
+    f32x4 v;
 #pragma unroll
-    for (int k = 0; k < kU; ++k) {
-      const int32_t qq = min(q + k * NT, q1 - 1);
-      r[k] = gcd::ld_stream(xperm + qq);
-      o[k] = gcd::ld_stream(xid16 + qq);
-    }
+    for (int e = 0; e < 4; ++e) v[e] = cs[(id >> (16 * e)) & 0xFFFFu];
+    *reinterpret_cast<f32x4*>(xc_out + r) = v;
+  } else {
 #pragma unroll
-    for (int k = 0; k < kU; ++k)
-      if (q + k * NT < q1) xc_out[r[k]] = cs[o[k]];
+    for (int e = 0; e < 4; ++e)
+      if (r + e >= st && r + e < en) xc_out[r + e] = cs[(id >> (16 * e)) & 0xFFFFu];
   }
+}
+
+// Writes the contributions of source block s (cs: in LDS) to the rows of
+// every block whose source lies in it; tbl: LDS room for 2B int32.
+// Long runs: the run bounds go to LDS and a wave takes kU runs at a time,
+// its lanes side by side along each, rows in groups of four (one 8-byte
+// read of their offsets, one 16-byte store), so every lane keeps kU reads
+// in flight. Short runs: threads stride over the source-major list of the
+// block (a read of the row and of its offset per position).
+template <int NT>
+__device__ __forceinline__ void push_expand(const PushX& x, int32_t s, const float* cs, int32_t* tbl,
+                                            float* __restrict__ xc_out) {
+  constexpr int kWaves = NT / kWave, kU = 8;
+  if (x.xperm) {  // uniform
+    const int32_t q0 = x.xstart[s], q1 = x.xstart[s + 1];
+    constexpr int kV = 4;  // positions per thread and step, loads issued together
+    for (int32_t q = q0 + static_cast<int32_t>(threadIdx.x); q < q1; q += kV * NT) {
+      int32_t r[kV];
+      uint32_t o[kV];
+#pragma unroll
+      for (int k = 0; k < kV; ++k) {
+        const int32_t qq = min(q + k * NT, q1 - 1);
+        r[k] = gcd::ld_stream(x.xperm + qq);
+        o[k] = gcd::ld_stream(x.xid16 + qq);
+      }
+#pragma unroll
+      for (int k = 0; k < kV; ++k)
+        if (q + k * NT < q1) xc_out[r[k]] = cs[o[k]];
+    }
+    return;
+  }
+  const int32_t B = x.B;
+  int32_t* lo = tbl;
+  int32_t* hi = tbl + B;
+  {
+    const int64_t j0 = static_cast<int64_t>(s) << x.shift;
+    const int64_t j1 = min<int64_t>(x.R, (static_cast<int64_t>(s) + 1) << x.shift);
+    for (int32_t b = threadIdx.x; b < B; b += NT) {
+      lo[b] = x.range_ptr[j0 * B + b];
+      hi[b] = x.range_ptr[j1 * B + b];
+    }
+  }
+  __syncthreads();
+  const uint64_t* x4 = reinterpret_cast<const uint64_t*>(x.xid16);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t wid = __builtin_amdgcn_readfirstlane(static_cast<int32_t>(threadIdx.x) / kWave);
+  for (int32_t b0 = wid * kU; b0 < B; b0 += kWaves * kU) {  // uniform
+    int32_t g0[kU], st[kU], en[kU], ng[kU];
+    int32_t gmax = 0;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int32_t b = b0 + u;
+      st[u] = b < B ? lo[b] : 0;
+      en[u] = b < B ? hi[b] : 0;
+      g0[u] = st[u] >> 2;  // groups of four rows covering the run
+      ng[u] = en[u] > st[u] ? ((en[u] - 1) >> 2) - g0[u] + 1 : 0;
+      gmax = max(gmax, ng[u]);
+    }
+    for (int32_t k = 0; k < gmax; k += kWave) {  // uniform
+      uint64_t id[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) id[u] = gcd::ld_stream(x4 + g0[u] + min(k + lane, max(ng[u] - 1, 0)));
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (k + lane < ng[u]) push_store4(xc_out, 4 * (g0[u] + k + lane), st[u], en[u], id[u], cs);
+    }
+  }
+}
+
+PushX push_x(gc_tocab t) {
+  return PushX{t->range_ptr, t->B, t->R, t->log2W - t->log2k, t->xid16, t->xperm, t->xstart};
+}
+
+// Dynamic LDS of the expanded push kernels: the block's FP64 sums, or its
+// FP32 contributions followed by the run bounds of every block.
+__host__ __device__ constexpr size_t push_x_lds(int32_t W, int32_t B) {
+  return 8 * static_cast<size_t>(W) > 4 * static_cast<size_t>(W) + 8 * static_cast<size_t>(B)
+             ? 8 * static_cast<size_t>(W)
+             : 4 * static_cast<size_t>(W) + 8 * static_cast<size_t>(B);
 }
 
 // The expanded contributions of the starting vector: work-group s stages
 // c[sW, sW + W) in LDS and writes them to the rows of source block s.
-__global__ __launch_bounds__(kPushLdsThreads) void k_pr_push_expand(const int32_t* __restrict__ xstart,
-                                                                    const int32_t* __restrict__ xperm,
-                                                                    const uint16_t* __restrict__ xid16,
-                                                                    int32_t log2W, int32_t n,
+__global__ __launch_bounds__(kPushLdsThreads) void k_pr_push_expand(PushX x, int32_t log2W, int32_t n,
                                                                     const float* __restrict__ c,
                                                                     float* __restrict__ xc_out) {
   extern __shared__ float cs[];
+  const int32_t W = 1 << log2W;
   const int32_t v0 = static_cast<int32_t>(blockIdx.x) << log2W;
-  const int32_t cnt = min(1 << log2W, n - v0);
+  const int32_t cnt = min(W, n - v0);
   for (int32_t i = threadIdx.x; i < cnt; i += kPushLdsThreads) cs[i] = c[v0 + i];
   __syncthreads();
-  push_expand<kPushLdsThreads>(xstart, xperm, xid16, blockIdx.x, cs, xc_out);
+  push_expand<kPushLdsThreads>(x, blockIdx.x, cs, reinterpret_cast<int32_t*>(cs + W), xc_out);
 }
 
 // One iteration of the TOCAB push over expanded contributions: block s's
@@ -917,8 +996,7 @@ __global__ __launch_bounds__(kPushLdsThreads) void k_pr_push_expand(const int32_
 __global__ __launch_bounds__(kPushLdsThreads) void k_pr_push_lds_x(
     const int32_t* __restrict__ blk_rowoff, const int32_t* __restrict__ row_ptr,
     const uint16_t* __restrict__ pcol16, const gc_head_word* __restrict__ pheads, int32_t log2W,
-    const float* __restrict__ xc_in, const int32_t* __restrict__ xstart, const int32_t* __restrict__ xperm,
-    const uint16_t* __restrict__ xid16, float* __restrict__ xc_out, Update u) {
+    const float* __restrict__ xc_in, PushX x, float* __restrict__ xc_out, Update u) {
   extern __shared__ double acc[];  // the block's W sums, then (as FP32) its W new contributions
   constexpr int kPer = kPushLdsMaxWidth / kPushLdsThreads;
   constexpr int kWaves = kPushLdsThreads / kWave;
@@ -966,7 +1044,7 @@ __global__ __launch_bounds__(kPushLdsThreads) void k_pr_push_lds_x(
     cv[k] = 0.0f;
     if (i < W && v0 + i < u.n) mine += update_vertex(u, v0 + i, acc[i], D, dl, cv[k]);
   }
-  __syncthreads();  // every sum has been read: the LDS now holds the contributions
+  __syncthreads();  // every sum has been read: the LDS now holds the contributions and the run bounds
   float* cs = reinterpret_cast<float*>(acc);
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
@@ -975,7 +1053,7 @@ __global__ __launch_bounds__(kPushLdsThreads) void k_pr_push_lds_x(
   }
   __syncthreads();
   publish_update<kPushLdsThreads>(u, mine, dl);
-  push_expand<kPushLdsThreads>(xstart, xperm, xid16, blockIdx.x, cs, xc_out);
+  push_expand<kPushLdsThreads>(x, blockIdx.x, cs, reinterpret_cast<int32_t*>(cs + W), xc_out);
 }
 
 __global__ __launch_bounds__(kThreads) void k_pr_apply(double* __restrict__ sums, Update u) {
@@ -1073,12 +1151,12 @@ hipError_t pagerank_setup() {
   GC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_push_lds),
                                  hipFuncAttributeMaxDynamicSharedMemorySize,
                                  static_cast<int>(sizeof(double)) * kPushLdsMaxWidth));
+  constexpr int kPushXLds = static_cast<int>(push_x_lds(kPushLdsMaxWidth, gcx::kPushExpandMaxBlocks));
+  static_assert(kPushXLds <= 160 * 1024 - 1024, "expanded push LDS");
   GC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_push_lds_x),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 static_cast<int>(sizeof(double)) * kPushLdsMaxWidth));
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kPushXLds));
   GC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_push_expand),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 static_cast<int>(sizeof(float)) * kPushLdsMaxWidth));
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, kPushXLds));
   GC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_tocab_pull_lds<false>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds_budget(kLdsMaxWidth)));
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_tocab_pull_lds<true>),
@@ -1300,8 +1378,8 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
     ProfScope prof("pr_init", s);
     k_pr_init<<<vgrid, kThreads, 0, s>>>(rank_in, u, push && !expanded ? buf.sums : nullptr);
     if (expanded)
-      k_pr_push_expand<<<t->n_sblk, kPushLdsThreads, sizeof(float) * static_cast<size_t>(t->W), s>>>(
-          t->xstart, t->xperm, t->xid16, t->log2W, n, buf.contrib[0], t->xc);
+      k_pr_push_expand<<<t->n_sblk, kPushLdsThreads, push_x_lds(t->W, t->B), s>>>(push_x(t), t->log2W, n,
+                                                                                 buf.contrib[0], t->xc);
   }
   k_reduce_dangling<<<1, 1024, 0, s>>>(buf.dpart, vgrid, buf.dtotal, nullptr, nullptr);
   GC_HIP_TRY(hipGetLastError());
@@ -1376,10 +1454,10 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
       u.contrib = nullptr;  // the contributions go to the rows' expanded copies only
       parts = t->B;
       ProfScope prof("pr_tocab_push", s);
-      const int64_t P = t->P;
-      k_pr_push_lds_x<<<t->B, kPushLdsThreads, sizeof(double) * static_cast<size_t>(t->W), s>>>(
-          t->blk_rowoff, t->row_ptr, t->pcol16, t->pheads, t->log2W, t->xc + (it & 1) * P, t->xstart, t->xperm,
-          t->xid16, t->xc + ((it + 1) & 1) * P, u);
+      const int64_t P = push_xc_stride(t->P);
+      k_pr_push_lds_x<<<t->B, kPushLdsThreads, push_x_lds(t->W, t->B), s>>>(
+          t->blk_rowoff, t->row_ptr, t->pcol16, t->pheads, t->log2W, t->xc + (it & 1) * P, push_x(t),
+          t->xc + ((it + 1) & 1) * P, u);
     } else if (t && t->W <= kPushLdsMaxWidth) {
       u.contrib = buf.contrib[cur ^ 1];
       parts = t->B;
