@@ -27,6 +27,8 @@
 
 namespace {
 
+int g_cus = 256;  // compute units of the GPU (read once by pagerank_setup)
+
 // D for the next iteration: the partials summed in index order by one
 // work-group (deterministic).
 __device__ __forceinline__ double reduce_slots(const double* __restrict__ slots, int32_t count, double* part) {
@@ -702,21 +704,91 @@ __device__ __forceinline__ void stream_accumulate(const int32_t* __restrict__ rs
   __syncthreads();
 }
 
-template <int K, int kMergeThreads = merge_threads<K>()>
-__global__ __launch_bounds__(kMergeThreads) void k_pr_merge_stream(const int32_t* __restrict__ rstart,
-                                                                   const uint16_t* __restrict__ id16s,
-                                                                   const float* __restrict__ partial, Update u) {
+// The stream-layout merge as a persistent kernel: one work-group per CU
+// (two for ranges up to 8192 vertices) walks ranges j = blockIdx.x,
+// blockIdx.x + gridDim.x, ... With one work-group per CU, a work-group per
+// range would leave the CU idle while it clears its accumulator, waits for
+// its first loads and updates its vertices; here the update of one range
+// clears the accumulator as it reads it, and the first loads of the next
+// range are issued before that update runs. One dangling partial per
+// work-group (its ranges in order, so D stays reproducible).
+template <int K, int NT = merge_threads<K>()>
+__global__ __launch_bounds__(NT) void k_pr_merge_persist(const int32_t* __restrict__ rstart,
+                                                         const uint16_t* __restrict__ id16s,
+                                                         const float* __restrict__ partial, int32_t R, Update u) {
   __shared__ double acc[K];
-  stream_accumulate<K, kMergeThreads>(rstart, id16s, partial, acc);
-  const int32_t v0 = blockIdx.x * K;
+  for (int i = threadIdx.x; i < K; i += NT) acc[i] = 0.0;
+  __syncthreads();
+  const f32x4* p4 = reinterpret_cast<const f32x4*>(partial);
+  const uint64_t* i4 = reinterpret_cast<const uint64_t*>(id16s);
+  constexpr int kU = 4;  // groups of 4 entries per thread and step (two register sets in turn)
+  constexpr int32_t kStep = NT * kU;
+  f32x4 pa[kU], pb[kU];
+  uint64_t ia[kU], ib[kU];
+  int32_t a = 0, z = 0, g0 = 0, g1 = 0;  // the current range's entries [a, z), 4-entry groups [g0, g1)
+  auto bounds = [&](int32_t j) {
+    a = rstart[j];
+    z = rstart[j + 1];
+    g0 = a >> 2;
+    g1 = (z + 3) >> 2;
+  };
+  // (loads are clamped to the range's last group, so they need no branch
+  // and the compiler's count of outstanding loads holds on every path)
+  auto load = [&](int32_t g, f32x4 (&p)[kU], uint64_t (&id)[kU]) {
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      const int32_t gg = min(g + k * NT, g1 - 1);
+      p[k] = gcd::ld_stream(p4 + gg);
+      id[k] = gcd::ld_stream(i4 + gg);
+    }
+  };
+  auto add = [&](int32_t g, const f32x4 (&p)[kU], const uint64_t (&id)[kU]) {
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      const int32_t e0 = 4 * (g + k * NT);
+      const float pv[4] = {p[k][0], p[k][1], p[k][2], p[k][3]};
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (e0 + e >= a && e0 + e < z) atomicAdd(&acc[(id[k] >> (16 * e)) & 0xFFFFu], static_cast<double>(pv[e]));
+    }
+  };
   const double D = *u.dtotal_in;
   double mine = 0.0, dl = 0.0;
-  for (int i = threadIdx.x; i < K; i += kMergeThreads) {
-    const int32_t v = v0 + i;
-    if (v < u.n) mine += update_vertex(u, v, acc[i], D, dl);
+  const int32_t tid = threadIdx.x;
+  int32_t j = blockIdx.x;
+  if (j < R) {
+    bounds(j);
+    if (g0 < g1) load(g0 + tid, pa, ia);  // uniform
   }
-  publish_update<kMergeThreads>(u, mine, dl);
+  for (; j < R; j += gridDim.x) {
+    for (int32_t g = g0 + tid; g < g1; g += 2 * kStep) {
+      load(g + kStep, pb, ib);
+      add(g, pa, ia);
+      load(g + 2 * kStep, pa, ia);
+      add(g + kStep, pb, ib);
+    }
+    __syncthreads();
+    const int32_t v0 = j * K;
+    const int32_t jn = j + gridDim.x;
+    if (jn < R) {  // uniform: the next range's first loads, in flight during the update
+      bounds(jn);
+      if (g0 < g1) load(g0 + tid, pa, ia);
+    }
+    for (int i = tid; i < K; i += NT) {
+      const int32_t v = v0 + i;
+      if (v < u.n) mine += update_vertex(u, v, acc[i], D, dl);
+      acc[i] = 0.0;
+    }
+    __syncthreads();
+  }
+  publish_update<NT>(u, mine, dl);
 }
+
+// Work-groups of the persistent merge over R ranges of K vertices.
+int32_t merge_persist_grid(int32_t K, int32_t R) {
+  return std::max(1, std::min(R, (K >= 16384 ? 1 : 2) * g_cus));
+}
+
 
 // The same merge for SpMV: y[v] = the FP64 sum rounded to FP32.
 template <int K, int kMergeThreads = merge_threads<K>()>
@@ -1146,6 +1218,11 @@ int32_t pull_tile_arcs() { return kTileArcs; }
 int32_t wave_tile_arcs() { return kWaveTile; }
 
 hipError_t pagerank_setup() {
+  {
+    int dev = 0;
+    GC_HIP_TRY(hipGetDevice(&dev));
+    GC_HIP_TRY(hipDeviceGetAttribute(&g_cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
   // the LDS-resident pull holds a slice of up to kLdsMaxWidth floats plus its
   // position table; the LDS push a block's kPushLdsMaxWidth FP64 sums
   GC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pr_push_lds),
@@ -1410,19 +1487,15 @@ hipError_t pagerank_run(gc_graph g, gc_tocab t, int32_t dir, float damping, int3
         }
         u.contrib = buf.contrib[0];
         ProfScope prof("pr_merge", s);
+        const int32_t mg = merge_persist_grid(t->k, t->R);
         switch (t->k) {
-          case 256: k_pr_merge_stream<256><<<t->R, merge_threads<256>(), 0, s>>>(t->rstart, t->id16s, buf.partial, u); break;
-          case 512: k_pr_merge_stream<512><<<t->R, merge_threads<512>(), 0, s>>>(t->rstart, t->id16s, buf.partial, u); break;
-          case 1024: k_pr_merge_stream<1024><<<t->R, merge_threads<1024>(), 0, s>>>(t->rstart, t->id16s, buf.partial, u); break;
-          case 2048: k_pr_merge_stream<2048><<<t->R, merge_threads<2048>(), 0, s>>>(t->rstart, t->id16s, buf.partial, u); break;
-          case 4096: k_pr_merge_stream<4096><<<t->R, merge_threads<4096>(), 0, s>>>(t->rstart, t->id16s, buf.partial, u); break;
-          case 8192: k_pr_merge_stream<8192><<<t->R, merge_threads<8192>(), 0, s>>>(t->rstart, t->id16s, buf.partial, u); break;
-          case 16384:
-            k_pr_merge_stream<16384><<<t->R, merge_threads<16384>(), 0, s>>>(t->rstart, t->id16s, buf.partial, u);
-            break;
+#define GC_MERGE(K) \
+  case K: k_pr_merge_persist<K><<<mg, merge_threads<K>(), 0, s>>>(t->rstart, t->id16s, buf.partial, t->R, u); break;
+          GC_MERGE(256) GC_MERGE(512) GC_MERGE(1024) GC_MERGE(2048) GC_MERGE(4096) GC_MERGE(8192) GC_MERGE(16384)
+#undef GC_MERGE
           default: return hipErrorInvalidValue;
         }
-        parts = t->R;
+        parts = mg;
       } else {
         {
           ProfScope prof("pr_tocab_pull", s);
