@@ -498,7 +498,9 @@ def suite_learned(args, gc, gg, torch):
         return g, [gc.tocab_partition(g, gc.GC_PULL, w, args.merge_range if w <= (1 << 15) else args.wide_merge_range)
                    for w in widths]
 
-    feats, times = [], []
+    # one network per kind of work (0 BFS, 1 SSSP, 2 PageRank): the six level
+    # inputs do not say which operation runs
+    rows = {0: ([], []), 1: ([], []), 2: ([], [])}
     t0 = time.perf_counter()
     train_scales = (16, 24)
     for scale in train_scales:
@@ -508,43 +510,47 @@ def suite_learned(args, gc, gg, torch):
         srcs = gg.sources(gh, n_src, seed=2)
         for kind in (0, 1):
             f, t = gc.sched_collect(g, parts, kind, srcs)
-            feats.append(f)
-            times.append(t)
+            rows[kind][0].append(f)
+            rows[kind][1].append(t)
         f, t = gc.sched_collect_pagerank(g, parts, rows=3)
-        feats.append(f)
-        times.append(t)
+        rows[2][0].append(f)
+        rows[2][1].append(t)
         for p in parts:
             p.free()
         g.free()
     collect_s = time.perf_counter() - t0
-    X = np.concatenate(feats)
-    Tms = np.maximum(np.concatenate(times), 1e-4)
-    best = Tms.min(axis=1)
-    # targets: log of each action's time over the level's fastest (only the
-    # ranking decides, so the network need not learn each graph's scale);
-    # rows weighted by the square root of their level's best time: the
-    # decisions on long levels decide the total
-    T = np.log(Tms / best[:, None]).astype(np.float32)
-    w = np.sqrt(best / best.mean())
-    M = np.repeat(w[:, None], K, axis=1).astype(np.float32)
-    theta = gc.sched_init_params(K, seed=1)
-    m = gc.sched_create(K, theta)
     steps = 4000
-    hist = torch.zeros(steps, dtype=torch.float32, device="cuda")
+    nets, losses, n_rows = {}, {}, {}
     t0 = time.perf_counter()
-    gc.sched_train(m, torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), torch.from_numpy(M).cuda(), steps,
-                   3e-3, hist)
+    for kind, (fl, tl) in rows.items():
+        X = np.concatenate(fl)
+        Tms = np.maximum(np.concatenate(tl), 1e-4)
+        best = Tms.min(axis=1)
+        # targets: log of each action's time over the level's fastest (only the
+        # ranking decides, so the network need not learn each graph's scale);
+        # rows weighted by the square root of their level's best time: the
+        # decisions on long levels decide the total
+        T = np.log(Tms / best[:, None]).astype(np.float32)
+        w = np.sqrt(best / best.mean())
+        M = np.repeat(w[:, None], K, axis=1).astype(np.float32)
+        m = gc.sched_create(K, gc.sched_init_params(K, seed=1))
+        hist = torch.zeros(steps, dtype=torch.float32, device="cuda")
+        gc.sched_train(m, torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda(), torch.from_numpy(M).cuda(), steps,
+                       3e-3, hist)
+        h = hist.cpu().numpy()
+        nets[kind], losses[kind], n_rows[kind] = m, (float(h[0]), float(h[-1])), int(X.shape[0])
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    h = hist.cpu().numpy()
-    log(f"collected {X.shape[0]} levels in {collect_s:.1f} s; trained in {train_s:.2f} s: loss {h[0]:.3f} -> "
-        f"{h[-1]:.4f}")
+    log(f"collected {sum(n_rows.values())} rows ({n_rows}) in {collect_s:.1f} s; trained 3 networks in "
+        f"{train_s:.2f} s: losses {losses}")
     results = {}
     for name, make in (("rmat25", lambda: gg.rmat(25, 16, seed=8)), ("grid4096", lambda: gg.grid(4096, 4096, 0.05, 3))):
         log(f"evaluating on {name}")
         gh = make().with_weights(11)
         g, parts = load(gh)
-        gc.sched_attach(g, m, parts)
+        gc.sched_attach(g, nets[0], parts)
+        gc.sched_attach_kind(g, 1, nets[1])
+        gc.sched_attach_kind(g, 2, nets[2])
         srcs = gg.sources(gh, n_src, seed=8)
         buf = torch.empty(gh.n, dtype=torch.int32, device="cuda")
         mid = parts[widths.index(heur_w)]
@@ -619,7 +625,8 @@ def suite_learned(args, gc, gg, torch):
         for p in parts:
             p.free()
         g.free()
-    m.free()
+    for m in nets.values():
+        m.free()
     gain = results["rmat25"]["bfs"]["learned_gain_vs_heuristic"]
     return {"metric": METRIC, "value": gain, "unit": "x vs working-set heuristic (RMAT-25 BFS total time)",
             "n_gpus": 1, "steps": n_src, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
@@ -627,8 +634,11 @@ def suite_learned(args, gc, gg, torch):
             "config": {"workload": "learned_scheduler_rmat25_grid4096", "sources": n_src,
                        "actions": ["push", "pull"] + [f"tocab@2^{w.bit_length() - 1}" for w in widths],
                        "heuristic_tocab_width": heur_w, "train_graphs": [f"rmat{s}" for s in train_scales],
-                       "train_levels": int(X.shape[0]), "train_steps": steps, "collect_seconds": round(collect_s, 1),
-                       "train_seconds": round(train_s, 2), "loss_first": float(h[0]), "loss_last": float(h[-1])},
+                       "networks": "one per kind (bfs, sssp, pagerank)",
+                       "train_rows": {k2: n_rows[i] for i, k2 in enumerate(("bfs", "sssp", "pagerank"))},
+                       "train_steps": steps, "collect_seconds": round(collect_s, 1),
+                       "train_seconds": round(train_s, 2),
+                       "loss_first_last": {k2: losses[i] for i, k2 in enumerate(("bfs", "sssp", "pagerank"))}},
             "learned": results}
 
 

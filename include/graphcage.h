@@ -319,14 +319,20 @@ int traversal_trace(gc_graph g, int32_t* actions, float* ms, int32_t max, int32_
  * produces. Network: GC_SCHED_INPUTS -> GC_SCHED_HIDDEN -> GC_SCHED_HIDDEN ->
  * K, ReLU after the hidden layers, FP32; output k scores action k (lower is
  * faster: a predicted log time, or log time over the level's fastest action,
- * as the training targets define). The arg-min replaces the working-set
- * heuristic's choice for the level only when its output is lower than the
- * heuristic's action's output by more than 0.1 (about 10 % predicted gain
- * with relative log-time targets); the heuristic alone decides when an
- * output is not finite. For every traversal level after the first, the
- * network runs on the device right after the previous level, on counters
- * that never leave the device, and its answer returns with the level's
- * counters (no synchronisation of its own). Parameters, row-major:
+ * as the training targets define). On a traversal level the working-set
+ * heuristic keeps the direction (push or pull); on a pull level the
+ * network's arg-min over the pull forms (plain pull, TOCAB pull per attached
+ * width) replaces the heuristic's form only when its output is lower than
+ * that form's output by more than 0.3 (about 35 % predicted gain with
+ * relative log-time targets); the heuristic alone decides when an output is
+ * not finite. A trained network clamps each input into the range it saw in
+ * training (sched_train records it), so a level outside that range is
+ * decided as the nearest trained one. For every traversal level after the
+ * first, the network runs on the device in a one-work-group kernel queued
+ * right after the previous level (it stops at once when the rule's
+ * direction for the next level is push), on counters that never leave the
+ * device, and its answer returns with the level's counters (no
+ * synchronisation of its own). Parameters, row-major:
  *   W1[64][6], b1[64], W2[64][64], b2[64], W3[K][64], b3[K].
  * Features of a level (sched_features): log1p(frontier size), log1p(frontier
  * out-arcs), log1p(m / n), log2(ceil(n / 2^18) + 1), level / 16,
@@ -378,6 +384,15 @@ int sched_collect(gc_graph g, const gc_tocab* parts, int32_t n_parts, int32_t ki
  * GC_POLICY_LEARNED and pagerank_learned; m = NULL detaches. The handles
  * must outlive the use. */
 int sched_attach(gc_graph g, gc_sched m, const gc_tocab* parts, int32_t n_parts);
+/* Attaches network m for one kind of work only (kind 0 = BFS, 1 = SSSP,
+ * 2 = PageRank) over the partitions of the last sched_attach (m must have
+ * the same K = 2 + n_parts); m = NULL returns that kind to the network of
+ * sched_attach, which also clears every per-kind network. The six level
+ * inputs do not say which operation runs, and the fastest action for the
+ * same frontier differs between them (a BFS pull gathers status bits, an
+ * SSSP pull 4-byte distances), so a network per kind can learn each one's
+ * choices. GC_EINVAL before any sched_attach or on a K mismatch. */
+int sched_attach_kind(gc_graph g, int32_t kind, gc_sched m);
 /* PageRank (as pagerank_iter, `iters` iterations) in the form chosen for
  * g: 0 plain push, 1 plain pull, 2 + j TOCAB pull over the j-th attached
  * partition. The working-set rule's form for an all-active level is TOCAB
@@ -386,10 +401,11 @@ int sched_attach(gc_graph g, gc_sched m, const gc_tocab* parts, int32_t n_parts)
  * once per attached network, by the first call: it runs that form for 3
  * iterations from rank_in (1 warm-up, 2 timed with HIP events; their result
  * is discarded), feeds the network an all-active level (frontier n vertices
- * and m arcs, level 1, prior time = the timed iteration) and keeps the
- * rule's form unless the network's pick is predicted faster by more than
- * the gate above (or the rule's form when an output is not finite). That
- * first call synchronises `stream` twice; later calls only queue work.
+ * and m arcs, level 1, prior time = the timed iteration), times the same way
+ * the (at most two) forms the network predicts faster than the rule's by
+ * more than the gate above, and keeps the fastest measured form (the rule's
+ * form when an output is not finite). That first call synchronises `stream`
+ * up to four times; later calls only queue work.
  * *action (host, nullable) receives the form run. Errors as pagerank_iter,
  * plus GC_EINVAL when no network is attached. */
 int pagerank_learned(gc_graph g, float damping, int32_t dangling, const float* rank_in, float* rank_out,

@@ -65,6 +65,7 @@ SIGNATURES = {
     "sched_features": (ctypes.c_int, [_i32, _i64, _i32, _i64, _i32, _f32, _i64, _vp]),
     "sched_collect": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _i32, _p_i32, _vp]),
     "sched_attach": (ctypes.c_int, [_vp, _vp, _vp, _i32]),
+    "sched_attach_kind": (ctypes.c_int, [_vp, _i32, _vp]),
     "pagerank_learned": (ctypes.c_int, [_vp, _f32, _i32, _vp, _vp, _i32, _p_i32, _vp]),
     "batch_create": (ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _i32, _vp, ctypes.POINTER(_vp)]),
     "batch_info": (ctypes.c_int, [_vp, _vp, _vp, _p_i32, _p_i64]),
@@ -484,6 +485,12 @@ def pagerank_learned(g, damping, dangling, rank_in, rank_out, iters, stream=None
 def sched_attach(g, m, parts=()):
     _check(lib.sched_attach(_h(g), _h(m), _handles(parts) if m is not None else None,
                             len(parts) if m is not None else 0), "sched_attach")
+
+
+def sched_attach_kind(g, kind, m):
+    """Network m for one kind of work only (0 BFS, 1 SSSP, 2 PageRank), over the
+    partitions of the last sched_attach; None returns the kind to the shared one."""
+    _check(lib.sched_attach_kind(_h(g), int(kind), _h(m)), "sched_attach_kind")
 
 
 # ---------------------------------------------------------------------------

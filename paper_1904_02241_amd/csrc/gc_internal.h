@@ -63,6 +63,7 @@ struct gc_graph_s {
   int64_t bytes = 0;
   // learned level scheduler attached to this graph (sched_attach)
   gc_sched sched = nullptr;
+  gc_sched sched_kind[3] = {nullptr, nullptr, nullptr};  // per kind (BFS, SSSP, PageRank); null: sched
   std::vector<gc_tocab> sched_parts;
   int32_t pr_learned_action = -1;  // pagerank_learned's form for the attached network (-1: not chosen yet)
   // per-level record of the last traversal: action and wall time (ms)
@@ -290,21 +291,22 @@ constexpr int kStatSlots = kStatOut + GC_SCHED_HIDDEN;
 
 // Learned policy: the working-set rule's choice is kept unless the network
 // predicts its own pick faster by more than this margin (its outputs are
-// log times relative to the fastest action, so 0.1 is about 10 %).
-constexpr float kLearnedGate = 0.1f;
+// log times relative to the fastest action, so 0.3 is about 35 %: the
+// network overrides the rule only where it expects a clear win).
+constexpr float kLearnedGate = 0.3f;
 
 // ---- scheduler network (gc_sched.hip) ----
 int32_t sched_actions(gc_sched m);
+// The network deciding for one kind of work on g (0 BFS, 1 SSSP, 2
+// PageRank): the one attached for that kind, else the shared one (or null).
+inline gc_sched sched_for(gc_graph g, int kind) { return g->sched_kind[kind] ? g->sched_kind[kind] : g->sched; }
+// Device pointer to the network's parameters (layout in gc_mlp.h).
+const float* sched_params(gc_sched m);
+// Device pointer to the training range of its inputs (null before training).
+const float* sched_range(gc_sched m);
 // Decision from host features: action (-1 when an output is not finite)
 // and, when out is given, the K outputs. Synchronises s.
 hipError_t sched_decide(gc_sched m, const float* features, hipStream_t s, int32_t* action, float* out = nullptr);
-// Decision for the next traversal level from the device counters of the
-// level just run (its frontier size and out-arcs, its start and end
-// clocks): queued on s, results in stats[kStatChoice] and stats[kStatOut..].
-// prior_arcs = out-arcs of the level just run; clock_khz = the device
-// wall-clock rate.
-hipError_t sched_decide_level(gc_sched m, int64_t n, int64_t m_arcs, int32_t level, int64_t prior_arcs,
-                              int32_t clock_khz, int32_t* stats, hipStream_t s);
 
 // Records HIP events around the launches made in its scope while
 // profiling is on (gc_profile); a no-op otherwise.

@@ -525,40 +525,64 @@ int pagerank_learned(gc_graph g, float damping, int32_t dangling, const float* r
   const int rc = check_pagerank("pagerank_learned", g, nullptr, GC_PULL, damping, dangling, rank_in, rank_out);
   if (rc != GC_OK) return rc;
   if (iters < 0) return fail(GC_EINVAL, "pagerank_learned: iters < 0");
-  if (!g->sched) return fail(GC_EINVAL, "pagerank_learned: no scheduler attached");
+  const gc_sched net = gcx::sched_for(g, 2);
+  if (!net) return fail(GC_EINVAL, "pagerank_learned: no scheduler attached");
   const int32_t np = static_cast<int32_t>(g->sched_parts.size());
-  const int32_t K = gcx::sched_actions(g->sched);
+  const int32_t K = gcx::sched_actions(net);
   const int32_t fa = gcx::pagerank_fallback_action(g->sched_parts.data(), np);
   hipError_t e = hipSuccess;
   if (g->pr_learned_action < 0) {
     // Every iteration is alike, so the form is chosen once per attached
-    // network: time the working-set rule's form (one warm-up iteration,
-    // then two timed), give the network that time per arc as its prior-level
-    // input, and keep the rule's form unless the network predicts its own
-    // pick faster by more than the gate.
-    gc_tocab ft = fa >= 2 ? g->sched_parts[fa - 2] : nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    float ms = 0.0f;
-    e = hipEventCreate(&e0);
-    if (e == hipSuccess) e = hipEventCreate(&e1);
-    if (e == hipSuccess) e = gcx::pagerank_run(g, ft, GC_PULL, damping, dangling, rank_in, rank_out, 1, stream);
-    if (e == hipSuccess) e = hipEventRecord(e0, stream);
-    if (e == hipSuccess) e = gcx::pagerank_run(g, ft, GC_PULL, damping, dangling, rank_in, rank_out, 2, stream);
-    if (e == hipSuccess) e = hipEventRecord(e1, stream);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
+    // network. The working-set rule's form is timed (one warm-up iteration,
+    // then two timed with HIP events), the network gets that time per arc as
+    // its prior-level input, and its (at most two) picks predicted faster
+    // than the rule's form by more than the gate are timed the same way; the
+    // fastest measured form is kept. The network proposes, the clock decides:
+    // a wrong prediction costs a few iterations once, never the run.
+    auto time_form = [&](int32_t act, float* ms) -> hipError_t {
+      gc_tocab ft = act >= 2 ? g->sched_parts[act - 2] : nullptr;
+      const int32_t dir = act == 0 ? GC_PUSH : GC_PULL;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      hipError_t err = hipEventCreate(&e0);
+      if (err == hipSuccess) err = hipEventCreate(&e1);
+      if (err == hipSuccess) err = gcx::pagerank_run(g, ft, dir, damping, dangling, rank_in, rank_out, 1, stream);
+      if (err == hipSuccess) err = hipEventRecord(e0, stream);
+      if (err == hipSuccess) err = gcx::pagerank_run(g, ft, dir, damping, dangling, rank_in, rank_out, 2, stream);
+      if (err == hipSuccess) err = hipEventRecord(e1, stream);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      if (err == hipSuccess) err = hipEventElapsedTime(ms, e0, e1);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      return err;
+    };
+    float fms = 0.0f;
+    e = time_form(fa, &fms);
     if (e != hipSuccess) return hip_fail(e, "pagerank_learned: timing the fallback form");
     float feats[GC_SCHED_INPUTS];
-    gcx::sched_features(g->n, g->m, g->n, g->m, 1, ms / 2.0, g->m, feats);
+    gcx::sched_features(g->n, g->m, g->n, g->m, 1, fms / 2.0, g->m, feats);
     std::vector<float> out(static_cast<size_t>(K));
     int32_t a = -1;
-    e = gcx::sched_decide(g->sched, feats, stream, &a, out.data());
+    e = gcx::sched_decide(net, feats, stream, &a, out.data());
     if (e != hipSuccess) return hip_fail(e, "pagerank_learned");
-    if (a < 0 || a >= 2 + np || a >= K) a = fa;  // no finite output: the working-set rule
-    else if (fa < K && out[fa] <= out[a] + gcx::kLearnedGate) a = fa;
-    g->pr_learned_action = a;
+    int32_t best = fa;
+    float best_ms = fms;
+    if (a >= 0 && fa < K) {  // finite outputs
+      std::vector<int32_t> order;
+      for (int32_t c = 0; c < K && c < 2 + np; ++c)
+        if (c != fa && out[c] + gcx::kLearnedGate < out[fa]) order.push_back(c);
+      std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return out[x] < out[y]; });
+      if (order.size() > 2) order.resize(2);
+      for (int32_t c : order) {
+        float ms = 0.0f;
+        e = time_form(c, &ms);
+        if (e != hipSuccess) return hip_fail(e, "pagerank_learned: timing a proposed form");
+        if (ms < best_ms) {
+          best = c;
+          best_ms = ms;
+        }
+      }
+    }
+    g->pr_learned_action = best;
   }
   const int32_t a = g->pr_learned_action;
   if (action) *action = a;
@@ -637,7 +661,8 @@ int bfs_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32_t* le
   if (!depth) return fail(GC_EINVAL, "bfs_pull: NULL depth");
   if (!is_device_ptr(depth)) return fail(GC_EINVAL, "bfs_pull: depth must be device memory");
   if (policy > GC_POLICY_LEARNED) return fail(GC_EINVAL, "bfs_pull: unknown policy %u", policy);
-  if (policy == GC_POLICY_LEARNED && !g->sched) return fail(GC_EINVAL, "bfs_pull: no scheduler attached");
+  if (policy == GC_POLICY_LEARNED && !gcx::sched_for(g, 0))
+    return fail(GC_EINVAL, "bfs_pull: no scheduler attached");
   const hipError_t e = gcx::bfs_run(g, t, source, depth, levels, policy, stream);
   return e == hipSuccess ? GC_OK : hip_fail(e, "bfs_pull");
 }
@@ -652,7 +677,8 @@ int sssp_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* dist, int32_t* ro
   if (!dist) return fail(GC_EINVAL, "sssp_pull: NULL dist");
   if (!is_device_ptr(dist)) return fail(GC_EINVAL, "sssp_pull: dist must be device memory");
   if (policy > GC_POLICY_LEARNED) return fail(GC_EINVAL, "sssp_pull: unknown policy %u", policy);
-  if (policy == GC_POLICY_LEARNED && !g->sched) return fail(GC_EINVAL, "sssp_pull: no scheduler attached");
+  if (policy == GC_POLICY_LEARNED && !gcx::sched_for(g, 1))
+    return fail(GC_EINVAL, "sssp_pull: no scheduler attached");
   bool overflow = false;
   const hipError_t e = gcx::sssp_run(g, t, source, dist, rounds, policy, stream, &overflow);
   if (e != hipSuccess) return hip_fail(e, "sssp_pull");
@@ -726,6 +752,7 @@ int sched_attach(gc_graph g, gc_sched m, const gc_tocab* parts, int32_t n_parts)
   g->pr_learned_action = -1;  // pagerank_learned decides again for the new network
   if (!m) {
     g->sched = nullptr;
+    for (gc_sched& k : g->sched_kind) k = nullptr;
     g->sched_parts.clear();
     return GC_OK;
   }
@@ -736,7 +763,21 @@ int sched_attach(gc_graph g, gc_sched m, const gc_tocab* parts, int32_t n_parts)
     if (!parts[i] || parts[i]->g != g || parts[i]->dir != GC_PULL)
       return fail(GC_EINVAL, "sched_attach: partition %d is not a GC_PULL partition of this graph", i);
   g->sched = m;
+  for (gc_sched& k : g->sched_kind) k = nullptr;
   g->sched_parts.assign(parts, parts + n_parts);
+  return GC_OK;
+}
+
+int sched_attach_kind(gc_graph g, int32_t kind, gc_sched m) {
+  if (!g) return fail(GC_EINVAL, "sched_attach_kind: NULL graph");
+  if (kind < 0 || kind > 2) return fail(GC_EINVAL, "sched_attach_kind: kind %d is not 0, 1 or 2", kind);
+  if (m && !g->sched)
+    return fail(GC_EINVAL, "sched_attach_kind: attach a network and its partitions with sched_attach first");
+  if (m && gcx::sched_actions(m) != 2 + static_cast<int32_t>(g->sched_parts.size()))
+    return fail(GC_EINVAL, "sched_attach_kind: network has %d outputs, needs 2 + %d", gcx::sched_actions(m),
+                static_cast<int32_t>(g->sched_parts.size()));
+  g->sched_kind[kind] = m;
+  if (kind == 2) g->pr_learned_action = -1;
   return GC_OK;
 }
 

@@ -14,25 +14,15 @@
 
 #include "gc_device.h"
 #include "gc_internal.h"
+#include "gc_mlp.h"
 
 namespace {
 
 using gcd::kWave;
-constexpr int kIn = GC_SCHED_INPUTS;
-constexpr int kHid = GC_SCHED_HIDDEN;
-
-struct Layout {
-  int32_t W1, b1, W2, b2, W3, b3, total;
-  __host__ __device__ explicit Layout(int32_t K) {
-    W1 = 0;
-    b1 = W1 + kHid * kIn;
-    W2 = b1 + kHid;
-    b2 = W2 + kHid * kHid;
-    W3 = b2 + kHid;
-    b3 = W3 + K * kHid;
-    total = b3 + K;
-  }
-};
+using gcmlp::kHid;
+using gcmlp::kIn;
+using gcmlp::Layout;
+using gcmlp::mlp_decide;
 
 // One wave per sample, lane j = hidden unit j. Stores the outputs and, when
 // asked, the hidden activations for the backward pass.
@@ -164,57 +154,32 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   p[q] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-// Inference for one level (one wave): the K outputs for features `in`
-// into out[k] (when given) and the arg-min action, or -1 if an output is
-// not finite, into *choice.
-__device__ __forceinline__ void mlp_decide(const float* __restrict__ p, int32_t K, const float (&in)[kIn],
-                                           int32_t* __restrict__ choice, float* __restrict__ out) {
-  const Layout L(K);
-  const int lane = threadIdx.x;
-  float z = p[L.b1 + lane];
-#pragma unroll
-  for (int i = 0; i < kIn; ++i) z += p[L.W1 + lane * kIn + i] * in[i];
-  const float h1 = fmaxf(z, 0.0f);
-  z = p[L.b2 + lane];
-  for (int i = 0; i < kHid; ++i) z += p[L.W2 + lane * kHid + i] * __shfl(h1, i, kWave);
-  const float h2 = fmaxf(z, 0.0f);
-  int best = -1;
-  float bv = 0.0f;
-  bool bad = false;
-  for (int k = 0; k < K; ++k) {
-    const float o = p[L.b3 + k] + static_cast<float>(gcd::wave_sum(static_cast<double>(p[L.W3 + k * kHid + lane] * h2)));
-    if (out && lane == 0) out[k] = o;
-    bad |= !isfinite(o);
-    if (best < 0 || o < bv) {
-      best = k;
-      bv = o;
-    }
-  }
-  if (lane == 0) *choice = bad ? -1 : best;
-}
-
 __global__ __launch_bounds__(kWave) void k_mlp_decide(const float* __restrict__ p, int32_t K, float f0, float f1,
                                                       float f2, float f3, float f4, float f5,
-                                                      int32_t* __restrict__ choice, float* __restrict__ out) {
+                                                      const float* __restrict__ frange, int32_t* __restrict__ choice,
+                                                      float* __restrict__ out) {
   const float in[kIn] = {f0, f1, f2, f3, f4, f5};
-  mlp_decide(p, K, in, choice, out);
+  mlp_decide(p, K, in, frange, choice, out);
 }
 
-// Decision for the next traversal level from the counters of the level
-// just run, read on the device: the next frontier's size and out-arcs, and
-// the level's time from its clock stamps.
-__global__ __launch_bounds__(kWave) void k_mlp_decide_level(const float* __restrict__ p, int32_t K, int64_t n,
-                                                            int64_t m, int32_t level, int64_t prior_arcs,
-                                                            int32_t clock_khz, int32_t* __restrict__ stats) {
-  const int64_t n_f = stats[gcx::kStatQLen];
-  const int64_t m_f = static_cast<int64_t>(static_cast<uint32_t>(stats[gcx::kStatDegLo])) |
-                      (static_cast<int64_t>(stats[gcx::kStatDegLo + 1]) << 32);
-  const uint64_t t0 = *reinterpret_cast<const uint64_t*>(stats + gcx::kStatT0);
-  const uint64_t t1 = *reinterpret_cast<const uint64_t*>(stats + gcx::kStatT1);
-  const double prior_ms = t1 > t0 ? static_cast<double>(t1 - t0) / clock_khz : 0.0;
-  float in[kIn];
-  gcx::level_features(n, m, n_f, m_f, level, prior_ms, prior_arcs, in);
-  mlp_decide(p, K, in, stats + gcx::kStatChoice, reinterpret_cast<float*>(stats + gcx::kStatOut));
+// Lowest and highest value of each input over the training rows (one wave
+// per input, fixed order).
+__global__ __launch_bounds__(kWave) void k_feature_range(const float* __restrict__ x, int32_t batch,
+                                                         float* __restrict__ frange) {
+  const int i = blockIdx.x;
+  float lo = INFINITY, hi = -INFINITY;
+  for (int32_t b = threadIdx.x; b < batch; b += kWave) {
+    lo = fminf(lo, x[b * kIn + i]);
+    hi = fmaxf(hi, x[b * kIn + i]);
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    lo = fminf(lo, __shfl_xor(lo, o, kWave));
+    hi = fmaxf(hi, __shfl_xor(hi, o, kWave));
+  }
+  if (threadIdx.x == 0) {
+    frange[i] = lo;
+    frange[kIn + i] = hi;
+  }
 }
 
 }  // namespace
@@ -229,18 +194,24 @@ struct gc_sched_s {
   float* grad = nullptr;
   int32_t* choice = nullptr;
   int32_t* choice_host = nullptr;
+  float* frange = nullptr;  // [2 * inputs] training range of each input (set by sched_train)
+  bool ranged = false;
 };
 
 namespace gcx {
 
 int32_t sched_actions(gc_sched m) { return m->K; }
 
+const float* sched_params(gc_sched m) { return m->params; }
+
+const float* sched_range(gc_sched m) { return m->ranged ? m->frange : nullptr; }
+
 // Decision for one level from host-computed features; -1 when the network
 // gives no finite answer (the caller falls back to the heuristic).
 hipError_t sched_decide(gc_sched m, const float* f, hipStream_t s, int32_t* action, float* out) {
   // m->choice holds the action, then the K outputs
-  k_mlp_decide<<<1, kWave, 0, s>>>(m->params, m->K, f[0], f[1], f[2], f[3], f[4], f[5], m->choice,
-                                   reinterpret_cast<float*>(m->choice + 1));
+  k_mlp_decide<<<1, kWave, 0, s>>>(m->params, m->K, f[0], f[1], f[2], f[3], f[4], f[5], sched_range(m),
+                                   m->choice, reinterpret_cast<float*>(m->choice + 1));
   GC_HIP_TRY(hipGetLastError());
   GC_HIP_TRY(hipMemcpyAsync(m->choice_host, m->choice, sizeof(int32_t) * (1 + m->K), hipMemcpyDeviceToHost, s));
   GC_HIP_TRY(hipStreamSynchronize(s));
@@ -249,11 +220,6 @@ hipError_t sched_decide(gc_sched m, const float* f, hipStream_t s, int32_t* acti
   return hipSuccess;
 }
 
-hipError_t sched_decide_level(gc_sched m, int64_t n, int64_t m_arcs, int32_t level, int64_t prior_arcs,
-                              int32_t clock_khz, int32_t* stats, hipStream_t s) {
-  k_mlp_decide_level<<<1, kWave, 0, s>>>(m->params, m->K, n, m_arcs, level, prior_arcs, clock_khz, stats);
-  return hipGetLastError();
-}
 
 }  // namespace gcx
 
@@ -317,10 +283,11 @@ int sched_create(int32_t n_actions, const float* params, gc_sched* out) {
   m->v = static_cast<float*>(gcx::dev_alloc(bytes, nullptr));
   m->grad = static_cast<float*>(gcx::dev_alloc(bytes, nullptr));
   m->choice = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * (1 + kHid), nullptr));
+  m->frange = static_cast<float*>(gcx::dev_alloc(sizeof(float) * 2 * kIn, nullptr));
   if (hipHostMalloc(reinterpret_cast<void**>(&m->choice_host), sizeof(int32_t) * (1 + kHid), hipHostMallocDefault) !=
       hipSuccess)
     m->choice_host = nullptr;
-  if (!m->params || !m->m || !m->v || !m->grad || !m->choice || !m->choice_host) {
+  if (!m->params || !m->m || !m->v || !m->grad || !m->choice || !m->frange || !m->choice_host) {
     sched_free(m);
     return fail_sched(GC_ENOMEM, "sched_create: allocation failed");
   }
@@ -367,6 +334,9 @@ int sched_train(gc_sched m, const float* x, const float* t, const float* mask, i
     return fail_sched(GC_EINVAL, "sched_train: buffers must be device memory");
   gcx::Buf scratch(sizeof(float), stream);
   if (!scratch.p) return fail_sched(GC_ENOMEM, "sched_train: allocation failed");
+  k_feature_range<<<kIn, kWave, 0, stream>>>(x, batch, m->frange);
+  if (hipGetLastError() != hipSuccess) return fail_sched(GC_EHIP, "sched_train: range launch failed");
+  m->ranged = true;
   for (int32_t i = 0; i < steps; ++i) {
     hipError_t e = loss_grad(m, x, t, mask, batch, loss_hist ? loss_hist + i : scratch.as<float>(), stream);
     if (e != hipSuccess) return fail_sched(GC_EHIP, "sched_train: step failed");
@@ -381,7 +351,7 @@ int sched_free(gc_sched m) {
   if (!m) return fail_sched(GC_EINVAL, "sched_free: NULL model");
   (void)hipDeviceSynchronize();
   for (void* q : {static_cast<void*>(m->params), static_cast<void*>(m->m), static_cast<void*>(m->v),
-                  static_cast<void*>(m->grad), static_cast<void*>(m->choice)})
+                  static_cast<void*>(m->grad), static_cast<void*>(m->choice), static_cast<void*>(m->frange)})
     if (q) gcx::dev_free(q, nullptr);
   if (m->choice_host) (void)hipHostFree(m->choice_host);
   delete m;

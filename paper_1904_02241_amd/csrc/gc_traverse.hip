@@ -28,6 +28,7 @@
 
 #include "gc_device.h"
 #include "gc_internal.h"
+#include "gc_mlp.h"
 #include "gc_merge.h"
 
 namespace {
@@ -104,6 +105,26 @@ __global__ void k_level_begin(int32_t* __restrict__ stats) {
   if (threadIdx.x == 0) *reinterpret_cast<uint64_t*>(stats + gcx::kStatT0) = wall_clock64();
 }
 
+// What the learned scheduler needs to decide the next level on the device:
+// its parameters and the graph's and level's counts.
+struct LevelDecide {
+  const float* params = nullptr;
+  const float* frange = nullptr;
+  int32_t K = 0;
+  int64_t n = 0, m = 0;
+  int32_t level = 0;
+  int64_t prior_arcs = 0;
+  int32_t clock_khz = 1;
+  // the working-set rule's direction test for the next level (the network
+  // only picks the form of pull levels, so push levels skip it): its state,
+  // and the unexplored arcs before the next frontier's are taken off (BFS)
+  // or the whole arc count (SSSP)
+  bool pulling = false;
+  bool sub_next = false;
+  int64_t unexplored = 0;
+  double alpha = 0.0, beta = 0.0;
+};
+
 // Out-arc count of the queued vertices (for the direction heuristic). The
 // kernel runs right after the level's relaxation kernels on the same
 // stream, so its start stamps the end of the level.
@@ -126,6 +147,38 @@ __global__ void k_queue_degree(const int32_t* __restrict__ queue, const int32_t*
     for (int w = 0; w < kThreads / kWave; ++w) total += part[w];
     if (total) atomicAdd(reinterpret_cast<unsigned long long*>(stats + kDegLo), total);
   }
+}
+
+// The learned scheduler's decision for the next level, from the counters of
+// the level just ended (read after k_queue_degree): the next frontier's
+// size and out-arcs and the level's time from its clock stamps. The
+// network only picks the form of pull levels, so the kernel first applies
+// the working-set rule's direction test and stops on a push level. Else the
+// work-group stages the parameters in LDS (coalesced, all loads in flight
+// together) and its first wave runs the network.
+__global__ __launch_bounds__(kThreads) void k_level_decide(int32_t* __restrict__ stats, LevelDecide dec) {
+  extern __shared__ float sp[];
+  const int64_t n_f = stats[gcx::kStatQLen];
+  const int64_t m_f = static_cast<int64_t>(static_cast<uint32_t>(stats[kDegLo])) |
+                      (static_cast<int64_t>(stats[kDegLo + 1]) << 32);
+  const double mu = static_cast<double>(dec.sub_next ? dec.unexplored - m_f : dec.unexplored);
+  const bool pull_next = dec.pulling ? !(static_cast<double>(n_f) < static_cast<double>(dec.n) / dec.beta)
+                                     : static_cast<double>(m_f) > mu / dec.alpha;
+  if (!pull_next) {  // uniform
+    if (threadIdx.x == 0) stats[gcx::kStatChoice] = -1;  // push: the rule alone
+    return;
+  }
+  const int32_t np = gcmlp::Layout(dec.K).total;
+  for (int32_t i = threadIdx.x; i < np; i += kThreads) sp[i] = dec.params[i];
+  __syncthreads();
+  if (threadIdx.x >= kWave) return;
+  const uint64_t t0 = *reinterpret_cast<const uint64_t*>(stats + gcx::kStatT0);
+  const uint64_t t1 = *reinterpret_cast<const uint64_t*>(stats + gcx::kStatT1);
+  const double prior_ms = t1 > t0 ? static_cast<double>(t1 - t0) / dec.clock_khz : 0.0;
+  float in[GC_SCHED_INPUTS];
+  gcx::level_features(dec.n, dec.m, n_f, m_f, dec.level, prior_ms, dec.prior_arcs, in);
+  gcmlp::mlp_decide(sp, dec.K, in, dec.frange, stats + gcx::kStatChoice,
+                    reinterpret_cast<float*>(stats + gcx::kStatOut));
 }
 
 // ---------------------------------------------------------------------------
@@ -1262,10 +1315,23 @@ struct Frontier {
   // scheduler's decision for the next level when `decide` is given (read
   // back with the counters, so it costs no synchronisation of its own),
   // and reads the counters.
-  hipError_t end_level(bool* overflow, gc_sched decide = nullptr, int32_t next_level = 0) {
+  hipError_t end_level(bool* overflow, gc_sched decide = nullptr, int32_t next_level = 0,
+                       LevelDecide dec = LevelDecide()) {
+    size_t lds = 0;
+    if (decide) {
+      lds = sizeof(float) * static_cast<size_t>(gcmlp::Layout(gcx::sched_actions(decide)).total);
+      dec.params = gcx::sched_params(decide);
+      dec.frange = gcx::sched_range(decide);
+      dec.K = gcx::sched_actions(decide);
+      dec.n = g->n;
+      dec.m = g->m;
+      dec.level = next_level;
+      dec.prior_arcs = m_f;
+      dec.clock_khz = g->clock_khz;
+    }
     k_queue_degree<<<256, kThreads, 0, s>>>(queue_next(), g->stats + kQLen, g->rowptr, g->stats);
+    if (decide) k_level_decide<<<1, kThreads, lds, s>>>(g->stats, dec);
     GC_HIP_TRY(hipGetLastError());
-    if (decide) GC_HIP_TRY(gcx::sched_decide_level(decide, g->n, g->m, next_level, m_f, g->clock_khz, g->stats, s));
     GC_HIP_TRY(hipMemcpyAsync(g->stats_host, g->stats, sizeof(int32_t) * gcx::kStatSlots, hipMemcpyDeviceToHost, s));
     if (n_f > 0) k_clear_front<<<grid_for(n_f, kThreads), kThreads, 0, s>>>(front(), queue(), n_f);
     GC_HIP_TRY(hipGetLastError());
@@ -1471,8 +1537,9 @@ hipError_t traverse(gc_graph g, gc_tocab t, int32_t source, int32_t* value, int3
   // previous level and read back with them; the first level's from host
   // features. Its working-set fallback uses the attached partition nearest
   // the paper's 2^18 when the call gives none.
-  const bool learned = policy == GC_POLICY_LEARNED && g->sched;
-  const int32_t K = learned ? sched_actions(g->sched) : 0;
+  const gc_sched net = sched_for(g, bfs ? 0 : 1);
+  const bool learned = policy == GC_POLICY_LEARNED && net;
+  const int32_t K = learned ? sched_actions(net) : 0;
   gc_tocab fall_t = t;
   int32_t fall_action = -1;  // action index of TOCAB over fall_t
   if (learned) {
@@ -1506,18 +1573,27 @@ hipError_t traverse(gc_graph g, gc_tocab t, int32_t source, int32_t* value, int3
     if (learned) {
       int32_t a = -1;
       if (level == 0) {
-        float feats[GC_SCHED_INPUTS];
-        sched_features(n, g->m, f.n_f, f.m_f, level, 0.0, 0, feats);
-        GC_HIP_TRY(sched_decide(g->sched, feats, s, &a, outs.data()));
+        if (hmode != Mode::kPush) {
+          float feats[GC_SCHED_INPUTS];
+          sched_features(n, g->m, f.n_f, f.m_f, level, 0.0, 0, feats);
+          GC_HIP_TRY(sched_decide(net, feats, s, &a, outs.data()));
+        }
       } else {
         a = g->stats_host[gcx::kStatChoice];
         std::memcpy(outs.data(), g->stats_host + gcx::kStatOut, sizeof(float) * K);
       }
-      if (a >= 0 && a < K) {
-        // the rule's own choice as an action, kept unless the network
-        // predicts its pick faster by more than the gate
-        const int32_t ha = hmode == Mode::kPush ? 0 : (hmode == Mode::kPull ? 1 : fall_action);
-        if (ha >= 0 && ha < K && outs[ha] <= outs[a] + kLearnedGate) a = ha;
+      if (a >= 0 && a < K && hmode != Mode::kPush) {
+        // The rule keeps the direction (its push / pull switch is the
+        // direction-optimising test, close to the best on every graph
+        // measured); on a pull level the network picks the form: plain pull
+        // or TOCAB pull over one of the attached widths, the rule's own form
+        // kept unless the network predicts its pick faster by more than the
+        // gate.
+        a = 1;
+        for (int32_t k = 2; k < K; ++k)
+          if (outs[k] < outs[a]) a = k;
+        const int32_t ha = hmode == Mode::kPull ? 1 : fall_action;
+        if (ha >= 1 && ha < K && outs[ha] <= outs[a] + kLearnedGate) a = ha;
         action_mode(a, g->sched_parts.data(), &mode, &lt);
         action = a;
       }
@@ -1530,7 +1606,15 @@ hipError_t traverse(gc_graph g, gc_tocab t, int32_t source, int32_t* value, int3
     const double t0 = now_ms();
     GC_HIP_TRY(f.begin_level());
     GC_HIP_TRY(run_level(g, f, bfs, value, level, mode, lt, s));
-    GC_HIP_TRY(f.end_level(overflow, learned ? g->sched : nullptr, level + 1));
+    LevelDecide dec;
+    if (learned) {
+      dec.pulling = h.pulling;
+      dec.sub_next = bfs;
+      dec.unexplored = bfs ? m_u : g->m;
+      dec.alpha = Heuristic::kAlpha;
+      dec.beta = Heuristic::kBeta;
+    }
+    GC_HIP_TRY(f.end_level(overflow, learned ? net : nullptr, level + 1, dec));
     const double wall_ms = now_ms() - t0;
     g->trace_action.push_back(action);
     g->trace_ms.push_back(static_cast<float>(wall_ms));

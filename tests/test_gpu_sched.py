@@ -149,44 +149,59 @@ def test_network_without_finite_output_falls_back_to_heuristic():
     h.free()
 
 
+def _train(gc, X, T, K, steps=3000, seed=1):
+    """A network trained on rows X (features) and T (ms per action): targets
+    are log times over each row's fastest action, rows weighted by the square
+    root of their best time."""
+    Tms = np.maximum(T, 1e-4)
+    best = Tms.min(axis=1)
+    M = np.repeat(np.sqrt(best / best.mean())[:, None], K, axis=1).astype(np.float32)
+    m = gc.sched_create(K, mlp.init_params(K, seed=seed).astype(np.float32))
+    gc.sched_train(m, dev(X), dev(np.log(Tms / best[:, None]).astype(np.float32)), dev(M), steps, 3e-3)
+    return m
+
+
 def test_trained_network_gains_over_heuristic():
-    """Trains the network on levels collected on R-MAT 16 and R-MAT 22 (seed
-    1) and runs BFS and SSSP on R-MAT 21 of another seed under the learned
-    policy, the working-set heuristic and always-pull. Prints the gains; fails only if the learned
-    policy is clearly worse than the heuristic or not better than always
-    pulling (timings carry noise, and the learned policy pays one more
-    synchronisation per level for its device-side decision, about 25 us, so
-    the graph is large enough that levels take far longer than that). The
-    held-out graph lies inside the trained range of sizes: the block-count
-    feature of a larger graph would lie outside what the network saw."""
+    """Trains one network per traversal kind on levels collected on R-MAT 16
+    and R-MAT 22 (seed 1, 8 sources) and runs BFS and SSSP on R-MAT 22 of
+    another seed under the learned policy, the working-set heuristic (TOCAB
+    over the attached partition nearest the paper's 2^18 blocks) and
+    always-pull. Timings are the best of three runs per source over four
+    sources.
+
+    The rule keeps the direction of every level; the network picks the form
+    of pull levels. SSSP gains: its pull levels run over 2^15 blocks, whose
+    distances sit in LDS, where the rule's 2^18 blocks leave them in L2.
+    BFS cannot: its pull levels read a status bitmap that already fits in
+    L2, so plain pull (the rule's form) is the fastest form on every pull
+    level of the training rows, the network keeps it, and BFS pays only the
+    decision kernel queued after every level (about 5 us, some 5 % of a
+    BFS of this size). The bars: SSSP a gain (1.05), BFS that cost and
+    nothing more (0.9)."""
     import time
     import paper_1904_02241_amd as gc
-    widths = [1 << s for s in range(16, 21)]
+    widths = [1 << 15, 1 << 16, 1 << 18, 1 << 20]
     K = 2 + len(widths)
-    X, T = [], []
+    rows = {0: ([], []), 1: ([], [])}
     for scale in (16, 22):
         g = gg.rmat(scale, 16, seed=1).with_weights(11)
         h = load(g, weights=True)
-        parts = [gc.tocab_partition(h, gc.GC_PULL, W, 4096) for W in widths]
-        srcs = gg.sources(g, 4, seed=2)
+        parts = [gc.tocab_partition(h, gc.GC_PULL, W, 16384 if W <= (1 << 15) else 4096) for W in widths]
+        srcs = gg.sources(g, 8, seed=2)
         for kind in (0, 1):
             f, t = gc.sched_collect(h, parts, kind, srcs)
-            X.append(f)
-            T.append(t)
+            rows[kind][0].append(f)
+            rows[kind][1].append(t)
         for p in parts:
             p.free()
         h.free()
-    X = np.concatenate(X)
-    Tms = np.maximum(np.concatenate(T), 1e-4)
-    best = Tms.min(axis=1)
-    M = np.repeat(np.sqrt(best / best.mean())[:, None], K, axis=1).astype(np.float32)
-    m = gc.sched_create(K, mlp.init_params(K, seed=1).astype(np.float32))
-    gc.sched_train(m, dev(X), dev(np.log(Tms / best[:, None]).astype(np.float32)), dev(M), 3000, 3e-3)
+    nets = {kind: _train(gc, np.concatenate(rows[kind][0]), np.concatenate(rows[kind][1]), K) for kind in (0, 1)}
 
-    g = gg.rmat(21, 16, seed=8).with_weights(11)
+    g = gg.rmat(22, 16, seed=8).with_weights(11)
     h = load(g, weights=True)
-    parts = [gc.tocab_partition(h, gc.GC_PULL, W, 4096) for W in widths]
-    gc.sched_attach(h, m, parts)
+    parts = [gc.tocab_partition(h, gc.GC_PULL, W, 16384 if W <= (1 << 15) else 4096) for W in widths]
+    gc.sched_attach(h, nets[0], parts)
+    gc.sched_attach_kind(h, 1, nets[1])
     d = torch().empty(g.n, dtype=torch().int32, device="cuda")
     srcs = gg.sources(g, 4, seed=8)
     mid = parts[widths.index(1 << 18)]
@@ -199,7 +214,7 @@ def test_trained_network_gains_over_heuristic():
             ms = 0.0
             for s in srcs:
                 best_ms = np.inf
-                for _ in range(2):
+                for _ in range(3):
                     torch().cuda.synchronize()
                     t0 = time.perf_counter()
                     fn(h, part, int(s), d, pol)
@@ -218,17 +233,14 @@ def test_trained_network_gains_over_heuristic():
               f"{total['always_pull']:.2f} ms -> gain {gains[kind][0]:.3f}x over the heuristic, "
               f"{gains[kind][1]:.3f}x over always-pull")
     gc.sched_attach(h, None)
-    m.free()
+    for m in nets.values():
+        m.free()
     for p in parts:
         p.free()
     h.free()
-    # the network learns from timings taken on this GPU, so its choices (and
-    # the gain) vary from box to box (on this small graph, runs measured
-    # between 0.78 and 0.94 of the heuristic's speed, while it wins on R-MAT
-    # 25 in the benchmark); the bar only catches a policy that is
-    # clearly worse than the heuristic or no better than always pulling
+    assert gains["sssp"][0] >= 1.05, gains
+    assert gains["bfs"][0] >= 0.9, gains
     for kind, (vs_heur, vs_pull) in gains.items():
-        assert vs_heur >= 0.6, (kind, vs_heur)
         assert vs_pull > 1.0, (kind, vs_pull)
 
 
@@ -244,7 +256,7 @@ def test_learned_pagerank_form():
     pagerank_learned on R-MAT 21. The form it picks gives ranks within L1
     1e-6 of the oracle after 20 iterations, and its time per iteration is no
     worse than that of the method without the network (the working-set
-    rule's TOCAB pull at 2^18) plus 20 % for timing noise."""
+    rule's TOCAB pull at 2^18)."""
     import time
     import paper_1904_02241_amd as gc
     widths = [1 << 15, 1 << 16, 1 << 18, 1 << 20]
@@ -298,7 +310,10 @@ def test_learned_pagerank_form():
           f"{[round(x * 1e3, 3) for x in fixed]}")
     fallback = fixed[2 + widths.index(1 << 18)]
     print(f"gain over the working-set rule's form: {fallback / learned:.2f}x")
-    assert learned <= 1.2 * fallback
+    # the network's picks are timed against the rule's form before one is
+    # kept, so the learned form is never the slower one (here 2^15 blocks,
+    # about 4x faster than the rule's 2^18)
+    assert learned <= fallback
 
     # a network without finite outputs: the working-set rule (TOCAB pull over
     # the attached width nearest 2^18)
@@ -337,5 +352,22 @@ def test_learned_pagerank_edges():
     np.testing.assert_allclose(f[0], gc.sched_features(g.n, g.m, g.n, g.m, 1, float(t[0][1]), g.m), rtol=1e-6)
     with pytest.raises(gc.GraphCageError):
         gc.sched_collect(h, [], 3, [0])
+    # per-kind networks: refused before sched_attach, on a wrong kind or K;
+    # a PageRank network attached for kind 2 decides pagerank_learned alone
+    two = gc.sched_create(2, np.full(gc.sched_param_count(2), np.nan, np.float32))
+    with pytest.raises(gc.GraphCageError):
+        gc.sched_attach_kind(h, 2, two)
+    gc.sched_attach(h, two, [])
+    with pytest.raises(gc.GraphCageError):
+        gc.sched_attach_kind(h, 3, two)
+    three = gc.sched_create(3, np.zeros(gc.sched_param_count(3), np.float32))
+    with pytest.raises(gc.GraphCageError):
+        gc.sched_attach_kind(h, 0, three)
+    gc.sched_attach_kind(h, 2, nan_net)
+    assert gc.pagerank_learned(h, 0.85, gc.GC_DANGLING_UNIFORM, rin, rout, 3) == 1
+    gc.sched_attach_kind(h, 2, None)
+    gc.sched_attach(h, None)
+    three.free()
+    two.free()
     nan_net.free()
     h.free()
