@@ -874,7 +874,7 @@ hipError_t build_partition(gc_tocab t, const int32_t* a_rowptr, const int32_t* a
   // padded for 4-wide reads, and past the pull's buffer resource (its range
   // check leaves out a store's scalar offset, at most 512 floats)
   t->partial = static_cast<float*>(dev_alloc(sizeof(float) * (Pn + 8 + 512), s));
-  t->pmin = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * Pn, s));
+  t->pmin = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * (Pn + 8), s));  // padded for 16-byte reads
   t->col = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * mn, s));
   if (t->weighted) t->w = static_cast<int32_t*>(dev_alloc(sizeof(int32_t) * mn, s));
   if (!t->id_map || !t->row_ptr || !t->partial || !t->pmin || !t->col || (t->weighted && !t->w))

@@ -118,10 +118,11 @@ struct gc_tocab_s {
   int32_t* chunk_ns = nullptr;    // [n_chunks] number of merge ranges the chunk's rows span
   int32_t n_chunks = 0;
   int32_t seg_max = 0;            // largest chunk_ns (sizes the work-group's LDS table)
-  int32_t* pmin = nullptr;        // [P] traversal partials (next flags / min)
+  int32_t* pmin = nullptr;        // [P + 8] traversal partials (next flags / min; range-major for SSSP over the stream layout)
   double* bc_part = nullptr;      // [P] BC path-count partials (allocated on first use)
   float* val32 = nullptr;         // [m_pad] FP32 arc values in stream order (first valued SpMV)
   int32_t* w_pad = nullptr;       // [m_pad] integer weights in stream order, 0 past m (first SSSP over the stream layout)
+  uint8_t* w8 = nullptr;          // [m_pad] the same as bytes, instead of w_pad when every weight lies in [0, 255]
   // Expanded contributions of a GC_PUSH partition with block sums in LDS
   // (W <= kPushLdsMaxWidth, B <= kPushExpandMaxBlocks): the work-group that
   // updates source block s writes the new contribution of each local row

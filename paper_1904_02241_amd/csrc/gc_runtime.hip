@@ -86,7 +86,7 @@ void free_tocab(gc_tocab t) {
   void* bufs[] = {t->blk_rowoff, t->row_ptr, t->id_map, t->col, t->w, t->range_ptr, t->partial, t->pmin,
                   t->tile_row, t->col16, t->chunk_beg, t->chunk_end, t->chunk_blk, t->wtile_row, t->id16,
                   t->heads, t->seg, t->rstart, t->id16s, t->chunk_j0, t->chunk_ns, t->bc_part,
-                  t->val32, t->w_pad, t->xid16, t->xperm, t->xstart, t->xc, t->pcol16, t->pheads};
+                  t->val32, t->w_pad, t->w8, t->xid16, t->xperm, t->xstart, t->xc, t->pcol16, t->pheads};
   for (void* p : bufs)
     if (p) gcx::dev_free(p, nullptr);
   delete t;

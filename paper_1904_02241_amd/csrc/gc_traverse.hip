@@ -51,22 +51,23 @@ constexpr int kDegLo = gcx::kStatDegLo;
 // serialise in L2 when most waves of a large grid append); positions follow
 // the thread order inside the work-group. Synchronises the work-group: every
 // thread must reach each call.
+template <int NT = kThreads>
 __device__ __forceinline__ void block_append(bool take, int32_t v, int32_t* __restrict__ queue,
                                              int32_t* __restrict__ qlen) {
-  __shared__ int32_t wave_cnt[kThreads / kWave];
-  __shared__ int32_t wave_off[kThreads / kWave];
+  __shared__ int32_t wave_cnt[NT / kWave];
+  __shared__ int32_t wave_off[NT / kWave];
   const uint64_t mask = __ballot(take);
   const int wid = threadIdx.x / kWave;
   if (gcd::lane_id() == 0) wave_cnt[wid] = __popcll(mask);
   __syncthreads();
   if (threadIdx.x == 0) {
     int32_t tot = 0;
-    for (int w = 0; w < kThreads / kWave; ++w) {
+    for (int w = 0; w < NT / kWave; ++w) {
       wave_off[w] = tot;
       tot += wave_cnt[w];
     }
     const int32_t base = tot ? atomicAdd(qlen, tot) : 0;
-    for (int w = 0; w < kThreads / kWave; ++w) wave_off[w] += base;
+    for (int w = 0; w < NT / kWave; ++w) wave_off[w] += base;
   }
   __syncthreads();
   if (take) queue[wave_off[wid] + __popcll(mask & gcd::lanemask_lt())] = v;
@@ -483,6 +484,7 @@ __global__ __launch_bounds__(kThreads) void k_sssp_tocab(const int32_t* __restri
 // (block-major, as the wide-block kernel writes it) is the minimum over
 // local row l's arcs, INT32_MAX when no source of the row is active.
 constexpr int kLdsRowThreads = 1024;
+constexpr int kSeekPad = 4;  // position-table entries past the chunk's ns ranges: sb[ns] (past the chunk), sentinels
 constexpr int kLdsRowWaves = kLdsRowThreads / kWave;
 constexpr int kRowTile = 512;  // arcs per wave tile: 8 per lane
 
@@ -495,15 +497,30 @@ struct MinTile {
   int32_t row0;     // local row holding the lane's arc 0 when it is no head (row before the first head)
 };
 
+// Weights of a stream-layout partition in its arc order: one byte each
+// when every weight lies in [0, 255] (k8), else int32.
+template <bool k8>
 __device__ __forceinline__ MinTile load_min_tile(const uint16_t* __restrict__ col16,
                                                  const gc_head_word* __restrict__ heads,
-                                                 const int32_t* __restrict__ w_pad, const int32_t* ad, int64_t q,
+                                                 const void* __restrict__ w_arcs, const int32_t* ad, int64_t q,
                                                  int lane, bool* ovf) {
   MinTile t;
   const int64_t tb = q * kRowTile;
   const tu32x4 cols = gcd::ld_stream(reinterpret_cast<const tu32x4*>(col16 + tb) + lane);
-  const ti32x4 wa = gcd::ld_stream(reinterpret_cast<const ti32x4*>(w_pad + tb) + 2 * lane);
-  const ti32x4 wb = gcd::ld_stream(reinterpret_cast<const ti32x4*>(w_pad + tb) + 2 * lane + 1);
+  ti32x4 wa, wb;
+  if (k8) {
+    const uint64_t w8 = gcd::ld_stream(reinterpret_cast<const uint64_t*>(static_cast<const uint8_t*>(w_arcs) + tb) +
+                                       lane);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      wa[e] = static_cast<int32_t>((w8 >> (8 * e)) & 0xFFu);
+      wb[e] = static_cast<int32_t>((w8 >> (8 * e + 32)) & 0xFFu);
+    }
+  } else {
+    const int32_t* w_pad = static_cast<const int32_t*>(w_arcs);
+    wa = gcd::ld_stream(reinterpret_cast<const ti32x4*>(w_pad + tb) + 2 * lane);
+    wb = gcd::ld_stream(reinterpret_cast<const ti32x4*>(w_pad + tb) + 2 * lane + 1);
+  }
   const tu32x4 hw = *reinterpret_cast<const tu32x4*>(heads + (tb >> 6) + (lane >> 3));
   const uint64_t bits = static_cast<uint64_t>(hw[0]) | (static_cast<uint64_t>(hw[1]) << 32);
   const int sub = lane & 7;
@@ -523,20 +540,35 @@ __device__ __forceinline__ MinTile load_min_tile(const uint16_t* __restrict__ co
   return t;
 }
 
+template <bool k8>
 __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
     const int32_t* __restrict__ row_ptr, const uint16_t* __restrict__ col16, const gc_head_word* __restrict__ heads,
-    const int32_t* __restrict__ w_pad, const int32_t* __restrict__ chunk_beg, const int32_t* __restrict__ chunk_end,
-    const int32_t* __restrict__ chunk_blk, int32_t log2W, int32_t n, const uint32_t* __restrict__ front,
+    const void* __restrict__ w_arcs, const int32_t* __restrict__ chunk_beg, const int32_t* __restrict__ chunk_end,
+    const int32_t* __restrict__ chunk_blk, const int32_t* __restrict__ chunk_j0, const int32_t* __restrict__ chunk_ns,
+    const int2* __restrict__ seg, int32_t R, int32_t log2W, int32_t n, const uint32_t* __restrict__ front,
     const int32_t* __restrict__ dist, int32_t* __restrict__ pmin, int32_t* __restrict__ stats) {
   extern __shared__ int32_t ad[];
   const int32_t ch = blockIdx.x;
-  const int32_t r0 = chunk_beg[ch], r1 = chunk_end[ch], b = chunk_blk[ch];
+  const int32_t r0 = chunk_beg[ch], r1 = chunk_end[ch], b = chunk_blk[ch], j0 = chunk_j0[ch], ns = chunk_ns[ch];
   if (r0 >= r1) return;  // padding of the dispatch order (uniform)
   const int32_t W = 1 << log2W, v0 = b << log2W, cnt = min(W, n - v0);
   for (int32_t i = threadIdx.x; i < W; i += kLdsRowThreads) {
     int32_t a = kInf;
     if (i < cnt && bit_test(front, v0 + i)) a = dist[v0 + i];
     ad[i] = a;
+  }
+  // the chunk's part of the position table: sb[i] = first row of merge range
+  // j0 + i, sd[i] = its shift to the range-major index; sb[ns] lies past the
+  // chunk, then sentinels
+  int32_t* sb = ad + W;
+  int32_t* sd = sb + ns + kSeekPad;
+  {
+    const int2* sg = seg + static_cast<int64_t>(b) * (R + 1) + j0;
+    for (int32_t i = threadIdx.x; i < ns + kSeekPad; i += kLdsRowThreads) {
+      const int2 e = i <= ns ? sg[i] : make_int2(INT32_MAX, 0);
+      sb[i] = e.x;
+      sd[i] = e.y;
+    }
   }
   __syncthreads();
   const int lane = gcd::lane_id();
@@ -551,8 +583,9 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
   bool ovf = false;
   int32_t carry = kInf;  // minimum so far of the row open at the previous tile's end
   int32_t open_row = -1;
+  int32_t jw = 0;  // merge range of the wave's rows so far (ranges ascend with rows)
   for (int32_t q = qa; q <= qz; ++q) {
-    const MinTile t = load_min_tile(col16, heads, w_pad, ad, q, lane, &ovf);
+    const MinTile t = load_min_tile<k8>(col16, heads, w_arcs, ad, q, lane, &ovf);
     // lane-local runs: reset at every head; lane 0 starts from the carry
     int32_t run = (lane == 0) ? carry : kInf;
     int32_t rv[8];
@@ -575,6 +608,28 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
     }
     const int32_t in = __shfl_up(A, 1, kWave);  // the row flowing into this lane
     const int32_t lin = lane == 0 ? kInf : in;
+    // Merge range of the rows this lane may store (those of its arcs 0 .. 7,
+    // rows rlo .. rhi): the wave walks the range boundaries inside the
+    // tile's rows once (the same LDS word for every lane), each lane
+    // counting those at or below its first and last row. A lane whose rows
+    // stay in one range (almost all: a range holds tens to hundreds of a
+    // block's rows) stores with one shift; one that crosses a boundary
+    // looks each row's range up.
+    const int32_t rlo = t.row0 + static_cast<int32_t>(t.my9 & 1u);
+    const int32_t rhi = t.row0 + __popc(t.my9 & 0xFFu);
+    const int32_t maxrow = __builtin_amdgcn_readlane(rhi, kWave - 1);
+    int32_t cf = 0, cl = 0, kb = jw + 1;
+    for (;;) {
+      const int32_t bnd = sb[kb];
+      if (bnd > maxrow) break;  // uniform
+      cf += rlo >= bnd;
+      cl += rhi >= bnd;
+      ++kb;
+    }
+    const int32_t jf = jw + cf;
+    const bool cross = jw + cl != jf;
+    const int32_t d0 = sd[jf];
+    jw = kb - 1;
     int32_t row = t.row0;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -583,7 +638,15 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
       if ((t.my9 >> (e + 1)) & 1u) {  // arc e ends its row
         const bool started_here = (t.my9 & ((2u << e) - 1u)) != 0u;
         const int32_t v = started_here ? rv[e] : min(rv[e], lin);
-        if (row >= own0 && row < r1) pmin[row] = v;
+        if (row >= own0 && row < r1) {
+          int32_t d = d0;
+          if (cross) {
+            int32_t j = jf;
+            while (sb[j + 1] <= row) ++j;
+            d = sd[j];
+          }
+          pmin[row + d] = v;  // stored at the row's range-major index
+        }
       }
     }
     carry = __builtin_amdgcn_readlane(A, kWave - 1);
@@ -594,7 +657,7 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
   const bool continues = !((heads[end_arc >> 6].bits) & 1ull);
   if (continues && open_row >= own0 && open_row < r1) {
     for (int64_t q = qz + 1;; ++q) {
-      const MinTile t = load_min_tile(col16, heads, w_pad, ad, q, lane, &ovf);
+      const MinTile t = load_min_tile<k8>(col16, heads, w_arcs, ad, q, lane, &ovf);
       // arcs before the tile's first head belong to the open row
       const int fh = (t.my9 & 0xFFu) ? __ffs(t.my9 & 0xFFu) - 1 : 8;  // first head in the lane
       const uint64_t hl = __ballot(fh < 8);
@@ -606,9 +669,97 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
       carry = min(carry, gcd::wave_min(mine));
       if (first_lane < kWave) break;  // bits past the last arc are set, so this ends
     }
-    if (lane == 0) pmin[open_row] = carry;
+    if (lane == 0) {
+      int32_t j = jw;
+      while (sb[j + 1] <= open_row) ++j;
+      pmin[open_row + sd[j]] = carry;
+    }
   }
   if (__any(ovf) && lane == 0) stats[kOverflow] = 1;
+}
+
+// Figure 5 merge of the stream-layout SSSP partial minima, read as streams:
+// range j's partials of every block are one contiguous slice [rstart[j],
+// rstart[j+1]) of pmin / id16s (the position table's range-major order). A
+// persistent work-group (two per CU) walks ranges j = blockIdx.x,
+// blockIdx.x + gridDim.x, ...: 16-byte / 8-byte loads of 4 entries, LDS
+// minima, then the range's vertices are updated (distance, next status
+// bit, queue) and the minima reset for the next range, whose first loads
+// are issued before that update.
+template <int K, int NT>
+__global__ __launch_bounds__(NT) void k_sssp_merge_stream(const int32_t* __restrict__ rstart,
+                                                          const uint16_t* __restrict__ id16s,
+                                                          const int32_t* __restrict__ pmin, int32_t R, int32_t n,
+                                                          int32_t* __restrict__ dist, uint32_t* __restrict__ next,
+                                                          int32_t* __restrict__ queue, int32_t* __restrict__ stats) {
+  __shared__ int32_t best[K];
+  for (int i = threadIdx.x; i < K; i += NT) best[i] = kInf;
+  __syncthreads();
+  const ti32x4* p4 = reinterpret_cast<const ti32x4*>(pmin);
+  const uint64_t* i4 = reinterpret_cast<const uint64_t*>(id16s);
+  constexpr int kU = 4;  // groups of 4 entries per thread and step (two register sets in turn)
+  constexpr int32_t kStep = NT * kU;
+  ti32x4 pa[kU], pb[kU];
+  uint64_t ia[kU], ib[kU];
+  int32_t a = 0, z = 0, g0 = 0, g1 = 0;
+  auto bounds = [&](int32_t j) {
+    a = rstart[j];
+    z = rstart[j + 1];
+    g0 = a >> 2;
+    g1 = (z + 3) >> 2;
+  };
+  // loads clamped to the range's last group: no branch, so the compiler's
+  // count of outstanding loads holds on every path
+  auto load = [&](int32_t g, ti32x4 (&p)[kU], uint64_t (&id)[kU]) {
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      const int32_t gg = min(g + k * NT, g1 - 1);
+      p[k] = gcd::ld_stream(p4 + gg);
+      id[k] = gcd::ld_stream(i4 + gg);
+    }
+  };
+  auto take = [&](int32_t g, const ti32x4 (&p)[kU], const uint64_t (&id)[kU]) {
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      const int32_t e0 = 4 * (g + k * NT);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (e0 + e >= a && e0 + e < z && p[k][e] != kInf) atomicMin(&best[(id[k] >> (16 * e)) & 0xFFFFu], p[k][e]);
+    }
+  };
+  const int32_t tid = threadIdx.x;
+  int32_t j = blockIdx.x;
+  if (j < R) {
+    bounds(j);
+    if (g0 < g1) load(g0 + tid, pa, ia);  // uniform
+  }
+  for (; j < R; j += gridDim.x) {
+    for (int32_t g = g0 + tid; g < g1; g += 2 * kStep) {
+      load(g + kStep, pb, ib);
+      take(g, pa, ia);
+      load(g + 2 * kStep, pa, ia);
+      take(g + kStep, pb, ib);
+    }
+    __syncthreads();
+    const int32_t v0 = j * K;
+    const int32_t jn = j + gridDim.x;
+    if (jn < R) {  // uniform: the next range's first loads, in flight during the update
+      bounds(jn);
+      if (g0 < g1) load(g0 + tid, pa, ia);
+    }
+    for (int i = tid; i < K; i += NT) {  // every thread the same count: block_append synchronises
+      const int32_t v = v0 + i;
+      bool improved = false;
+      if (v < n && best[i] < dist[v]) {
+        dist[v] = best[i];
+        bit_set(next, v);
+        improved = true;
+      }
+      best[i] = kInf;
+      block_append<NT>(improved, v, queue, stats + kQLen);
+    }
+    __syncthreads();
+  }
 }
 
 template <int K, bool kFlat>
@@ -1268,16 +1419,85 @@ struct SsspMerge {
   }
 };
 
+// Compute units of the GPU (read once).
+int32_t device_cus() {
+  static const int32_t cus = [] {
+    int dev = 0, c = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || c <= 0)
+      c = 256;
+    return c;
+  }();
+  return cus;
+}
+
+template <int K>
+struct SsspMergeStream {
+  static constexpr int kNT = K >= 8192 ? 1024 : 512;  // LDS minima of K int32: two work-groups per CU
+  template <class... A>
+  static void run(int32_t R, hipStream_t s, A... a) {
+    const int32_t grid = std::max(1, std::min(R, 2 * device_cus()));
+    k_sssp_merge_stream<K, kNT><<<grid, kNT, 0, s>>>(a...);
+  }
+};
+
+// *flag = 1 if a weight lies outside [0, 255].
+__global__ void k_weight_range(const int32_t* __restrict__ w, int64_t m, int32_t* __restrict__ flag) {
+  bool wide = false;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < m;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    wide |= static_cast<uint32_t>(w[i]) > 255u;
+  if (__any(wide) && gcd::lane_id() == 0) *flag = 1;
+}
+
+// Weights as bytes in arc order, zero past m.
+__global__ void k_weight_bytes(const int32_t* __restrict__ w, int64_t m, int64_t m_pad, uint8_t* __restrict__ w8) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < m_pad;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    w8[i] = i < m ? static_cast<uint8_t>(w[i]) : 0;
+}
+
+// One device int32 for the weight check (per process, allocated once).
+int32_t* g_range_flag() {
+  static int32_t* flag = [] {
+    void* p = nullptr;
+    return hipMalloc(&p, sizeof(int32_t)) == hipSuccess ? static_cast<int32_t*>(p) : nullptr;
+  }();
+  return flag;
+}
+
 // Integer weights of a stream-layout partition in its arc order, padded with
 // zeros to the layout's length (built by the first SSSP round over it), and
 // the LDS limit of the kernel that reads them.
 hipError_t stream_weights(gc_tocab t, hipStream_t s) {
-  static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sssp_tocab_lds),
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                     static_cast<int>(sizeof(int32_t)) * gcx::kLdsMaxWidth);
+  static const hipError_t attr = [] {
+    const int lds = gcx::lds_budget(gcx::kLdsMaxWidth);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sssp_tocab_lds<true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sssp_tocab_lds<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    return e;
+  }();
   GC_HIP_TRY(attr);
-  if (t->w_pad) return hipSuccess;
+  if (t->w_pad || t->w8) return hipSuccess;
   if (!t->w) return hipErrorInvalidValue;
+  // one byte per weight when every weight fits (checked once, on the device)
+  int32_t* flag = g_range_flag();
+  if (!flag) return hipErrorOutOfMemory;
+  GC_HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+  if (t->m > 0) k_weight_range<<<grid_for(t->m, kThreads), kThreads, 0, s>>>(t->w, t->m, flag);
+  GC_HIP_TRY(hipGetLastError());
+  int32_t wide = 0;
+  GC_HIP_TRY(hipMemcpyAsync(&wide, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GC_HIP_TRY(hipStreamSynchronize(s));
+  if (!wide) {
+    t->w8 = static_cast<uint8_t*>(gcx::dev_alloc(static_cast<size_t>(t->m_pad), s));
+    if (!t->w8) return hipErrorOutOfMemory;
+    t->bytes += t->m_pad;
+    k_weight_bytes<<<grid_for(t->m_pad, kThreads), kThreads, 0, s>>>(t->w, t->m, t->m_pad, t->w8);
+    return hipGetLastError();
+  }
   t->w_pad = static_cast<int32_t*>(gcx::dev_alloc(sizeof(int32_t) * static_cast<size_t>(t->m_pad), s));
   if (!t->w_pad) return hipErrorOutOfMemory;
   t->bytes += static_cast<int64_t>(sizeof(int32_t)) * t->m_pad;
@@ -1417,13 +1637,26 @@ hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t 
       k_sssp_pull<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, g->t_w, n, f.front(), value,
                                                               f.next(), f.queue_next(), g->stats);
     } else {
-      if (t->col16) {  // stream layout: the block's distances in LDS
+      if (t->col16) {  // stream layout: the block's distances in LDS, partial minima range-major
         GC_HIP_TRY(stream_weights(t, s));
-        ProfScope prof("sssp_tocab", s);
-        if (t->n_chunks > 0)
-          k_sssp_tocab_lds<<<t->n_chunks, kLdsRowThreads, sizeof(int32_t) * static_cast<size_t>(t->W), s>>>(
-              t->row_ptr, t->col16, t->heads, t->w_pad, t->chunk_beg, t->chunk_end, t->chunk_blk, t->log2W, n,
-              f.front(), value, t->pmin, g->stats);
+        {
+          ProfScope prof("sssp_tocab", s);
+          const size_t lds = sizeof(int32_t) * (static_cast<size_t>(t->W) + 2 * (t->seg_max + kSeekPad));
+          if (t->n_chunks > 0 && t->w8)
+            k_sssp_tocab_lds<true><<<t->n_chunks, kLdsRowThreads, lds, s>>>(
+                t->row_ptr, t->col16, t->heads, t->w8, t->chunk_beg, t->chunk_end, t->chunk_blk, t->chunk_j0,
+                t->chunk_ns, t->seg, t->R, t->log2W, n, f.front(), value, t->pmin, g->stats);
+          else if (t->n_chunks > 0)
+            k_sssp_tocab_lds<false><<<t->n_chunks, kLdsRowThreads, lds, s>>>(
+                t->row_ptr, t->col16, t->heads, t->w_pad, t->chunk_beg, t->chunk_end, t->chunk_blk, t->chunk_j0,
+                t->chunk_ns, t->seg, t->R, t->log2W, n, f.front(), value, t->pmin, g->stats);
+        }
+        ProfScope prof("sssp_merge", s);
+        GC_HIP_TRY((launch_by_k<SsspMergeStream>(t->k, t->R, s, static_cast<const int32_t*>(t->rstart),
+                                                 static_cast<const uint16_t*>(t->id16s),
+                                                 static_cast<const int32_t*>(t->pmin), t->R, n, value, f.next(),
+                                                 f.queue_next(), g->stats)));
+        return hipGetLastError();
       } else {
         ProfScope prof("sssp_tocab", s);
         k_sssp_tocab<<<row_grid(t->P), kThreads, 0, s>>>(t->row_ptr, t->col, t->w, t->P, f.front(), value,

@@ -76,6 +76,38 @@ def test_sssp_bit_exact(name, policy, tocab):
     h.free()
 
 
+@pytest.mark.parametrize("W,k", [(1 << 10, 1024), (1 << 15, 16384)])
+def test_sssp_wide_weights_stream_layout(W, k):
+    """Weights above 255 keep the int32 weight stream of the stream-layout
+    SSSP pull (weights in [0, 255] are read as bytes); TOCAB pull and the
+    heuristic stay bit-exact either way, and a path length past INT32_MAX is
+    reported from the TOCAB pull as from the other forms."""
+    import paper_1904_02241_amd as gc
+    g = gg.rmat(14, 16, seed=12)
+    rng = np.random.default_rng(5)
+    g.weights = rng.integers(1, 100000, g.m, dtype=np.int32)
+    h = load(g, weights=True)
+    part = gc.tocab_partition(h, gc.GC_PULL, W, k)
+    dist = torch().empty(g.n, dtype=torch().int32, device="cuda")
+    for s in gg.sources(g, 3, seed=3):
+        want = oracle.dijkstra(g.n, g.rowptr, g.colidx, g.weights, s)
+        for pol in (gc.GC_POLICY_PULL, gc.GC_POLICY_HEURISTIC):
+            gc.sssp_pull(h, part, int(s), dist, pol)
+            np.testing.assert_array_equal(host(dist), want)
+    part.free()
+    h.free()
+    c = graphs.chain(5)
+    c.weights = np.full(c.m, 1 << 30, np.int32)
+    hc = load(c, weights=True)
+    pc = gc.tocab_partition(hc, gc.GC_PULL, 1 << 10, 1024)
+    d = torch().empty(c.n, dtype=torch().int32, device="cuda")
+    with pytest.raises(gc.GraphCageError) as e:
+        gc.sssp_pull(hc, pc, 0, d, gc.GC_POLICY_PULL)
+    assert e.value.code == gc.GC_EOVERFLOW
+    pc.free()
+    hc.free()
+
+
 def test_bfs_equals_unit_weight_sssp():
     import paper_1904_02241_amd as gc
     g = gg.rmat(14, 16, seed=9)
