@@ -49,6 +49,11 @@ def kernel_bytes(name, n, m, info):
         return 4 * P + 2 * P + 4 * (R + 1) * B + 4 * (n + 1) + 4 * n
     if name == "pr_plain_pull":  # in-CSR + c once + outdeg + c' writes
         return 4 * m + 4 * (n + 1) + 4 * n + 4 * (n + 1) + 4 * n
+    if name == "pr_tocab_push" and 0 < info.get("W", 0) <= (1 << 14) and info.get("k", 0) <= info.get("W", 0):
+        # expanded contributions: 16-bit columns + head words + one contribution per local row read,
+        # then the block's new contributions written to its rows (16-bit source offsets + FP32 values)
+        # + outdeg (rowptr) of the updated vertices
+        return 2 * m + m // 4 + 4 * P + 2 * P + 4 * P + 4 * (n + 1)
     if name in ("pr_tocab_push", "pr_plain_push"):  # col + row_ptr (+ id_map) + c + sums line per arc...
         extra = 4 * P if name == "pr_tocab_push" else 0
         rows = P if name == "pr_tocab_push" else n
@@ -159,6 +164,9 @@ def mall_from_profiles():
     if not os.path.exists(path):
         return {"status": "unmeasured"}
     text = open(path).read()
+    st = re.search(r"^status:\s*(.+)$", text, re.M)
+    if st:
+        return {"status": st.group(1).strip(), "evidence": "profiles/mall_requests.md"}
     rows = re.findall(r"^mall:\s*(\S+)\s+([0-9.]+)\s+([0-9.]+)", text, re.M)
     if not rows:
         return {"status": "unmeasured"}
