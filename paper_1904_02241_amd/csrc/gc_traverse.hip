@@ -497,9 +497,11 @@ struct MinTile {
   int32_t row0;     // local row holding the lane's arc 0 when it is no head (row before the first head)
 };
 
-// Weights of a stream-layout partition in its arc order: one byte each
-// when every weight lies in [0, 255] (k8), else int32.
-template <bool k8>
+// Weights of a stream-layout partition in its arc order (kW): int32
+// (kW32), one byte each when every weight lies in [0, 255] (kW8), or none:
+// BFS, whose candidates are the sources' own values (0 when in the frontier).
+constexpr int kW32 = 0, kW8 = 1, kWNone = 2;
+template <int kW>
 __device__ __forceinline__ MinTile load_min_tile(const uint16_t* __restrict__ col16,
                                                  const gc_head_word* __restrict__ heads,
                                                  const void* __restrict__ w_arcs, const int32_t* ad, int64_t q,
@@ -507,8 +509,8 @@ __device__ __forceinline__ MinTile load_min_tile(const uint16_t* __restrict__ co
   MinTile t;
   const int64_t tb = q * kRowTile;
   const tu32x4 cols = gcd::ld_stream(reinterpret_cast<const tu32x4*>(col16 + tb) + lane);
-  ti32x4 wa, wb;
-  if (k8) {
+  ti32x4 wa = {0, 0, 0, 0}, wb = {0, 0, 0, 0};
+  if (kW == kW8) {
     const uint64_t w8 = gcd::ld_stream(reinterpret_cast<const uint64_t*>(static_cast<const uint8_t*>(w_arcs) + tb) +
                                        lane);
 #pragma unroll
@@ -516,7 +518,7 @@ __device__ __forceinline__ MinTile load_min_tile(const uint16_t* __restrict__ co
       wa[e] = static_cast<int32_t>((w8 >> (8 * e)) & 0xFFu);
       wb[e] = static_cast<int32_t>((w8 >> (8 * e + 32)) & 0xFFu);
     }
-  } else {
+  } else if (kW == kW32) {
     const int32_t* w_pad = static_cast<const int32_t*>(w_arcs);
     wa = gcd::ld_stream(reinterpret_cast<const ti32x4*>(w_pad + tb) + 2 * lane);
     wb = gcd::ld_stream(reinterpret_cast<const ti32x4*>(w_pad + tb) + 2 * lane + 1);
@@ -540,7 +542,7 @@ __device__ __forceinline__ MinTile load_min_tile(const uint16_t* __restrict__ co
   return t;
 }
 
-template <bool k8>
+template <int kW>
 __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
     const int32_t* __restrict__ row_ptr, const uint16_t* __restrict__ col16, const gc_head_word* __restrict__ heads,
     const void* __restrict__ w_arcs, const int32_t* __restrict__ chunk_beg, const int32_t* __restrict__ chunk_end,
@@ -554,7 +556,7 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
   const int32_t W = 1 << log2W, v0 = b << log2W, cnt = min(W, n - v0);
   for (int32_t i = threadIdx.x; i < W; i += kLdsRowThreads) {
     int32_t a = kInf;
-    if (i < cnt && bit_test(front, v0 + i)) a = dist[v0 + i];
+    if (i < cnt && bit_test(front, v0 + i)) a = kW == kWNone ? 0 : dist[v0 + i];
     ad[i] = a;
   }
   // the chunk's part of the position table: sb[i] = first row of merge range
@@ -585,7 +587,7 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
   int32_t open_row = -1;
   int32_t jw = 0;  // merge range of the wave's rows so far (ranges ascend with rows)
   for (int32_t q = qa; q <= qz; ++q) {
-    const MinTile t = load_min_tile<k8>(col16, heads, w_arcs, ad, q, lane, &ovf);
+    const MinTile t = load_min_tile<kW>(col16, heads, w_arcs, ad, q, lane, &ovf);
     // lane-local runs: reset at every head; lane 0 starts from the carry
     int32_t run = (lane == 0) ? carry : kInf;
     int32_t rv[8];
@@ -657,7 +659,7 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
   const bool continues = !((heads[end_arc >> 6].bits) & 1ull);
   if (continues && open_row >= own0 && open_row < r1) {
     for (int64_t q = qz + 1;; ++q) {
-      const MinTile t = load_min_tile<k8>(col16, heads, w_arcs, ad, q, lane, &ovf);
+      const MinTile t = load_min_tile<kW>(col16, heads, w_arcs, ad, q, lane, &ovf);
       // arcs before the tile's first head belong to the open row
       const int fh = (t.my9 & 0xFFu) ? __ffs(t.my9 & 0xFFu) - 1 : 8;  // first head in the lane
       const uint64_t hl = __ballot(fh < 8);
@@ -686,12 +688,13 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
 // minima, then the range's vertices are updated (distance, next status
 // bit, queue) and the minima reset for the next range, whose first loads
 // are issued before that update.
-template <int K, int NT>
+template <int K, int NT, bool kBfs>
 __global__ __launch_bounds__(NT) void k_sssp_merge_stream(const int32_t* __restrict__ rstart,
                                                           const uint16_t* __restrict__ id16s,
                                                           const int32_t* __restrict__ pmin, int32_t R, int32_t n,
                                                           int32_t* __restrict__ dist, uint32_t* __restrict__ next,
-                                                          int32_t* __restrict__ queue, int32_t* __restrict__ stats) {
+                                                          int32_t* __restrict__ queue, int32_t* __restrict__ stats,
+                                                          int32_t level, uint32_t* __restrict__ visited) {
   __shared__ int32_t best[K];
   for (int i = threadIdx.x; i < K; i += NT) best[i] = kInf;
   __syncthreads();
@@ -750,7 +753,14 @@ __global__ __launch_bounds__(NT) void k_sssp_merge_stream(const int32_t* __restr
     for (int i = tid; i < K; i += NT) {  // every thread the same count: block_append synchronises
       const int32_t v = v0 + i;
       bool improved = false;
-      if (v < n && best[i] < dist[v]) {
+      if (kBfs) {  // depth: a vertex not yet reached with an in-neighbour in the frontier
+        if (v < n && best[i] == 0 && !bit_test(visited, v)) {
+          dist[v] = level + 1;
+          bit_set(next, v);
+          bit_set(visited, v);
+          improved = true;
+        }
+      } else if (v < n && best[i] < dist[v]) {
         dist[v] = best[i];
         bit_set(next, v);
         improved = true;
@@ -1437,7 +1447,17 @@ struct SsspMergeStream {
   template <class... A>
   static void run(int32_t R, hipStream_t s, A... a) {
     const int32_t grid = std::max(1, std::min(R, 2 * device_cus()));
-    k_sssp_merge_stream<K, kNT><<<grid, kNT, 0, s>>>(a...);
+    k_sssp_merge_stream<K, kNT, false><<<grid, kNT, 0, s>>>(a...);
+  }
+};
+
+template <int K>
+struct BfsMergeStream {
+  static constexpr int kNT = SsspMergeStream<K>::kNT;
+  template <class... A>
+  static void run(int32_t R, hipStream_t s, A... a) {
+    const int32_t grid = std::max(1, std::min(R, 2 * device_cus()));
+    k_sssp_merge_stream<K, kNT, true><<<grid, kNT, 0, s>>>(a...);
   }
 };
 
@@ -1469,17 +1489,23 @@ int32_t* g_range_flag() {
 // Integer weights of a stream-layout partition in its arc order, padded with
 // zeros to the layout's length (built by the first SSSP round over it), and
 // the LDS limit of the kernel that reads them.
-hipError_t stream_weights(gc_tocab t, hipStream_t s) {
+// The LDS limit of the stream-layout traversal pull (a block's values and
+// its chunk's position table).
+hipError_t stream_pull_setup() {
   static const hipError_t attr = [] {
     const int lds = gcx::lds_budget(gcx::kLdsMaxWidth);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sssp_tocab_lds<true>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sssp_tocab_lds<false>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipError_t e = hipSuccess;
+    for (const void* k : {reinterpret_cast<const void*>(&k_sssp_tocab_lds<kW32>),
+                          reinterpret_cast<const void*>(&k_sssp_tocab_lds<kW8>),
+                          reinterpret_cast<const void*>(&k_sssp_tocab_lds<kWNone>)})
+      if (e == hipSuccess) e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     return e;
   }();
-  GC_HIP_TRY(attr);
+  return attr;
+}
+
+hipError_t stream_weights(gc_tocab t, hipStream_t s) {
+  GC_HIP_TRY(stream_pull_setup());
   if (t->w_pad || t->w8) return hipSuccess;
   if (!t->w) return hipErrorInvalidValue;
   // one byte per weight when every weight fits (checked once, on the device)
@@ -1610,6 +1636,24 @@ hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t 
       ProfScope prof("bfs_pull", s);
       k_bfs_pull<<<grid_for(n, kThreads), kThreads, 0, s>>>(g->t_rowptr, g->t_colidx, n, f.front(), value, level,
                                                              f.next(), g->visited, f.queue_next(), g->stats);
+    } else if (t->col16) {
+      // stream layout: the block's frontier bits (as 0 / INT32_MAX) in LDS,
+      // per-(row, block) minima stored range-major (0: an in-neighbour of
+      // the row is in the frontier), merged as one stream per range
+      GC_HIP_TRY(stream_pull_setup());
+      {
+        ProfScope prof("bfs_tocab", s);
+        const size_t lds = sizeof(int32_t) * (static_cast<size_t>(t->W) + 2 * (t->seg_max + kSeekPad));
+        if (t->n_chunks > 0)
+          k_sssp_tocab_lds<kWNone><<<t->n_chunks, kLdsRowThreads, lds, s>>>(
+              t->row_ptr, t->col16, t->heads, nullptr, t->chunk_beg, t->chunk_end, t->chunk_blk, t->chunk_j0,
+              t->chunk_ns, t->seg, t->R, t->log2W, n, f.front(), nullptr, t->pmin, g->stats);
+      }
+      ProfScope prof("bfs_merge", s);
+      GC_HIP_TRY((launch_by_k<BfsMergeStream>(t->k, t->R, s, static_cast<const int32_t*>(t->rstart),
+                                              static_cast<const uint16_t*>(t->id16s),
+                                              static_cast<const int32_t*>(t->pmin), t->R, n, value, f.next(),
+                                              f.queue_next(), g->stats, level, g->visited)));
     } else {
       uint8_t* flag = reinterpret_cast<uint8_t*>(t->pmin);
       {
@@ -1643,11 +1687,11 @@ hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t 
           ProfScope prof("sssp_tocab", s);
           const size_t lds = sizeof(int32_t) * (static_cast<size_t>(t->W) + 2 * (t->seg_max + kSeekPad));
           if (t->n_chunks > 0 && t->w8)
-            k_sssp_tocab_lds<true><<<t->n_chunks, kLdsRowThreads, lds, s>>>(
+            k_sssp_tocab_lds<kW8><<<t->n_chunks, kLdsRowThreads, lds, s>>>(
                 t->row_ptr, t->col16, t->heads, t->w8, t->chunk_beg, t->chunk_end, t->chunk_blk, t->chunk_j0,
                 t->chunk_ns, t->seg, t->R, t->log2W, n, f.front(), value, t->pmin, g->stats);
           else if (t->n_chunks > 0)
-            k_sssp_tocab_lds<false><<<t->n_chunks, kLdsRowThreads, lds, s>>>(
+            k_sssp_tocab_lds<kW32><<<t->n_chunks, kLdsRowThreads, lds, s>>>(
                 t->row_ptr, t->col16, t->heads, t->w_pad, t->chunk_beg, t->chunk_end, t->chunk_blk, t->chunk_j0,
                 t->chunk_ns, t->seg, t->R, t->log2W, n, f.front(), value, t->pmin, g->stats);
         }
@@ -1655,7 +1699,7 @@ hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t 
         GC_HIP_TRY((launch_by_k<SsspMergeStream>(t->k, t->R, s, static_cast<const int32_t*>(t->rstart),
                                                  static_cast<const uint16_t*>(t->id16s),
                                                  static_cast<const int32_t*>(t->pmin), t->R, n, value, f.next(),
-                                                 f.queue_next(), g->stats)));
+                                                 f.queue_next(), g->stats, level, g->visited)));
         return hipGetLastError();
       } else {
         ProfScope prof("sssp_tocab", s);
