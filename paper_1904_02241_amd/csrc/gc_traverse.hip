@@ -491,6 +491,27 @@ constexpr int kRowTile = 512;  // arcs per wave tile: 8 per lane
 typedef uint32_t tu32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t ti32x4 __attribute__((ext_vector_type(4)));
 
+// Value a DPP control moves into each lane; INT32_MAX (the identity of the
+// minimum) where the move has no source lane or the lane's row is masked off.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int32_t dpp_in(int32_t a) {
+  return __builtin_amdgcn_update_dpp(kInf, a, kCtrl, kRowMask, 0xF, false);
+}
+
+// Lanes of the wave selected by a mask held in scalar registers.
+__device__ __forceinline__ bool lane_in_mask(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// One step of a wave-wide segmented inclusive minimum: a lane outside F
+// (no head met yet within the reach of the steps so far) takes the minimum
+// with the value the DPP control moves in. The move is made by every lane
+// before the select: under a narrower EXEC mask it could not read the
+// values of the lanes in F.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ void seg_min_step(int32_t& A, uint64_t F) {
+  const int32_t m = min(A, dpp_in<kCtrl, kRowMask>(A));
+  A = lane_in_mask(F) ? A : m;
+}
+
 struct MinTile {
   int32_t x[8];     // candidates of the lane's 8 arcs
   uint32_t my9;     // head bits of the lane's arcs, bit 8: the arc after them
@@ -501,45 +522,73 @@ struct MinTile {
 // (kW32), one byte each when every weight lies in [0, 255] (kW8), or none:
 // BFS, whose candidates are the sources' own values (0 when in the frontier).
 constexpr int kW32 = 0, kW8 = 1, kWNone = 2;
+// A tile's raw streams for one lane: its 8 columns, its head word and its
+// 8 weights (as loaded), so that the loads of later tiles can be issued
+// before an earlier tile is reduced.
+struct RawTile {
+  tu32x4 cols;
+  tu32x4 hw;
+  ti32x4 wa, wb;  // int32 weights (kW32)
+  uint64_t w8;    // byte weights (kW8)
+};
+
+template <int kW>
+__device__ __forceinline__ RawTile load_raw_tile(const uint16_t* __restrict__ col16,
+                                                 const gc_head_word* __restrict__ heads,
+                                                 const void* __restrict__ w_arcs, int64_t q, int lane) {
+  RawTile r;
+  const int64_t tb = q * kRowTile;
+  r.cols = gcd::ld_stream(reinterpret_cast<const tu32x4*>(col16 + tb) + lane);
+  r.w8 = 0;
+  r.wa = ti32x4{0, 0, 0, 0};
+  r.wb = ti32x4{0, 0, 0, 0};
+  if (kW == kW8) {
+    r.w8 = gcd::ld_stream(reinterpret_cast<const uint64_t*>(static_cast<const uint8_t*>(w_arcs) + tb) + lane);
+  } else if (kW == kW32) {
+    const int32_t* w_pad = static_cast<const int32_t*>(w_arcs);
+    r.wa = gcd::ld_stream(reinterpret_cast<const ti32x4*>(w_pad + tb) + 2 * lane);
+    r.wb = gcd::ld_stream(reinterpret_cast<const ti32x4*>(w_pad + tb) + 2 * lane + 1);
+  }
+  r.hw = *reinterpret_cast<const tu32x4*>(heads + (tb >> 6) + (lane >> 3));
+  return r;
+}
+
+// The lane's candidates ad[col] + w and its row structure from a raw tile.
+template <int kW>
+__device__ __forceinline__ MinTile finish_min_tile(const RawTile& r, const int32_t* ad, int lane, bool* ovf) {
+  MinTile t;
+  const uint64_t bits = static_cast<uint64_t>(r.hw[0]) | (static_cast<uint64_t>(r.hw[1]) << 32);
+  const int sub = lane & 7;
+  const uint32_t after = sub < 7 ? static_cast<uint32_t>(bits >> (8 * sub + 8)) & 1u : r.hw[3] & 1u;
+  t.my9 = (static_cast<uint32_t>(bits >> (8 * sub)) & 0xFFu) | (after << 8);
+  const uint64_t below = sub ? (bits & ((1ull << (8 * sub)) - 1ull)) : 0ull;
+  t.row0 = static_cast<int32_t>(r.hw[2]) + __popcll(below) - 1;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const uint32_t c = (r.cols[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+    const int32_t a = ad[c];
+    if (kW == kWNone) {  // BFS: the source's own value
+      t.x[e] = a;
+      continue;
+    }
+    uint32_t w = 0;
+    if (kW == kW8) w = static_cast<uint32_t>(r.w8 >> (8 * e)) & 0xFFu;
+    else w = static_cast<uint32_t>(e < 4 ? r.wa[e] : r.wb[e - 4]);
+    // a <= INT32_MAX and 0 <= w <= INT32_MAX, so the sum fits in 32 unsigned bits
+    const uint32_t cand = static_cast<uint32_t>(a) + w;
+    const bool sat = cand >= static_cast<uint32_t>(kInf);
+    *ovf |= a != kInf && sat;
+    t.x[e] = (a == kInf || sat) ? kInf : static_cast<int32_t>(cand);
+  }
+  return t;
+}
+
 template <int kW>
 __device__ __forceinline__ MinTile load_min_tile(const uint16_t* __restrict__ col16,
                                                  const gc_head_word* __restrict__ heads,
                                                  const void* __restrict__ w_arcs, const int32_t* ad, int64_t q,
                                                  int lane, bool* ovf) {
-  MinTile t;
-  const int64_t tb = q * kRowTile;
-  const tu32x4 cols = gcd::ld_stream(reinterpret_cast<const tu32x4*>(col16 + tb) + lane);
-  ti32x4 wa = {0, 0, 0, 0}, wb = {0, 0, 0, 0};
-  if (kW == kW8) {
-    const uint64_t w8 = gcd::ld_stream(reinterpret_cast<const uint64_t*>(static_cast<const uint8_t*>(w_arcs) + tb) +
-                                       lane);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      wa[e] = static_cast<int32_t>((w8 >> (8 * e)) & 0xFFu);
-      wb[e] = static_cast<int32_t>((w8 >> (8 * e + 32)) & 0xFFu);
-    }
-  } else if (kW == kW32) {
-    const int32_t* w_pad = static_cast<const int32_t*>(w_arcs);
-    wa = gcd::ld_stream(reinterpret_cast<const ti32x4*>(w_pad + tb) + 2 * lane);
-    wb = gcd::ld_stream(reinterpret_cast<const ti32x4*>(w_pad + tb) + 2 * lane + 1);
-  }
-  const tu32x4 hw = *reinterpret_cast<const tu32x4*>(heads + (tb >> 6) + (lane >> 3));
-  const uint64_t bits = static_cast<uint64_t>(hw[0]) | (static_cast<uint64_t>(hw[1]) << 32);
-  const int sub = lane & 7;
-  const uint32_t after = sub < 7 ? static_cast<uint32_t>(bits >> (8 * sub + 8)) & 1u : hw[3] & 1u;
-  t.my9 = (static_cast<uint32_t>(bits >> (8 * sub)) & 0xFFu) | (after << 8);
-  const uint64_t below = sub ? (bits & ((1ull << (8 * sub)) - 1ull)) : 0ull;
-  t.row0 = static_cast<int32_t>(hw[2]) + __popcll(below) - 1;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const uint32_t c = (cols[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-    const int32_t a = ad[c];
-    const int32_t w = e < 4 ? wa[e] : wb[e - 4];
-    const int64_t cand = static_cast<int64_t>(a) + w;
-    *ovf |= a != kInf && cand >= kInf;
-    t.x[e] = (a == kInf || cand >= kInf) ? kInf : static_cast<int32_t>(cand);
-  }
-  return t;
+  return finish_min_tile<kW>(load_raw_tile<kW>(col16, heads, w_arcs, q, lane), ad, lane, ovf);
 }
 
 template <int kW>
@@ -586,8 +635,15 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
   int32_t carry = kInf;  // minimum so far of the row open at the previous tile's end
   int32_t open_row = -1;
   int32_t jw = 0;  // merge range of the wave's rows so far (ranges ascend with rows)
+  // the raw streams of the next two tiles are in flight while a tile is
+  // reduced (loads clamped to the wave's last tile, so every path issues them)
+  RawTile n1 = load_raw_tile<kW>(col16, heads, w_arcs, qa, lane);
+  RawTile n2 = load_raw_tile<kW>(col16, heads, w_arcs, min(qa + 1, qz), lane);
   for (int32_t q = qa; q <= qz; ++q) {
-    const MinTile t = load_min_tile<kW>(col16, heads, w_arcs, ad, q, lane, &ovf);
+    const RawTile cur = n1;
+    n1 = n2;
+    n2 = load_raw_tile<kW>(col16, heads, w_arcs, min(q + 2, qz), lane);
+    const MinTile t = finish_min_tile<kW>(cur, ad, lane, &ovf);
     // lane-local runs: reset at every head; lane 0 starts from the carry
     int32_t run = (lane == 0) ? carry : kInf;
     int32_t rv[8];
@@ -596,20 +652,26 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
       run = ((t.my9 >> e) & 1u) ? t.x[e] : min(run, t.x[e]);
       rv[e] = run;
     }
-    // wave-wide segmented inclusive minimum of the lanes' open runs
+    // Wave-wide segmented inclusive minimum of the lanes' open runs, with DPP
+    // lane moves: a lane that has met a head within the reach of the steps
+    // so far (a lane mask in scalar registers, widened after each step the
+    // way the moves carry data) keeps its value, the others take the minimum
+    // with the value moved in (INT32_MAX where a move has no source).
+    const uint64_t H = __ballot((t.my9 & 0xFFu) != 0u);
     int32_t A = run;
-    int F = (t.my9 & 0xFFu) != 0u;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int32_t ta = __shfl_up(A, o, kWave);
-      const int tf = __shfl_up(F, o, kWave);
-      if (lane >= o) {
-        if (!F) A = min(A, ta);
-        F |= tf;
-      }
-    }
-    const int32_t in = __shfl_up(A, 1, kWave);  // the row flowing into this lane
-    const int32_t lin = lane == 0 ? kInf : in;
+    uint64_t F = H;
+    seg_min_step<0x111, 0xF>(A, F);  // row_shr:1
+    F |= (F << 1) & 0xFFFEFFFEFFFEFFFEull;
+    seg_min_step<0x112, 0xF>(A, F);  // row_shr:2
+    F |= (F << 2) & 0xFFFCFFFCFFFCFFFCull;
+    seg_min_step<0x114, 0xF>(A, F);  // row_shr:4
+    F |= (F << 4) & 0xFFF0FFF0FFF0FFF0ull;
+    seg_min_step<0x118, 0xF>(A, F);  // row_shr:8
+    F |= (F << 8) & 0xFF00FF00FF00FF00ull;
+    seg_min_step<0x142, 0xA>(A, F);  // row_bcast:15 into rows 1 and 3
+    F |= ((F & (1ull << 15)) ? 0x00000000FFFF0000ull : 0ull) | ((F & (1ull << 47)) ? 0xFFFF000000000000ull : 0ull);
+    seg_min_step<0x143, 0xC>(A, F);  // row_bcast:31 into rows 2 and 3
+    const int32_t lin = dpp_in<0x138, 0xF>(A);  // wave_shr:1, the row flowing into this lane (lane 0: none)
     // Merge range of the rows this lane may store (those of its arcs 0 .. 7,
     // rows rlo .. rhi): the wave walks the range boundaries inside the
     // tile's rows once (the same LDS word for every lane), each lane
