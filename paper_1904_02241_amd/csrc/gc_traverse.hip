@@ -635,6 +635,10 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
   int32_t carry = kInf;  // minimum so far of the row open at the previous tile's end
   int32_t open_row = -1;
   int32_t jw = 0;  // merge range of the wave's rows so far (ranges ascend with rows)
+  // window of the position table's row boundaries: lane l holds sb[jwin + l]
+  // (past the table: its last sentinel)
+  int32_t jwin = 0;
+  int32_t sbw = sb[min(lane, ns + kSeekPad - 1)];
   // the raw streams of the next two tiles are in flight while a tile is
   // reduced (loads clamped to the wave's last tile, so every path issues them)
   RawTile n1 = load_raw_tile<kW>(col16, heads, w_arcs, qa, lane);
@@ -673,27 +677,39 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
     seg_min_step<0x143, 0xC>(A, F);  // row_bcast:31 into rows 2 and 3
     const int32_t lin = dpp_in<0x138, 0xF>(A);  // wave_shr:1, the row flowing into this lane (lane 0: none)
     // Merge range of the rows this lane may store (those of its arcs 0 .. 7,
-    // rows rlo .. rhi): the wave walks the range boundaries inside the
-    // tile's rows once (the same LDS word for every lane), each lane
-    // counting those at or below its first and last row. A lane whose rows
-    // stay in one range (almost all: a range holds tens to hundreds of a
-    // block's rows) stores with one shift; one that crosses a boundary
-    // looks each row's range up.
+    // rows rlo .. rhi). The range boundaries inside the tile's rows are
+    // counted from the register window (a ballot gives how many lie at or
+    // below the tile's last row) and walked through scalar registers, each
+    // lane counting those at or below its first and last row; the window
+    // moves on when the tile's rows run past its last entry. A lane's rows
+    // cross at most one boundary when the block's ranges hold 8 rows or
+    // more (tens to hundreds here): the row's shift is then one of the two
+    // read below, and only a lane crossing several looks each row's range up.
     const int32_t rlo = t.row0 + static_cast<int32_t>(t.my9 & 1u);
     const int32_t rhi = t.row0 + __popc(t.my9 & 0xFFu);
     const int32_t maxrow = __builtin_amdgcn_readlane(rhi, kWave - 1);
-    int32_t cf = 0, cl = 0, kb = jw + 1;
-    for (;;) {
-      const int32_t bnd = sb[kb];
-      if (bnd > maxrow) break;  // uniform
-      cf += rlo >= bnd;
-      cl += rhi >= bnd;
-      ++kb;
+    int32_t cf = 0, cl = 0, jz = jw;
+    for (;;) {  // uniform
+      if (jz + 1 - jwin >= kWave) {
+        jwin = jz;
+        sbw = sb[min(jwin + lane, ns + kSeekPad - 1)];
+      }
+      const int32_t cnt = __popcll(__ballot(sbw <= maxrow));  // a prefix: the table ascends
+      const int32_t jend = jwin + cnt - 1;
+      for (int32_t jj = jz + 1; jj <= jend; ++jj) {
+        const int32_t bnd = __builtin_amdgcn_readlane(sbw, jj - jwin);
+        cf += rlo >= bnd;
+        cl += rhi >= bnd;
+      }
+      jz = max(jz, jend);
+      if (cnt < kWave) break;
     }
+    // jz <= ns (sb[ns + 1 ..] are sentinels above every row), so jf + 1 lies
+    // inside the table
     const int32_t jf = jw + cf;
-    const bool cross = jw + cl != jf;
-    const int32_t d0 = sd[jf];
-    jw = kb - 1;
+    const int32_t nx = cl - cf;  // boundaries inside the lane's rows
+    const int32_t d0 = sd[jf], b1 = sb[jf + 1], d1 = sd[jf + 1];
+    jw = jz;
     int32_t row = t.row0;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -703,8 +719,8 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
         const bool started_here = (t.my9 & ((2u << e) - 1u)) != 0u;
         const int32_t v = started_here ? rv[e] : min(rv[e], lin);
         if (row >= own0 && row < r1) {
-          int32_t d = d0;
-          if (cross) {
+          int32_t d = row >= b1 ? d1 : d0;
+          if (nx > 1) {
             int32_t j = jf;
             while (sb[j + 1] <= row) ++j;
             d = sd[j];
