@@ -73,6 +73,43 @@ __device__ __forceinline__ void block_append(bool take, int32_t v, int32_t* __re
   if (take) queue[wave_off[wid] + __popcll(mask & gcd::lanemask_lt())] = v;
 }
 
+// Appends to the queue, with one atomic for the work-group, the vertices
+// vbase + u * stride of every thread for the set bits u of took (at most
+// 32 per thread). Every thread of the work-group calls it (it synchronises).
+template <int NT>
+__device__ __forceinline__ void block_append_bits(uint32_t took, int32_t vbase, int32_t stride,
+                                                  int32_t* __restrict__ queue, int32_t* __restrict__ qlen) {
+  __shared__ int32_t wave_cnt[NT / kWave];
+  __shared__ int32_t wave_off[NT / kWave];
+  const int lane = gcd::lane_id();
+  const int wid = threadIdx.x / kWave;
+  const int32_t c = __popc(took);
+  int32_t x = c;  // inclusive sum of the counts over the wave's lanes
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) wave_cnt[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t tot = 0;
+    for (int w = 0; w < NT / kWave; ++w) {
+      wave_off[w] = tot;
+      tot += wave_cnt[w];
+    }
+    const int32_t base = tot ? atomicAdd(qlen, tot) : 0;
+    for (int w = 0; w < NT / kWave; ++w) wave_off[w] += base;
+  }
+  __syncthreads();
+  int32_t pos = wave_off[wid] + x - c;
+  while (took) {
+    const int u = __ffs(took) - 1;
+    took &= took - 1u;
+    queue[pos++] = vbase + u * stride;
+  }
+}
+
 __device__ __forceinline__ bool bit_test(const uint32_t* bits, int32_t v) {
   return (bits[v >> 5] >> (v & 31)) & 1u;
 }
@@ -484,6 +521,9 @@ __global__ __launch_bounds__(kThreads) void k_sssp_tocab(const int32_t* __restri
 // (block-major, as the wide-block kernel writes it) is the minimum over
 // local row l's arcs, INT32_MAX when no source of the row is active.
 constexpr int kLdsRowThreads = 1024;
+// Buffer offset of a dropped store: past any partition's minima (whose
+// stream layout keeps 4 (P + 8) below 2^31 bytes).
+constexpr uint32_t kDropOff = 0x80000000u;
 constexpr int kSeekPad = 4;  // position-table entries past the chunk's ns ranges: sb[ns] (past the chunk), sentinels
 constexpr int kLdsRowWaves = kLdsRowThreads / kWave;
 constexpr int kRowTile = 512;  // arcs per wave tile: 8 per lane
@@ -597,16 +637,39 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
     const void* __restrict__ w_arcs, const int32_t* __restrict__ chunk_beg, const int32_t* __restrict__ chunk_end,
     const int32_t* __restrict__ chunk_blk, const int32_t* __restrict__ chunk_j0, const int32_t* __restrict__ chunk_ns,
     const int2* __restrict__ seg, int32_t R, int32_t log2W, int32_t n, const uint32_t* __restrict__ front,
-    const int32_t* __restrict__ dist, int32_t* __restrict__ pmin, int32_t* __restrict__ stats) {
+    const int32_t* __restrict__ dist, int32_t* __restrict__ pmin, uint32_t pmin_bytes, int32_t* __restrict__ stats) {
   extern __shared__ int32_t ad[];
+  const __amdgpu_buffer_rsrc_t out = __builtin_amdgcn_make_buffer_rsrc(pmin, 0, static_cast<int>(pmin_bytes), 0x00020000);
   const int32_t ch = blockIdx.x;
   const int32_t r0 = chunk_beg[ch], r1 = chunk_end[ch], b = chunk_blk[ch], j0 = chunk_j0[ch], ns = chunk_ns[ch];
   if (r0 >= r1) return;  // padding of the dispatch order (uniform)
-  const int32_t W = 1 << log2W, v0 = b << log2W, cnt = min(W, n - v0);
-  for (int32_t i = threadIdx.x; i < W; i += kLdsRowThreads) {
-    int32_t a = kInf;
-    if (i < cnt && bit_test(front, v0 + i)) a = kW == kWNone ? 0 : dist[v0 + i];
-    ad[i] = a;
+  const int32_t W = 1 << log2W, v0 = b << log2W, cnt = min(W, n - v0);  // cnt >= 1
+  // The block's frontier values in LDS, in batches of kFill vertices per
+  // thread whose loads are all issued before the first is used: the status
+  // words first, then the distances, a load whose vertex lies outside the
+  // frontier's words (or past n) reading the block's first vertex instead,
+  // so that a sparse frontier costs no slice of distances.
+  constexpr int kFill = 16;
+  for (int32_t k0 = 0; k0 < W; k0 += kFill * kLdsRowThreads) {
+    uint32_t wd[kFill];
+    int32_t dv[kFill];
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) {
+      const int32_t i = min(k0 + u * kLdsRowThreads + static_cast<int32_t>(threadIdx.x), cnt - 1);
+      wd[u] = front[(v0 + i) >> 5];
+    }
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) {
+      const int32_t i = k0 + u * kLdsRowThreads + static_cast<int32_t>(threadIdx.x);
+      dv[u] = 0;
+      if (kW != kWNone) dv[u] = dist[v0 + ((wd[u] != 0u && i < cnt) ? i : 0)];
+    }
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) {
+      const int32_t i = k0 + u * kLdsRowThreads + static_cast<int32_t>(threadIdx.x);
+      const bool on = i < cnt && ((wd[u] >> ((v0 + i) & 31)) & 1u);
+      if (i < W) ad[i] = on ? dv[u] : kInf;
+    }
   }
   // the chunk's part of the position table: sb[i] = first row of merge range
   // j0 + i, sd[i] = its shift to the range-major index; sb[ns] lies past the
@@ -710,22 +773,34 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
     const int32_t nx = cl - cf;  // boundaries inside the lane's rows
     const int32_t d0 = sd[jf], b1 = sb[jf + 1], d1 = sd[jf + 1];
     jw = jz;
+    // Every lane issues its 8 stores, one per arc: an arc that ends a row
+    // the wave writes stores the row's minimum at its range-major index, any
+    // other store gets an offset past the buffer and is dropped (no branch
+    // around a store: the loads of the next tiles stay in flight). Lanes
+    // crossing several boundaries store on the path below instead.
+    const bool slow = nx > 1;
     int32_t row = t.row0;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const bool head = (t.my9 >> e) & 1u;
-      row += head ? 1 : 0;
-      if ((t.my9 >> (e + 1)) & 1u) {  // arc e ends its row
-        const bool started_here = (t.my9 & ((2u << e) - 1u)) != 0u;
-        const int32_t v = started_here ? rv[e] : min(rv[e], lin);
-        if (row >= own0 && row < r1) {
-          int32_t d = row >= b1 ? d1 : d0;
-          if (nx > 1) {
-            int32_t j = jf;
-            while (sb[j + 1] <= row) ++j;
-            d = sd[j];
-          }
-          pmin[row + d] = v;  // stored at the row's range-major index
+      row += static_cast<int32_t>((t.my9 >> e) & 1u);
+      const bool ends = (t.my9 >> (e + 1)) & 1u;  // arc e ends its row
+      const bool started_here = (t.my9 & ((2u << e) - 1u)) != 0u;
+      const int32_t v = started_here ? rv[e] : min(rv[e], lin);
+      const int32_t d = row >= b1 ? d1 : d0;
+      const bool ok = ends && !slow && row >= own0 && row < r1;
+      const uint32_t off = ok ? 4u * static_cast<uint32_t>(row + d) : kDropOff + 4u * e;
+      __builtin_amdgcn_raw_buffer_store_b32(static_cast<uint32_t>(v), out, off, 0, 0);
+    }
+    if (__any(slow)) {
+      row = t.row0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        row += static_cast<int32_t>((t.my9 >> e) & 1u);
+        if (slow && ((t.my9 >> (e + 1)) & 1u) && row >= own0 && row < r1) {
+          const bool started_here = (t.my9 & ((2u << e) - 1u)) != 0u;
+          int32_t j = jf;
+          while (sb[j + 1] <= row) ++j;
+          pmin[row + sd[j]] = started_here ? rv[e] : min(rv[e], lin);
         }
       }
     }
@@ -757,6 +832,10 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
   }
   if (__any(ovf) && lane == 0) stats[kOverflow] = 1;
 }
+
+// Size in bytes of the partial minima of a stream-layout partition (P + 8
+// entries, below 2^31 bytes by the layout's own limit).
+inline uint32_t pmin_bytes(const gc_tocab_s* t) { return static_cast<uint32_t>(sizeof(int32_t) * (t->P + 8)); }
 
 // Figure 5 merge of the stream-layout SSSP partial minima, read as streams:
 // range j's partials of every block are one contiguous slice [rstart[j],
@@ -828,24 +907,40 @@ __global__ __launch_bounds__(NT) void k_sssp_merge_stream(const int32_t* __restr
       bounds(jn);
       if (g0 < g1) load(g0 + tid, pa, ia);
     }
-    for (int i = tid; i < K; i += NT) {  // every thread the same count: block_append synchronises
+    // The range's vertices v0 + tid + u NT: distance (or depth) and status
+    // bits, with one atomic per 32-bit status word (a wave's 32 lanes hold
+    // one word's vertices, the range starts on a word), then one queue
+    // append for the work-group.
+    static_assert(K % NT == 0 && NT % kWave == 0, "whole waves over the range");
+    uint32_t took = 0;  // bit u: vertex v0 + tid + u NT entered the next frontier
+#pragma unroll
+    for (int u = 0; u < K / NT; ++u) {
+      const int32_t i = tid + u * NT;
       const int32_t v = v0 + i;
+      const int32_t bi = best[i];
+      best[i] = kInf;
       bool improved = false;
       if (kBfs) {  // depth: a vertex not yet reached with an in-neighbour in the frontier
-        if (v < n && best[i] == 0 && !bit_test(visited, v)) {
+        if (v < n && bi == 0 && !bit_test(visited, v)) {
           dist[v] = level + 1;
-          bit_set(next, v);
-          bit_set(visited, v);
           improved = true;
         }
-      } else if (v < n && best[i] < dist[v]) {
-        dist[v] = best[i];
-        bit_set(next, v);
-        improved = true;
+      } else if (v < n && bi != kInf) {
+        if (bi < dist[v]) {
+          dist[v] = bi;
+          improved = true;
+        }
       }
-      best[i] = kInf;
-      block_append<NT>(improved, v, queue, stats + kQLen);
+      const uint64_t m = __ballot(improved);
+      const int lane = tid & (kWave - 1);
+      const uint32_t word = static_cast<uint32_t>(m >> (lane & 32));
+      if ((lane & 31) == 0 && word != 0u) {
+        atomicOr(&next[v >> 5], word);
+        if (kBfs) atomicOr(&visited[v >> 5], word);
+      }
+      took |= static_cast<uint32_t>(improved) << u;
     }
+    block_append_bits<NT>(took, v0 + tid, NT, queue, stats + kQLen);
     __syncthreads();
   }
 }
@@ -1521,7 +1616,8 @@ int32_t device_cus() {
 
 template <int K>
 struct SsspMergeStream {
-  static constexpr int kNT = K >= 8192 ? 1024 : 512;  // LDS minima of K int32: two work-groups per CU
+  // LDS minima of K int32: two work-groups per CU; no more threads than K
+  static constexpr int kNT = K >= 8192 ? 1024 : (K >= 512 ? 512 : K);
   template <class... A>
   static void run(int32_t R, hipStream_t s, A... a) {
     const int32_t grid = std::max(1, std::min(R, 2 * device_cus()));
@@ -1725,7 +1821,7 @@ hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t 
         if (t->n_chunks > 0)
           k_sssp_tocab_lds<kWNone><<<t->n_chunks, kLdsRowThreads, lds, s>>>(
               t->row_ptr, t->col16, t->heads, nullptr, t->chunk_beg, t->chunk_end, t->chunk_blk, t->chunk_j0,
-              t->chunk_ns, t->seg, t->R, t->log2W, n, f.front(), nullptr, t->pmin, g->stats);
+              t->chunk_ns, t->seg, t->R, t->log2W, n, f.front(), nullptr, t->pmin, pmin_bytes(t), g->stats);
       }
       ProfScope prof("bfs_merge", s);
       GC_HIP_TRY((launch_by_k<BfsMergeStream>(t->k, t->R, s, static_cast<const int32_t*>(t->rstart),
@@ -1767,11 +1863,11 @@ hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t 
           if (t->n_chunks > 0 && t->w8)
             k_sssp_tocab_lds<kW8><<<t->n_chunks, kLdsRowThreads, lds, s>>>(
                 t->row_ptr, t->col16, t->heads, t->w8, t->chunk_beg, t->chunk_end, t->chunk_blk, t->chunk_j0,
-                t->chunk_ns, t->seg, t->R, t->log2W, n, f.front(), value, t->pmin, g->stats);
+                t->chunk_ns, t->seg, t->R, t->log2W, n, f.front(), value, t->pmin, pmin_bytes(t), g->stats);
           else if (t->n_chunks > 0)
             k_sssp_tocab_lds<kW32><<<t->n_chunks, kLdsRowThreads, lds, s>>>(
                 t->row_ptr, t->col16, t->heads, t->w_pad, t->chunk_beg, t->chunk_end, t->chunk_blk, t->chunk_j0,
-                t->chunk_ns, t->seg, t->R, t->log2W, n, f.front(), value, t->pmin, g->stats);
+                t->chunk_ns, t->seg, t->R, t->log2W, n, f.front(), value, t->pmin, pmin_bytes(t), g->stats);
         }
         ProfScope prof("sssp_merge", s);
         GC_HIP_TRY((launch_by_k<SsspMergeStream>(t->k, t->R, s, static_cast<const int32_t*>(t->rstart),
