@@ -116,6 +116,18 @@ __device__ __forceinline__ bool bit_test(const uint32_t* bits, int32_t v) {
 
 __device__ __forceinline__ void bit_set(uint32_t* bits, int32_t v) { atomicOr(&bits[v >> 5], 1u << (v & 31)); }
 
+// Sets bit v in `bits` for the lanes where `take` holds, one atomic per
+// 32-bit word: every lane of the wave calls it, and lane l holds vertex
+// v0 + l for a v0 that is a multiple of 32 (a wave of consecutive
+// vertices). Per-vertex atomics on the few words a wave shares serialise in
+// L2 on levels that discover millions of vertices.
+__device__ __forceinline__ void wave_bits_set(uint32_t* bits, int32_t v, bool take) {
+  const uint64_t m = __ballot(take);
+  const int lane = gcd::lane_id();
+  const uint32_t word = static_cast<uint32_t>(m >> (lane & 32));
+  if ((lane & 31) == 0 && word != 0u) atomicOr(&bits[v >> 5], word);
+}
+
 __global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t x) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) a[i] = x;
@@ -140,6 +152,7 @@ __global__ void k_clear_front(uint32_t* __restrict__ front, const int32_t* __res
 // the device wall clock.
 __global__ void k_level_begin(int32_t* __restrict__ stats) {
   if (threadIdx.x < gcx::kStatT0) stats[threadIdx.x] = 0;
+  if (threadIdx.x < 2) stats[gcx::kStatInDegLo + threadIdx.x] = 0;
   if (threadIdx.x == 0) *reinterpret_cast<uint64_t*>(stats + gcx::kStatT0) = wall_clock64();
 }
 
@@ -167,23 +180,35 @@ struct LevelDecide {
 // kernel runs right after the level's relaxation kernels on the same
 // stream, so its start stamps the end of the level.
 __global__ void k_queue_degree(const int32_t* __restrict__ queue, const int32_t* __restrict__ qlen,
-                               const int32_t* __restrict__ rowptr, int32_t* __restrict__ stats) {
+                               const int32_t* __restrict__ rowptr, const int32_t* __restrict__ t_rowptr,
+                               int32_t* __restrict__ stats) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *reinterpret_cast<uint64_t*>(stats + gcx::kStatT1) = wall_clock64();
   const int32_t qn = *qlen;
-  uint64_t sum = 0;
+  uint64_t sum = 0, sum_in = 0;  // out-arcs and in-arcs of the queued vertices
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < qn; i += gridDim.x * blockDim.x) {
     const int32_t v = queue[i];
     sum += static_cast<uint64_t>(rowptr[v + 1] - rowptr[v]);
+    if (t_rowptr) sum_in += static_cast<uint64_t>(t_rowptr[v + 1] - t_rowptr[v]);
   }
-  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, kWave);
+  for (int o = 32; o > 0; o >>= 1) {
+    sum += __shfl_xor(sum, o, kWave);
+    sum_in += __shfl_xor(sum_in, o, kWave);
+  }
   // one atomic per work-group (per-wave atomics on the one counter serialise)
-  __shared__ uint64_t part[kThreads / kWave];
-  if (gcd::lane_id() == 0) part[threadIdx.x / kWave] = sum;
+  __shared__ uint64_t part[kThreads / kWave], part_in[kThreads / kWave];
+  if (gcd::lane_id() == 0) {
+    part[threadIdx.x / kWave] = sum;
+    part_in[threadIdx.x / kWave] = sum_in;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint64_t total = 0;
-    for (int w = 0; w < kThreads / kWave; ++w) total += part[w];
+    uint64_t total = 0, total_in = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) {
+      total += part[w];
+      total_in += part_in[w];
+    }
     if (total) atomicAdd(reinterpret_cast<unsigned long long*>(stats + kDegLo), total);
+    if (total_in) atomicAdd(reinterpret_cast<unsigned long long*>(stats + gcx::kStatInDegLo), total_in);
   }
 }
 
@@ -280,11 +305,9 @@ __global__ __launch_bounds__(kThreads) void k_bfs_pull(const int32_t* __restrict
     e = t_rowptr[v + 1];
   }
   const bool found = scan_front(t_col, front, active, b, e);
-  if (found) {
-    depth[v] = level + 1;
-    bit_set(next, v);
-    bit_set(visited, v);
-  }
+  if (found) depth[v] = level + 1;
+  wave_bits_set(next, v, found);
+  wave_bits_set(visited, v, found);
   block_append(found, v, queue, stats + kQLen);
 }
 
@@ -332,11 +355,9 @@ __global__ __launch_bounds__(kThreads) void k_bfs_merge(const int32_t* __restric
   for (int i = threadIdx.x; i < K; i += kThreads) {
     const int32_t v = v0 + i;
     const bool found = v < n && hit[i] && !bit_test(visited, v);
-    if (found) {
-      depth[v] = level + 1;
-      bit_set(next, v);
-      bit_set(visited, v);
-    }
+    if (found) depth[v] = level + 1;
+    wave_bits_set(next, v, found);
+    wave_bits_set(visited, v, found);
     block_append(found, v, queue, stats + kQLen);
   }
 }
@@ -477,9 +498,9 @@ __global__ __launch_bounds__(kThreads) void k_sssp_pull(const int32_t* __restric
   bool improved = false;
   if (v < n && best < dist[v]) {
     dist[v] = static_cast<int32_t>(best);
-    bit_set(next, v);
     improved = true;
   }
+  wave_bits_set(next, v, improved);
   block_append(improved, v, queue, stats + kQLen);
 }
 
@@ -962,9 +983,9 @@ __global__ __launch_bounds__(kThreads) void k_sssp_merge(const int32_t* __restri
     bool improved = false;
     if (v < n && best[i] < dist[v]) {
       dist[v] = best[i];
-      bit_set(next, v);
       improved = true;
     }
+    wave_bits_set(next, v, improved);
     block_append(improved, v, queue, stats + kQLen);
   }
 }
@@ -1109,9 +1130,9 @@ __global__ __launch_bounds__(kThreads) void k_bc_pull(const int32_t* __restrict_
   if (found) {
     depth[v] = level + 1;
     sigma[v] = sum;
-    bit_set(next, v);
-    bit_set(visited, v);
   }
+  wave_bits_set(next, v, found);
+  wave_bits_set(visited, v, found);
   block_append(found, v, queue, stats + kQLen);
 }
 
@@ -1157,9 +1178,9 @@ __global__ __launch_bounds__(kThreads) void k_bc_merge(const int32_t* __restrict
     if (found) {
       depth[v] = level + 1;
       sigma[v] = acc[i];
-      bit_set(next, v);
-      bit_set(visited, v);
     }
+    wave_bits_set(next, v, found);
+    wave_bits_set(visited, v, found);
     block_append(found, v, queue, stats + kQLen);
   }
 }
@@ -1556,11 +1577,31 @@ enum class Mode { kPull, kTocab, kPush };
 struct Heuristic {
   static constexpr double kAlpha = 14.0, kBeta = 24.0;
   static constexpr double kCacheBytes = 4.0 * 1024 * 1024;  // one XCD's L2
+  // BFS over a stream-layout partition: TOCAB pull on graphs with at most
+  // kBfsTocabDegree arcs per vertex, while at least 1/64 of the arcs still
+  // end at unvisited vertices. Measured per level on the grid (4 arcs per
+  // vertex), uniform (8) and R-MAT 22 / 24 (16) graphs: a TOCAB pull level
+  // costs 3-6 ps per arc, a plain-pull level about 50 ps per vertex while
+  // many vertices are unvisited (one thread per vertex, early exit, status
+  // bits in L2), so TOCAB halves the grid's dense levels, gains a quarter
+  // on the uniform graph's and ties on R-MAT's; once fewer than 1/64 of the
+  // arcs end at unvisited vertices the plain pull is up to three times
+  // faster.
+  static constexpr double kBfsTocabShare = 1.0 / 64.0;
+  static constexpr double kBfsTocabDegree = 10.0;
   bool pulling = false;
-  Mode pick(int64_t n, int64_t n_f, int64_t m_f, int64_t m_u, bool have_tocab, bool bfs) {
+  // m_u: unexplored out-arcs (the direction test); m_u_in: in-arcs of the
+  // unvisited vertices; stream: the TOCAB partition has the stream layout
+  Mode pick(int64_t n, int64_t n_f, int64_t m_f, int64_t m_u, bool have_tocab, bool bfs, int64_t m = 0,
+            int64_t m_u_in = 0, bool stream = false) {
     if (!pulling && static_cast<double>(m_f) > static_cast<double>(m_u) / kAlpha) pulling = true;
     else if (pulling && static_cast<double>(n_f) < static_cast<double>(n) / kBeta) pulling = false;
     if (!pulling) return Mode::kPush;
+    if (bfs && have_tocab && stream)
+      return static_cast<double>(m) <= kBfsTocabDegree * static_cast<double>(n) &&
+                     static_cast<double>(m_u_in) >= kBfsTocabShare * static_cast<double>(m)
+                 ? Mode::kTocab
+                 : Mode::kPull;
     const double gathered = static_cast<double>(n) / 8.0 + (bfs ? 0.0 : 4.0 * static_cast<double>(n));
     const bool large = 4.0 * static_cast<double>(m_f) > kCacheBytes && gathered > kCacheBytes;
     return (have_tocab && large) ? Mode::kTocab : Mode::kPull;
@@ -1713,6 +1754,8 @@ struct Frontier {
   int cur = 0;
   int32_t n_f = 1;
   int64_t m_f = 0;
+  int64_t m_f_in = 0;  // in-arcs of the frontier when count_in (the source's are not counted)
+  bool count_in = false;
   uint32_t* front() { return cur == 0 ? g->front : g->next; }
   uint32_t* next() { return cur == 0 ? g->next : g->front; }
   int32_t* queue() { return g->queue[cur]; }
@@ -1749,7 +1792,8 @@ struct Frontier {
       dec.prior_arcs = m_f;
       dec.clock_khz = g->clock_khz;
     }
-    k_queue_degree<<<256, kThreads, 0, s>>>(queue_next(), g->stats + kQLen, g->rowptr, g->stats);
+    k_queue_degree<<<256, kThreads, 0, s>>>(queue_next(), g->stats + kQLen, g->rowptr, count_in ? g->t_rowptr : nullptr,
+                                            g->stats);
     if (decide) k_level_decide<<<1, kThreads, lds, s>>>(g->stats, dec);
     GC_HIP_TRY(hipGetLastError());
     GC_HIP_TRY(hipMemcpyAsync(g->stats_host, g->stats, sizeof(int32_t) * gcx::kStatSlots, hipMemcpyDeviceToHost, s));
@@ -1759,6 +1803,8 @@ struct Frontier {
     n_f = g->stats_host[kQLen];
     m_f = static_cast<int64_t>(static_cast<uint32_t>(g->stats_host[kDegLo])) |
           (static_cast<int64_t>(g->stats_host[kDegLo + 1]) << 32);
+    m_f_in = static_cast<int64_t>(static_cast<uint32_t>(g->stats_host[gcx::kStatInDegLo])) |
+             (static_cast<int64_t>(g->stats_host[gcx::kStatInDegLo + 1]) << 32);
     if (overflow && g->stats_host[kOverflow]) *overflow = true;
     cur ^= 1;
     return hipSuccess;
@@ -1978,6 +2024,7 @@ hipError_t traverse(gc_graph g, gc_tocab t, int32_t source, int32_t* value, int3
   f.m_f = source_degree(g, source, s, &e);
   GC_HIP_TRY(e);
   int64_t m_u = g->m - f.m_f;
+  int64_t m_u_in = g->m;  // in-arcs of the unvisited vertices (the source's own few left in)
   Heuristic h;
   int32_t level = 0;
   g->trace_action.clear();
@@ -2006,6 +2053,10 @@ hipError_t traverse(gc_graph g, gc_tocab t, int32_t source, int32_t* value, int3
     if (!t && fall_action >= 0) fall_t = g->sched_parts[fall_action - 2];
     if (t) fall_action = -1;  // the caller's partition is not among the network's actions
   }
+  // the working-set rule's BFS arm over a stream-layout partition reads the
+  // unvisited vertices' in-arcs
+  f.count_in = bfs && (policy == GC_POLICY_HEURISTIC || policy == GC_POLICY_LEARNED) && fall_t != nullptr &&
+               fall_t->col16 != nullptr && static_cast<double>(g->m) <= Heuristic::kBfsTocabDegree * n;
   std::vector<float> outs(static_cast<size_t>(std::max(K, 1)));
   while (f.n_f > 0) {
     if (!bfs && level > n) return hipErrorInvalidValue;  // cannot happen with positive weights
@@ -2017,7 +2068,9 @@ hipError_t traverse(gc_graph g, gc_tocab t, int32_t source, int32_t* value, int3
     Mode hmode;
     if (policy == GC_POLICY_PUSH) hmode = Mode::kPush;
     else if (policy == GC_POLICY_PULL) hmode = t ? Mode::kTocab : Mode::kPull;
-    else hmode = h.pick(n, f.n_f, f.m_f, unexplored, fall_t != nullptr, bfs);
+    else
+      hmode = h.pick(n, f.n_f, f.m_f, unexplored, fall_t != nullptr, bfs, g->m, m_u_in,
+                     fall_t != nullptr && fall_t->col16 != nullptr);
     Mode mode = hmode;
     gc_tocab lt = fall_t;
     int32_t action = -1;
@@ -2070,7 +2123,10 @@ hipError_t traverse(gc_graph g, gc_tocab t, int32_t source, int32_t* value, int3
     g->trace_action.push_back(action);
     g->trace_ms.push_back(static_cast<float>(wall_ms));
     if (overflow && *overflow) break;
-    if (bfs) m_u -= f.m_f;
+    if (bfs) {
+      m_u -= f.m_f;
+      m_u_in -= f.m_f_in;
+    }
     ++level;
   }
   if (count) *count = level;
