@@ -266,8 +266,13 @@ int spmv(gc_graph g, gc_tocab t, const float* x, float* y, hipStream_t stream);
  * GC_PULL partition t they run blocked, each block writing a local `next`
  * that the merge reduces; t == NULL pulls over the whole transposed graph.
  * policy chooses pull, data-driven push, or the working-set heuristic per
- * level. levels (host, nullable) receives the number of levels run.
- * Synchronises `stream` once per level to read the frontier size. */
+ * level (direction by the direction-optimising test; the form of a pull
+ * level by the working-set test, except over a partition with the LDS
+ * stream layout (blocks up to 2^15), where a pull level runs as TOCAB on
+ * graphs with at most 10 arcs per vertex while at least 1/64 of the arcs
+ * end at unvisited vertices, as plain pull otherwise). levels (host,
+ * nullable) receives the number of levels run. Synchronises `stream` once
+ * per level to read the frontier size. */
 int bfs_pull(gc_graph g, gc_tocab t, int32_t source, int32_t* depth, int32_t* levels,
              uint32_t policy, hipStream_t stream);
 
