@@ -180,3 +180,51 @@ def test_isolated_source():
     gc.sssp_pull(h, None, 5, d, gc.GC_POLICY_PULL)
     np.testing.assert_array_equal(host(d), want)
     h.free()
+
+
+def test_heuristic_bfs_tocab_arm():
+    """The working-set rule's BFS arm over a stream-layout partition: on a
+    rewired grid (4 arcs per vertex) its dense middle pull levels run as
+    TOCAB pull (trace action 2) and the late ones as plain pull; on R-MAT
+    (16 arcs per vertex) no level runs as TOCAB. The level sequence on the
+    grid follows the rule replayed on the host from the oracle's depths
+    (direction-optimising test, then TOCAB while at least 1/64 of the arcs
+    end at unvisited vertices). Depths stay bit-exact."""
+    import paper_1904_02241_amd as gc
+    cases = (("grid400", gg.grid(400, 400, 0.05, seed=3), True), ("rmat16", gg.rmat(16, 16, seed=1), False))
+    for name, g, expect_tocab in cases:
+        h = load(g)
+        part = gc.tocab_partition(h, gc.GC_PULL, 1 << 12, 4096)
+        assert gc.tocab_layout(part)["stream"]
+        n, m = g.n, int(g.rowptr[-1])
+        outd = np.diff(g.rowptr).astype(np.int64)
+        ind = np.bincount(g.colidx, minlength=n).astype(np.int64)
+        d = torch().empty(n, dtype=torch().int32, device="cuda")
+        for s in gg.sources(g, 2, seed=21):
+            print(f"heuristic bfs arm {name} source {s}", flush=True)
+            gc.bfs_pull(h, part, int(s), d, gc.GC_POLICY_HEURISTIC)
+            depth = host(d)
+            want = oracle.bfs(n, g.rowptr, g.colidx, int(s))
+            np.testing.assert_array_equal(depth, want)
+            acts, _ = gc.traversal_trace(h)
+            # the rule replayed from the oracle's levels
+            exp, pulling = [], False
+            m_u, m_u_in = m - int(outd[s]), m
+            for lev in range(int(want[want != np.iinfo(np.int32).max].max()) + 1):
+                fr = want == lev
+                n_f, m_f = int(fr.sum()), int(outd[fr].sum())
+                if not pulling and m_f > m_u / 14.0:
+                    pulling = True
+                elif pulling and n_f < n / 24.0:
+                    pulling = False
+                if not pulling:
+                    exp.append(0)
+                else:
+                    exp.append(2 if (m <= 10 * n and m_u_in >= m / 64.0) else 1)
+                nxt = want == lev + 1
+                m_u -= int(outd[nxt].sum())
+                m_u_in -= int(ind[nxt].sum())
+            assert list(acts) == exp, (name, list(acts), exp)
+            assert (2 in exp) == expect_tocab
+        part.free()
+        h.free()
