@@ -769,14 +769,40 @@ __global__ __launch_bounds__(NT) void k_pr_merge_persist(const int32_t* __restri
     }
     __syncthreads();
     const int32_t v0 = j * K;
+    // The range's out-degrees (and previous ranks in convergence mode) are
+    // loaded into registers before the next range's first partials: the
+    // wait for them then does not wait for those, and the update below
+    // runs on registers (a load per vertex inside it made every one of its
+    // steps a memory round trip).
+    constexpr int kPer = (K + NT - 1) / NT;
+    int32_t deg[kPer];
+    float prev[kPer];
+    // vertex v0 + tid + q NT, clamped to the last vertex (those past it are not updated)
+    const uint32_t last = static_cast<uint32_t>(u.n - 1 - v0);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const uint32_t o = min(static_cast<uint32_t>(tid + q * NT), last);
+      const int32_t* rp = u.rowptr + v0;  // uniform base, 32-bit offsets
+      deg[q] = rp[o + 1] - rp[o];
+      prev[q] = 0.0f;
+    }
+    if (u.rank_prev) {
+      const float* pp = u.rank_prev + v0;
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) prev[q] = pp[min(static_cast<uint32_t>(tid + q * NT), last)];
+    }
     const int32_t jn = j + gridDim.x;
     if (jn < R) {  // uniform: the next range's first loads, in flight during the update
       bounds(jn);
       if (g0 < g1) load(g0 + tid, pa, ia);
     }
-    for (int i = tid; i < K; i += NT) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int32_t i = tid + q * NT;
+      if (K % NT != 0 && i >= K) break;
       const int32_t v = v0 + i;
-      if (v < u.n) mine += update_vertex(u, v, acc[i], D, dl);
+      float cv;
+      if (v < u.n) mine += update_vertex_loaded(u, v, acc[i], D, dl, cv, deg[q], prev[q]);
       acc[i] = 0.0;
     }
     __syncthreads();

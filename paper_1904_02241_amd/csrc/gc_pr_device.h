@@ -43,17 +43,22 @@ struct Update {
 // In convergence mode also adds |r'[v] - r[v]| (FP64 over the FP32
 // iterates) to dl.
 // The new contribution is also returned in cv (u.contrib may be null when
-// the caller keeps it elsewhere).
-__device__ __forceinline__ double update_vertex(const Update& u, int32_t v, double sum, double D, double& dl,
-                                                float& cv) {
+// the caller keeps it elsewhere). update_vertex_loaded takes v's out-degree
+// and previous rank (read only in convergence mode) from the caller.
+__device__ __forceinline__ double update_vertex_loaded(const Update& u, int32_t v, double sum, double D, double& dl,
+                                                       float& cv, int32_t deg, float prev) {
   const double r = u.base + u.d * (sum + D * u.inv_n);
   const float r32 = static_cast<float>(r);
-  const int32_t deg = u.rowptr[v + 1] - u.rowptr[v];
   cv = deg ? static_cast<float>(static_cast<double>(r32) / deg) : 0.0f;
   if (u.contrib) u.contrib[v] = cv;
   if (u.rank_out) u.rank_out[v] = r32;
-  if (u.rank_prev) dl += fabs(static_cast<double>(r32) - static_cast<double>(u.rank_prev[v]));
+  if (u.rank_prev) dl += fabs(static_cast<double>(r32) - static_cast<double>(prev));
   return deg ? 0.0 : static_cast<double>(r32);
+}
+
+__device__ __forceinline__ double update_vertex(const Update& u, int32_t v, double sum, double D, double& dl,
+                                                float& cv) {
+  return update_vertex_loaded(u, v, sum, D, dl, cv, u.rowptr[v + 1] - u.rowptr[v], u.rank_prev ? u.rank_prev[v] : 0.0f);
 }
 
 __device__ __forceinline__ double update_vertex(const Update& u, int32_t v, double sum, double D, double& dl) {
