@@ -923,34 +923,48 @@ __global__ __launch_bounds__(NT) void k_sssp_merge_stream(const int32_t* __restr
     }
     __syncthreads();
     const int32_t v0 = j * K;
+    static_assert(K % NT == 0 && NT % kWave == 0, "whole waves over the range");
+    constexpr int kPer = K / NT;
+    // The range's vertices v0 + tid + u NT. Their minima come from LDS and,
+    // for those with a candidate, their distance (BFS: their visited word)
+    // is loaded into registers before the next range's first minima, so
+    // that the update waits for neither those loads nor one load per step;
+    // a vertex with no candidate (or past n) reads the range's first vertex
+    // instead, one line per wave.
+    int32_t bi[kPer], cur[kPer];
+    const uint32_t last = static_cast<uint32_t>(n - 1 - v0);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int32_t i = tid + u * NT;
+      bi[u] = best[i];
+      best[i] = kInf;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const uint32_t o = static_cast<uint32_t>(tid + u * NT);
+      const bool need = o <= last && (kBfs ? bi[u] == 0 : bi[u] != kInf);
+      const uint32_t oo = need ? o : 0u;
+      cur[u] = kBfs ? static_cast<int32_t>(visited[(static_cast<uint32_t>(v0) + oo) >> 5]) : dist[v0 + oo];
+    }
     const int32_t jn = j + gridDim.x;
     if (jn < R) {  // uniform: the next range's first loads, in flight during the update
       bounds(jn);
       if (g0 < g1) load(g0 + tid, pa, ia);
     }
-    // The range's vertices v0 + tid + u NT: distance (or depth) and status
-    // bits, with one atomic per 32-bit status word (a wave's 32 lanes hold
-    // one word's vertices, the range starts on a word), then one queue
-    // append for the work-group.
-    static_assert(K % NT == 0 && NT % kWave == 0, "whole waves over the range");
+    // distance (or depth) and status bits, with one atomic per 32-bit status
+    // word (a wave's 32 lanes hold one word's vertices, the range starts on
+    // a word), then one queue append for the work-group
     uint32_t took = 0;  // bit u: vertex v0 + tid + u NT entered the next frontier
 #pragma unroll
-    for (int u = 0; u < K / NT; ++u) {
-      const int32_t i = tid + u * NT;
-      const int32_t v = v0 + i;
-      const int32_t bi = best[i];
-      best[i] = kInf;
-      bool improved = false;
+    for (int u = 0; u < kPer; ++u) {
+      const int32_t v = v0 + tid + u * NT;
+      bool improved;
       if (kBfs) {  // depth: a vertex not yet reached with an in-neighbour in the frontier
-        if (v < n && bi == 0 && !bit_test(visited, v)) {
-          dist[v] = level + 1;
-          improved = true;
-        }
-      } else if (v < n && bi != kInf) {
-        if (bi < dist[v]) {
-          dist[v] = bi;
-          improved = true;
-        }
+        improved = v < n && bi[u] == 0 && !((static_cast<uint32_t>(cur[u]) >> (v & 31)) & 1u);
+        if (improved) dist[v] = level + 1;
+      } else {
+        improved = v < n && bi[u] != kInf && bi[u] < cur[u];
+        if (improved) dist[v] = bi[u];
       }
       const uint64_t m = __ballot(improved);
       const int lane = tid & (kWave - 1);
