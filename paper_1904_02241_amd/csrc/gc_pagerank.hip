@@ -1135,12 +1135,27 @@ __global__ __launch_bounds__(kPushLdsThreads) void k_pr_push_lds_x(
   __syncthreads();
   const double D = *u.dtotal_in;
   double mine = 0.0, dl = 0.0;
-  float cv[kPer];
+  // the block's out-degrees (and previous ranks) in registers first, then
+  // the update on them (a load per vertex inside it is a round trip per step)
+  int32_t deg[kPer];
+  float prev[kPer], cv[kPer];
+  const uint32_t last = static_cast<uint32_t>(u.n - 1 - v0);  // v0 < n: the block has vertices
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const uint32_t o = min(static_cast<uint32_t>(threadIdx.x + k * kPushLdsThreads), last);
+    const int32_t* rp = u.rowptr + v0;
+    deg[k] = rp[o + 1] - rp[o];
+    prev[k] = 0.0f;
+  }
+  if (u.rank_prev) {
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) prev[k] = u.rank_prev[v0 + min(static_cast<uint32_t>(threadIdx.x + k * kPushLdsThreads), last)];
+  }
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     const int32_t i = threadIdx.x + k * kPushLdsThreads;
     cv[k] = 0.0f;
-    if (i < W && v0 + i < u.n) mine += update_vertex(u, v0 + i, acc[i], D, dl, cv[k]);
+    if (i < W && v0 + i < u.n) mine += update_vertex_loaded(u, v0 + i, acc[i], D, dl, cv[k], deg[k], prev[k]);
   }
   __syncthreads();  // every sum has been read: the LDS now holds the contributions and the run bounds
   float* cs = reinterpret_cast<float*>(acc);
