@@ -185,7 +185,21 @@ __global__ void k_queue_degree(const int32_t* __restrict__ queue, const int32_t*
   if (blockIdx.x == 0 && threadIdx.x == 0) *reinterpret_cast<uint64_t*>(stats + gcx::kStatT1) = wall_clock64();
   const int32_t qn = *qlen;
   uint64_t sum = 0, sum_in = 0;  // out-arcs and in-arcs of the queued vertices
-  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < qn; i += gridDim.x * blockDim.x) {
+  // four queue entries per step, their loads issued together (one
+  // dependent pair of round trips per step, not per entry)
+  const int32_t stride = static_cast<int32_t>(gridDim.x * blockDim.x);
+  int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+  for (; static_cast<int64_t>(i) + 3 * static_cast<int64_t>(stride) < qn; i += 4 * stride) {
+    int32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = queue[i + k * stride];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      sum += static_cast<uint64_t>(rowptr[v[k] + 1] - rowptr[v[k]]);
+      if (t_rowptr) sum_in += static_cast<uint64_t>(t_rowptr[v[k] + 1] - t_rowptr[v[k]]);
+    }
+  }
+  for (; i < qn; i += stride) {
     const int32_t v = queue[i];
     sum += static_cast<uint64_t>(rowptr[v + 1] - rowptr[v]);
     if (t_rowptr) sum_in += static_cast<uint64_t>(t_rowptr[v + 1] - t_rowptr[v]);
@@ -1806,12 +1820,20 @@ struct Frontier {
       dec.prior_arcs = m_f;
       dec.clock_khz = g->clock_khz;
     }
-    k_queue_degree<<<256, kThreads, 0, s>>>(queue_next(), g->stats + kQLen, g->rowptr, count_in ? g->t_rowptr : nullptr,
+    k_queue_degree<<<1024, kThreads, 0, s>>>(queue_next(), g->stats + kQLen, g->rowptr, count_in ? g->t_rowptr : nullptr,
                                             g->stats);
     if (decide) k_level_decide<<<1, kThreads, lds, s>>>(g->stats, dec);
     GC_HIP_TRY(hipGetLastError());
     GC_HIP_TRY(hipMemcpyAsync(g->stats_host, g->stats, sizeof(int32_t) * gcx::kStatSlots, hipMemcpyDeviceToHost, s));
-    if (n_f > 0) k_clear_front<<<grid_for(n_f, kThreads), kThreads, 0, s>>>(front(), queue(), n_f);
+    if (n_f > 0) {
+      // the old frontier's bits: through its queue, or, for a frontier of at
+      // least one vertex per 16 words (one per 64-byte line), every word
+      const int64_t words = (static_cast<int64_t>(g->n) + 31) / 32;
+      if (16 * static_cast<int64_t>(n_f) >= words)
+        k_fill_i32<<<grid_for(words, kThreads), kThreads, 0, s>>>(reinterpret_cast<int32_t*>(front()), words, 0);
+      else
+        k_clear_front<<<grid_for(n_f, kThreads), kThreads, 0, s>>>(front(), queue(), n_f);
+    }
     GC_HIP_TRY(hipGetLastError());
     GC_HIP_TRY(hipStreamSynchronize(s));
     n_f = g->stats_host[kQLen];
