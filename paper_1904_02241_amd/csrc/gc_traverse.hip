@@ -311,13 +311,16 @@ __global__ __launch_bounds__(kThreads) void k_bfs_pull(const int32_t* __restrict
                                                        uint32_t* __restrict__ visited, int32_t* __restrict__ queue,
                                                        int32_t* __restrict__ stats) {
   const int32_t v = blockIdx.x * kThreads + threadIdx.x;
-  bool active = false;
+  // the visited word and the row bounds are loaded together (one memory
+  // round trip before the scan, not two)
+  uint32_t vw = ~0u;
   int32_t b = 0, e = 0;
-  if (v < n && !bit_test(visited, v)) {
-    active = true;
+  if (v < n) {
+    vw = visited[v >> 5];
     b = t_rowptr[v];
     e = t_rowptr[v + 1];
   }
+  const bool active = !((vw >> (v & 31)) & 1u);
   const bool found = scan_front(t_col, front, active, b, e);
   if (found) depth[v] = level + 1;
   wave_bits_set(next, v, found);
