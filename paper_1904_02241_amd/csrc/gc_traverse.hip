@@ -110,6 +110,41 @@ __device__ __forceinline__ void block_append_bits(uint32_t took, int32_t vbase, 
   }
 }
 
+// Appends to the queue, with one atomic for the work-group, vals[u] of
+// every thread for the set bits u of took. Every thread of the work-group
+// calls it (it synchronises).
+template <int NT, int kN>
+__device__ __forceinline__ void block_append_list(uint32_t took, const int32_t (&vals)[kN],
+                                                  int32_t* __restrict__ queue, int32_t* __restrict__ qlen) {
+  __shared__ int32_t wave_cnt[NT / kWave];
+  __shared__ int32_t wave_off[NT / kWave];
+  const int lane = gcd::lane_id();
+  const int wid = threadIdx.x / kWave;
+  const int32_t c = __popc(took);
+  int32_t x = c;  // inclusive sum of the counts over the wave's lanes
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int32_t y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) wave_cnt[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t tot = 0;
+    for (int w = 0; w < NT / kWave; ++w) {
+      wave_off[w] = tot;
+      tot += wave_cnt[w];
+    }
+    const int32_t base = tot ? atomicAdd(qlen, tot) : 0;
+    for (int w = 0; w < NT / kWave; ++w) wave_off[w] += base;
+  }
+  __syncthreads();
+  int32_t pos = wave_off[wid] + x - c;
+#pragma unroll
+  for (int u = 0; u < kN; ++u)
+    if ((took >> u) & 1u) queue[pos++] = vals[u];
+}
+
 __device__ __forceinline__ bool bit_test(const uint32_t* bits, int32_t v) {
   return (bits[v >> 5] >> (v & 31)) & 1u;
 }
@@ -1378,12 +1413,15 @@ __global__ __launch_bounds__(kThreads) void k_push_arcs(const int32_t* __restric
     rb = rowptr[u];
     x = r.src(u);
   }
-  // every thread runs the same kPushArcs steps (block_append synchronises the work-group)
-#pragma unroll 1
+  // the thread's kPushArcs arcs; the vertices they discover are appended
+  // together at the end (a work-group append per arc step kept the waves in
+  // lock-step through two barriers per step)
+  int32_t found[kPushArcs];
+  uint32_t took = 0;
+#pragma unroll
   for (int k = 0; k < kPushArcs; ++k) {
     const int64_t a = a0 + k;
-    bool disc = false;
-    int32_t v = 0;
+    found[k] = 0;
     if (a < end) {
       while (a >= ue) {  // next queued vertex with an arc at a
         ++i;
@@ -1394,11 +1432,12 @@ __global__ __launch_bounds__(kThreads) void k_push_arcs(const int32_t* __restric
         x = r.src(u);
       }
       const int64_t e = rb + (a - ub);
-      v = colidx[e];
-      disc = r.relax(v, e, x);
+      const int32_t v = colidx[e];
+      found[k] = v;
+      took |= static_cast<uint32_t>(r.relax(v, e, x)) << k;
     }
-    block_append(disc, v, queue, stats + kQLen);
   }
+  block_append_list<kThreads, kPushArcs>(took, found, queue, stats + kQLen);
 }
 
 __global__ void k_order_degree(const int32_t* __restrict__ order, int32_t cnt, const int32_t* __restrict__ rowptr,
