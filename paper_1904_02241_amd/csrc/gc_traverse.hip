@@ -716,6 +716,26 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
   const int32_t ch = blockIdx.x;
   const int32_t r0 = chunk_beg[ch], r1 = chunk_end[ch], b = chunk_blk[ch], j0 = chunk_j0[ch], ns = chunk_ns[ch];
   if (r0 >= r1) return;  // padding of the dispatch order (uniform)
+  // Each wave streams a contiguous range [qa, qz] of the chunk's tiles. Its
+  // bounds, its first owned row and its first two tiles depend on the
+  // chunk alone, so their loads are issued before the block's LDS fill and
+  // overlap it.
+  const int lane = gcd::lane_id();
+  const int wid = static_cast<int>(threadIdx.x) / kWave;
+  const int32_t q0 = row_ptr[r0] / kRowTile, q1 = (row_ptr[r1] - 1) / kRowTile;
+  const int32_t nt = q1 - q0 + 1;
+  const int32_t qa = q0 + static_cast<int32_t>(static_cast<int64_t>(nt) * wid / kLdsRowWaves);
+  const int32_t qz = q0 + static_cast<int32_t>(static_cast<int64_t>(nt) * (wid + 1) / kLdsRowWaves) - 1;
+  // rows this wave writes: heads at or after its first arc, inside the chunk
+  int32_t own0 = r0;
+  // the raw streams of the next two tiles are in flight while a tile is
+  // reduced (loads clamped to the wave's last tile, so every path issues them)
+  RawTile n1{}, n2{};
+  if (qa <= qz) {  // uniform over the wave
+    own0 = max(heads[static_cast<int64_t>(qa) * (kRowTile / 64)].row, r0);
+    n1 = load_raw_tile<kW>(col16, heads, w_arcs, qa, lane);
+    n2 = load_raw_tile<kW>(col16, heads, w_arcs, min(qa + 1, qz), lane);
+  }
   const int32_t W = 1 << log2W, v0 = b << log2W, cnt = min(W, n - v0);  // cnt >= 1
   // The block's frontier values in LDS, in batches of kFill vertices per
   // thread whose loads are all issued before the first is used: the status
@@ -758,15 +778,7 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
     }
   }
   __syncthreads();
-  const int lane = gcd::lane_id();
-  const int wid = static_cast<int>(threadIdx.x) / kWave;
-  const int32_t q0 = row_ptr[r0] / kRowTile, q1 = (row_ptr[r1] - 1) / kRowTile;
-  const int32_t nt = q1 - q0 + 1;
-  const int32_t qa = q0 + static_cast<int32_t>(static_cast<int64_t>(nt) * wid / kLdsRowWaves);
-  const int32_t qz = q0 + static_cast<int32_t>(static_cast<int64_t>(nt) * (wid + 1) / kLdsRowWaves) - 1;
   if (qa > qz) return;  // no barrier follows
-  // rows this wave writes: heads at or after its first arc, inside the chunk
-  const int32_t own0 = max(heads[static_cast<int64_t>(qa) * (kRowTile / 64)].row, r0);
   bool ovf = false;
   int32_t carry = kInf;  // minimum so far of the row open at the previous tile's end
   int32_t open_row = -1;
@@ -775,10 +787,6 @@ __global__ __launch_bounds__(kLdsRowThreads) void k_sssp_tocab_lds(
   // (past the table: its last sentinel)
   int32_t jwin = 0;
   int32_t sbw = sb[min(lane, ns + kSeekPad - 1)];
-  // the raw streams of the next two tiles are in flight while a tile is
-  // reduced (loads clamped to the wave's last tile, so every path issues them)
-  RawTile n1 = load_raw_tile<kW>(col16, heads, w_arcs, qa, lane);
-  RawTile n2 = load_raw_tile<kW>(col16, heads, w_arcs, min(qa + 1, qz), lane);
   for (int32_t q = qa; q <= qz; ++q) {
     const RawTile cur = n1;
     n1 = n2;
