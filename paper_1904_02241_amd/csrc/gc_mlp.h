@@ -35,9 +35,13 @@ struct Layout {
 // not finite, into *choice. frange (nullable): per input the lowest, then
 // the highest value seen in training; inputs are clamped into it, so a
 // level outside the trained range is decided as the nearest trained one.
-__device__ __forceinline__ void mlp_decide(const float* __restrict__ p, int32_t K, const float (&in_raw)[kIn],
-                                           const float* __restrict__ frange, int32_t* __restrict__ choice,
-                                           float* __restrict__ out) {
+// W2's rows are read from w2 at a pitch of kPitch words (kHid in the
+// parameter vector itself; kHid + 1 for a copy in LDS, where each lane
+// reads its own row and a pitch of kHid would put all of them in one bank).
+template <int kPitch = kHid>
+__device__ __forceinline__ void mlp_decide(const float* __restrict__ p, const float* __restrict__ w2, int32_t K,
+                                           const float (&in_raw)[kIn], const float* __restrict__ frange,
+                                           int32_t* __restrict__ choice, float* __restrict__ out) {
   const Layout L(K);
   const int lane = threadIdx.x;
   float in[kIn];
@@ -48,7 +52,8 @@ __device__ __forceinline__ void mlp_decide(const float* __restrict__ p, int32_t 
   for (int i = 0; i < kIn; ++i) z += p[L.W1 + lane * kIn + i] * in[i];
   const float h1 = fmaxf(z, 0.0f);
   z = p[L.b2 + lane];
-  for (int i = 0; i < kHid; ++i) z += p[L.W2 + lane * kHid + i] * __shfl(h1, i, kWave);
+  for (int i = 0; i < kHid; ++i)
+    z += w2[lane * kPitch + i] * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h1), i));
   const float h2 = fmaxf(z, 0.0f);
   int best = -1;
   float bv = 0.0f;

@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kWave) void k_mlp_decide(const float* __restrict__ 
                                                       const float* __restrict__ frange, int32_t* __restrict__ choice,
                                                       float* __restrict__ out) {
   const float in[kIn] = {f0, f1, f2, f3, f4, f5};
-  mlp_decide(p, K, in, frange, choice, out);
+  mlp_decide(p, p + Layout(K).W2, K, in, frange, choice, out);
 }
 
 // Lowest and highest value of each input over the training rows (one wave

@@ -261,13 +261,20 @@ __global__ void k_queue_degree(const int32_t* __restrict__ queue, const int32_t*
   }
 }
 
+// LDS the learned decision needs: the parameters, and W2 again at a pitch
+// of one word more than its rows.
+size_t level_decide_lds(int32_t K) {
+  return sizeof(float) * (static_cast<size_t>(gcmlp::Layout(K).total) + gcmlp::kHid * (gcmlp::kHid + 1));
+}
+
 // The learned scheduler's decision for the next level, from the counters of
 // the level just ended (read after k_queue_degree): the next frontier's
 // size and out-arcs and the level's time from its clock stamps. The
 // network only picks the form of pull levels, so the kernel first applies
 // the working-set rule's direction test and stops on a push level. Else the
 // work-group stages the parameters in LDS (coalesced, all loads in flight
-// together) and its first wave runs the network.
+// together; W2 at a pitch of kHid + 1, since each lane reads its own row)
+// and its first wave runs the network. Dynamic LDS: level_decide_lds(K).
 __global__ __launch_bounds__(kThreads) void k_level_decide(int32_t* __restrict__ stats, LevelDecide dec) {
   extern __shared__ float sp[];
   const int64_t n_f = stats[gcx::kStatQLen];
@@ -280,8 +287,14 @@ __global__ __launch_bounds__(kThreads) void k_level_decide(int32_t* __restrict__
     if (threadIdx.x == 0) stats[gcx::kStatChoice] = -1;  // push: the rule alone
     return;
   }
-  const int32_t np = gcmlp::Layout(dec.K).total;
-  for (int32_t i = threadIdx.x; i < np; i += kThreads) sp[i] = dec.params[i];
+  const gcmlp::Layout L(dec.K);
+  float* w2 = sp + L.total;  // row r at r * (kHid + 1)
+  for (int32_t i = threadIdx.x; i < L.total; i += kThreads) {
+    const float x = dec.params[i];
+    const int32_t r = i - L.W2;
+    if (r >= 0 && r < gcmlp::kHid * gcmlp::kHid) w2[r + r / gcmlp::kHid] = x;
+    else sp[i] = x;
+  }
   __syncthreads();
   if (threadIdx.x >= kWave) return;
   const uint64_t t0 = *reinterpret_cast<const uint64_t*>(stats + gcx::kStatT0);
@@ -289,8 +302,8 @@ __global__ __launch_bounds__(kThreads) void k_level_decide(int32_t* __restrict__
   const double prior_ms = t1 > t0 ? static_cast<double>(t1 - t0) / dec.clock_khz : 0.0;
   float in[GC_SCHED_INPUTS];
   gcx::level_features(dec.n, dec.m, n_f, m_f, dec.level, prior_ms, dec.prior_arcs, in);
-  gcmlp::mlp_decide(sp, dec.K, in, dec.frange, stats + gcx::kStatChoice,
-                    reinterpret_cast<float*>(stats + gcx::kStatOut));
+  gcmlp::mlp_decide<gcmlp::kHid + 1>(sp, w2, dec.K, in, dec.frange, stats + gcx::kStatChoice,
+                                     reinterpret_cast<float*>(stats + gcx::kStatOut));
 }
 
 // ---------------------------------------------------------------------------
@@ -1860,7 +1873,7 @@ struct Frontier {
                        LevelDecide dec = LevelDecide()) {
     size_t lds = 0;
     if (decide) {
-      lds = sizeof(float) * static_cast<size_t>(gcmlp::Layout(gcx::sched_actions(decide)).total);
+      lds = level_decide_lds(gcx::sched_actions(decide));
       dec.params = gcx::sched_params(decide);
       dec.frange = gcx::sched_range(decide);
       dec.K = gcx::sched_actions(decide);

@@ -149,6 +149,46 @@ def test_network_without_finite_output_falls_back_to_heuristic():
     h.free()
 
 
+@pytest.mark.parametrize("target", [1, 2])
+def test_device_decision_follows_the_network(target):
+    """A network with zero weights whose last-layer biases put action
+    `target` (1 plain pull, 2 TOCAB pull over the attached partition) far
+    below the others: under the learned policy every pull level runs as
+    `target` and every push level as the rule's push. The decision for each
+    level after the first is made on the device, by the last work-group of
+    the previous level's count. BFS levels are unique, so the direction of
+    each level is the rule's run with the partition given; SSSP is checked
+    level by level for {push, target}. Results stay exact."""
+    import paper_1904_02241_amd as gc
+    g = gg.rmat(13, 16, seed=6).with_weights(5)
+    h = load(g, weights=True)
+    part = gc.tocab_partition(h, gc.GC_PULL, 1 << 11, 1024)
+    K = 3
+    theta = np.zeros(gc.sched_param_count(K), np.float32)
+    theta[-K + target] = -5.0  # b3[target]: the only nonzero parameter
+    m = gc.sched_create(K, theta)
+    gc.sched_attach(h, m, [part])  # the network of every kind
+    d = torch().empty(g.n, dtype=torch().int32, device="cuda")
+    for s in gg.sources(g, 2, seed=3):
+        s = int(s)
+        print(f"device decision target {target} source {s}", flush=True)
+        gc.bfs_pull(h, part, s, d, gc.GC_POLICY_HEURISTIC)
+        heur, _ = gc.traversal_trace(h)
+        gc.bfs_pull(h, None, s, d, gc.GC_POLICY_LEARNED)
+        learned, _ = gc.traversal_trace(h)
+        np.testing.assert_array_equal(host(d), oracle.bfs(g.n, g.rowptr, g.colidx, s))
+        assert np.any(heur != 0) and heur[0] == 0
+        np.testing.assert_array_equal(learned, np.where(heur == 0, 0, target))
+        gc.sssp_pull(h, None, s, d, gc.GC_POLICY_LEARNED)
+        learned, _ = gc.traversal_trace(h)
+        np.testing.assert_array_equal(host(d), oracle.dijkstra(g.n, g.rowptr, g.colidx, g.weights, s))
+        assert set(learned.tolist()) == {0, target}, learned
+    gc.sched_attach(h, None)
+    m.free()
+    part.free()
+    h.free()
+
+
 def _train(gc, X, T, K, steps=3000, seed=1):
     """A network trained on rows X (features) and T (ms per action): targets
     are log times over each row's fastest action, rows weighted by the square
