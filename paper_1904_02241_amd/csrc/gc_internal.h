@@ -288,6 +288,7 @@ constexpr int kStatT0 = 4;        // device wall clock at the level's start (64-
 constexpr int kStatT1 = 6;        // device wall clock when its relaxation kernels have finished (64-bit)
 constexpr int kStatChoice = 8;    // learned scheduler: action for the next level (-1: no finite output)
 constexpr int kStatInDegLo = 10;  // in-arcs of the next frontier (64-bit: lo, hi)
+constexpr int kStatMaxDeg = 12;   // largest out-degree in the next frontier
 constexpr int kStatOut = 16;      // learned scheduler: its K outputs (FP32 bit patterns)
 constexpr int kStatSlots = kStatOut + GC_SCHED_HIDDEN;
 

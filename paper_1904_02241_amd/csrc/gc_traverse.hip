@@ -188,6 +188,7 @@ __global__ void k_clear_front(uint32_t* __restrict__ front, const int32_t* __res
 __global__ void k_level_begin(int32_t* __restrict__ stats) {
   if (threadIdx.x < gcx::kStatT0) stats[threadIdx.x] = 0;
   if (threadIdx.x < 2) stats[gcx::kStatInDegLo + threadIdx.x] = 0;
+  if (threadIdx.x == 0) stats[gcx::kStatMaxDeg] = 0;
   if (threadIdx.x == 0) *reinterpret_cast<uint64_t*>(stats + gcx::kStatT0) = wall_clock64();
 }
 
@@ -211,15 +212,17 @@ struct LevelDecide {
   double alpha = 0.0, beta = 0.0;
 };
 
-// Out-arc count of the queued vertices (for the direction heuristic). The
-// kernel runs right after the level's relaxation kernels on the same
-// stream, so its start stamps the end of the level.
+// Out-arc count of the queued vertices (for the direction heuristic) and
+// their largest out-degree (for the choice of push kernel). The kernel
+// runs right after the level's relaxation kernels on the same stream, so
+// its start stamps the end of the level.
 __global__ void k_queue_degree(const int32_t* __restrict__ queue, const int32_t* __restrict__ qlen,
                                const int32_t* __restrict__ rowptr, const int32_t* __restrict__ t_rowptr,
                                int32_t* __restrict__ stats) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *reinterpret_cast<uint64_t*>(stats + gcx::kStatT1) = wall_clock64();
   const int32_t qn = *qlen;
   uint64_t sum = 0, sum_in = 0;  // out-arcs and in-arcs of the queued vertices
+  int32_t mx = 0;                 // largest out-degree among them
   // four queue entries per step, their loads issued together (one
   // dependent pair of round trips per step, not per entry)
   const int32_t stride = static_cast<int32_t>(gridDim.x * blockDim.x);
@@ -230,34 +233,44 @@ __global__ void k_queue_degree(const int32_t* __restrict__ queue, const int32_t*
     for (int k = 0; k < 4; ++k) v[k] = queue[i + k * stride];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      sum += static_cast<uint64_t>(rowptr[v[k] + 1] - rowptr[v[k]]);
+      const int32_t d = rowptr[v[k] + 1] - rowptr[v[k]];
+      sum += static_cast<uint64_t>(d);
+      mx = max(mx, d);
       if (t_rowptr) sum_in += static_cast<uint64_t>(t_rowptr[v[k] + 1] - t_rowptr[v[k]]);
     }
   }
   for (; i < qn; i += stride) {
     const int32_t v = queue[i];
-    sum += static_cast<uint64_t>(rowptr[v + 1] - rowptr[v]);
+    const int32_t d = rowptr[v + 1] - rowptr[v];
+    sum += static_cast<uint64_t>(d);
+    mx = max(mx, d);
     if (t_rowptr) sum_in += static_cast<uint64_t>(t_rowptr[v + 1] - t_rowptr[v]);
   }
   for (int o = 32; o > 0; o >>= 1) {
     sum += __shfl_xor(sum, o, kWave);
     sum_in += __shfl_xor(sum_in, o, kWave);
+    mx = max(mx, __shfl_xor(mx, o, kWave));
   }
   // one atomic per work-group (per-wave atomics on the one counter serialise)
   __shared__ uint64_t part[kThreads / kWave], part_in[kThreads / kWave];
+  __shared__ int32_t part_mx[kThreads / kWave];
   if (gcd::lane_id() == 0) {
     part[threadIdx.x / kWave] = sum;
     part_in[threadIdx.x / kWave] = sum_in;
+    part_mx[threadIdx.x / kWave] = mx;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint64_t total = 0, total_in = 0;
+    int32_t top = 0;
     for (int w = 0; w < kThreads / kWave; ++w) {
       total += part[w];
       total_in += part_in[w];
+      top = max(top, part_mx[w]);
     }
     if (total) atomicAdd(reinterpret_cast<unsigned long long*>(stats + kDegLo), total);
     if (total_in) atomicAdd(reinterpret_cast<unsigned long long*>(stats + gcx::kStatInDegLo), total_in);
+    if (top) atomicMax(stats + gcx::kStatMaxDeg, top);
   }
 }
 
@@ -1845,6 +1858,9 @@ struct Frontier {
   int cur = 0;
   int32_t n_f = 1;
   int64_t m_f = 0;
+  // largest out-degree in the frontier (a traversal's first level: its one
+  // vertex's m_f)
+  int64_t max_deg = INT64_MAX;
   int64_t m_f_in = 0;  // in-arcs of the frontier when count_in (the source's are not counted)
   bool count_in = false;
   uint32_t* front() { return cur == 0 ? g->front : g->next; }
@@ -1902,6 +1918,7 @@ struct Frontier {
     n_f = g->stats_host[kQLen];
     m_f = static_cast<int64_t>(static_cast<uint32_t>(g->stats_host[kDegLo])) |
           (static_cast<int64_t>(g->stats_host[kDegLo + 1]) << 32);
+    max_deg = g->stats_host[gcx::kStatMaxDeg];
     m_f_in = static_cast<int64_t>(static_cast<uint32_t>(g->stats_host[gcx::kStatInDegLo])) |
              (static_cast<int64_t>(g->stats_host[gcx::kStatInDegLo + 1]) << 32);
     if (overflow && g->stats_host[kOverflow]) *overflow = true;
@@ -1923,7 +1940,7 @@ hipError_t init_state(gc_graph g, int32_t* value, int32_t source, bool bfs, hipS
 }
 
 // Arc-balanced push of one level with relaxation r (frontiers with more
-// than one work-group's worth of arcs).
+// than one work-group's worth of arcs, see arc_balanced).
 template <class Relax>
 hipError_t push_arcs(gc_graph g, Frontier& f, Relax r, hipStream_t s) {
   k_order_degree<<<grid_for(f.n_f, kThreads), kThreads, 0, s>>>(f.queue(), f.n_f, g->rowptr, g->arc_deg);
@@ -1935,7 +1952,17 @@ hipError_t push_arcs(gc_graph g, Frontier& f, Relax r, hipStream_t s) {
   return hipGetLastError();
 }
 
-bool arc_balanced(const Frontier& f) { return f.m_f > kThreads * kPushArcs; }
+// The vertex-parallel push kernels balance the arcs of each work-group's
+// kThreads vertices across its threads, so only the spread between
+// work-groups is left: a frontier whose out-degrees are all small takes
+// one launch instead of the five of the arc-balanced form (degree order,
+// scan, push), up to frontiers large enough for launches not to matter.
+constexpr int64_t kBlockPushDegree = 64;
+constexpr int64_t kBlockPushArcs = int64_t{1} << 20;
+
+bool arc_balanced(const Frontier& f) {
+  return f.m_f > kThreads * kPushArcs && (f.max_deg > kBlockPushDegree || f.m_f > kBlockPushArcs);
+}
 
 // Enqueues one level (BFS depth `level` -> level+1, or SSSP round `level`)
 // in the given mode; t is the partition used by a TOCAB level.
@@ -2121,6 +2148,7 @@ hipError_t traverse(gc_graph g, gc_tocab t, int32_t source, int32_t* value, int3
   Frontier f{g, s};
   hipError_t e;
   f.m_f = source_degree(g, source, s, &e);
+  f.max_deg = f.m_f;
   GC_HIP_TRY(e);
   int64_t m_u = g->m - f.m_f;
   int64_t m_u_in = g->m;  // in-arcs of the unvisited vertices (the source's own few left in)
@@ -2286,6 +2314,7 @@ hipError_t bc_run(gc_graph g, gc_tocab t, const int32_t* sources, int32_t n_src,
     Frontier f{g, s};
     hipError_t e;
     f.m_f = source_degree(g, src, s, &e);
+    f.max_deg = f.m_f;
     GC_HIP_TRY(e);
     int64_t m_u = g->m - f.m_f;
     lv_arcs.push_back(f.m_f);
@@ -2382,6 +2411,7 @@ hipError_t collect(gc_graph g, gc_tocab* parts, int32_t n_parts, bool bfs, const
     if (err != hipSuccess) break;
     Frontier f{g, s};
     f.m_f = source_degree(g, sources[si], s, &err);
+    f.max_deg = f.m_f;
     int32_t level = 0;
     double prior_ms = 0.0;  // device time of the previous level (its fastest action), from the clock stamps
     int64_t prior_arcs = 0;
