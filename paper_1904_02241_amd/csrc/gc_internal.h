@@ -50,6 +50,7 @@ struct gc_graph_s {
   int32_t* mark = nullptr;      // SSSP push: round in which a vertex was queued
   int32_t* arc_deg = nullptr;   // out-degrees of a vertex list (arc-balanced push, BC backward)
   int32_t* arc_pre = nullptr;   // [n+1] their exclusive scan
+  int32_t max_out_deg = -1;     // largest out-degree (-1: not found yet; set by the first traversal)
   // betweenness centrality (allocated by the first bc_accumulate call):
   // path counts, two alternating arrays of (1 + delta) / sigma, BFS depths
   // and the vertices in level order of the current source
@@ -288,7 +289,6 @@ constexpr int kStatT0 = 4;        // device wall clock at the level's start (64-
 constexpr int kStatT1 = 6;        // device wall clock when its relaxation kernels have finished (64-bit)
 constexpr int kStatChoice = 8;    // learned scheduler: action for the next level (-1: no finite output)
 constexpr int kStatInDegLo = 10;  // in-arcs of the next frontier (64-bit: lo, hi)
-constexpr int kStatMaxDeg = 12;   // largest out-degree in the next frontier
 constexpr int kStatOut = 16;      // learned scheduler: its K outputs (FP32 bit patterns)
 constexpr int kStatSlots = kStatOut + GC_SCHED_HIDDEN;
 

@@ -188,7 +188,6 @@ __global__ void k_clear_front(uint32_t* __restrict__ front, const int32_t* __res
 __global__ void k_level_begin(int32_t* __restrict__ stats) {
   if (threadIdx.x < gcx::kStatT0) stats[threadIdx.x] = 0;
   if (threadIdx.x < 2) stats[gcx::kStatInDegLo + threadIdx.x] = 0;
-  if (threadIdx.x == 0) stats[gcx::kStatMaxDeg] = 0;
   if (threadIdx.x == 0) *reinterpret_cast<uint64_t*>(stats + gcx::kStatT0) = wall_clock64();
 }
 
@@ -212,17 +211,15 @@ struct LevelDecide {
   double alpha = 0.0, beta = 0.0;
 };
 
-// Out-arc count of the queued vertices (for the direction heuristic) and
-// their largest out-degree (for the choice of push kernel). The kernel
-// runs right after the level's relaxation kernels on the same stream, so
-// its start stamps the end of the level.
+// Out-arc count of the queued vertices (for the direction heuristic). The
+// kernel runs right after the level's relaxation kernels on the same
+// stream, so its start stamps the end of the level.
 __global__ void k_queue_degree(const int32_t* __restrict__ queue, const int32_t* __restrict__ qlen,
                                const int32_t* __restrict__ rowptr, const int32_t* __restrict__ t_rowptr,
                                int32_t* __restrict__ stats) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *reinterpret_cast<uint64_t*>(stats + gcx::kStatT1) = wall_clock64();
   const int32_t qn = *qlen;
   uint64_t sum = 0, sum_in = 0;  // out-arcs and in-arcs of the queued vertices
-  int32_t mx = 0;                 // largest out-degree among them
   // four queue entries per step, their loads issued together (one
   // dependent pair of round trips per step, not per entry)
   const int32_t stride = static_cast<int32_t>(gridDim.x * blockDim.x);
@@ -233,44 +230,34 @@ __global__ void k_queue_degree(const int32_t* __restrict__ queue, const int32_t*
     for (int k = 0; k < 4; ++k) v[k] = queue[i + k * stride];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int32_t d = rowptr[v[k] + 1] - rowptr[v[k]];
-      sum += static_cast<uint64_t>(d);
-      mx = max(mx, d);
+      sum += static_cast<uint64_t>(rowptr[v[k] + 1] - rowptr[v[k]]);
       if (t_rowptr) sum_in += static_cast<uint64_t>(t_rowptr[v[k] + 1] - t_rowptr[v[k]]);
     }
   }
   for (; i < qn; i += stride) {
     const int32_t v = queue[i];
-    const int32_t d = rowptr[v + 1] - rowptr[v];
-    sum += static_cast<uint64_t>(d);
-    mx = max(mx, d);
+    sum += static_cast<uint64_t>(rowptr[v + 1] - rowptr[v]);
     if (t_rowptr) sum_in += static_cast<uint64_t>(t_rowptr[v + 1] - t_rowptr[v]);
   }
   for (int o = 32; o > 0; o >>= 1) {
     sum += __shfl_xor(sum, o, kWave);
     sum_in += __shfl_xor(sum_in, o, kWave);
-    mx = max(mx, __shfl_xor(mx, o, kWave));
   }
   // one atomic per work-group (per-wave atomics on the one counter serialise)
   __shared__ uint64_t part[kThreads / kWave], part_in[kThreads / kWave];
-  __shared__ int32_t part_mx[kThreads / kWave];
   if (gcd::lane_id() == 0) {
     part[threadIdx.x / kWave] = sum;
     part_in[threadIdx.x / kWave] = sum_in;
-    part_mx[threadIdx.x / kWave] = mx;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint64_t total = 0, total_in = 0;
-    int32_t top = 0;
     for (int w = 0; w < kThreads / kWave; ++w) {
       total += part[w];
       total_in += part_in[w];
-      top = max(top, part_mx[w]);
     }
     if (total) atomicAdd(reinterpret_cast<unsigned long long*>(stats + kDegLo), total);
     if (total_in) atomicAdd(reinterpret_cast<unsigned long long*>(stats + gcx::kStatInDegLo), total_in);
-    if (top) atomicMax(stats + gcx::kStatMaxDeg, top);
   }
 }
 
@@ -317,6 +304,25 @@ __global__ __launch_bounds__(kThreads) void k_level_decide(int32_t* __restrict__
   gcx::level_features(dec.n, dec.m, n_f, m_f, dec.level, prior_ms, dec.prior_arcs, in);
   gcmlp::mlp_decide<gcmlp::kHid + 1>(sp, w2, dec.K, in, dec.frange, stats + gcx::kStatChoice,
                                      reinterpret_cast<float*>(stats + gcx::kStatOut));
+}
+
+// Largest out-degree of the graph into *out (zero on entry): one atomic
+// per work-group.
+__global__ __launch_bounds__(kThreads) void k_max_out_degree(const int32_t* __restrict__ rowptr, int32_t n,
+                                                             int32_t* __restrict__ out) {
+  int32_t mx = 0;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+  for (int64_t v = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x; v < n; v += stride)
+    mx = max(mx, rowptr[v + 1] - rowptr[v]);
+  for (int o = kWave / 2; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, kWave));
+  __shared__ int32_t part[kThreads / kWave];
+  if (gcd::lane_id() == 0) part[threadIdx.x / kWave] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t top = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) top = max(top, part[w]);
+    if (top) atomicMax(out, top);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1858,9 +1864,6 @@ struct Frontier {
   int cur = 0;
   int32_t n_f = 1;
   int64_t m_f = 0;
-  // largest out-degree in the frontier (a traversal's first level: its one
-  // vertex's m_f)
-  int64_t max_deg = INT64_MAX;
   int64_t m_f_in = 0;  // in-arcs of the frontier when count_in (the source's are not counted)
   bool count_in = false;
   uint32_t* front() { return cur == 0 ? g->front : g->next; }
@@ -1918,7 +1921,6 @@ struct Frontier {
     n_f = g->stats_host[kQLen];
     m_f = static_cast<int64_t>(static_cast<uint32_t>(g->stats_host[kDegLo])) |
           (static_cast<int64_t>(g->stats_host[kDegLo + 1]) << 32);
-    max_deg = g->stats_host[gcx::kStatMaxDeg];
     m_f_in = static_cast<int64_t>(static_cast<uint32_t>(g->stats_host[gcx::kStatInDegLo])) |
              (static_cast<int64_t>(g->stats_host[gcx::kStatInDegLo + 1]) << 32);
     if (overflow && g->stats_host[kOverflow]) *overflow = true;
@@ -1939,8 +1941,7 @@ hipError_t init_state(gc_graph g, int32_t* value, int32_t source, bool bfs, hipS
   return hipGetLastError();
 }
 
-// Arc-balanced push of one level with relaxation r (frontiers with more
-// than one work-group's worth of arcs, see arc_balanced).
+// Arc-balanced push of one level with relaxation r (see arc_balanced).
 template <class Relax>
 hipError_t push_arcs(gc_graph g, Frontier& f, Relax r, hipStream_t s) {
   k_order_degree<<<grid_for(f.n_f, kThreads), kThreads, 0, s>>>(f.queue(), f.n_f, g->rowptr, g->arc_deg);
@@ -1954,14 +1955,15 @@ hipError_t push_arcs(gc_graph g, Frontier& f, Relax r, hipStream_t s) {
 
 // The vertex-parallel push kernels balance the arcs of each work-group's
 // kThreads vertices across its threads, so only the spread between
-// work-groups is left: a frontier whose out-degrees are all small takes
-// one launch instead of the five of the arc-balanced form (degree order,
-// scan, push), up to frontiers large enough for launches not to matter.
-constexpr int64_t kBlockPushDegree = 64;
+// work-groups is left: on a graph whose out-degrees are all small a
+// frontier takes one launch instead of the five of the arc-balanced form
+// (degree order, scan, push), up to frontiers large enough for launches
+// not to matter.
+constexpr int32_t kBlockPushDegree = 64;
 constexpr int64_t kBlockPushArcs = int64_t{1} << 20;
 
-bool arc_balanced(const Frontier& f) {
-  return f.m_f > kThreads * kPushArcs && (f.max_deg > kBlockPushDegree || f.m_f > kBlockPushArcs);
+bool arc_balanced(const gc_graph_s* g, const Frontier& f) {
+  return f.m_f > kThreads * kPushArcs && (g->max_out_deg > kBlockPushDegree || f.m_f > kBlockPushArcs);
 }
 
 // Enqueues one level (BFS depth `level` -> level+1, or SSSP round `level`)
@@ -1970,7 +1972,7 @@ hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t 
                      hipStream_t s) {
   const int32_t n = g->n;
   if (bfs) {
-    if (mode == Mode::kPush && arc_balanced(f)) {
+    if (mode == Mode::kPush && arc_balanced(g, f)) {
       ProfScope prof("bfs_push", s);
       GC_HIP_TRY(push_arcs(g, f, BfsRelax{value, level, f.next(), g->visited}, s));
     } else if (mode == Mode::kPush) {
@@ -2014,7 +2016,7 @@ hipError_t run_level(gc_graph g, Frontier& f, bool bfs, int32_t* value, int32_t 
                                         f.queue_next(), g->stats)));
     }
   } else {
-    if (mode == Mode::kPush && arc_balanced(f)) {
+    if (mode == Mode::kPush && arc_balanced(g, f)) {
       ProfScope prof("sssp_push", s);
       GC_HIP_TRY(push_arcs(g, f, SsspRelax{g->w, value, level, g->mark, f.next(), g->stats}, s));
     } else if (mode == Mode::kPush) {
@@ -2067,8 +2069,20 @@ double now_ms() {
 }
 
 int64_t source_degree(gc_graph g, int32_t source, hipStream_t s, hipError_t* e) {
-  int32_t rp[2] = {0, 0};
-  *e = hipMemcpyAsync(rp, g->rowptr + source, sizeof(rp), hipMemcpyDeviceToHost, s);
+  int32_t rp[3] = {0, 0, 0};
+  *e = hipMemcpyAsync(rp, g->rowptr + source, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (*e == hipSuccess && g->max_out_deg < 0) {
+    // once per graph: its largest out-degree (arc_balanced), through the
+    // first word of the push's degree scratch
+    k_fill_i32<<<1, kThreads, 0, s>>>(g->arc_deg, 1, 0);
+    k_max_out_degree<<<std::min<int64_t>(grid_for(g->n, kThreads), 1024), kThreads, 0, s>>>(g->rowptr, g->n,
+                                                                                           g->arc_deg);
+    *e = hipGetLastError();
+    if (*e == hipSuccess) *e = hipMemcpyAsync(rp + 2, g->arc_deg, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (*e == hipSuccess) *e = hipStreamSynchronize(s);
+    if (*e == hipSuccess) g->max_out_deg = rp[2];
+    return rp[1] - rp[0];
+  }
   if (*e == hipSuccess) *e = hipStreamSynchronize(s);
   return rp[1] - rp[0];
 }
@@ -2104,7 +2118,7 @@ int32_t mode_action(Mode m) { return m == Mode::kPush ? 0 : (m == Mode::kPull ? 
 // frontier, in the given mode.
 hipError_t run_bc_level(gc_graph g, Frontier& f, int32_t level, Mode mode, gc_tocab t, hipStream_t s) {
   const int32_t n = g->n;
-  if (mode == Mode::kPush && arc_balanced(f)) {
+  if (mode == Mode::kPush && arc_balanced(g, f)) {
     ProfScope prof("bc_push", s);
     GC_HIP_TRY(push_arcs(g, f, BcRelax{g->bc_depth, level, g->bc_sigma, f.next(), g->visited}, s));
   } else if (mode == Mode::kPush) {
@@ -2148,7 +2162,6 @@ hipError_t traverse(gc_graph g, gc_tocab t, int32_t source, int32_t* value, int3
   Frontier f{g, s};
   hipError_t e;
   f.m_f = source_degree(g, source, s, &e);
-  f.max_deg = f.m_f;
   GC_HIP_TRY(e);
   int64_t m_u = g->m - f.m_f;
   int64_t m_u_in = g->m;  // in-arcs of the unvisited vertices (the source's own few left in)
@@ -2314,7 +2327,6 @@ hipError_t bc_run(gc_graph g, gc_tocab t, const int32_t* sources, int32_t n_src,
     Frontier f{g, s};
     hipError_t e;
     f.m_f = source_degree(g, src, s, &e);
-    f.max_deg = f.m_f;
     GC_HIP_TRY(e);
     int64_t m_u = g->m - f.m_f;
     lv_arcs.push_back(f.m_f);
@@ -2411,7 +2423,6 @@ hipError_t collect(gc_graph g, gc_tocab* parts, int32_t n_parts, bool bfs, const
     if (err != hipSuccess) break;
     Frontier f{g, s};
     f.m_f = source_degree(g, sources[si], s, &err);
-    f.max_deg = f.m_f;
     int32_t level = 0;
     double prior_ms = 0.0;  // device time of the previous level (its fastest action), from the clock stamps
     int64_t prior_arcs = 0;
