@@ -91,7 +91,8 @@ Csr build_csr(int32_t n, int64_t num_edges, bool symmetrize, EdgeFn edge) {
 #pragma omp parallel for schedule(dynamic, 4096)
   for (int32_t i = 0; i < n; ++i) {
     const int64_t len = kept[i + 1] - kept[i];
-    std::memcpy(g.colidx.data() + kept[i], tmp.data() + start[i], len * sizeof(int32_t));
+    // (an empty row copies nothing: with no arcs at all colidx has no storage)
+    if (len) std::memcpy(g.colidx.data() + kept[i], tmp.data() + start[i], len * sizeof(int32_t));
   }
   for (int32_t i = 0; i <= n; ++i) g.rowptr[i] = static_cast<int32_t>(kept[i]);
   return g;
@@ -239,7 +240,7 @@ int64_t gg_m(const gg_csr* g) { return g->g.m; }
 
 void gg_export(const gg_csr* g, int32_t* rowptr, int32_t* colidx) {
   std::memcpy(rowptr, g->g.rowptr.data(), (static_cast<size_t>(g->g.n) + 1) * sizeof(int32_t));
-  std::memcpy(colidx, g->g.colidx.data(), static_cast<size_t>(g->g.m) * sizeof(int32_t));
+  if (g->g.m) std::memcpy(colidx, g->g.colidx.data(), static_cast<size_t>(g->g.m) * sizeof(int32_t));
 }
 
 void gg_free(gg_csr* g) { delete g; }

@@ -2,7 +2,7 @@
  * graphs (up to 300 vertices, mean out-degree up to 8, weights in
  * [1, 255]) through every oracle entry point, including the partition's
  * two-call size protocol. Built with AddressSanitizer and UBSan by
- * tests/test_oracle_sanitized.py; exits non-zero if a call fails. */
+ * tests/test_host_sanitizers.py; exits non-zero if a call fails. */
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
