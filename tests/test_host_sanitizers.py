@@ -1,7 +1,9 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer: the C
 oracle (tests/oracle_sanitize_driver.c: every entry point on 200 random
-small graphs) and the graph generators (tests/graphgen_sanitize_driver.cpp:
-each generator at small and degenerate sizes, then weights and sources).
+small graphs), the graph generators (tests/graphgen_sanitize_driver.cpp:
+each generator at small and degenerate sizes, then weights and sources)
+and the OpenMP CPU baseline (tests/cpubase_sanitize_driver.c: transpose,
+pull PageRank and BFS on 100 random small graphs).
 Any out-of-bounds access, leak, undefined operation or malformed result
 ends the run with an error."""
 import os
@@ -46,3 +48,8 @@ def test_oracle_is_clean_under_sanitizers(tmp_path):
 def test_generators_are_clean_under_sanitizers(tmp_path):
     _build_and_run("g++", "c++17", [ROOT / "tests" / "graphgen_sanitize_driver.cpp", ROOT / "graphgen" / "gen.cpp"],
                    tmp_path / "graphgen_drv", extra=("-fopenmp",))
+
+
+def test_cpu_baseline_is_clean_under_sanitizers(tmp_path):
+    _build_and_run("gcc", "gnu11", [ROOT / "tests" / "cpubase_sanitize_driver.c", ROOT / "cpubase" / "cpubase.c"],
+                   tmp_path / "cpubase_drv", extra=("-fopenmp",))
