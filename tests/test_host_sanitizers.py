@@ -2,8 +2,10 @@
 oracle (tests/oracle_sanitize_driver.c: every entry point on 200 random
 small graphs), the graph generators (tests/graphgen_sanitize_driver.cpp:
 each generator at small and degenerate sizes, then weights and sources)
-and the OpenMP CPU baseline (tests/cpubase_sanitize_driver.c: transpose,
-pull PageRank and BFS on 100 random small graphs).
+the OpenMP CPU baseline (tests/cpubase_sanitize_driver.c: transpose, pull
+PageRank and BFS on 100 random small graphs) and the library's C ABI
+argument checks (tests/abi_sanitize_driver.cpp, linked with the library's
+sources built with host-only sanitizers; no GPU needed).
 Any out-of-bounds access, leak, undefined operation or malformed result
 ends the run with an error."""
 import os
@@ -53,3 +55,39 @@ def test_generators_are_clean_under_sanitizers(tmp_path):
 def test_cpu_baseline_is_clean_under_sanitizers(tmp_path):
     _build_and_run("gcc", "gnu11", [ROOT / "tests" / "cpubase_sanitize_driver.c", ROOT / "cpubase" / "cpubase.c"],
                    tmp_path / "cpubase_drv", extra=("-fopenmp",))
+
+
+
+def test_abi_argument_checks_are_clean_under_sanitizers(tmp_path):
+    hipcc = shutil.which("hipcc") or ("/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else None)
+    if hipcc is None:
+        pytest.skip("hipcc not found")
+    import concurrent.futures
+    csrc = ROOT / "paper_1904_02241_amd" / "csrc"
+    # sanitizers on the host side only (each flag behind -Xarch_host)
+    host_san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                "-Xarch_host", "-fno-omit-frame-pointer"]
+    common = ["--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang",
+              "-packed-fp32-ops", "-I", str(ROOT / "include"), "-I", str(csrc), *host_san]
+    sources = sorted(csrc.glob("*.hip")) + [ROOT / "tests" / "abi_sanitize_driver.cpp"]
+
+    def compile_one(src):
+        obj = tmp_path / (src.name + ".o")
+        r = subprocess.run([hipcc, *common, "-c", str(src), "-o", str(obj)], capture_output=True, text=True,
+                           timeout=600)
+        return obj, r
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=8) as ex:
+        built = list(ex.map(compile_one, sources))
+    for obj, r in built:
+        if r.returncode != 0:
+            pytest.skip(f"hipcc could not build {obj.name} with host sanitizers: {r.stderr[-300:]}")
+    exe = tmp_path / "abi_drv"
+    link = subprocess.run([hipcc, "--offload-arch=gfx950", "-Xarch_host", "-fsanitize=address", "-Xarch_host",
+                           "-fsanitize=undefined", *[str(o) for o, _ in built], "-o", str(exe)],
+                          capture_output=True, text=True, timeout=300)
+    if link.returncode != 0:
+        pytest.skip(f"no host sanitizer runtime for hipcc: {link.stderr[-300:]}")
+    run = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120, env=_env())
+    assert run.returncode == 0, run.stdout[-2000:] + run.stderr[-4000:]
+    assert "fails 0" in run.stdout
