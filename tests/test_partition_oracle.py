@@ -107,3 +107,29 @@ def test_block_count_reproduces_table4():
     assert consistent(1 << 18) == 8
     for W in (256, 1 << 16, 1 << 17, 1 << 19, 1 << 20, 250000):
         assert consistent(W) < 8
+
+
+def _random_csr(n, m, seed):
+    """n vertices, up to m distinct arcs (duplicates merged), rows sorted."""
+    rng = np.random.default_rng(seed)
+    keys = np.unique(rng.integers(0, n, m).astype(np.int64) * n + rng.integers(0, n, m))
+    rows, cols = keys // n, (keys % n).astype(np.int32)
+    rowptr = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=n))]).astype(np.int32)
+    return rowptr, cols, rng.integers(1, 256, cols.shape[0]).astype(np.int32)
+
+
+try:
+    from hypothesis import given, settings, strategies as st
+except ImportError:  # pragma: no cover
+    given = None
+
+if given is not None:
+    @settings(max_examples=80, deadline=None, derandomize=True)
+    @given(n=st.integers(1, 48), m=st.integers(0, 300), W=st.integers(1, 60), k=st.integers(1, 60),
+           seed=st.integers(0, 2 ** 31))
+    def test_partition_invariants_random(n, m, W, k, seed):
+        """Random graphs (including arc-free ones) with widths and merge
+        ranges that need not be powers of two or divide n."""
+        rowptr, cols, w = _random_csr(n, m, seed)
+        p = oracle.partition(n, n, rowptr, cols, W, k, w)
+        check_partition(n, n, rowptr, cols, w, W, k, p)
