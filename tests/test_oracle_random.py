@@ -86,3 +86,42 @@ def test_pagerank_matches_dense_recurrence(n, m, seed, iters):
         want = (1 - d) / n + d * (M @ want)
     got = oracle.pagerank(n, rowptr, cols, d, iters, mode=oracle.LEAK, r0=r0)
     np.testing.assert_allclose(got, want, rtol=0, atol=1e-13)
+
+
+@settings(max_examples=30, deadline=None, derandomize=True)
+@given(n=st.integers(1, 30), m=st.integers(0, 150), seed=st.integers(0, 2 ** 31), n_src=st.integers(1, 6))
+def test_bc_matches_networkx_subset(n, m, seed, n_src):
+    import networkx as nx
+    rowptr, cols, _ = random_csr(n, m, seed)
+    G = nx.DiGraph()
+    G.add_nodes_from(range(n))
+    src = np.repeat(np.arange(n), np.diff(rowptr))
+    G.add_edges_from(zip(src.tolist(), cols.tolist()))
+    sources = sorted(set(np.random.default_rng(seed + 7).integers(0, n, n_src).tolist()))
+    want = nx.betweenness_centrality_subset(G, sources, list(range(n)), normalized=False)
+    got = oracle.bc(n, rowptr, cols, sources)
+    np.testing.assert_allclose(got, [want[v] for v in range(n)], rtol=1e-12, atol=1e-12)
+
+
+@settings(max_examples=40, deadline=None, derandomize=True)
+@given(**GRAPHS, iters=st.integers(0, 12))
+def test_ppr_and_spmv_match_dense(n, m, seed, iters):
+    rowptr, cols, _ = random_csr(n, m, seed)
+    A = as_scipy(n, rowptr, cols).toarray()
+    deg = A.sum(axis=1)
+    M = np.zeros((n, n))
+    nz = deg > 0
+    M[:, nz] = (A[nz, :] / deg[nz, None]).T
+    rng = np.random.default_rng(seed + 3)
+    p = rng.random(n)
+    p /= p.sum()
+    d = 0.85
+    # personalised: the teleport and the dangling mass both go to p
+    want = p.copy()
+    for _ in range(iters):
+        want = (1 - d) * p + d * (M @ want + want[~nz].sum() * p)
+    np.testing.assert_allclose(oracle.ppr(n, rowptr, cols, p, d, iters), want, rtol=0, atol=1e-13)
+    vals = rng.uniform(-1.0, 1.0, cols.shape[0])
+    x = rng.uniform(-1.0, 1.0, n)
+    np.testing.assert_allclose(oracle.spmv(n, rowptr, cols, vals, x), as_scipy(n, rowptr, cols, vals).T @ x,
+                               rtol=0, atol=1e-12)
